@@ -1,0 +1,21 @@
+"""Shared pytest setup: the ``gpu`` marker and import paths."""
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+
+
+@pytest.fixture(scope="session")
+def orc():
+    """The FP64 CPU oracle (built on first use)."""
+    from oracle import build_oracle, oracle
+    build_oracle.build(force=False)
+    return oracle
