@@ -1,0 +1,179 @@
+"""Pin of the oracle's closure tensors (items 9-11) against the Chapman-Enskog
+relations they come from, derived symbolically here without the item-11
+expressions:
+
+* eq. 3eps1 and eq. xi1:  Xi = (h/3) (g^2+4g+1)/(g+1) [d_t phi0 + d_d psi0];
+* eq. sigma2:  Sigma = h (g+1)/2 d_t2 pi0 + h (g^2+4g+1)/(6(g-1)) d_t1 (pi* - pi)^(1),
+  with (pi* - pi)^(1)/h = d_t1 pi0 + d_g phi0 (eq. 2eps1) where, as in App. C,
+  phi0 is replaced by pi0_ab u_g + p (u_a d_bg + u_b d_ag) (terms of order u^3
+  neglected),
+  d_t2 j_a = -(1/2)(g+1)/(g-1) d_b (pi* - pi)^(1)_ab (eq. 1eps2 with
+  eq. plusminuspi and Sigma^(1) = 0) and d_t2 rho = 0;
+* pi0, phi0, psi0 = equilibrium moments (eqs. euler00, phi00, psi00);
+* d_t1 from the Euler equations (eqs. 0eps1, 1eps1): d_t rho = -d_b (rho u_b),
+  d_t u_a = -u_b d_b u_a - d_a p / rho;
+* p(rho) = rho c_s^2(rho) of App. B, differentiated by sympy.
+
+The oracle evaluates its finite-difference closure on long-wavelength fields;
+the two agree up to the O(k^4) truncation of the fourth-order stencils.
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+import sympy as sp
+
+GAMMA = 0.2
+EOS = dict(A=0.8, rho1=0.3, rho2=1.0, cs2_1=0.45)
+
+
+def _setup(d):
+    xs = sp.symbols("x y z")[:d]
+    t = sp.Symbol("t")
+    rho = sp.Function("rho")(*xs, t)
+    us = [sp.Function(f"u{a}")(*xs, t) for a in range(d)]
+    D = EOS["rho2"] - EOS["rho1"]
+    R = sp.Symbol("R", positive=True)
+    cs2 = EOS["cs2_1"] * sp.exp(EOS["A"] * D / sp.pi * (1 - sp.cos(sp.pi * (R - EOS["rho1"]) / D)))
+    pR = R * cs2
+    p = pR.subs(R, rho)
+    rhs = {rho: -sum(sp.diff(rho * us[b], xs[b]) for b in range(d))}
+    for a in range(d):
+        rhs[us[a]] = -sum(us[b] * sp.diff(us[a], xs[b]) for b in range(d)) - sp.diff(p, xs[a]) / rho
+    return xs, t, rho, us, p, rhs
+
+
+def _dt(expr, t, rhs):
+    """Total time derivative with the Euler right-hand sides substituted."""
+    e = sp.diff(expr, t)
+    reps = {}
+    for der in e.atoms(sp.Derivative):
+        if t in der.variables:
+            spatial = [v for v in der.variables if v != t]
+            base = rhs[der.expr]
+            reps[der] = sp.diff(base, *spatial) if spatial else base
+    return e.xreplace(reps)
+
+
+def _moments(d, rho, us, p):
+    I = lambda a, b: 1 if a == b else 0
+    pi0 = [[p * I(a, b) + rho * us[a] * us[b] for b in range(d)] for a in range(d)]
+    phi0 = {}
+    for a, b, g in itertools.product(range(d), repeat=3):
+        phi0[a, b, g] = p * (I(a, b) * us[g] + I(a, g) * us[b] + I(b, g) * us[a])
+    psi0 = {}
+    for a, b, g, e in itertools.product(range(d), repeat=4):
+        psi0[a, b, g, e] = (p**2 / rho * (I(a, b) * I(g, e) + I(a, g) * I(b, e) + I(a, e) * I(b, g))
+                            + p * (I(a, b) * us[g] * us[e] + I(a, g) * us[b] * us[e]
+                                   + I(a, e) * us[b] * us[g] + I(g, e) * us[a] * us[b]
+                                   + I(b, e) * us[a] * us[g] + I(b, g) * us[a] * us[e]))
+    return pi0, phi0, psi0
+
+
+def derived_closure(d):
+    xs, t, rho, us, p, rhs = _setup(d)
+    g = sp.Float(GAMMA)
+    pi0, phi0, psi0 = _moments(d, rho, us, p)
+    # (pi* - pi)^(1) / h by eq. 2eps1, with App. C's form of phi0 in which
+    # terms of order u^3 are neglected: phi0 ~ pi0_ab u_g + p (u_a d_bg + u_b d_ag)
+    I = lambda a, b: 1 if a == b else 0
+    phi0_c = {(a, b, c): pi0[a][b] * us[c] + p * (us[a] * I(b, c) + us[b] * I(a, c))
+              for a, b, c in itertools.product(range(d), repeat=3)}
+    dpi = [[_dt(pi0[a][b], t, rhs) + sum(sp.diff(phi0_c[a, b, c], xs[c]) for c in range(d))
+            for b in range(d)] for a in range(d)]
+    dt2j = [-(g + 1) / (2 * (g - 1)) * sum(sp.diff(dpi[a][b], xs[b]) for b in range(d))
+            for a in range(d)]
+    Sigma = {}
+    for a in range(d):
+        for b in range(a, d):
+            dt2pi = us[a] * dt2j[b] + us[b] * dt2j[a]     # d_t2 rho = 0
+            Sigma[a, b] = (g + 1) / 2 * dt2pi + (g**2 + 4 * g + 1) / (6 * (g - 1)) * _dt(dpi[a][b], t, rhs)
+    Xi = {}
+    for a, b, c in itertools.combinations_with_replacement(range(d), 3):
+        bracket = _dt(phi0[a, b, c], t, rhs) + sum(sp.diff(psi0[a, b, c, e], xs[e]) for e in range(d))
+        Xi[a, b, c] = (g**2 + 4 * g + 1) / (3 * (g + 1)) * bracket
+    return xs, t, rho, us, Sigma, Xi
+
+
+def _fields(d, L):
+    k = 2 * math.pi / L
+    X = sp.symbols("x y z")[:d]
+    if d == 2:
+        x, y = X
+        rho = 1.38 + 0.06 * sp.sin(k * x + 0.3) * sp.cos(k * y - 0.7) + 0.03 * sp.cos(k * y + 1.1)
+        u = [0.04 * sp.sin(k * y + 0.2) + 0.02 * sp.cos(k * x - 0.4),
+             0.03 * sp.cos(k * x + 0.9) * sp.sin(k * y) - 0.02 * sp.sin(k * x)]
+    else:
+        x, y, z = X
+        rho = (1.38 + 0.05 * sp.sin(k * x + 0.3) * sp.cos(k * y - 0.7)
+               + 0.03 * sp.cos(k * z + 1.1) + 0.02 * sp.sin(k * y) * sp.sin(k * z))
+        u = [0.04 * sp.sin(k * y + 0.2) + 0.02 * sp.cos(k * z - 0.4),
+             0.03 * sp.cos(k * x + 0.9) * sp.sin(k * z) - 0.02 * sp.sin(k * x),
+             0.025 * sp.sin(k * x - 0.5) + 0.02 * sp.cos(k * y + 0.8) * sp.cos(k * z)]
+    return X, rho, u
+
+
+def closure_errors(orc, d, L, derived):
+    """max relative error of every independent component at box size L."""
+    xs, t, rho_f, u_f, Sigma, Xi = derived
+    X, rho_e, u_e = _fields(d, L)
+    sub = {rho_f: rho_e}
+    for a in range(d):
+        sub[u_f[a]] = u_e[a]
+    grids = np.meshgrid(*[np.arange(L, dtype=float)] * d, indexing="ij")[::-1]
+    coords = [gg.ravel() for gg in grids]     # x fastest in the flattened order
+
+    cache = {}
+
+    def ev_atom(atom):
+        # a field or one of its spatial derivatives, on the concrete fields
+        if atom not in cache:
+            f = sp.lambdify(X, atom.subs(sub).doit(), "numpy")
+            cache[atom] = np.broadcast_to(np.asarray(f(*coords), dtype=float), coords[0].shape)
+        return cache[atom]
+
+    def ev(expr):
+        atoms = sorted(expr.atoms(sp.Derivative), key=sp.default_sort_key)
+        atoms += [fn for fn in [rho_f, *u_f] if expr.has(fn)]
+        syms = sp.symbols(f"w0:{len(atoms)}")
+        f = sp.lambdify(syms, expr.xreplace(dict(zip(atoms, syms))), "numpy")
+        out = f(*[ev_atom(a) for a in atoms])
+        return np.broadcast_to(np.asarray(out, dtype=float), coords[0].shape)
+
+    N = L**d
+    rho = ev(rho_f).copy()
+    u = np.stack([ev(uf) for uf in u_f], axis=1)
+    m = orc.Model(Q=59 if d == 3 else 21, nx=L, ny=L, nz=L if d == 3 else 1, gamma=GAMMA,
+                  rho0=0.3, **EOS)
+    j = np.zeros((N, 3))
+    j[:, :d] = rho[:, None] * u
+    Sig_o, Xi_o = orc.closure(m, rho, j, np.zeros((N, 3)))
+    out = {}
+    for (a, b), expr in Sigma.items():
+        ref = ev(expr)
+        scale = np.abs(ref).max()
+        assert scale > 1e-7
+        out["S", a, b] = max(np.abs(Sig_o[:, a, b] - ref).max(), np.abs(Sig_o[:, b, a] - ref).max()) / scale
+    for (a, b, c), expr in Xi.items():
+        ref = ev(expr)
+        scale = np.abs(ref).max()
+        assert scale > 1e-7
+        out["X", a, b, c] = max(np.abs(Xi_o[:, q[0], q[1], q[2]] - ref).max()
+                                for q in set(itertools.permutations((a, b, c)))) / scale
+    return out
+
+
+@pytest.mark.parametrize("d,L,bound", [(2, 48, 5e-5), (3, 16, 5e-3)])
+def test_closure_matches_chapman_enskog(orc, d, L, bound):
+    """Every component of Sigma and Xi' (with j~ = 0) converges to the
+    derived continuum closure at the fourth order of the stencils: the error
+    drops by 2^4 = 16 when the wavelength doubles (12..20 accepted) and is
+    small in absolute terms.  A wrong or missing term would leave an O(1)
+    error floor that does not shrink."""
+    derived = derived_closure(d)
+    e1 = closure_errors(orc, d, L, derived)
+    e2 = closure_errors(orc, d, 2 * L, derived)
+    for k in e1:
+        assert e2[k] < bound, (k, e2[k])
+        assert 12.0 < e1[k] / e2[k] < 20.0, (k, e1[k], e2[k])
