@@ -1,0 +1,185 @@
+/*
+ * lb2p.h -- C ABI of the MI355X (gfx950) implementation of the consistent
+ * two-phase lattice Boltzmann step of Zelko & Duenweg, "Consistent two-phase
+ * Lattice Boltzmann model for gas-liquid systems" (arXiv:1402.2920).
+ *
+ * One call of lb2p_step advances the lattice by one time step h = 1: the
+ * Supplemental Material's items 1-12 (moments, equation of state, interface
+ * force, the implicit solve for the correction current j~ and the flow
+ * velocity u, the closure tensors Sigma and Xi', the bulk, interface and
+ * correction collision operators, streaming).  Lattice units h = a = 1
+ * (Tables I and II); every boundary is periodic (Sec. VI).
+ *
+ * Conventions common to every entry point
+ *   - Every function returns an lb2p_status; no C++ exception crosses the ABI.
+ *   - Site index s = x + nx*(y + ny*z).  Scalar fields are arrays [N], vector
+ *     fields are structure-of-arrays [d][N] (d = 2 for D2Q21, 3 for D3Q59).
+ *     N = nx*ny*nz (nz = 1 for D2Q21).
+ *   - Pointers marked "host or device" are host memory when on_device == 0 and
+ *     device memory of the context's GPU when on_device != 0.  The caller owns
+ *     them; the library reads/writes them only during the call, which is
+ *     synchronous with respect to the caller's buffers (device pointers are
+ *     used on the context's stream, which the call synchronises before
+ *     returning).
+ *   - The context owns all device state (two population buffers and the
+ *     per-site fields) until lb2p_destroy.
+ *   - Errors LB2P_ENOCONV and LB2P_ENONFINITE are sticky: every later call
+ *     reports them until the next lb2p_init / lb2p_set_populations.
+ */
+#ifndef LB2P_H
+#define LB2P_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LB2P_OK = 0,
+    LB2P_EINVAL = 1,      /* bad argument: lattice, grid side < 8, gamma not in
+                             (-1,1), kappa < 0, tol < 0, null pointer, ...     */
+    LB2P_EEOS = 2,        /* equation of state outside App. B's admissible set,
+                             or a reference weight w_i(rho0) not positive      */
+    LB2P_ENOCONV = 3,     /* j~ iteration reached max_iter before tol; the step
+                             is still taken with the last iterate              */
+    LB2P_ENONFINITE = 4,  /* NaN or Inf found in the density                   */
+    LB2P_ENOMEM = 5,      /* device allocation failed                          */
+    LB2P_EHIP = 6,        /* HIP runtime error                                 */
+    LB2P_ESTATE = 7       /* call out of order (e.g. step before init)        */
+} lb2p_status;
+
+/* Velocity sets of Tables I (D3Q59) and II (D2Q21). */
+typedef enum { LB2P_D2Q21 = 21, LB2P_D3Q59 = 59 } lb2p_lattice;
+
+/* Population storage.  F64 computes in FP64; every other form computes in
+ * FP32.  BF16/F16 store n_i as deviations from o_i = W_i rho_ref scaled by
+ * 1/W_i, where W_i are the rest weights at the reference density rho_ref
+ * (lb2p_params.store_rho_ref). */
+typedef enum {
+    LB2P_STORE_F64 = 0,
+    LB2P_STORE_F32 = 1,
+    LB2P_STORE_BF16 = 2,
+    LB2P_STORE_F16 = 3
+} lb2p_storage;
+
+/* Element type of caller buffers. */
+typedef enum { LB2P_DTYPE_F64 = 0, LB2P_DTYPE_F32 = 1 } lb2p_dtype;
+
+/* Field selectors for lb2p_get_field (state of the last step's items 1-11,
+ * or of the last lb2p_moments call).  Tensor components are listed with the
+ * field. */
+typedef enum {
+    LB2P_FIELD_RHO = 0,     /* [N]      density, item 1                       */
+    LB2P_FIELD_J0 = 1,      /* [d][N]   sum_i n_i c_i, item 1                 */
+    LB2P_FIELD_FORCE = 2,   /* [d][N]   interface force f, item 2             */
+    LB2P_FIELD_JTILDE = 3,  /* [d][N]   correction current j~, items 3-8      */
+    LB2P_FIELD_U = 4,       /* [d][N]   flow velocity u = j/rho, item 8       */
+    LB2P_FIELD_SIGMA = 5,   /* [3][N] 2D: xx yy xy; [6][N] 3D: xx yy zz xy xz yz */
+    LB2P_FIELD_XI = 6       /* [4][N] 2D: xxx yyy xxy xyy;
+                               [10][N] 3D: xxx yyy zzz xxy xxz xyy xzz yyz yzz xyz */
+} lb2p_field;
+
+/* App. B: psi(rho) = A sin(pi (rho-rho1)/(rho2-rho1)) on (rho1, 2 rho2 - rho1),
+ * zero elsewhere; c_s^2(rho) = cs2_rho1 exp(int_{rho1}^{rho} psi); p = rho c_s^2. */
+typedef struct {
+    double rho1, rho2, A, cs2_rho1;
+} lb2p_eos;
+
+typedef struct {
+    int lattice;            /* lb2p_lattice                                    */
+    int nx, ny, nz;         /* every side >= 8; nz == 1 for D2Q21              */
+    int storage;            /* lb2p_storage                                    */
+    double gamma;           /* BGK parameter, -1 < gamma < 1 (Sec. II)         */
+    double kappa;           /* interfacial stiffness >= 0 (Sec. II)            */
+    lb2p_eos eos;           /* equation of state (App. B)                      */
+    double rho0;            /* fixed reference density of Delta^int and
+                               Delta^corr (Secs. VI, VIII)                     */
+    double tol;             /* j~ iteration stops when max_r |j~new - j~| <=
+                               tol * max_r |j0'|  (Sec. IX)                    */
+    int max_iter;           /* iteration cap (> 0)                             */
+    int fixed_iter;         /* > 0: exactly this many iterations, no test and
+                               no host synchronisation inside lb2p_step        */
+    int warm_start;         /* != 0: start from the previous step's j~ (Sec. IX
+                               allows zero or the previous value)              */
+    int check_every;        /* convergence readback granularity in iterations
+                               (0 = library default)                          */
+    double store_rho_ref;   /* reference density of BF16/F16 deviation storage
+                               (<= 0: mean of the density given to lb2p_init) */
+} lb2p_params;
+
+/* Diagnostics of the state (FP64 sums over all sites). */
+typedef struct {
+    double mass;            /* sum_r rho                                       */
+    double mom[3];          /* sum_r j0                                        */
+    int iters;              /* iterations used by the last j~ solve            */
+    double resid;           /* last max_r |j~new - j~|                         */
+    double jscale;          /* max_r |j0'| of the last solve                   */
+    int nonfinite;          /* 1 if a NaN/Inf density was seen                 */
+} lb2p_stats;
+
+typedef struct lb2p_ctx lb2p_ctx;
+
+/* Fill *out with defaults for a lattice and grid: gamma 0, kappa 0, the EOS
+ * rho1 0.3, rho2 1.0, A 0, cs2_rho1 0.45, rho0 = rho1, FP32 storage,
+ * tol 1e-6 (F32) / 1e-13 (F64), max_iter 200, warm_start 1. */
+lb2p_status lb2p_default_params(int lattice, int nx, int ny, int nz, int storage,
+                                lb2p_params *out);
+
+/* Validate params (Sec. II gamma range, App. B admissibility: weights positive
+ * for every c_s^2 the EOS takes, a two-phase region psi < -1/rho, positive
+ * bulk viscosity psi < (2/d)/rho (Sec. VII); W_i(rho0) > 0) and allocate the
+ * device state on the current HIP device.  hip_stream is a hipStream_t (NULL
+ * = default stream); every later call enqueues its work there.
+ * Errors: EINVAL, EEOS, ENOMEM, EHIP. */
+lb2p_status lb2p_create(const lb2p_params *params, void *hip_stream, lb2p_ctx **out);
+
+/* Set the initial populations n_i(r, 0) = n_eq(rho(r), u(r)) of Sec. III with
+ * the local weights.  rho [N], u [d][N]; dtype lb2p_dtype; host or device.
+ * Resets the sticky status and the warm-start j~ to zero.
+ * Errors: EINVAL, EHIP. */
+lb2p_status lb2p_init(lb2p_ctx *ctx, const void *rho, const void *u, int dtype, int on_device);
+
+/* Advance nsteps >= 0 time steps (Supplemental items 1-12 each).
+ * Asynchronous on the context's stream when fixed_iter > 0; otherwise the
+ * iteration's convergence test reads one flag back every check_every
+ * iterations.  Returns ENOCONV if any step's solve hit max_iter.
+ * Errors: ESTATE (no init), ENOCONV, EHIP. */
+lb2p_status lb2p_step(lb2p_ctx *ctx, int nsteps);
+
+/* Density and converged flow velocity u = j/rho of the CURRENT state
+ * (items 1-8 evaluated without colliding).  rho_out [N], u_out [d][N]
+ * (either may be NULL); dtype lb2p_dtype; host or device.  st may be NULL.
+ * Errors: ESTATE, ENOCONV, ENONFINITE, EHIP. */
+lb2p_status lb2p_moments(lb2p_ctx *ctx, void *rho_out, void *u_out, int dtype,
+                         int on_device, lb2p_stats *st);
+
+/* One per-site field of the last evaluated items 1-11 (see lb2p_field), as
+ * dtype into out (host or device), component-major.  Sigma and Xi' are only
+ * defined after a lb2p_step (they are not part of lb2p_moments).
+ * Errors: EINVAL, ESTATE, EHIP. */
+lb2p_status lb2p_get_field(lb2p_ctx *ctx, int field, void *out, int dtype, int on_device);
+
+/* Pre-collision populations n_i(r, t) as [Q][N] FP64 in the library's
+ * velocity order (lb2p_velocities); host or device.  set_ replaces the state
+ * (and resets the sticky status); get_ decodes the stored form.
+ * Errors: EINVAL, ESTATE, EHIP. */
+lb2p_status lb2p_get_populations(lb2p_ctx *ctx, double *n_out, int on_device);
+lb2p_status lb2p_set_populations(lb2p_ctx *ctx, const double *n_in, int on_device);
+
+/* The library's velocity order: c_out[3*Q] (z = 0 for D2Q21).  Returns Q in
+ * *q_out.  Host memory.  Errors: EINVAL. */
+lb2p_status lb2p_velocities(int lattice, int *c_out, int *q_out);
+
+/* Diagnostics (FP64 totals of mass and momentum of the current state, last
+ * solve's iteration count and residual, non-finite flag).  Errors: EHIP. */
+lb2p_status lb2p_stats_get(lb2p_ctx *ctx, lb2p_stats *st);
+
+/* Release everything the context owns.  NULL is accepted. */
+void lb2p_destroy(lb2p_ctx *ctx);
+
+/* Static description of a status code. */
+const char *lb2p_strerror(lb2p_status st);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LB2P_H */

@@ -1,0 +1,800 @@
+// kernels.hpp -- gfx950 kernels of one consistent two-phase LB step.
+//
+// Populations live in two structure-of-arrays buffers A/B of Q planes
+// [Q][nz][ny][nx].  The buffer read by a step holds post-collision values at
+// their source sites, so the pre-collision population of the step is the pull
+// n_i(r) = A_i(r - c_i); the collision writes n*_i(r) at r into the other
+// buffer.  (The paper pushes n*_i to r + c_i; on a periodic lattice the two
+// forms are the same map.)
+//
+// Threads map one-to-one onto sites with x fastest; a block covers whole x
+// rows when nx <= 256 so the misaligned x offsets of the pull stay inside a
+// block.  All per-site fields are structure-of-arrays [comp][N].
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "lattice.hpp"
+
+namespace lb2p {
+
+struct Geom {
+    int nx, ny, nz;
+    long long N;
+};
+
+// Constants of the collision (one context).
+struct Coef {
+    double gamma, kappa;
+    double c0sq;          // c_s^2(rho0)
+    double Wk[8];         // W_k = w_k(c0^2), reference shell weights
+    EosParams eos;
+};
+
+// Population storage codecs.  Plain forms hold n_i; deviation forms hold
+// (n_i - off_k) / scl_k with per-shell constants.
+struct DevScale {
+    float off[8];
+    float scl[8];
+    float inv[8];
+};
+
+template <class S>
+struct Codec;
+
+template <>
+struct Codec<double> {
+    using R = double;
+    __device__ static inline double dec(double v, const DevScale&, int) { return v; }
+    __device__ static inline double enc(double v, const DevScale&, int) { return v; }
+};
+template <>
+struct Codec<float> {
+    __device__ static inline float dec(float v, const DevScale&, int) { return v; }
+    __device__ static inline float enc(float v, const DevScale&, int) { return v; }
+};
+template <>
+struct Codec<_Float16> {
+    __device__ static inline float dec(_Float16 v, const DevScale& s, int k)
+    {
+        return fmaf(static_cast<float>(v), s.scl[k], s.off[k]);
+    }
+    __device__ static inline _Float16 enc(float v, const DevScale& s, int k)
+    {
+        return static_cast<_Float16>((v - s.off[k]) * s.inv[k]);
+    }
+};
+template <>
+struct Codec<__bf16> {
+    __device__ static inline float dec(__bf16 v, const DevScale& s, int k)
+    {
+        return fmaf(static_cast<float>(v), s.scl[k], s.off[k]);
+    }
+    __device__ static inline __bf16 enc(float v, const DevScale& s, int k)
+    {
+        return static_cast<__bf16>((v - s.off[k]) * s.inv[k]);
+    }
+};
+
+__device__ __forceinline__ int wrap(int v, int n)
+{
+    v += (v < 0) ? n : 0;
+    v -= (v >= n) ? n : 0;
+    return v;
+}
+
+__device__ __forceinline__ long long sidx(const Geom& g, int x, int y, int z)
+{
+    return (long long)x + (long long)g.nx * ((long long)y + (long long)g.ny * z);
+}
+
+__device__ __forceinline__ long long nbr(const Geom& g, int x, int y, int z, int dx, int dy, int dz)
+{
+    return sidx(g, wrap(x + dx, g.nx), wrap(y + dy, g.ny), wrap(z + dz, g.nz));
+}
+
+struct SiteXYZ {
+    int x, y, z;
+    bool ok;
+};
+
+__device__ __forceinline__ SiteXYZ site_of_thread(const Geom& g)
+{
+    SiteXYZ s;
+    s.x = blockIdx.x * blockDim.x + threadIdx.x;
+    s.y = blockIdx.y * blockDim.y + threadIdx.y;
+    s.z = blockIdx.z;
+    s.ok = s.x < g.nx && s.y < g.ny;
+    return s;
+}
+
+// Axis offsets: axis a -> unit vector.
+__device__ __forceinline__ void unit(int a, int& dx, int& dy, int& dz)
+{
+    dx = (a == 0);
+    dy = (a == 1);
+    dz = (a == 2);
+}
+
+// D1 (Sec. IV B) of component `comp` of an SoA field along axis a.
+template <class R>
+__device__ __forceinline__ R d1_field(const Geom& g, const R* F, int x, int y, int z, int a)
+{
+    int dx, dy, dz;
+    unit(a, dx, dy, dz);
+    R m2 = F[nbr(g, x, y, z, -2 * dx, -2 * dy, -2 * dz)];
+    R m1 = F[nbr(g, x, y, z, -dx, -dy, -dz)];
+    R p1 = F[nbr(g, x, y, z, dx, dy, dz)];
+    R p2 = F[nbr(g, x, y, z, 2 * dx, 2 * dy, 2 * dz)];
+    return d1<R>(m2, m1, p1, p2);
+}
+
+// Symmetric rank-2 component index (xx yy zz xy xz yz / xx yy xy).
+template <int D>
+__host__ __device__ constexpr int sym2(int a, int b)
+{
+    if (a == b) return a;
+    int lo = a < b ? a : b, hi = a < b ? b : a;
+    if (D == 2) return 2;
+    return lo == 0 ? (hi == 1 ? 3 : 4) : 5;
+}
+
+// Symmetric rank-3 component index.
+// 3D: xxx yyy zzz xxy xxz xyy xzz yyz yzz xyz ; 2D: xxx yyy xxy xyy.
+template <int D>
+__host__ __device__ constexpr int sym3(int a, int b, int c)
+{
+    int n[3] = {0, 0, 0};
+    n[a]++; n[b]++; n[c]++;
+    if (D == 2) {
+        if (n[0] == 3) return 0;
+        if (n[1] == 3) return 1;
+        if (n[0] == 2) return 2;
+        return 3;
+    }
+    if (n[0] == 3) return 0;
+    if (n[1] == 3) return 1;
+    if (n[2] == 3) return 2;
+    if (n[0] == 2 && n[1] == 1) return 3;
+    if (n[0] == 2 && n[2] == 1) return 4;
+    if (n[1] == 2 && n[0] == 1) return 5;
+    if (n[2] == 2 && n[0] == 1) return 6;
+    if (n[1] == 2 && n[2] == 1) return 7;
+    if (n[2] == 2 && n[1] == 1) return 8;
+    return 9;
+}
+
+// Wavefront (64-lane) reductions.
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Non-negative doubles order like their bit patterns.
+__device__ __forceinline__ void atomic_max_nonneg(unsigned long long* addr, double v)
+{
+    atomicMax(addr, (unsigned long long)__double_as_longlong(v));
+}
+
+// Block-wide max of a non-negative value into *addr (one atomic per block).
+// NaN is mapped to +inf so that it is never lost.
+__device__ inline void block_max_to(unsigned long long* addr, double v)
+{
+    __shared__ double red[16];
+    if (v != v) v = __longlong_as_double(0x7ff0000000000000LL);
+    v = wave_max(v);
+    const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+    const int lane = tid & 63, wid = tid >> 6;
+    const int nw = (blockDim.x * blockDim.y + 63) >> 6;
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    if (tid == 0) {
+        double m = red[0];
+        for (int k = 1; k < nw; ++k) m = fmax(m, red[k]);
+        atomic_max_nonneg(addr, m);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Initial populations: n_i(r) = n_eq(rho(r), u(r)) with local weights,
+// written pre-shifted so that the first pull returns them.
+// ---------------------------------------------------------------------------
+template <int Q, class R, class S>
+__global__ void k_init(Geom g, Coef cf, DevScale ds, const R* __restrict__ rho,
+                       const R* __restrict__ u, S* __restrict__ A)
+{
+    using L = Lattice<Q>;
+    SiteXYZ s = site_of_thread(g);
+    if (!s.ok) return;
+    const long long i0 = sidx(g, s.x, s.y, s.z);
+    const R r = rho[i0];
+    R uu[3] = {R(0), R(0), R(0)};
+#pragma unroll
+    for (int a = 0; a < L::D; ++a) uu[a] = u[a * g.N + i0];
+    const R cs2 = eos_cs2<R>(cf.eos, r);
+    R w[8];
+    shell_weights<Q, R>(cs2, w);
+    const R inv = R(1) / cs2;
+    const R a0 = R(1) - (uu[0] * uu[0] + uu[1] * uu[1] + uu[2] * uu[2]) * R(0.5) * inv;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const R uc = uu[0] * R(L::cx(i)) + uu[1] * R(L::cy(i)) + uu[2] * R(L::cz(i));
+        const R neq = w[L::shell(i)] * r * (a0 + uc * inv + R(0.5) * uc * uc * inv * inv);
+        const long long dst = nbr(g, s.x, s.y, s.z, -L::cx(i), -L::cy(i), -L::cz(i));
+        A[(size_t)i * g.N + dst] = Codec<S>::enc(neq, ds, L::shell(i));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Item 1: rho = sum_i n_i, j0 = sum_i n_i c_i of the pulled populations, and
+// FP64 block partial sums of mass and momentum plus a non-finite flag.
+// ---------------------------------------------------------------------------
+template <int Q, class R, class S>
+__global__ void k_moments(Geom g, DevScale ds, const S* __restrict__ A, R* __restrict__ rho,
+                          R* __restrict__ j0, double* __restrict__ partial,
+                          int* __restrict__ flags)
+{
+    using L = Lattice<Q>;
+    SiteXYZ s = site_of_thread(g);
+    double m[4] = {0.0, 0.0, 0.0, 0.0};
+    if (s.ok) {
+        const long long i0 = sidx(g, s.x, s.y, s.z);
+        R r = R(0), jx = R(0), jy = R(0), jz = R(0);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const long long src = nbr(g, s.x, s.y, s.z, -L::cx(i), -L::cy(i), -L::cz(i));
+            const R v = Codec<S>::dec(A[(size_t)i * g.N + src], ds, L::shell(i));
+            r += v;
+            if (L::cx(i)) jx += R(L::cx(i)) * v;
+            if (L::cy(i)) jy += R(L::cy(i)) * v;
+            if (L::cz(i)) jz += R(L::cz(i)) * v;
+        }
+        rho[i0] = r;
+        j0[i0] = jx;
+        j0[g.N + i0] = jy;
+        if (L::D == 3) j0[2 * g.N + i0] = jz;
+        if (!(r > R(0) && r < R(1e30))) atomicOr(flags, 1);
+        m[0] = r; m[1] = jx; m[2] = jy; m[3] = jz;
+    }
+    __shared__ double red[4][16];
+    const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+    const int lane = tid & 63, wid = tid >> 6;
+    const int nw = (blockDim.x * blockDim.y + 63) >> 6;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double v = wave_sum(m[k]);
+        if (lane == 0) red[k][wid] = v;
+    }
+    __syncthreads();
+    if (tid < 4) {
+        double acc = 0.0;
+        for (int w = 0; w < nw; ++w) acc += red[tid][w];
+        const long long b = blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z);
+        partial[4 * b + tid] = acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Item 2: f = kappa rho d_a d_b d_b rho (Sec. IV E), j0' = j0 + f/2.
+// Also the iteration's start: j~ (zero or the previous step's), u = (j0'+j~)/rho,
+// and max|j0'| for the stop rule.
+// ---------------------------------------------------------------------------
+template <int Q, class R>
+__global__ void k_force(Geom g, Coef cf, const R* __restrict__ rho, const R* __restrict__ j0,
+                        R* __restrict__ f, R* __restrict__ j0p, R* __restrict__ u,
+                        const R* jt_prev, R* jt0,
+                        unsigned long long* __restrict__ jscale)
+{
+    using L = Lattice<Q>;
+    SiteXYZ s = site_of_thread(g);
+    double amax = 0.0;
+    if (s.ok) {
+        const int x = s.x, y = s.y, z = s.z;
+        const long long i0 = sidx(g, x, y, z);
+        const R r = rho[i0];
+        auto RH = [&](int dx, int dy, int dz) { return rho[nbr(g, x, y, z, dx, dy, dz)]; };
+        R fa[3] = {R(0), R(0), R(0)};
+        if constexpr (L::D == 3) {
+            // (100): tau -3 ; (110): tau 1/2 ; (200): tau 1/4 (Table III)
+            fa[0] = R(-3) * (RH(1, 0, 0) - RH(-1, 0, 0)) +
+                    R(0.5) * (RH(1, 1, 0) + RH(1, -1, 0) + RH(1, 0, 1) + RH(1, 0, -1) -
+                              RH(-1, 1, 0) - RH(-1, -1, 0) - RH(-1, 0, 1) - RH(-1, 0, -1)) +
+                    R(0.5) * (RH(2, 0, 0) - RH(-2, 0, 0));
+            fa[1] = R(-3) * (RH(0, 1, 0) - RH(0, -1, 0)) +
+                    R(0.5) * (RH(1, 1, 0) + RH(-1, 1, 0) + RH(0, 1, 1) + RH(0, 1, -1) -
+                              RH(1, -1, 0) - RH(-1, -1, 0) - RH(0, -1, 1) - RH(0, -1, -1)) +
+                    R(0.5) * (RH(0, 2, 0) - RH(0, -2, 0));
+            fa[2] = R(-3) * (RH(0, 0, 1) - RH(0, 0, -1)) +
+                    R(0.5) * (RH(1, 0, 1) + RH(-1, 0, 1) + RH(0, 1, 1) + RH(0, -1, 1) -
+                              RH(1, 0, -1) - RH(-1, 0, -1) - RH(0, 1, -1) - RH(0, -1, -1)) +
+                    R(0.5) * (RH(0, 0, 2) - RH(0, 0, -2));
+        } else {
+            // (10): tau -2 ; (11): tau 1/2 ; (20): tau 1/4
+            fa[0] = R(-2) * (RH(1, 0, 0) - RH(-1, 0, 0)) +
+                    R(0.5) * (RH(1, 1, 0) + RH(1, -1, 0) - RH(-1, 1, 0) - RH(-1, -1, 0)) +
+                    R(0.5) * (RH(2, 0, 0) - RH(-2, 0, 0));
+            fa[1] = R(-2) * (RH(0, 1, 0) - RH(0, -1, 0)) +
+                    R(0.5) * (RH(1, 1, 0) + RH(-1, 1, 0) - RH(1, -1, 0) - RH(-1, -1, 0)) +
+                    R(0.5) * (RH(0, 2, 0) - RH(0, -2, 0));
+        }
+        const R kr = R(cf.kappa) * r;
+        const R inv = R(1) / r;
+#pragma unroll
+        for (int a = 0; a < L::D; ++a) {
+            const R fv = kr * fa[a];
+            const R jp = j0[a * g.N + i0] + R(0.5) * fv;
+            const R jt = jt_prev ? jt_prev[a * g.N + i0] : R(0);
+            f[a * g.N + i0] = fv;
+            j0p[a * g.N + i0] = jp;
+            jt0[a * g.N + i0] = jt;
+            u[a * g.N + i0] = (jp + jt) * inv;
+            amax = fmax(amax, fabs((double)jp));
+        }
+    }
+    block_max_to(jscale, amax);
+}
+
+// Iteration control shared by the two kernels of one pass.
+struct IterCtl {
+    unsigned long long* res;     // res[k] = bits of max|j~new - j~| of pass k
+    unsigned long long* jscale;  // bits of max|j0'|
+    int* done_at;                // pass index at which the stop rule held, or -1
+    double tol;                  // < 0: never stop early (fixed count)
+};
+
+__device__ __forceinline__ bool iter_skip(const IterCtl& c, int it)
+{
+    if (*((volatile int*)c.done_at) >= 0) return true;
+    if (it > 0 && c.tol >= 0.0) {
+        const double r = __longlong_as_double((long long)c.res[it - 1]);
+        const double thr = c.tol * __longlong_as_double((long long)*c.jscale);
+        if (r <= thr) {
+            *((volatile int*)c.done_at) = it;
+            return true;
+        }
+    }
+    return false;
+}
+
+// ---------------------------------------------------------------------------
+// Item 4: q_ab = (p - rho dp/drho) d_ab d_g u_g + p (d_b u_a + d_a u_b),
+// derivatives with the stencil of Sec. IV B.  q is symmetric.
+// ---------------------------------------------------------------------------
+template <int Q, class R>
+__global__ void k_iter_q(Geom g, Coef cf, IterCtl ic, int it, const R* __restrict__ rho,
+                         const R* __restrict__ u, R* __restrict__ q)
+{
+    using L = Lattice<Q>;
+    constexpr int D = L::D;
+    if (iter_skip(ic, it)) return;
+    SiteXYZ s = site_of_thread(g);
+    if (!s.ok) return;
+    const long long i0 = sidx(g, s.x, s.y, s.z);
+    R G[3][3];
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = 0; b < D; ++b) G[a][b] = d1_field<R>(g, u + b * g.N, s.x, s.y, s.z, a);
+    R trG = R(0);
+#pragma unroll
+    for (int a = 0; a < D; ++a) trG += G[a][a];
+    const EosVal<R> e = eos_all<R>(cf.eos, rho[i0]);
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = a; b < D; ++b) {
+            R v = e.p * (G[a][b] + G[b][a]);
+            if (a == b) v += e.P1 * trG;
+            q[sym2<D>(a, b) * g.N + i0] = v;
+        }
+}
+
+// ---------------------------------------------------------------------------
+// Item 5: j~new_a = -(1/12) d_b q_ab; item 6 residual; item 3 of the next
+// pass: u = (j0' + j~new)/rho.
+// ---------------------------------------------------------------------------
+template <int Q, class R>
+__global__ void k_iter_jt(Geom g, IterCtl ic, int it, const R* __restrict__ rho,
+                          const R* __restrict__ q, const R* __restrict__ j0p,
+                          const R* __restrict__ jt_old, R* __restrict__ jt_new, R* __restrict__ u)
+{
+    using L = Lattice<Q>;
+    constexpr int D = L::D;
+    if (*((volatile int*)ic.done_at) >= 0) return;
+    SiteXYZ s = site_of_thread(g);
+    double dmax = 0.0;
+    if (s.ok) {
+        const long long i0 = sidx(g, s.x, s.y, s.z);
+        const R inv = R(1) / rho[i0];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            R acc = R(0);
+#pragma unroll
+            for (int b = 0; b < D; ++b) acc += d1_field<R>(g, q + sym2<D>(a, b) * g.N, s.x, s.y, s.z, b);
+            const R jn = -acc * R(1.0 / 12.0);
+            dmax = fmax(dmax, fabs((double)(jn - jt_old[a * g.N + i0])));
+            jt_new[a * g.N + i0] = jn;
+            u[a * g.N + i0] = (j0p[a * g.N + i0] + jn) * inv;
+        }
+    }
+    block_max_to(ic.res + it, dmax);
+}
+
+// Which j~ buffer holds the final iterate, and the pass count.
+struct SolveInfo {
+    int final_buf;
+    int iters;
+    int converged;
+    int pad;
+};
+
+__global__ void k_iter_finish(IterCtl ic, int launched, SolveInfo* info)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int d = *((volatile int*)ic.done_at);
+    if (d < 0 && ic.tol >= 0.0 && launched > 0) {
+        // stop rule on the last launched pass (no later pass tested it)
+        const double r = __longlong_as_double((long long)ic.res[launched - 1]);
+        const double thr = ic.tol * __longlong_as_double((long long)*ic.jscale);
+        if (r <= thr) d = launched;
+    }
+    const int iters = d >= 0 ? d : launched;
+    info->iters = iters;
+    info->final_buf = iters & 1;
+    info->converged = d >= 0 || ic.tol < 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Items 9-11, first part: per site X = (p - rho dp/drho) d_g u_g,
+// T_ag = p (d_a u_g + d_g u_a), Y_b = rho^-1 d_b p + u_g d_g u_b, and the
+// rank-3 tensor Xi' (all first-order derivatives of per-site products).
+// ---------------------------------------------------------------------------
+template <int Q, class R>
+__global__ void k_closure1(Geom g, Coef cf, const SolveInfo* __restrict__ info,
+                           const R* __restrict__ rho, const R* __restrict__ u,
+                           const R* __restrict__ jtA, const R* __restrict__ jtB,
+                           R* __restrict__ X, R* __restrict__ T, R* __restrict__ Y,
+                           R* __restrict__ Xi)
+{
+    using L = Lattice<Q>;
+    constexpr int D = L::D;
+    SiteXYZ s = site_of_thread(g);
+    if (!s.ok) return;
+    const int x = s.x, y = s.y, z = s.z;
+    const long long i0 = sidx(g, x, y, z);
+    const R* jt = info->final_buf ? jtB : jtA;
+
+    R G[3][3] = {};   // d_a u_b
+    R M[3][3][3] = {};// d_a (p u_b u_g)
+    R Pg[3] = {}, C[3] = {};  // d_a p, d_a (p/rho)
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        int dx, dy, dz;
+        unit(a, dx, dy, dz);
+        // values at the four stencil points along axis a
+        R pv[4], cv[4], uv[4][3];
+        const int off[4] = {-2, -1, 1, 2};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const long long t = nbr(g, x, y, z, off[k] * dx, off[k] * dy, off[k] * dz);
+            const R rt = rho[t];
+            const R cs2 = eos_cs2<R>(cf.eos, rt);
+            cv[k] = cs2;
+            pv[k] = rt * cs2;
+#pragma unroll
+            for (int b = 0; b < D; ++b) uv[k][b] = u[b * g.N + t];
+        }
+        Pg[a] = d1<R>(pv[0], pv[1], pv[2], pv[3]);
+        C[a] = d1<R>(cv[0], cv[1], cv[2], cv[3]);
+#pragma unroll
+        for (int b = 0; b < D; ++b) {
+            G[a][b] = d1<R>(uv[0][b], uv[1][b], uv[2][b], uv[3][b]);
+#pragma unroll
+            for (int c = b; c < D; ++c) {
+                R m = d1<R>(pv[0] * uv[0][b] * uv[0][c], pv[1] * uv[1][b] * uv[1][c],
+                            pv[2] * uv[2][b] * uv[2][c], pv[3] * uv[3][b] * uv[3][c]);
+                M[a][b][c] = m;
+                M[a][c][b] = m;
+            }
+        }
+    }
+    const R r = rho[i0];
+    const EosVal<R> e = eos_all<R>(cf.eos, r);
+    R us[3] = {R(0), R(0), R(0)};
+#pragma unroll
+    for (int a = 0; a < D; ++a) us[a] = u[a * g.N + i0];
+    R trG = R(0);
+#pragma unroll
+    for (int a = 0; a < D; ++a) trG += G[a][a];
+
+    X[i0] = e.P1 * trG;
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int c = a; c < D; ++c) T[sym2<D>(a, c) * g.N + i0] = e.p * (G[a][c] + G[c][a]);
+    const R inv = R(1) / r;
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+        R acc = Pg[b] * inv;
+#pragma unroll
+        for (int c = 0; c < D; ++c) acc += us[c] * G[c][b];
+        Y[b * g.N + i0] = acc;
+    }
+
+    const R gm = R(cf.gamma);
+    const R KX = (gm * gm + R(4) * gm + R(1)) / (R(3) * (gm + R(1)));
+    const R KJ = (R(1) - gm) * R(cf.c0sq);
+    R jts[3] = {R(0), R(0), R(0)};
+#pragma unroll
+    for (int a = 0; a < D; ++a) jts[a] = jt[a * g.N + i0];
+    R V[3];
+#pragma unroll
+    for (int a = 0; a < D; ++a) V[a] = e.p * C[a] + e.P1 * us[a] * trG;
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = a; b < D; ++b)
+#pragma unroll
+            for (int c = b; c < D; ++c) {
+                R br = M[c][a][b] + M[b][a][c] + M[a][b][c];
+                R dj = R(0);
+                if (a == b) { br += V[c]; dj += jts[c]; }
+                if (a == c) { br += V[b]; dj += jts[b]; }
+                if (b == c) { br += V[a]; dj += jts[a]; }
+                Xi[sym3<D>(a, b, c) * g.N + i0] = KX * br + KJ * dj;
+            }
+}
+
+// ---------------------------------------------------------------------------
+// Item 11, second part: Sigma_ab from the derivatives of X, T, Y and the
+// site values (with d_a j_b recomputed from j = rho u).
+// ---------------------------------------------------------------------------
+template <int Q, class R>
+__global__ void k_closure2(Geom g, Coef cf, const R* __restrict__ rho, const R* __restrict__ u,
+                           const R* __restrict__ X, const R* __restrict__ T,
+                           const R* __restrict__ Y, R* __restrict__ Sig)
+{
+    using L = Lattice<Q>;
+    constexpr int D = L::D;
+    SiteXYZ s = site_of_thread(g);
+    if (!s.ok) return;
+    const int x = s.x, y = s.y, z = s.z;
+    const long long i0 = sidx(g, x, y, z);
+    R DX[3] = {}, DT[3] = {}, DY[3][3] = {}, G[3][3] = {};
+    R trJ = R(0);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        DX[a] = d1_field<R>(g, X, x, y, z, a);
+#pragma unroll
+        for (int c = 0; c < D; ++c) DT[a] += d1_field<R>(g, T + sym2<D>(a, c) * g.N, x, y, z, c);
+#pragma unroll
+        for (int b = 0; b < D; ++b) DY[a][b] = d1_field<R>(g, Y + b * g.N, x, y, z, a);
+        int dx, dy, dz;
+        unit(a, dx, dy, dz);
+        R jv[4];
+        const int off[4] = {-2, -1, 1, 2};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const long long t = nbr(g, x, y, z, off[k] * dx, off[k] * dy, off[k] * dz);
+            jv[k] = rho[t] * u[a * g.N + t];
+        }
+        trJ += d1<R>(jv[0], jv[1], jv[2], jv[3]);
+#pragma unroll
+        for (int b = 0; b < D; ++b) G[a][b] = d1_field<R>(g, u + b * g.N, x, y, z, a);
+    }
+    const R r = rho[i0];
+    const EosVal<R> e = eos_all<R>(cf.eos, r);
+    R us[3] = {R(0), R(0), R(0)};
+#pragma unroll
+    for (int a = 0; a < D; ++a) us[a] = u[a * g.N + i0];
+    R trG = R(0), trDY = R(0);
+#pragma unroll
+    for (int a = 0; a < D; ++a) { trG += G[a][a]; trDY += DY[a][a]; }
+    const R gm = R(cf.gamma);
+    const R KS1 = R(-0.25) * (gm + R(1)) * (gm + R(1)) / (gm - R(1));
+    const R KS2 = (gm * gm + R(4) * gm + R(1)) / (R(6) * (gm - R(1)));
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = a; b < D; ++b) {
+            const R br1 = us[a] * DX[b] + us[b] * DX[a] + us[b] * DT[a] + us[a] * DT[b];
+            R br2 = -e.dp * trJ * (G[a][b] + G[b][a]) - e.p * (DY[a][b] + DY[b][a]);
+            if (a == b) br2 += -e.P1 * trDY + e.P2 * trG * trJ;
+            Sig[sym2<D>(a, b) * g.N + i0] = KS1 * br1 + KS2 * br2;
+        }
+}
+
+// ---------------------------------------------------------------------------
+// Item 11 per velocity and item 12: pull n_i(r), collide with
+// Delta^bulk + Delta^int + Delta^corr and store n*_i(r) in the other buffer.
+// Velocities come in antipodal pairs; each pair shares its even part.
+// ---------------------------------------------------------------------------
+template <int Q, class R, class S>
+__global__ void k_collide(Geom g, Coef cf, DevScale ds, const SolveInfo* __restrict__ info,
+                          const S* __restrict__ A, S* __restrict__ B, const R* __restrict__ rho,
+                          const R* __restrict__ u, const R* __restrict__ f,
+                          const R* __restrict__ jtA, const R* __restrict__ jtB,
+                          const R* __restrict__ Sig, const R* __restrict__ Xi)
+{
+    using L = Lattice<Q>;
+    constexpr int D = L::D;
+    SiteXYZ s = site_of_thread(g);
+    if (!s.ok) return;
+    const int x = s.x, y = s.y, z = s.z;
+    const long long i0 = sidx(g, x, y, z);
+    const R* jt = info->final_buf ? jtB : jtA;
+
+    const R r = rho[i0];
+    R us[3] = {R(0), R(0), R(0)}, fs[3] = {R(0), R(0), R(0)}, js[3] = {R(0), R(0), R(0)};
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        us[a] = u[a * g.N + i0];
+        fs[a] = f[a * g.N + i0];
+        js[a] = jt[a * g.N + i0];
+    }
+    R Sg[6], Xp[10];
+#pragma unroll
+    for (int k = 0; k < L::NSIG; ++k) Sg[k] = Sig[k * g.N + i0];
+#pragma unroll
+    for (int k = 0; k < L::NXI; ++k) Xp[k] = Xi[k * g.N + i0];
+
+    const R gm = R(cf.gamma);
+    const R c0 = R(cf.c0sq);
+    const R ic0 = R(1) / c0;
+    // n_eq pieces (local weights)
+    const R cs2 = eos_cs2<R>(cf.eos, r);
+    R wl[8];
+    shell_weights<Q, R>(cs2, wl);
+    const R ics = R(1) / cs2;
+    const R uu = us[0] * us[0] + us[1] * us[1] + us[2] * us[2];
+    const R a0 = R(1) - R(0.5) * uu * ics;
+    const R a1 = ics;
+    const R a2 = R(0.5) * ics * ics;
+    const R omg = R(1) - gm;  // weight of n_eq
+#pragma unroll
+    for (int k = 0; k < L::NSHELL; ++k) wl[k] *= omg * r;
+    // Delta^corr pieces: W_k [ b.c + c.S'.c + s0 + X'(c,c,c) ]
+    R trS = R(0);
+#pragma unroll
+    for (int a = 0; a < D; ++a) trS += Sg[a];
+    R v[3] = {R(0), R(0), R(0)};   // v_g = sum_a Xi'_aag
+#pragma unroll
+    for (int gg = 0; gg < D; ++gg)
+#pragma unroll
+        for (int a = 0; a < D; ++a) v[gg] += Xp[sym3<D>(a, a, gg)];
+    const R kS = R(0.5) * ic0 * ic0;
+    const R kX = ic0 * ic0 * ic0 / R(6);
+    R bvec[3];
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+        bvec[a] = R(0.5) * (R(1) + gm) * ic0 * fs[a] + (gm - R(1)) * ic0 * js[a] - R(0.5) * ic0 * ic0 * v[a];
+    const R s0 = -R(0.5) * ic0 * trS;
+
+    // rest velocity (index 0): even part only
+    {
+        const R neq = wl[0] * a0;
+        const R corr = R(cf.Wk[0]) * s0;
+        const R n0 = Codec<S>::dec(A[i0], ds, 0);  // c = 0: pull from r itself
+        B[i0] = Codec<S>::enc(gm * n0 + neq + corr, ds, 0);
+    }
+#pragma unroll
+    for (int p = 0; p < L::NPAIR; ++p) {
+        const int ip = 2 * p + 1, im = 2 * p + 2;
+        constexpr int dummy = 0;
+        (void)dummy;
+        const int cxv = L::cx(ip), cyv = L::cy(ip), czv = L::cz(ip);
+        const int k = L::shell(ip);
+        const R cx = R(cxv), cy = R(cyv), cz = R(czv);
+        const R uc = us[0] * cx + us[1] * cy + us[2] * cz;
+        // c.Sigma.c
+        R cSc = Sg[0] * cx * cx + Sg[1] * cy * cy;
+        if (D == 3) {
+            cSc += Sg[2] * cz * cz + R(2) * (Sg[3] * cx * cy + Sg[4] * cx * cz + Sg[5] * cy * cz);
+        } else {
+            cSc += R(2) * Sg[2] * cx * cy;
+        }
+        // Xi'(c,c,c)
+        R cXc;
+        if (D == 3) {
+            cXc = Xp[0] * cx * cx * cx + Xp[1] * cy * cy * cy + Xp[2] * cz * cz * cz +
+                  R(3) * (Xp[3] * cx * cx * cy + Xp[4] * cx * cx * cz + Xp[5] * cx * cy * cy +
+                          Xp[6] * cx * cz * cz + Xp[7] * cy * cy * cz + Xp[8] * cy * cz * cz) +
+                  R(6) * Xp[9] * cx * cy * cz;
+        } else {
+            cXc = Xp[0] * cx * cx * cx + Xp[1] * cy * cy * cy +
+                  R(3) * (Xp[2] * cx * cx * cy + Xp[3] * cx * cy * cy);
+        }
+        const R bc = bvec[0] * cx + bvec[1] * cy + (D == 3 ? bvec[2] * cz : R(0));
+        const R Wk = R(cf.Wk[k]);
+        const R even = wl[k] * (a0 + a2 * uc * uc) + Wk * (kS * cSc + s0);
+        const R odd = wl[k] * a1 * uc + Wk * (bc + kX * cXc);
+        const long long sp = nbr(g, x, y, z, -cxv, -cyv, -czv);
+        const long long sm = nbr(g, x, y, z, cxv, cyv, czv);
+        const R np = Codec<S>::dec(A[(size_t)ip * g.N + sp], ds, k);
+        const R nm = Codec<S>::dec(A[(size_t)im * g.N + sm], ds, k);
+        B[(size_t)ip * g.N + i0] = Codec<S>::enc(gm * np + even + odd, ds, k);
+        B[(size_t)im * g.N + i0] = Codec<S>::enc(gm * nm + even - odd, ds, k);
+    }
+}
+
+// Pre-collision populations of the current state as FP64 [Q][N].
+template <int Q, class S>
+__global__ void k_export(Geom g, DevScale ds, const S* __restrict__ A, double* __restrict__ out)
+{
+    using L = Lattice<Q>;
+    SiteXYZ s = site_of_thread(g);
+    if (!s.ok) return;
+    const long long i0 = sidx(g, s.x, s.y, s.z);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const long long src = nbr(g, s.x, s.y, s.z, -L::cx(i), -L::cy(i), -L::cz(i));
+        out[(size_t)i * g.N + i0] = (double)Codec<S>::dec(A[(size_t)i * g.N + src], ds, L::shell(i));
+    }
+}
+
+template <int Q, class S>
+__global__ void k_import(Geom g, DevScale ds, const double* __restrict__ in, S* __restrict__ A)
+{
+    using L = Lattice<Q>;
+    SiteXYZ s = site_of_thread(g);
+    if (!s.ok) return;
+    const long long i0 = sidx(g, s.x, s.y, s.z);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const long long dst = nbr(g, s.x, s.y, s.z, -L::cx(i), -L::cy(i), -L::cz(i));
+        using RT = decltype(Codec<S>::dec(S(), ds, 0));
+        A[(size_t)i * g.N + dst] = Codec<S>::enc((RT)in[(size_t)i * g.N + i0], ds, L::shell(i));
+    }
+}
+
+// Small helpers.
+__global__ void k_reset_ctl(unsigned long long* res, int nres, unsigned long long* jscale,
+                            int* done_at)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < nres) res[t] = 0ull;
+    if (t == 0) {
+        *jscale = 0ull;
+        *done_at = -1;
+    }
+}
+
+// Deterministic sum of block partials (one block).
+__global__ void k_sum_partials(const double* __restrict__ partial, long long nblk, double* out)
+{
+    __shared__ double red[4][16];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (long long b = threadIdx.x; b < nblk; b += blockDim.x)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[k] += partial[4 * b + k];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double v = wave_sum(acc[k]);
+        if (lane == 0) red[k][wid] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        double t = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[threadIdx.x][w];
+        out[threadIdx.x] = t;
+    }
+}
+
+template <class Rin, class Rout>
+__global__ void k_convert(const Rin* __restrict__ in, Rout* __restrict__ out, long long n)
+{
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (t < n) out[t] = (Rout)in[t];
+}
+
+}  // namespace lb2p

@@ -1,0 +1,83 @@
+"""CPU checks of the C-ABI library: it loads, exports every function that
+include/lb2p.h declares, and its host-side validation and tables behave
+(no GPU compute is called here).
+
+Failure injection on the host: an inadmissible equation of state (App. B)
+gives LB2P_EEOS, out-of-range gamma (Sec. II) or a grid side below 8 gives
+LB2P_EINVAL, before any device call.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1402_2920_amd import build, lb2p
+    build.build(force=False)
+    lb2p.lib()
+    return lb2p
+
+
+def test_every_declared_symbol_is_exported(L):
+    hdr = open(os.path.join(ROOT, "include", "lb2p.h")).read()
+    names = set(re.findall(r"\b(lb2p_[a-z_]+)\s*\(", hdr))
+    assert len(names) >= 12
+    lib = ctypes.CDLL(L.LIB_PATH)
+    for n in sorted(names):
+        assert hasattr(lib, n), n
+    assert names == set(L.EXPORTED)
+
+
+@pytest.mark.parametrize("Q", [21, 59])
+def test_velocity_table(L, orc, Q):
+    c = L.velocities(Q)
+    assert c.shape == (Q, 3)
+    co, _ = orc.velocities(Q)
+    assert {tuple(v) for v in c} == {tuple(v) for v in co}
+    assert tuple(c[0]) == (0, 0, 0)
+    # antipodal pairs (2p+1, 2p+2)
+    for p in range((Q - 1) // 2):
+        assert tuple(c[2 * p + 2]) == tuple(-c[2 * p + 1])
+
+
+def test_default_params(L):
+    prm = L._Params()
+    st = L.lib().lb2p_default_params(59, 32, 32, 32, L.STORE_F32, ctypes.byref(prm))
+    assert st == L.OK
+    assert (prm.nx, prm.ny, prm.nz, prm.storage) == (32, 32, 32, L.STORE_F32)
+    assert prm.gamma == 0.0 and prm.tol == 1e-6 and prm.max_iter == 200 and prm.warm_start == 1
+    assert prm.eos.rho1 == 0.3 and prm.eos.rho2 == 1.0 and prm.rho0 == 0.3
+    assert L.lib().lb2p_default_params(59, 8, 8, 8, L.STORE_F64, None) == L.EINVAL
+
+
+def _p(L, **kw):
+    base = dict(lattice=59, nx=16, ny=16, nz=16, A=0.745, cs2_rho1=0.39, kappa=0.01)
+    base.update(kw)
+    return L.Params(**base)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(gamma=1.0), "EINVAL"), (dict(gamma=-1.0), "EINVAL"), (dict(nx=7), "EINVAL"),
+    (dict(lattice=21, nz=4), "EINVAL"), (dict(lattice=20), "EINVAL"), (dict(kappa=-1.0), "EINVAL"),
+    (dict(tol=-1.0), "EINVAL"), (dict(max_iter=0), "EINVAL"), (dict(storage=7), "EINVAL"),
+    # App. B: the paper's example EOS violates positive bulk viscosity in 3D
+    (dict(A=1.2, rho1=0.5, cs2_rho1=0.6), "EEOS"),
+    # weights negative for c_s^2 below the Sec. III window
+    (dict(cs2_rho1=0.38), "EEOS"),
+    # A > 0 without a two-phase region
+    (dict(A=0.5), "EEOS"),
+])
+def test_create_rejects_bad_parameters(L, kw, status):
+    assert L.create_status(_p(L, **kw)) == getattr(L, status)
+
+
+def test_strerror(L):
+    for s in range(8):
+        assert isinstance(L.strerror(s), str) and L.strerror(s)
+    assert L.strerror(99) == "unknown status"

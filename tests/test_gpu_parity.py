@@ -1,0 +1,73 @@
+"""GPU parity: the HIP library against the FP64 oracle on the same seeded
+inputs (small grids spanning several blocks with ragged edges).
+
+Per-field bar: FP64 path 1e-10 relative (max |G-O| / max |O|); FP32 path
+1e-5 relative for rho and the populations.  Derived FP32 fields (u, j~,
+Sigma, Xi') are differences of O(1) numbers and carry the FP32 rounding of
+their inputs amplified by the stencils; their bounds are stated per field
+below.
+"""
+import numpy as np
+import pytest
+
+from parity_util import compare, gpu_run, oracle_reference, small_case
+
+pytestmark = pytest.mark.gpu
+
+F64_TOL = 1e-10
+
+CASES = [
+    ("d2q21", 21, (40, 24)),
+    ("d3q59", 59, (20, 12, 10)),
+]
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1402_2920_amd import lb2p
+    lb2p.lib()
+    return lb2p
+
+
+@pytest.mark.parametrize("name,lattice,shape", CASES)
+def test_f64_matches_oracle(orc, L, name, lattice, shape):
+    rho, u, model = small_case(lattice, shape)
+    ref = oracle_reference(orc, model, rho, u, nsteps_long=10)
+    gpu = gpu_run(L, model, L.STORE_F64, rho, u, nsteps_long=10, tol=1e-14)
+    e = compare(orc, ref, gpu)
+    print(name, "f64", {k: f"{v:.2e}" for k, v in e.items()}, flush=True)
+    for k, v in e.items():
+        assert v <= F64_TOL, (k, v)
+
+
+# FP32 bounds.  rho and the populations: 1e-5 (the FP32 target).  Fields
+# built by finite differences of FP32 inputs: the input rounding eps32*|g|
+# (eps32 = 6e-8) times the stencil gain (sum |tau| = 11 for the force stencil,
+# about 2 per first-derivative level) over the field's own scale, which is
+# 1e-2..1e-3 of |g| for these smooth inputs -> 1e-4..1e-3; u after 10 steps
+# also carries the implicit solve's high-k gain 1/(1-lambda) <= 5.
+F32_TOL = dict(rho_t0=1e-5, u_t0=2e-4, j0_t0=2e-4, force_t0=5e-4, jtilde_t0=1e-3, sigma_t0=3e-3,
+               xi_t0=1e-3, pop_t1=1e-5, rho_tL=1e-5, u_tL=1e-3)
+
+
+@pytest.mark.parametrize("name,lattice,shape", CASES)
+def test_f32_matches_oracle(orc, L, name, lattice, shape):
+    rho, u, model = small_case(lattice, shape)
+    ref = oracle_reference(orc, model, rho, u, nsteps_long=10)
+    gpu = gpu_run(L, model, L.STORE_F32, rho, u, nsteps_long=10, tol=1e-7)
+    e = compare(orc, ref, gpu)
+    print(name, "f32", {k: f"{v:.2e}" for k, v in e.items()}, flush=True)
+    for k, v in e.items():
+        assert v <= F32_TOL[k], (k, v)
+
+
+@pytest.mark.parametrize("name,lattice,shape", CASES)
+def test_invariants_on_gpu(orc, L, name, lattice, shape):
+    """Mass and total momentum are conserved (Sec. VI: the lattice force sums
+    to zero on a periodic lattice; j~ is a divergence)."""
+    rho, u, model = small_case(lattice, shape)
+    gpu = gpu_run(L, model, L.STORE_F64, rho, u, nsteps_long=10, tol=1e-14)
+    s0, sL = gpu["stats0"], gpu["statsL"]
+    assert abs(sL["mass"] - s0["mass"]) <= 1e-13 * s0["mass"]
+    assert np.max(np.abs(sL["mom"] - s0["mom"])) <= 1e-13 * s0["mass"]
+    assert not sL["nonfinite"]
