@@ -1,0 +1,238 @@
+"""Throughput of the consistent two-phase LB step on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--storage f32]
+
+Prints ONE JSON line.  A step is one full time step (Supplemental items 1-12:
+moments, force, the implicit j~/u solve to the paper's stop rule, closure,
+collision, streaming) over the whole lattice; value = lattice sites x steps /
+wall time of the timed region / 1e6 (MLUPS), inputs already in HBM.
+
+roofline: the kernel class with the largest share of the timed region,
+its algorithmic bytes per launch (per-site bytes below x sites) over its
+average HIP-event duration on the library's stream, against 8 TB/s.
+cpu_baseline: the FP64 oracle, unchanged, on a bounded sample of the same
+workload (a 16 x 16 x nz column for 3D grids), on this host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+DEFAULT_WORKLOAD = "d3q59_256_slab"
+
+
+def site_bytes(kernel, Q, D, s, r, warm):
+    """Algorithmic bytes per site of one launch of a kernel class: every
+    population or field word the kernel must read or write once (stencil
+    neighbours are reuse, not extra traffic)."""
+    nsig = 6 if D == 3 else 3
+    nxi = 10 if D == 3 else 4
+    return {
+        "moments": Q * s + (1 + D) * r,
+        "force": (1 + D) * r + (D * r if warm else 0) + 4 * D * r,
+        "iter_q": (1 + D) * r + nsig * r,
+        "iter_jt": (nsig + 1 + 2 * D) * r + 2 * D * r,
+        "closure1": (1 + 2 * D) * r + (1 + nsig + D + nxi) * r,
+        "closure2": (2 + nsig + 2 * D) * r + nsig * r,
+        "collide": 2 * Q * s + (1 + 3 * D + nsig + nxi) * r,
+    }[kernel]
+
+
+STORE_BYTES = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}
+
+
+def run_gpu(workload, storage, steps, warmup, shape=None, profile=True, tol=None):
+    import torch
+    import lb2p_workloads as W
+    from paper_1402_2920_amd import lb2p
+    entry, shape, rho, u = W.build(workload, shape)
+    d = len(shape)
+    st = lb2p.STORAGE_NAMES[storage]
+    P = lb2p.Params(nx=shape[0], ny=shape[1], nz=shape[2] if d == 3 else 1, storage=st,
+                    tol=tol, max_iter=200, warm_start=1, **W.model_kwargs(entry["model"]))
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    dt = torch.float64
+    rho_d = torch.tensor(rho, dtype=dt, device="cuda:0")
+    u_d = torch.tensor(u, dtype=dt, device="cuda:0").contiguous()
+    out = {}
+    with lb2p.Context(P, stream=stream) as ctx:
+        ctx.init(rho_d, u_d)
+        del rho_d, u_d
+        ctx.step(warmup)
+        if profile:
+            ctx.profile_enable(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.step(steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        prof = ctx.profile_read() if profile else None
+        stats = ctx.stats()
+        out.update(seconds=t1 - t0, prof=prof, stats=stats, N=P.N, Q=P.lattice, D=d, shape=shape,
+                   params=P)
+    return out
+
+
+def roofline(res, storage, warm=True):
+    prof = res["prof"]
+    Q, D, N = res["Q"], res["D"], res["N"]
+    s = STORE_BYTES[storage]
+    r = 8 if storage == "f64" else 4
+    total = {k: v[0] for k, v in prof.items()}
+    dom = max(total, key=total.get)
+    ms, n = prof[dom]
+    avg_s = ms / 1e3 / max(n, 1)
+    bytes_launch = site_bytes(dom, Q, D, s, r, warm) * N
+    achieved = bytes_launch / avg_s / 1e9
+    per_kernel = {k: dict(ms_total=round(v[0], 3), launches=v[1],
+                          avg_us=round(1e3 * v[0] / max(v[1], 1), 2),
+                          gbs=round(site_bytes(k, Q, D, s, r, warm) * N / (v[0] / 1e3 / max(v[1], 1)) / 1e9, 1)
+                          if v[1] else None)
+                  for k, v in prof.items()}
+    traffic = measured_traffic(dom, res)
+    return dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
+                bytes_per_site=site_bytes(dom, Q, D, s, r, warm), launches=n,
+                avg_launch_us=round(avg_s * 1e6, 2)), per_kernel
+
+
+def measured_traffic(kernel, res):
+    """HBM bytes per launch from committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    counters (scaled by a plain copy kernel's reading), if they were taken on
+    the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+        from paper_1402_2920_amd import build as B
+        if t.get("src_sha") != B.source_sha():
+            return None
+        ent = t["kernels"].get(kernel)
+        return None if ent is None else ent["bytes_per_launch"]
+    except Exception:
+        return None
+
+
+def cpu_baseline(workload, nsteps_max=30, budget_s=15.0):
+    """Oracle MLUPS on a bounded sample of the workload (16 x 16 x nz column
+    in 3D, 64 x 64 in 2D); returns (dict, sample results for the error check)."""
+    from oracle import build_oracle, oracle as orc
+    import lb2p_workloads as W
+    build_oracle.build(force=False)
+    full = tuple(W.load_params()[workload]["shape"])
+    shape = (16, 16, full[2]) if len(full) == 3 else (64, 64)
+    entry, shape, rho, u = W.build(workload, shape)
+    d = len(shape)
+    m = orc.Model(nx=shape[0], ny=shape[1], nz=shape[2] if d == 3 else 1, tol=1e-13, max_iter=2000,
+                  **W.oracle_kwargs(entry["model"]))
+    n = orc.init(m, rho, u.T.copy())
+    t0 = time.perf_counter()
+    steps = 0
+    while steps < nsteps_max and time.perf_counter() - t0 < budget_s:
+        orc.step(m, n, 1)
+        steps += 1
+    dt = time.perf_counter() - t0
+    F = orc.fields(m, n)
+    N = int(np.prod(shape))
+    res = dict(value=round(N * steps / dt / 1e6, 4), unit="MLUPS", cores=orc.num_threads(), kind="oracle",
+               sample=f"{'x'.join(map(str, shape))} sample of the {workload} workload (same EOS, kappa, "
+                      f"profile), {steps} steps, FP64, j~ from zero, tol 1e-13, {dt:.1f} s")
+    return res, dict(shape=shape, steps=steps, rho=F["rho"], u=F["u"][:, :d].T.copy())
+
+
+def sample_errors(workload, storage, ref):
+    """max and RMS error of rho and u on the cpu-baseline sample after the
+    same number of steps (GPU in `storage` vs the FP64 oracle)."""
+    import lb2p_workloads as W
+    from paper_1402_2920_amd import lb2p
+    entry, shape, rho, u = W.build(workload, ref["shape"])
+    d = len(shape)
+    P = lb2p.Params(nx=shape[0], ny=shape[1], nz=shape[2] if d == 3 else 1,
+                    storage=lb2p.STORAGE_NAMES[storage], max_iter=500, warm_start=1,
+                    tol=1e-13 if storage == "f64" else 1e-7, **W.model_kwargs(entry["model"]))
+    with lb2p.Context(P) as ctx:
+        ctx.init(rho, u)
+        ctx.step(ref["steps"])
+        rg, ug = ctx.moments()
+    er = rg - ref["rho"]
+    eu = np.sqrt(((ug - ref["u"]) ** 2).sum(axis=0))
+    umag = np.sqrt((ref["u"] ** 2).sum(axis=0))
+    return dict(e_rho_max=float(np.abs(er).max() / np.abs(ref["rho"]).max()),
+                e_rho_rms=float(np.sqrt((er**2).mean()) / np.abs(ref["rho"]).max()),
+                e_u_max=float(eu.max() / max(umag.max(), 1e-300)),
+                e_u_rms=float(np.sqrt((eu**2).mean()) / max(umag.max(), 1e-300)),
+                u_max=float(umag.max()), steps=ref["steps"])
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
+    ap.add_argument("--storage", default="f32", choices=list(STORE_BYTES))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-variants", action="store_true", help="skip the BF16/F16 storage lines")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the step would shard by z-slabs with halo exchange; not built).", file=sys.stderr)
+        sys.exit(2)
+
+    import lb2p_workloads as W
+    entry = W.load_params()[args.workload]
+    res = run_gpu(args.workload, args.storage, args.steps, args.warmup)
+    N, K = res["N"], args.steps
+    secs = res["seconds"]
+    roof, per_kernel = roofline(res, args.storage)
+    shape = res["shape"]
+    line = dict(
+        metric="MLUPS and % HBM peak, D3Q59 FP32 vs BF16-storage at stated error",
+        value=round(N * K / secs / 1e6, 2), unit="MLUPS", n_gpus=1, steps=K, warmup=args.warmup,
+        ms_per_step=round(1e3 * secs / K, 4), higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype=args.storage, data="synthetic",
+        config=dict(workload=f"{args.workload}: D{len(shape)}Q{res['Q']} {'x'.join(map(str, shape))} "
+                             f"periodic, {entry['kind']}, {args.storage} populations",
+                    sites=N, parallelism="single GPU",
+                    solve="j~ fixed point to the paper's stop rule, tol 1e-6 x max|j0'|, warm start",
+                    iters_last_step=res["stats"]["iters"]),
+        roofline=roof,
+        kernels=per_kernel,
+    )
+    ref = None
+    if not args.no_cpu:
+        cb, ref = cpu_baseline(args.workload)
+        line["cpu_baseline"] = cb
+    if not args.no_variants and args.storage == "f32":
+        var = {}
+        for stg in ("bf16", "f16"):
+            r2 = run_gpu(args.workload, stg, K, args.warmup)
+            rf, _ = roofline(r2, stg)
+            var[stg] = dict(value=round(N * K / r2["seconds"] / 1e6, 2), unit="MLUPS",
+                            ms_per_step=round(1e3 * r2["seconds"] / K, 4), roofline_frac=rf["frac"],
+                            dominant=rf["kernel"])
+        line["variants"] = var
+    if ref is not None:
+        errs = {}
+        stgs = [args.storage] + ([] if args.no_variants or args.storage != "f32" else ["bf16", "f16"])
+        for stg in stgs:
+            errs[stg] = {k: (float(f"{v:.3e}") if isinstance(v, float) else v)
+                         for k, v in sample_errors(args.workload, stg, ref).items()}
+        line["errors_vs_oracle"] = errs
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -173,6 +173,26 @@ lb2p_status lb2p_velocities(int lattice, int *c_out, int *q_out);
  * solve's iteration count and residual, non-finite flag).  Errors: EHIP. */
 lb2p_status lb2p_stats_get(lb2p_ctx *ctx, lb2p_stats *st);
 
+/* Kernel classes timed by the optional profiler. */
+typedef enum {
+    LB2P_K_MOMENTS = 0,    /* item 1 (pull + moments)                        */
+    LB2P_K_FORCE = 1,      /* item 2 (interface force, start of the solve)   */
+    LB2P_K_ITER_Q = 2,     /* item 4 of one pass                             */
+    LB2P_K_ITER_JT = 3,    /* items 5-6 of one pass                          */
+    LB2P_K_CLOSURE1 = 4,   /* items 9-10 and Xi'                             */
+    LB2P_K_CLOSURE2 = 5,   /* Sigma                                          */
+    LB2P_K_COLLIDE = 6,    /* item 11 per velocity and item 12               */
+    LB2P_NKERNEL = 7
+} lb2p_kernel;
+
+/* Diagnostic timing: when enabled, every launch of the classes above is
+ * bracketed by HIP events on the context's stream.  enable resets the
+ * totals; read synchronises the stream and returns, per class, the summed
+ * event time in ms (ms_out[LB2P_NKERNEL]) and the launch count
+ * (count_out[LB2P_NKERNEL]).  Errors: EINVAL. */
+lb2p_status lb2p_profile_enable(lb2p_ctx *ctx, int on);
+lb2p_status lb2p_profile_read(lb2p_ctx *ctx, double *ms_out, long long *count_out);
+
 /* Release everything the context owns.  NULL is accepted. */
 void lb2p_destroy(lb2p_ctx *ctx);
 

@@ -110,3 +110,42 @@ def batch_domains(n_domains, side_lo, side_hi, seed=1402000):
     tr = rng.uniform(0.0, 1.0, size=n_domains)
     return [dict(nx=int(a), ny=int(b), radius=float(f * min(a, b)), t_unit=float(t))
             for a, b, f, t in zip(nx, ny, frac, tr)]
+
+
+def model_kwargs(model: dict) -> dict:
+    """lb2p.Params keyword arguments of a params.json model entry."""
+    e = model["eos"]
+    return dict(lattice=model["lattice"], gamma=model["gamma"], kappa=model["kappa"], rho1=e["rho1"],
+                rho2=e["rho2"], A=e["A"], cs2_rho1=e["cs2_1"], rho0=model["rho0"])
+
+
+def oracle_kwargs(model: dict) -> dict:
+    """Oracle Model keyword arguments of a params.json model entry."""
+    e = model["eos"]
+    return dict(Q=model["lattice"], gamma=model["gamma"], kappa=model["kappa"], rho1=e["rho1"],
+                rho2=e["rho2"], A=e["A"], cs2_1=e["cs2_1"], rho0=model["rho0"])
+
+
+def build(name: str, shape=None):
+    """(entry, shape, rho, u) of a named workload; `shape` overrides the grid
+    (the initial condition keeps its geometry relative to the box: droplet
+    radius and slab walls scale with the box)."""
+    entry = load_params()[name]
+    full = tuple(entry["shape"])
+    shape = tuple(shape) if shape is not None else full
+    scale = shape[-1] / full[-1]
+    m = entry["model"]
+    if entry["kind"] == "droplet":
+        rho, u = droplet(shape, entry["radius"] * min(shape) / min(full), m["rho_g"], m["rho_l"],
+                         width=m["width"], noise=entry["noise"], seed=entry["seed"])
+    elif entry["kind"] == "slab":
+        rho, u = slab(shape, entry["z_lo"] * scale, entry["z_hi"] * scale, m["rho_g"], m["rho_l"],
+                      width=m["width"], noise=entry["noise"], seed=entry["seed"])
+    elif entry["kind"] == "two_droplets":
+        sx = shape[0] / full[0]
+        rho, u = two_droplets(shape, entry["radius"] * sx, entry["separation"] * sx, m["rho_g"],
+                              m["rho_l"], entry["speed"], width=m["width"], noise=entry["noise"],
+                              seed=entry["seed"])
+    else:
+        raise ValueError(name)
+    return entry, shape, rho, u

@@ -35,5 +35,16 @@ def build(force: bool = True, verbose: bool = False) -> str:
     return OUT
 
 
+
+def source_sha() -> str:
+    """Hash of the kernel and ABI sources (ties recorded counters to code)."""
+    import hashlib
+    h = hashlib.sha256()
+    for p in sorted(SOURCES + HEADERS):
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 if __name__ == "__main__":
     print(build(force=True, verbose="-v" in sys.argv))

@@ -12,6 +12,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "../../include/lb2p.h"
 #include "kernels.hpp"
@@ -106,6 +107,13 @@ struct lb2p_ctx {
     bool sigma_valid = false;
     lb2p_status sticky = LB2P_OK;
     int last_iters = 0;
+    // optional per-kernel-class event timing (lb2p_profile_*)
+    bool prof = false;
+    struct Pending { hipEvent_t a, b; int kid; };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+    double prof_ms[LB2P_NKERNEL] = {0};
+    long long prof_n[LB2P_NKERNEL] = {0};
 };
 
 namespace {
@@ -123,6 +131,59 @@ void choose_launch(lb2p_ctx* c)
     c->block = dim3(bx, by, 1);
     c->grid = dim3((c->g.nx + bx - 1) / bx, (c->g.ny + by - 1) / by, c->g.nz);
     c->nblk = (long long)c->grid.x * c->grid.y * c->grid.z;
+}
+
+hipEvent_t prof_event(lb2p_ctx* c)
+{
+    if (!c->pool.empty()) {
+        hipEvent_t e = c->pool.back();
+        c->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Bracket one launch of kernel class `kid` with events on the context stream.
+struct ProfScope {
+    lb2p_ctx* c;
+    int kid;
+    hipEvent_t a = nullptr;
+    ProfScope(lb2p_ctx* cc, int k) : c(cc), kid(k)
+    {
+        if (c->prof) {
+            a = prof_event(c);
+            if (a) (void)hipEventRecord(a, c->stream);
+        }
+    }
+    ~ProfScope()
+    {
+        if (c->prof && a) {
+            hipEvent_t b = prof_event(c);
+            if (b) {
+                (void)hipEventRecord(b, c->stream);
+                c->pending.push_back({a, b, kid});
+            }
+        }
+    }
+};
+
+// Resolve recorded events into per-class totals (synchronises the stream).
+void prof_collect(lb2p_ctx* c)
+{
+    if (c->pending.empty()) return;
+    (void)hipStreamSynchronize(c->stream);
+    for (auto& p : c->pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            c->prof_ms[p.kid] += ms;
+            c->prof_n[p.kid] += 1;
+        }
+        c->pool.push_back(p.a);
+        c->pool.push_back(p.b);
+    }
+    c->pending.clear();
 }
 
 struct HostScratch {
@@ -146,9 +207,12 @@ struct Impl {
 
     static void launch_moments(lb2p_ctx* c, bool write_fields)
     {
-        hipLaunchKernelGGL((k_moments<Q, R, S>), c->grid, c->block, 0, c->stream, c->g, c->ds,
-                           (const S*)c->A, write_fields ? (R*)c->rho : (R*)c->X,
-                           write_fields ? (R*)c->j0 : (R*)c->T, c->partial, c->flags);
+        {
+            ProfScope _ps(c, LB2P_K_MOMENTS);
+            hipLaunchKernelGGL((k_moments<Q, R, S>), c->grid, c->block, 0, c->stream, c->g, c->ds,
+                               (const S*)c->A, write_fields ? (R*)c->rho : (R*)c->X,
+                               write_fields ? (R*)c->j0 : (R*)c->T, c->partial, c->flags);
+        }
     }
 
     // Items 1-8; returns false on a HIP error.  iters/converged in c->host.
@@ -165,9 +229,12 @@ struct Impl {
             HostScratch* hs = (HostScratch*)c->host;
             prev = (const R*)(hs->info.final_buf ? c->jt1 : c->jt0);
         }
-        hipLaunchKernelGGL((k_force<Q, R>), c->grid, c->block, 0, c->stream, c->g, c->cf,
-                           (const R*)c->rho, (const R*)c->j0, (R*)c->f, (R*)c->j0p, (R*)c->u,
-                           prev, (R*)c->jt0, c->jscale);
+        {
+            ProfScope _ps(c, LB2P_K_FORCE);
+            hipLaunchKernelGGL((k_force<Q, R>), c->grid, c->block, 0, c->stream, c->g, c->cf,
+                               (const R*)c->rho, (const R*)c->j0, (R*)c->f, (R*)c->j0p, (R*)c->u,
+                               prev, (R*)c->jt0, c->jscale);
+        }
         IterCtl ic{c->res, c->jscale, c->done_at, p.fixed_iter > 0 ? -1.0 : p.tol};
         const int every = p.check_every > 0 ? p.check_every : 4;
         HostScratch* hs = (HostScratch*)c->host;
@@ -175,11 +242,17 @@ struct Impl {
         for (int it = 0; it < max_it; ++it) {
             R* jold = (R*)((it & 1) ? c->jt1 : c->jt0);
             R* jnew = (R*)((it & 1) ? c->jt0 : c->jt1);
-            hipLaunchKernelGGL((k_iter_q<Q, R>), c->grid, c->block, 0, c->stream, c->g, c->cf, ic,
-                               it, (const R*)c->rho, (const R*)c->u, (R*)c->q);
-            hipLaunchKernelGGL((k_iter_jt<Q, R>), c->grid, c->block, 0, c->stream, c->g, ic, it,
-                               (const R*)c->rho, (const R*)c->q, (const R*)c->j0p,
-                               (const R*)jold, jnew, (R*)c->u);
+            {
+                ProfScope _ps(c, LB2P_K_ITER_Q);
+                hipLaunchKernelGGL((k_iter_q<Q, R>), c->grid, c->block, 0, c->stream, c->g, c->cf, ic,
+                                   it, (const R*)c->rho, (const R*)c->u, (R*)c->q);
+            }
+            {
+                ProfScope _ps(c, LB2P_K_ITER_JT);
+                hipLaunchKernelGGL((k_iter_jt<Q, R>), c->grid, c->block, 0, c->stream, c->g, ic, it,
+                                   (const R*)c->rho, (const R*)c->q, (const R*)c->j0p,
+                                   (const R*)jold, jnew, (R*)c->u);
+            }
             launched = it + 1;
             if (p.fixed_iter <= 0 && (launched % every) == 0 && launched < max_it) {
                 HIPCHK(hipMemcpyAsync(&hs->done_at, c->done_at, sizeof(int), hipMemcpyDeviceToHost,
@@ -214,17 +287,26 @@ struct Impl {
     {
         lb2p_status st = solve(c);
         if (st != LB2P_OK) return st;
-        hipLaunchKernelGGL((k_closure1<Q, R>), c->grid, c->block, 0, c->stream, c->g, c->cf,
-                           (const SolveInfo*)c->info, (const R*)c->rho, (const R*)c->u,
-                           (const R*)c->jt0, (const R*)c->jt1, (R*)c->X, (R*)c->T, (R*)c->Y,
-                           (R*)c->Xi);
-        hipLaunchKernelGGL((k_closure2<Q, R>), c->grid, c->block, 0, c->stream, c->g, c->cf,
-                           (const R*)c->rho, (const R*)c->u, (const R*)c->X, (const R*)c->T,
-                           (const R*)c->Y, (R*)c->Sig);
-        hipLaunchKernelGGL((k_collide<Q, R, S>), c->grid, c->block, 0, c->stream, c->g, c->cf,
-                           c->ds, (const SolveInfo*)c->info, (const S*)c->A, (S*)c->B,
-                           (const R*)c->rho, (const R*)c->u, (const R*)c->f, (const R*)c->jt0,
-                           (const R*)c->jt1, (const R*)c->Sig, (const R*)c->Xi);
+        {
+            ProfScope _ps(c, LB2P_K_CLOSURE1);
+            hipLaunchKernelGGL((k_closure1<Q, R>), c->grid, c->block, 0, c->stream, c->g, c->cf,
+                               (const SolveInfo*)c->info, (const R*)c->rho, (const R*)c->u,
+                               (const R*)c->jt0, (const R*)c->jt1, (R*)c->X, (R*)c->T, (R*)c->Y,
+                               (R*)c->Xi);
+        }
+        {
+            ProfScope _ps(c, LB2P_K_CLOSURE2);
+            hipLaunchKernelGGL((k_closure2<Q, R>), c->grid, c->block, 0, c->stream, c->g, c->cf,
+                               (const R*)c->rho, (const R*)c->u, (const R*)c->X, (const R*)c->T,
+                               (const R*)c->Y, (R*)c->Sig);
+        }
+        {
+            ProfScope _ps(c, LB2P_K_COLLIDE);
+            hipLaunchKernelGGL((k_collide<Q, R, S>), c->grid, c->block, 0, c->stream, c->g, c->cf,
+                               c->ds, (const SolveInfo*)c->info, (const S*)c->A, (S*)c->B,
+                               (const R*)c->rho, (const R*)c->u, (const R*)c->f, (const R*)c->jt0,
+                               (const R*)c->jt1, (const R*)c->Sig, (const R*)c->Xi);
+        }
         HIPCHK(hipGetLastError());
         std::swap(c->A, c->B);
         c->sigma_valid = true;
@@ -335,6 +417,11 @@ void free_ctx(lb2p_ctx* c)
     if (c->partial) (void)hipFree(c->partial);
     if (c->scratch) (void)hipFree(c->scratch);
     if (c->host) (void)hipHostFree(c->host);
+    for (auto& p : c->pending) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (auto e : c->pool) (void)hipEventDestroy(e);
     delete c;
 }
 
@@ -682,6 +769,29 @@ lb2p_status lb2p_set_populations(lb2p_ctx* c, const double* n_in, int on_device)
     c->have_prev = false;
     c->sigma_valid = false;
     c->sticky = LB2P_OK;
+    return LB2P_OK;
+}
+
+lb2p_status lb2p_profile_enable(lb2p_ctx* c, int on)
+{
+    if (!c) return LB2P_EINVAL;
+    prof_collect(c);
+    for (int k = 0; k < LB2P_NKERNEL; ++k) {
+        c->prof_ms[k] = 0.0;
+        c->prof_n[k] = 0;
+    }
+    c->prof = on != 0;
+    return LB2P_OK;
+}
+
+lb2p_status lb2p_profile_read(lb2p_ctx* c, double* ms_out, long long* count_out)
+{
+    if (!c || !ms_out || !count_out) return LB2P_EINVAL;
+    prof_collect(c);
+    for (int k = 0; k < LB2P_NKERNEL; ++k) {
+        ms_out[k] = c->prof_ms[k];
+        count_out[k] = c->prof_n[k];
+    }
     return LB2P_OK;
 }
 

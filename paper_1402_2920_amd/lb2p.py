@@ -53,8 +53,9 @@ class _Stats(ctypes.Structure):
 EXPORTED = [
     "lb2p_default_params", "lb2p_create", "lb2p_init", "lb2p_step", "lb2p_moments",
     "lb2p_get_field", "lb2p_get_populations", "lb2p_set_populations", "lb2p_velocities",
-    "lb2p_stats_get", "lb2p_destroy", "lb2p_strerror",
+    "lb2p_stats_get", "lb2p_profile_enable", "lb2p_profile_read", "lb2p_destroy", "lb2p_strerror",
 ]
+KERNEL_NAMES = ["moments", "force", "iter_q", "iter_jt", "closure1", "closure2", "collide"]
 
 _lib = None
 
@@ -78,6 +79,9 @@ def lib():
         L.lb2p_set_populations.argtypes = [vp, vp, ctypes.c_int]
         L.lb2p_velocities.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
         L.lb2p_stats_get.argtypes = [vp, ctypes.POINTER(_Stats)]
+        L.lb2p_profile_enable.argtypes = [vp, ctypes.c_int]
+        L.lb2p_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_longlong)]
         L.lb2p_destroy.argtypes = [vp]
         L.lb2p_destroy.restype = None
         L.lb2p_strerror.argtypes = [ctypes.c_int]
@@ -257,6 +261,17 @@ class Context:
         assert n.shape == (self.Q, self.N)
         return self._check(lib().lb2p_set_populations(self._ctx, ctypes.c_void_p(n.ctypes.data), 0),
                            "lb2p_set_populations")
+
+    def profile_enable(self, on: bool = True):
+        return self._check(lib().lb2p_profile_enable(self._ctx, int(on)), "lb2p_profile_enable")
+
+    def profile_read(self) -> dict:
+        """{kernel class: (total ms, launches)} since profile_enable."""
+        n = len(KERNEL_NAMES)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_longlong * n)()
+        self._check(lib().lb2p_profile_read(self._ctx, ms, cnt), "lb2p_profile_read")
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(KERNEL_NAMES)}
 
     def stats(self) -> dict:
         st = _Stats()
