@@ -33,17 +33,22 @@ DEFAULT_WORKLOAD = "d3q59_256_slab"
 def site_bytes(kernel, Q, D, s, r, warm):
     """Algorithmic bytes per site of one launch of a kernel class: every
     population or field word the kernel must read or write once (stencil
-    neighbours are reuse, not extra traffic)."""
+    neighbours are reuse, not extra traffic).  The rest population is one
+    plane of t0 bytes (FP64 beside FP64/FP32 storage, FP32 beside BF16/FP16)."""
     nsig = 6 if D == 3 else 3
     nxi = 10 if D == 3 else 4
+    t0 = 8 if s >= 4 else 4
+    pops = (Q - 1) * s + t0
     return {
-        "moments": Q * s + (1 + D) * r,
+        "moments": pops + (1 + D) * r,
         "force": (1 + D) * r + (D * r if warm else 0) + 4 * D * r,
         "iter_q": (1 + D) * r + nsig * r,
         "iter_jt": (nsig + 1 + 2 * D) * r + 2 * D * r,
         "closure1": (1 + 2 * D) * r + (1 + nsig + D + nxi) * r,
         "closure2": (2 + nsig + 2 * D) * r + nsig * r,
-        "collide": 2 * Q * s + (1 + 3 * D + nsig + nxi) * r,
+        "collide": 2 * pops + (1 + 3 * D + nsig + nxi) * r,
+        # fused pass: read j~, j0', rho, write j~new
+        "iter_fused": (1 + 2 * D) * r + D * r,
     }[kernel]
 
 
@@ -80,6 +85,48 @@ def run_gpu(workload, storage, steps, warmup, shape=None, profile=True, tol=None
         stats = ctx.stats()
         out.update(seconds=t1 - t0, prof=prof, stats=stats, N=P.N, Q=P.lattice, D=d, shape=shape,
                    params=P)
+    return out
+
+
+def run_batch(workload, steps, warmup, fixed_iter, graph=True, limit=None, autotune=True):
+    """Batched workload: every domain in one context, `fixed_iter` passes of
+    the j~ iteration per step, the timed steps replayed from one captured HIP
+    graph.  A short eager pass with per-kernel events follows for the
+    roofline (events cannot sit inside a graph)."""
+    import torch
+    import lb2p_workloads as W
+    from paper_1402_2920_amd import lb2p
+    doms = W.build_batch(workload, limit)
+    plist = [lb2p.Params(nx=sh[0], ny=sh[1], nz=1, storage=lb2p.STORE_F32, max_iter=200, warm_start=1,
+                         fixed_iter=fixed_iter, graph_steps=steps if graph else 0,
+                         **W.model_kwargs(ent))
+             for ent, sh, _, _ in doms]
+    rho = np.concatenate([r for _, _, r, _ in doms])
+    u = np.ascontiguousarray(np.concatenate([uu for _, _, _, uu in doms], axis=1))
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    out = {}
+    with lb2p.Context(plist, stream=stream) as ctx:
+        ctx.init(torch.tensor(rho, device="cuda:0"), torch.tensor(u, device="cuda:0"))
+        if autotune:
+            ctx.autotune(2)
+        ctx.step(1)
+        tot0 = ctx.domain_totals()
+        # warm-up: the first steps-long call captures and instantiates the graph
+        ctx.step(steps if graph else warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.step(steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st = ctx.stats()
+        tot = ctx.domain_totals()
+        ctx.profile_enable(True)
+        ctx.step(4)
+        prof = ctx.profile_read()
+        ctx.profile_enable(False)
+        out.update(seconds=t1 - t0, prof=prof, stats=st, N=ctx.N, Q=21, D=2, ndom=len(doms),
+                   mass_drift=float(np.max(np.abs(tot[:, 0] - tot0[:, 0]) / tot0[:, 0])))
     return out
 
 
@@ -185,6 +232,9 @@ def main():
     ap.add_argument("--storage", default="f32", choices=list(STORE_BYTES))
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-variants", action="store_true", help="skip the BF16/F16 storage lines")
+    ap.add_argument("--batch-steps", type=int, default=1000,
+                    help="steps of the 512-domain batched workload in one graph (0: skip)")
+    ap.add_argument("--batch-iters", type=int, default=6, help="fixed j~ passes per batched step")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -224,6 +274,20 @@ def main():
                             ms_per_step=round(1e3 * r2["seconds"] / K, 4), roofline_frac=rf["frac"],
                             dominant=rf["kernel"])
         line["variants"] = var
+    if args.batch_steps > 0:
+        bw = "d2q21_batch512"
+        bres = run_batch(bw, args.batch_steps, args.warmup, args.batch_iters)
+        broof, _ = roofline(bres, "f32")
+        bN = bres["N"]
+        line["batched"] = dict(
+            workload=f"{bw}: {bres['ndom']} periodic D2Q21 domains, sides 32..256, one droplet each, "
+                     f"per-domain EOS (T_r 0.89..0.97) and kappa, f32 populations",
+            value=round(bN * args.batch_steps / bres["seconds"] / 1e6, 2), unit="MLUPS",
+            sites=bN, steps=args.batch_steps, ms_per_step=round(1e3 * bres["seconds"] / args.batch_steps, 4),
+            solve=f"{args.batch_iters} j~ passes per step (fixed), all timed steps in one HIP graph launch",
+            resid_over_jscale=float(f"{bres['stats']['resid'] / max(bres['stats']['jscale'], 1e-300):.3e}"),
+            max_rel_mass_drift=float(f"{bres['mass_drift']:.3e}"),
+            roofline=dict(broof, note="per-kernel HIP events from 4 eager steps after the graph run"))
     if ref is not None:
         errs = {}
         stgs = [args.storage] + ([] if args.no_variants or args.storage != "f32" else ["bf16", "f16"])

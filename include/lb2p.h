@@ -104,7 +104,15 @@ typedef struct {
                                (0 = library default)                          */
     double store_rho_ref;   /* reference density of BF16/F16 deviation storage
                                (<= 0: mean of the density given to lb2p_init) */
+    int flags;              /* LB2P_FLAG_* (0 = defaults)                      */
+    int graph_steps;        /* > 0 with fixed_iter > 0: lb2p_step replays a
+                               HIP graph of this many captured steps           */
 } lb2p_params;
+
+/* lb2p_params.flags: LB2P_FLAG_UNFUSED_SOLVE runs each pass of the j~
+ * iteration as two separate sweeps (items 4 and 5) instead of the fused
+ * D3Q59 kernel; the result is the same map. */
+#define LB2P_FLAG_UNFUSED_SOLVE 1
 
 /* Diagnostics of the state (FP64 sums over all sites). */
 typedef struct {
@@ -120,7 +128,7 @@ typedef struct lb2p_ctx lb2p_ctx;
 
 /* Fill *out with defaults for a lattice and grid: gamma 0, kappa 0, the EOS
  * rho1 0.3, rho2 1.0, A 0, cs2_rho1 0.45, rho0 = rho1, FP32 storage,
- * tol 1e-6 (F32) / 1e-13 (F64), max_iter 200, warm_start 1. */
+ * tol 1e-6 (F32) / 1e-13 (F64), max_iter 200, warm_start 1, no graph. */
 lb2p_status lb2p_default_params(int lattice, int nx, int ny, int nz, int storage,
                                 lb2p_params *out);
 
@@ -131,6 +139,29 @@ lb2p_status lb2p_default_params(int lattice, int nx, int ny, int nz, int storage
  * = default stream); every later call enqueues its work there.
  * Errors: EINVAL, EEOS, ENOMEM, EHIP. */
 lb2p_status lb2p_create(const lb2p_params *params, void *hip_stream, lb2p_ctx **out);
+
+/* A context advancing ndom independent periodic lattices together (each
+ * with its own grid, gamma, kappa, EOS and rho0; all with the same lattice,
+ * storage and iteration settings, taken from per_dom[0]).  Every buffer the
+ * other calls take or return then holds the domains packed in order:
+ * a scalar field is [S] with S = sum of the domain sizes, domain d starting
+ * at off_d = sum of the sizes before it; a vector field is [d][S].  The stop
+ * rule of the j~ iteration applies to each domain separately.
+ * Errors: as lb2p_create, and EINVAL when the shared settings differ. */
+lb2p_status lb2p_create_batch(int ndom, const lb2p_params *per_dom, void *hip_stream,
+                              lb2p_ctx **out);
+
+/* FP64 totals per domain of the current state: out[4*d + k] = mass (k=0)
+ * and momentum x, y, z (k=1..3) of domain d; host memory [4*ndom].
+ * Errors: EINVAL, ESTATE, EHIP. */
+lb2p_status lb2p_domain_totals(lb2p_ctx *ctx, double *out);
+
+/* Pick the kernel block shapes of this context by timing `steps` steps of
+ * each candidate on the current state (which is saved and restored), and
+ * remember the choice per (lattice, storage, domain sizes) for the process.
+ * If LB2P_TUNE_CACHE names a file, choices are read from and appended to it.
+ * Errors: ESTATE, ENOMEM, EHIP. */
+lb2p_status lb2p_autotune(lb2p_ctx *ctx, int steps);
 
 /* Set the initial populations n_i(r, 0) = n_eq(rho(r), u(r)) of Sec. III with
  * the local weights.  rho [N], u [d][N]; dtype lb2p_dtype; host or device.
@@ -182,7 +213,8 @@ typedef enum {
     LB2P_K_CLOSURE1 = 4,   /* items 9-10 and Xi'                             */
     LB2P_K_CLOSURE2 = 5,   /* Sigma                                          */
     LB2P_K_COLLIDE = 6,    /* item 11 per velocity and item 12               */
-    LB2P_NKERNEL = 7
+    LB2P_K_ITER_FUSED = 7, /* items 3-6 of one pass in one kernel (D3Q59)    */
+    LB2P_NKERNEL = 8
 } lb2p_kernel;
 
 /* Diagnostic timing: when enabled, every launch of the classes above is

@@ -149,3 +149,18 @@ def build(name: str, shape=None):
     else:
         raise ValueError(name)
     return entry, shape, rho, u
+
+
+def build_batch(name: str, limit=None):
+    """[(model, shape, rho, u)] of a batched workload: one droplet per domain
+    (the domain's own EOS, kappa and radius), noise seeded per domain."""
+    entry = load_params()[name]
+    if entry["kind"] != "batch":
+        raise ValueError(name)
+    out = []
+    for d in entry["domains"][:limit]:
+        shape = (d["nx"], d["ny"])
+        rho, u = droplet(shape, d["radius"], d["rho_g"], d["rho_l"], width=d["width"],
+                         noise=entry["noise"], seed=d["seed"])
+        out.append((d, shape, rho, u))
+    return out

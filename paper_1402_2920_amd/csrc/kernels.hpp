@@ -1,15 +1,19 @@
 // kernels.hpp -- gfx950 kernels of one consistent two-phase LB step.
 //
-// Populations live in two structure-of-arrays buffers A/B of Q planes
-// [Q][nz][ny][nx].  The buffer read by a step holds post-collision values at
-// their source sites, so the pre-collision population of the step is the pull
+// Populations live in two structure-of-arrays buffers A/B (a rest plane and
+// Q-1 moving planes, layout at RestOf below).  The
+// buffer read by a step holds post-collision values at their source sites,
+// so the pre-collision population of the step is the pull
 // n_i(r) = A_i(r - c_i); the collision writes n*_i(r) at r into the other
 // buffer.  (The paper pushes n*_i to r + c_i; on a periodic lattice the two
 // forms are the same map.)
 //
-// Threads map one-to-one onto sites with x fastest; a block covers whole x
-// rows when nx <= 256 so the misaligned x offsets of the pull stay inside a
-// block.  All per-site fields are structure-of-arrays [comp][N].
+// Every buffer may hold several independent lattices ("domains") packed one
+// after the other: component k of a field at local site s of domain d is
+// F[k*S + off_d + s], S the total number of sites.  A kernel block works on
+// one tile of one domain, read from a tile list; the domain table carries the
+// geometry, the collision constants and the storage scales of each domain.
+// Threads map one-to-one onto sites with x fastest.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -21,10 +25,11 @@ namespace lb2p {
 
 struct Geom {
     int nx, ny, nz;
-    long long N;
+    long long N;   // sites of the domain
+    long long S;   // component stride of the packed arrays
 };
 
-// Constants of the collision (one context).
+// Constants of the collision (one domain).
 struct Coef {
     double gamma, kappa;
     double c0sq;          // c_s^2(rho0)
@@ -40,12 +45,25 @@ struct DevScale {
     float inv[8];
 };
 
+struct Domain {
+    Geom g;
+    long long off;   // first site of the domain in the packed arrays
+    Coef cf;
+    DevScale ds;
+};
+
+// One block's work: a tile of a domain (dom < 0: padding, the block exits).
+struct Tile {
+    int dom, x0, y0, z0;
+    int len;   // planes marched by the solve kernel (z chunk)
+    int pad0, pad1, pad2;
+};
+
 template <class S>
 struct Codec;
 
 template <>
 struct Codec<double> {
-    using R = double;
     __device__ static inline double dec(double v, const DevScale&, int) { return v; }
     __device__ static inline double enc(double v, const DevScale&, int) { return v; }
 };
@@ -77,6 +95,54 @@ struct Codec<__bf16> {
     }
 };
 
+// The rest population (c = 0) is kept apart from the moving ones, at higher
+// precision: FP64 beside FP64/FP32 moving populations, FP32 beside BF16/FP16.
+// The collision sets it from the site's mass balance (the collision invariant
+// sum_i Delta_i = 0 of Sec. VI), so it absorbs the rounding of the stored
+// moving populations and the lattice mass stays conserved to the rounding of
+// that plane alone.  Buffer layout: rest plane [S] of RestOf<S>::T, padded
+// to 256 bytes, then the moving planes i = 1..Q-1 as [Q-1][S] of S.
+template <class S>
+struct RestOf {
+    using T = double;
+};
+template <>
+struct RestOf<__bf16> {
+    using T = float;
+};
+template <>
+struct RestOf<_Float16> {
+    using T = float;
+};
+
+template <class S>
+__host__ __device__ inline long long moving_offset_bytes(long long St)
+{
+    return (St * (long long)sizeof(typename RestOf<S>::T) + 255) / 256 * 256;
+}
+
+template <class S>
+__device__ inline typename RestOf<S>::T* rest_plane(S* A)
+{
+    return reinterpret_cast<typename RestOf<S>::T*>(A);
+}
+template <class S>
+__device__ inline const typename RestOf<S>::T* rest_plane(const S* A)
+{
+    return reinterpret_cast<const typename RestOf<S>::T*>(A);
+}
+// Moving population i (1..Q-1) of site s: moving_planes(A, St)[(i-1)*St + s].
+template <class S>
+__device__ inline S* moving_planes(S* A, long long St)
+{
+    return reinterpret_cast<S*>(reinterpret_cast<char*>(A) + moving_offset_bytes<S>(St));
+}
+template <class S>
+__device__ inline const S* moving_planes(const S* A, long long St)
+{
+    return reinterpret_cast<const S*>(reinterpret_cast<const char*>(A) + moving_offset_bytes<S>(St));
+}
+
 __device__ __forceinline__ int wrap(int v, int n)
 {
     v += (v < 0) ? n : 0;
@@ -94,19 +160,28 @@ __device__ __forceinline__ long long nbr(const Geom& g, int x, int y, int z, int
     return sidx(g, wrap(x + dx, g.nx), wrap(y + dy, g.ny), wrap(z + dz, g.nz));
 }
 
-struct SiteXYZ {
+// Where this thread works: its domain and site.  `ok` is false for threads
+// past the edge of a ragged tile; `dom` < 0 marks a padding block.
+struct Where {
+    int dom;
     int x, y, z;
     bool ok;
 };
 
-__device__ __forceinline__ SiteXYZ site_of_thread(const Geom& g)
+__device__ __forceinline__ Where locate(const Domain* __restrict__ tab, const Tile* __restrict__ tiles)
 {
-    SiteXYZ s;
-    s.x = blockIdx.x * blockDim.x + threadIdx.x;
-    s.y = blockIdx.y * blockDim.y + threadIdx.y;
-    s.z = blockIdx.z;
-    s.ok = s.x < g.nx && s.y < g.ny;
-    return s;
+    const Tile t = tiles[blockIdx.x];
+    Where w;
+    w.dom = t.dom;
+    w.x = t.x0 + threadIdx.x;
+    w.y = t.y0 + threadIdx.y;
+    w.z = t.z0;
+    w.ok = false;
+    if (t.dom >= 0) {
+        const Geom& g = tab[t.dom].g;
+        w.ok = w.x < g.nx && w.y < g.ny;
+    }
+    return w;
 }
 
 // Axis offsets: axis a -> unit vector.
@@ -117,7 +192,7 @@ __device__ __forceinline__ void unit(int a, int& dx, int& dy, int& dz)
     dz = (a == 2);
 }
 
-// D1 (Sec. IV B) of component `comp` of an SoA field along axis a.
+// D1 (Sec. IV B) of one component of an SoA field along axis a.
 template <class R>
 __device__ __forceinline__ R d1_field(const Geom& g, const R* F, int x, int y, int z, int a)
 {
@@ -186,7 +261,8 @@ __device__ __forceinline__ void atomic_max_nonneg(unsigned long long* addr, doub
 }
 
 // Block-wide max of a non-negative value into *addr (one atomic per block).
-// NaN is mapped to +inf so that it is never lost.
+// NaN is mapped to +inf so that it is never lost.  Every thread of the block
+// must call it.
 __device__ inline void block_max_to(unsigned long long* addr, double v)
 {
     __shared__ double red[16];
@@ -209,29 +285,40 @@ __device__ inline void block_max_to(unsigned long long* addr, double v)
 // written pre-shifted so that the first pull returns them.
 // ---------------------------------------------------------------------------
 template <int Q, class R, class S>
-__global__ void k_init(Geom g, Coef cf, DevScale ds, const R* __restrict__ rho,
-                       const R* __restrict__ u, S* __restrict__ A)
+__global__ void __launch_bounds__(256) k_init(const Domain* __restrict__ tab, const Tile* __restrict__ tiles,
+                                              const R* __restrict__ rho, const R* __restrict__ u,
+                                              S* __restrict__ A)
 {
     using L = Lattice<Q>;
-    SiteXYZ s = site_of_thread(g);
-    if (!s.ok) return;
-    const long long i0 = sidx(g, s.x, s.y, s.z);
+    const Where w = locate(tab, tiles);
+    if (!w.ok) return;
+    const Domain& dm = tab[w.dom];
+    const Geom g = dm.g;
+    const long long o = dm.off, St = g.S;
+    const long long i0 = o + sidx(g, w.x, w.y, w.z);
     const R r = rho[i0];
     R uu[3] = {R(0), R(0), R(0)};
 #pragma unroll
-    for (int a = 0; a < L::D; ++a) uu[a] = u[a * g.N + i0];
-    const R cs2 = eos_cs2<R>(cf.eos, r);
-    R w[8];
-    shell_weights<Q, R>(cs2, w);
+    for (int a = 0; a < L::D; ++a) uu[a] = u[a * St + i0];
+    const R cs2 = eos_cs2<R>(dm.cf.eos, r);
+    R wl[8];
+    shell_weights<Q, R>(cs2, wl);
     const R inv = R(1) / cs2;
     const R a0 = R(1) - (uu[0] * uu[0] + uu[1] * uu[1] + uu[2] * uu[2]) * R(0.5) * inv;
+    using T0 = typename RestOf<S>::T;
+    S* mv = moving_planes(A, St);
+    T0 moved = T0(0);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
+    for (int i = 1; i < Q; ++i) {
         const R uc = uu[0] * R(L::cx(i)) + uu[1] * R(L::cy(i)) + uu[2] * R(L::cz(i));
-        const R neq = w[L::shell(i)] * r * (a0 + uc * inv + R(0.5) * uc * uc * inv * inv);
-        const long long dst = nbr(g, s.x, s.y, s.z, -L::cx(i), -L::cy(i), -L::cz(i));
-        A[(size_t)i * g.N + dst] = Codec<S>::enc(neq, ds, L::shell(i));
+        const R neq = wl[L::shell(i)] * r * (a0 + uc * inv + R(0.5) * uc * uc * inv * inv);
+        const long long dst = o + nbr(g, w.x, w.y, w.z, -L::cx(i), -L::cy(i), -L::cz(i));
+        const S e = Codec<S>::enc(neq, dm.ds, L::shell(i));
+        mv[(size_t)(i - 1) * St + dst] = e;
+        moved += T0(Codec<S>::dec(e, dm.ds, L::shell(i)));
     }
+    // rest population: the site's density minus the stored moving ones
+    rest_plane(A)[i0] = T0(r) - moved;
 }
 
 // ---------------------------------------------------------------------------
@@ -239,31 +326,46 @@ __global__ void k_init(Geom g, Coef cf, DevScale ds, const R* __restrict__ rho,
 // FP64 block partial sums of mass and momentum plus a non-finite flag.
 // ---------------------------------------------------------------------------
 template <int Q, class R, class S>
-__global__ void k_moments(Geom g, DevScale ds, const S* __restrict__ A, R* __restrict__ rho,
-                          R* __restrict__ j0, double* __restrict__ partial,
-                          int* __restrict__ flags)
+__global__ void __launch_bounds__(256) k_moments(const Domain* __restrict__ tab,
+                                                 const Tile* __restrict__ tiles,
+                                                 const S* __restrict__ A, R* __restrict__ rho,
+                                                 R* __restrict__ j0, double* __restrict__ partial,
+                                                 int* __restrict__ flags)
 {
     using L = Lattice<Q>;
-    SiteXYZ s = site_of_thread(g);
+    const Where w = locate(tab, tiles);
+    if (w.dom < 0) {   // padding block: empty partial sums
+        const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+        if (tid < 4) partial[4 * (long long)blockIdx.x + tid] = 0.0;
+        return;
+    }
     double m[4] = {0.0, 0.0, 0.0, 0.0};
-    if (s.ok) {
-        const long long i0 = sidx(g, s.x, s.y, s.z);
-        R r = R(0), jx = R(0), jy = R(0), jz = R(0);
+    if (w.ok) {
+        const Domain& dm = tab[w.dom];
+        const Geom g = dm.g;
+        const long long o = dm.off, St = g.S;
+        const long long i0 = o + sidx(g, w.x, w.y, w.z);
+        // density accumulated at the rest plane's precision (the conserved sum)
+        using T0 = typename RestOf<S>::T;
+        T0 racc = rest_plane(A)[i0];
+        R jx = R(0), jy = R(0), jz = R(0);
+        const S* mv = moving_planes(A, St);
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const long long src = nbr(g, s.x, s.y, s.z, -L::cx(i), -L::cy(i), -L::cz(i));
-            const R v = Codec<S>::dec(A[(size_t)i * g.N + src], ds, L::shell(i));
-            r += v;
+        for (int i = 1; i < Q; ++i) {
+            const long long src = o + nbr(g, w.x, w.y, w.z, -L::cx(i), -L::cy(i), -L::cz(i));
+            const R v = Codec<S>::dec(mv[(size_t)(i - 1) * St + src], dm.ds, L::shell(i));
+            racc += T0(v);
             if (L::cx(i)) jx += R(L::cx(i)) * v;
             if (L::cy(i)) jy += R(L::cy(i)) * v;
             if (L::cz(i)) jz += R(L::cz(i)) * v;
         }
+        const R r = R(racc);
         rho[i0] = r;
         j0[i0] = jx;
-        j0[g.N + i0] = jy;
-        if (L::D == 3) j0[2 * g.N + i0] = jz;
+        j0[St + i0] = jy;
+        if (L::D == 3) j0[2 * St + i0] = jz;
         if (!(r > R(0) && r < R(1e30))) atomicOr(flags, 1);
-        m[0] = r; m[1] = jx; m[2] = jy; m[3] = jz;
+        m[0] = (double)racc; m[1] = jx; m[2] = jy; m[3] = jz;
     }
     __shared__ double red[4][16];
     const int tid = threadIdx.x + blockDim.x * threadIdx.y;
@@ -277,11 +379,29 @@ __global__ void k_moments(Geom g, DevScale ds, const S* __restrict__ A, R* __res
     __syncthreads();
     if (tid < 4) {
         double acc = 0.0;
-        for (int w = 0; w < nw; ++w) acc += red[tid][w];
-        const long long b = blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z);
-        partial[4 * b + tid] = acc;
+        for (int q = 0; q < nw; ++q) acc += red[tid][q];
+        partial[4 * (long long)blockIdx.x + tid] = acc;
     }
 }
+
+// Which j~ buffer holds each domain's final iterate, and its pass count.
+struct SolveInfo {
+    int final_buf;
+    int iters;
+    int converged;
+    int pad;
+};
+
+// Stop-rule bookkeeping of the j~ iteration, one set per domain:
+// res[dom*stride + k] = bits of max|j~new - j~| of pass k, jscale[dom] =
+// bits of max|j0'|, done_at[dom] = pass at which the rule held (or -1).
+struct IterCtl {
+    unsigned long long* res;
+    unsigned long long* jscale;
+    int* done_at;
+    int stride;
+    double tol;                  // < 0: never stop early (fixed count)
+};
 
 // ---------------------------------------------------------------------------
 // Item 2: f = kappa rho d_a d_b d_b rho (Sec. IV E), j0' = j0 + f/2.
@@ -289,19 +409,26 @@ __global__ void k_moments(Geom g, DevScale ds, const S* __restrict__ A, R* __res
 // and max|j0'| for the stop rule.
 // ---------------------------------------------------------------------------
 template <int Q, class R>
-__global__ void k_force(Geom g, Coef cf, const R* __restrict__ rho, const R* __restrict__ j0,
-                        R* __restrict__ f, R* __restrict__ j0p, R* __restrict__ u,
-                        const R* jt_prev, R* jt0,
-                        unsigned long long* __restrict__ jscale)
+__global__ void __launch_bounds__(256) k_force(const Domain* __restrict__ tab,
+                                               const Tile* __restrict__ tiles, IterCtl ic,
+                                               const R* __restrict__ rho, const R* __restrict__ j0,
+                                               R* __restrict__ f, R* __restrict__ j0p,
+                                               R* __restrict__ u, const R* jt_prevA,
+                                               const R* jt_prevB, const SolveInfo* prev_info,
+                                               R* jt0)
 {
     using L = Lattice<Q>;
-    SiteXYZ s = site_of_thread(g);
+    const Where w = locate(tab, tiles);
+    if (w.dom < 0) return;
     double amax = 0.0;
-    if (s.ok) {
-        const int x = s.x, y = s.y, z = s.z;
-        const long long i0 = sidx(g, x, y, z);
+    if (w.ok) {
+        const Domain& dm = tab[w.dom];
+        const Geom g = dm.g;
+        const long long o = dm.off, St = g.S;
+        const int x = w.x, y = w.y, z = w.z;
+        const long long i0 = o + sidx(g, x, y, z);
         const R r = rho[i0];
-        auto RH = [&](int dx, int dy, int dz) { return rho[nbr(g, x, y, z, dx, dy, dz)]; };
+        auto RH = [&](int dx, int dy, int dz) { return rho[o + nbr(g, x, y, z, dx, dy, dz)]; };
         R fa[3] = {R(0), R(0), R(0)};
         if constexpr (L::D == 3) {
             // (100): tau -3 ; (110): tau 1/2 ; (200): tau 1/4 (Table III)
@@ -326,39 +453,34 @@ __global__ void k_force(Geom g, Coef cf, const R* __restrict__ rho, const R* __r
                     R(0.5) * (RH(1, 1, 0) + RH(-1, 1, 0) - RH(1, -1, 0) - RH(-1, -1, 0)) +
                     R(0.5) * (RH(0, 2, 0) - RH(0, -2, 0));
         }
-        const R kr = R(cf.kappa) * r;
+        const R kr = R(dm.cf.kappa) * r;
         const R inv = R(1) / r;
+        // warm start: the previous step's final iterate of this domain
+        const R* prev = nullptr;
+        if (prev_info) prev = prev_info[w.dom].final_buf ? jt_prevB : jt_prevA;
 #pragma unroll
         for (int a = 0; a < L::D; ++a) {
             const R fv = kr * fa[a];
-            const R jp = j0[a * g.N + i0] + R(0.5) * fv;
-            const R jt = jt_prev ? jt_prev[a * g.N + i0] : R(0);
-            f[a * g.N + i0] = fv;
-            j0p[a * g.N + i0] = jp;
-            jt0[a * g.N + i0] = jt;
-            u[a * g.N + i0] = (jp + jt) * inv;
+            const R jp = j0[a * St + i0] + R(0.5) * fv;
+            const R jt = prev ? prev[a * St + i0] : R(0);
+            f[a * St + i0] = fv;
+            j0p[a * St + i0] = jp;
+            jt0[a * St + i0] = jt;
+            u[a * St + i0] = (jp + jt) * inv;
             amax = fmax(amax, fabs((double)jp));
         }
     }
-    block_max_to(jscale, amax);
+    block_max_to(ic.jscale + w.dom, amax);
 }
 
-// Iteration control shared by the two kernels of one pass.
-struct IterCtl {
-    unsigned long long* res;     // res[k] = bits of max|j~new - j~| of pass k
-    unsigned long long* jscale;  // bits of max|j0'|
-    int* done_at;                // pass index at which the stop rule held, or -1
-    double tol;                  // < 0: never stop early (fixed count)
-};
-
-__device__ __forceinline__ bool iter_skip(const IterCtl& c, int it)
+__device__ __forceinline__ bool iter_skip(const IterCtl& c, int dom, int it)
 {
-    if (*((volatile int*)c.done_at) >= 0) return true;
+    if (*((volatile int*)(c.done_at + dom)) >= 0) return true;
     if (it > 0 && c.tol >= 0.0) {
-        const double r = __longlong_as_double((long long)c.res[it - 1]);
-        const double thr = c.tol * __longlong_as_double((long long)*c.jscale);
+        const double r = __longlong_as_double((long long)c.res[(long long)dom * c.stride + it - 1]);
+        const double thr = c.tol * __longlong_as_double((long long)c.jscale[dom]);
         if (r <= thr) {
-            *((volatile int*)c.done_at) = it;
+            *((volatile int*)(c.done_at + dom)) = it;
             return true;
         }
     }
@@ -370,31 +492,35 @@ __device__ __forceinline__ bool iter_skip(const IterCtl& c, int it)
 // derivatives with the stencil of Sec. IV B.  q is symmetric.
 // ---------------------------------------------------------------------------
 template <int Q, class R>
-__global__ void k_iter_q(Geom g, Coef cf, IterCtl ic, int it, const R* __restrict__ rho,
-                         const R* __restrict__ u, R* __restrict__ q)
+__global__ void __launch_bounds__(256) k_iter_q(const Domain* __restrict__ tab,
+                                                const Tile* __restrict__ tiles, IterCtl ic, int it,
+                                                const R* __restrict__ rho, const R* __restrict__ u,
+                                                R* __restrict__ q)
 {
     using L = Lattice<Q>;
     constexpr int D = L::D;
-    if (iter_skip(ic, it)) return;
-    SiteXYZ s = site_of_thread(g);
-    if (!s.ok) return;
-    const long long i0 = sidx(g, s.x, s.y, s.z);
+    const Where w = locate(tab, tiles);
+    if (w.dom < 0 || iter_skip(ic, w.dom, it) || !w.ok) return;
+    const Domain& dm = tab[w.dom];
+    const Geom g = dm.g;
+    const long long o = dm.off, St = g.S;
+    const long long i0 = o + sidx(g, w.x, w.y, w.z);
     R G[3][3];
 #pragma unroll
     for (int a = 0; a < D; ++a)
 #pragma unroll
-        for (int b = 0; b < D; ++b) G[a][b] = d1_field<R>(g, u + b * g.N, s.x, s.y, s.z, a);
+        for (int b = 0; b < D; ++b) G[a][b] = d1_field<R>(g, u + b * St + o, w.x, w.y, w.z, a);
     R trG = R(0);
 #pragma unroll
     for (int a = 0; a < D; ++a) trG += G[a][a];
-    const EosVal<R> e = eos_all<R>(cf.eos, rho[i0]);
+    const EosVal<R> e = eos_all<R>(dm.cf.eos, rho[i0]);
 #pragma unroll
     for (int a = 0; a < D; ++a)
 #pragma unroll
         for (int b = a; b < D; ++b) {
             R v = e.p * (G[a][b] + G[b][a]);
             if (a == b) v += e.P1 * trG;
-            q[sym2<D>(a, b) * g.N + i0] = v;
+            q[sym2<D>(a, b) * St + i0] = v;
         }
 }
 
@@ -403,54 +529,69 @@ __global__ void k_iter_q(Geom g, Coef cf, IterCtl ic, int it, const R* __restric
 // pass: u = (j0' + j~new)/rho.
 // ---------------------------------------------------------------------------
 template <int Q, class R>
-__global__ void k_iter_jt(Geom g, IterCtl ic, int it, const R* __restrict__ rho,
-                          const R* __restrict__ q, const R* __restrict__ j0p,
-                          const R* __restrict__ jt_old, R* __restrict__ jt_new, R* __restrict__ u)
+__global__ void __launch_bounds__(256) k_iter_jt(const Domain* __restrict__ tab,
+                                                 const Tile* __restrict__ tiles, IterCtl ic, int it,
+                                                 const R* __restrict__ rho, const R* __restrict__ q,
+                                                 const R* __restrict__ j0p,
+                                                 const R* __restrict__ jt_old,
+                                                 R* __restrict__ jt_new, R* __restrict__ u)
 {
     using L = Lattice<Q>;
     constexpr int D = L::D;
-    if (*((volatile int*)ic.done_at) >= 0) return;
-    SiteXYZ s = site_of_thread(g);
+    const Where w = locate(tab, tiles);
+    if (w.dom < 0) return;
+    if (*((volatile int*)(ic.done_at + w.dom)) >= 0) return;   // uniform per block
     double dmax = 0.0;
-    if (s.ok) {
-        const long long i0 = sidx(g, s.x, s.y, s.z);
+    if (w.ok) {
+        const Domain& dm = tab[w.dom];
+        const Geom g = dm.g;
+        const long long o = dm.off, St = g.S;
+        const long long i0 = o + sidx(g, w.x, w.y, w.z);
         const R inv = R(1) / rho[i0];
 #pragma unroll
         for (int a = 0; a < D; ++a) {
             R acc = R(0);
 #pragma unroll
-            for (int b = 0; b < D; ++b) acc += d1_field<R>(g, q + sym2<D>(a, b) * g.N, s.x, s.y, s.z, b);
+            for (int b = 0; b < D; ++b)
+                acc += d1_field<R>(g, q + sym2<D>(a, b) * St + o, w.x, w.y, w.z, b);
             const R jn = -acc * R(1.0 / 12.0);
-            dmax = fmax(dmax, fabs((double)(jn - jt_old[a * g.N + i0])));
-            jt_new[a * g.N + i0] = jn;
-            u[a * g.N + i0] = (j0p[a * g.N + i0] + jn) * inv;
+            dmax = fmax(dmax, fabs((double)(jn - jt_old[a * St + i0])));
+            jt_new[a * St + i0] = jn;
+            u[a * St + i0] = (j0p[a * St + i0] + jn) * inv;
         }
     }
-    block_max_to(ic.res + it, dmax);
+    block_max_to(ic.res + (long long)w.dom * ic.stride + it, dmax);
 }
 
-// Which j~ buffer holds the final iterate, and the pass count.
-struct SolveInfo {
-    int final_buf;
-    int iters;
-    int converged;
-    int pad;
-};
-
-__global__ void k_iter_finish(IterCtl ic, int launched, SolveInfo* info)
+// One thread per domain.
+__global__ void k_iter_finish(IterCtl ic, int launched, int ndom, SolveInfo* info, int* nconv)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    int d = *((volatile int*)ic.done_at);
+    const int dom = blockIdx.x * blockDim.x + threadIdx.x;
+    if (dom >= ndom) return;
+    int d = *((volatile int*)(ic.done_at + dom));
     if (d < 0 && ic.tol >= 0.0 && launched > 0) {
         // stop rule on the last launched pass (no later pass tested it)
-        const double r = __longlong_as_double((long long)ic.res[launched - 1]);
-        const double thr = ic.tol * __longlong_as_double((long long)*ic.jscale);
+        const double r = __longlong_as_double((long long)ic.res[(long long)dom * ic.stride + launched - 1]);
+        const double thr = ic.tol * __longlong_as_double((long long)ic.jscale[dom]);
         if (r <= thr) d = launched;
     }
     const int iters = d >= 0 ? d : launched;
-    info->iters = iters;
-    info->final_buf = iters & 1;
-    info->converged = d >= 0 || ic.tol < 0.0;
+    info[dom].iters = iters;
+    info[dom].final_buf = iters & 1;
+    info[dom].converged = d >= 0 || ic.tol < 0.0;
+    if (!(d >= 0 || ic.tol < 0.0)) atomicAdd(nconv, 1);
+}
+
+// Number of domains whose stop rule has held (for the host's early exit).
+__global__ void k_count_done(const int* __restrict__ done_at, int ndom, int* out)
+{
+    __shared__ int cnt;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    for (int d = threadIdx.x; d < ndom; d += blockDim.x)
+        if (done_at[d] >= 0) atomicAdd(&cnt, 1);
+    __syncthreads();
+    if (threadIdx.x == 0) *out = cnt;
 }
 
 // ---------------------------------------------------------------------------
@@ -459,39 +600,43 @@ __global__ void k_iter_finish(IterCtl ic, int launched, SolveInfo* info)
 // rank-3 tensor Xi' (all first-order derivatives of per-site products).
 // ---------------------------------------------------------------------------
 template <int Q, class R>
-__global__ void k_closure1(Geom g, Coef cf, const SolveInfo* __restrict__ info,
-                           const R* __restrict__ rho, const R* __restrict__ u,
-                           const R* __restrict__ jtA, const R* __restrict__ jtB,
-                           R* __restrict__ X, R* __restrict__ T, R* __restrict__ Y,
-                           R* __restrict__ Xi)
+__global__ void __launch_bounds__(256) k_closure1(const Domain* __restrict__ tab,
+                                                  const Tile* __restrict__ tiles,
+                                                  const SolveInfo* __restrict__ info,
+                                                  const R* __restrict__ rho, const R* __restrict__ u,
+                                                  const R* __restrict__ jtA, const R* __restrict__ jtB,
+                                                  R* __restrict__ X, R* __restrict__ T,
+                                                  R* __restrict__ Y, R* __restrict__ Xi)
 {
     using L = Lattice<Q>;
     constexpr int D = L::D;
-    SiteXYZ s = site_of_thread(g);
-    if (!s.ok) return;
-    const int x = s.x, y = s.y, z = s.z;
-    const long long i0 = sidx(g, x, y, z);
-    const R* jt = info->final_buf ? jtB : jtA;
+    const Where w = locate(tab, tiles);
+    if (!w.ok) return;
+    const Domain& dm = tab[w.dom];
+    const Geom g = dm.g;
+    const long long o = dm.off, St = g.S;
+    const int x = w.x, y = w.y, z = w.z;
+    const long long i0 = o + sidx(g, x, y, z);
+    const R* jt = info[w.dom].final_buf ? jtB : jtA;
 
-    R G[3][3] = {};   // d_a u_b
-    R M[3][3][3] = {};// d_a (p u_b u_g)
+    R G[3][3] = {};    // d_a u_b
+    R M[3][3][3] = {}; // d_a (p u_b u_g)
     R Pg[3] = {}, C[3] = {};  // d_a p, d_a (p/rho)
 #pragma unroll
     for (int a = 0; a < D; ++a) {
         int dx, dy, dz;
         unit(a, dx, dy, dz);
-        // values at the four stencil points along axis a
         R pv[4], cv[4], uv[4][3];
         const int off[4] = {-2, -1, 1, 2};
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const long long t = nbr(g, x, y, z, off[k] * dx, off[k] * dy, off[k] * dz);
+            const long long t = o + nbr(g, x, y, z, off[k] * dx, off[k] * dy, off[k] * dz);
             const R rt = rho[t];
-            const R cs2 = eos_cs2<R>(cf.eos, rt);
+            const R cs2 = eos_cs2<R>(dm.cf.eos, rt);
             cv[k] = cs2;
             pv[k] = rt * cs2;
 #pragma unroll
-            for (int b = 0; b < D; ++b) uv[k][b] = u[b * g.N + t];
+            for (int b = 0; b < D; ++b) uv[k][b] = u[b * St + t];
         }
         Pg[a] = d1<R>(pv[0], pv[1], pv[2], pv[3]);
         C[a] = d1<R>(cv[0], cv[1], cv[2], cv[3]);
@@ -508,10 +653,10 @@ __global__ void k_closure1(Geom g, Coef cf, const SolveInfo* __restrict__ info,
         }
     }
     const R r = rho[i0];
-    const EosVal<R> e = eos_all<R>(cf.eos, r);
+    const EosVal<R> e = eos_all<R>(dm.cf.eos, r);
     R us[3] = {R(0), R(0), R(0)};
 #pragma unroll
-    for (int a = 0; a < D; ++a) us[a] = u[a * g.N + i0];
+    for (int a = 0; a < D; ++a) us[a] = u[a * St + i0];
     R trG = R(0);
 #pragma unroll
     for (int a = 0; a < D; ++a) trG += G[a][a];
@@ -520,22 +665,22 @@ __global__ void k_closure1(Geom g, Coef cf, const SolveInfo* __restrict__ info,
 #pragma unroll
     for (int a = 0; a < D; ++a)
 #pragma unroll
-        for (int c = a; c < D; ++c) T[sym2<D>(a, c) * g.N + i0] = e.p * (G[a][c] + G[c][a]);
+        for (int c = a; c < D; ++c) T[sym2<D>(a, c) * St + i0] = e.p * (G[a][c] + G[c][a]);
     const R inv = R(1) / r;
 #pragma unroll
     for (int b = 0; b < D; ++b) {
         R acc = Pg[b] * inv;
 #pragma unroll
         for (int c = 0; c < D; ++c) acc += us[c] * G[c][b];
-        Y[b * g.N + i0] = acc;
+        Y[b * St + i0] = acc;
     }
 
-    const R gm = R(cf.gamma);
+    const R gm = R(dm.cf.gamma);
     const R KX = (gm * gm + R(4) * gm + R(1)) / (R(3) * (gm + R(1)));
-    const R KJ = (R(1) - gm) * R(cf.c0sq);
+    const R KJ = (R(1) - gm) * R(dm.cf.c0sq);
     R jts[3] = {R(0), R(0), R(0)};
 #pragma unroll
-    for (int a = 0; a < D; ++a) jts[a] = jt[a * g.N + i0];
+    for (int a = 0; a < D; ++a) jts[a] = jt[a * St + i0];
     R V[3];
 #pragma unroll
     for (int a = 0; a < D; ++a) V[a] = e.p * C[a] + e.P1 * us[a] * trG;
@@ -550,7 +695,7 @@ __global__ void k_closure1(Geom g, Coef cf, const SolveInfo* __restrict__ info,
                 if (a == b) { br += V[c]; dj += jts[c]; }
                 if (a == c) { br += V[b]; dj += jts[b]; }
                 if (b == c) { br += V[a]; dj += jts[a]; }
-                Xi[sym3<D>(a, b, c) * g.N + i0] = KX * br + KJ * dj;
+                Xi[sym3<D>(a, b, c) * St + i0] = KX * br + KJ * dj;
             }
 }
 
@@ -559,47 +704,52 @@ __global__ void k_closure1(Geom g, Coef cf, const SolveInfo* __restrict__ info,
 // site values (with d_a j_b recomputed from j = rho u).
 // ---------------------------------------------------------------------------
 template <int Q, class R>
-__global__ void k_closure2(Geom g, Coef cf, const R* __restrict__ rho, const R* __restrict__ u,
-                           const R* __restrict__ X, const R* __restrict__ T,
-                           const R* __restrict__ Y, R* __restrict__ Sig)
+__global__ void __launch_bounds__(256) k_closure2(const Domain* __restrict__ tab,
+                                                  const Tile* __restrict__ tiles,
+                                                  const R* __restrict__ rho, const R* __restrict__ u,
+                                                  const R* __restrict__ X, const R* __restrict__ T,
+                                                  const R* __restrict__ Y, R* __restrict__ Sig)
 {
     using L = Lattice<Q>;
     constexpr int D = L::D;
-    SiteXYZ s = site_of_thread(g);
-    if (!s.ok) return;
-    const int x = s.x, y = s.y, z = s.z;
-    const long long i0 = sidx(g, x, y, z);
+    const Where w = locate(tab, tiles);
+    if (!w.ok) return;
+    const Domain& dm = tab[w.dom];
+    const Geom g = dm.g;
+    const long long o = dm.off, St = g.S;
+    const int x = w.x, y = w.y, z = w.z;
+    const long long i0 = o + sidx(g, x, y, z);
     R DX[3] = {}, DT[3] = {}, DY[3][3] = {}, G[3][3] = {};
     R trJ = R(0);
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        DX[a] = d1_field<R>(g, X, x, y, z, a);
+        DX[a] = d1_field<R>(g, X + o, x, y, z, a);
 #pragma unroll
-        for (int c = 0; c < D; ++c) DT[a] += d1_field<R>(g, T + sym2<D>(a, c) * g.N, x, y, z, c);
+        for (int c = 0; c < D; ++c) DT[a] += d1_field<R>(g, T + sym2<D>(a, c) * St + o, x, y, z, c);
 #pragma unroll
-        for (int b = 0; b < D; ++b) DY[a][b] = d1_field<R>(g, Y + b * g.N, x, y, z, a);
+        for (int b = 0; b < D; ++b) DY[a][b] = d1_field<R>(g, Y + b * St + o, x, y, z, a);
         int dx, dy, dz;
         unit(a, dx, dy, dz);
         R jv[4];
         const int off[4] = {-2, -1, 1, 2};
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const long long t = nbr(g, x, y, z, off[k] * dx, off[k] * dy, off[k] * dz);
-            jv[k] = rho[t] * u[a * g.N + t];
+            const long long t = o + nbr(g, x, y, z, off[k] * dx, off[k] * dy, off[k] * dz);
+            jv[k] = rho[t] * u[a * St + t];
         }
         trJ += d1<R>(jv[0], jv[1], jv[2], jv[3]);
 #pragma unroll
-        for (int b = 0; b < D; ++b) G[a][b] = d1_field<R>(g, u + b * g.N, x, y, z, a);
+        for (int b = 0; b < D; ++b) G[a][b] = d1_field<R>(g, u + b * St + o, x, y, z, a);
     }
     const R r = rho[i0];
-    const EosVal<R> e = eos_all<R>(cf.eos, r);
+    const EosVal<R> e = eos_all<R>(dm.cf.eos, r);
     R us[3] = {R(0), R(0), R(0)};
 #pragma unroll
-    for (int a = 0; a < D; ++a) us[a] = u[a * g.N + i0];
+    for (int a = 0; a < D; ++a) us[a] = u[a * St + i0];
     R trG = R(0), trDY = R(0);
 #pragma unroll
     for (int a = 0; a < D; ++a) { trG += G[a][a]; trDY += DY[a][a]; }
-    const R gm = R(cf.gamma);
+    const R gm = R(dm.cf.gamma);
     const R KS1 = R(-0.25) * (gm + R(1)) * (gm + R(1)) / (gm - R(1));
     const R KS2 = (gm * gm + R(4) * gm + R(1)) / (R(6) * (gm - R(1)));
 #pragma unroll
@@ -609,7 +759,7 @@ __global__ void k_closure2(Geom g, Coef cf, const R* __restrict__ rho, const R* 
             const R br1 = us[a] * DX[b] + us[b] * DX[a] + us[b] * DT[a] + us[a] * DT[b];
             R br2 = -e.dp * trJ * (G[a][b] + G[b][a]) - e.p * (DY[a][b] + DY[b][a]);
             if (a == b) br2 += -e.P1 * trDY + e.P2 * trG * trJ;
-            Sig[sym2<D>(a, b) * g.N + i0] = KS1 * br1 + KS2 * br2;
+            Sig[sym2<D>(a, b) * St + i0] = KS1 * br1 + KS2 * br2;
         }
 }
 
@@ -619,39 +769,45 @@ __global__ void k_closure2(Geom g, Coef cf, const R* __restrict__ rho, const R* 
 // Velocities come in antipodal pairs; each pair shares its even part.
 // ---------------------------------------------------------------------------
 template <int Q, class R, class S>
-__global__ void k_collide(Geom g, Coef cf, DevScale ds, const SolveInfo* __restrict__ info,
-                          const S* __restrict__ A, S* __restrict__ B, const R* __restrict__ rho,
-                          const R* __restrict__ u, const R* __restrict__ f,
-                          const R* __restrict__ jtA, const R* __restrict__ jtB,
-                          const R* __restrict__ Sig, const R* __restrict__ Xi)
+__global__ void __launch_bounds__(256) k_collide(const Domain* __restrict__ tab,
+                                                 const Tile* __restrict__ tiles,
+                                                 const SolveInfo* __restrict__ info,
+                                                 const S* __restrict__ A, S* __restrict__ B,
+                                                 const R* __restrict__ rho, const R* __restrict__ u,
+                                                 const R* __restrict__ f, const R* __restrict__ jtA,
+                                                 const R* __restrict__ jtB, const R* __restrict__ Sig,
+                                                 const R* __restrict__ Xi)
 {
     using L = Lattice<Q>;
     constexpr int D = L::D;
-    SiteXYZ s = site_of_thread(g);
-    if (!s.ok) return;
-    const int x = s.x, y = s.y, z = s.z;
-    const long long i0 = sidx(g, x, y, z);
-    const R* jt = info->final_buf ? jtB : jtA;
+    const Where w = locate(tab, tiles);
+    if (!w.ok) return;
+    const Domain& dm = tab[w.dom];
+    const Geom g = dm.g;
+    const long long o = dm.off, St = g.S;
+    const int x = w.x, y = w.y, z = w.z;
+    const long long i0 = o + sidx(g, x, y, z);
+    const R* jt = info[w.dom].final_buf ? jtB : jtA;
 
     const R r = rho[i0];
     R us[3] = {R(0), R(0), R(0)}, fs[3] = {R(0), R(0), R(0)}, js[3] = {R(0), R(0), R(0)};
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        us[a] = u[a * g.N + i0];
-        fs[a] = f[a * g.N + i0];
-        js[a] = jt[a * g.N + i0];
+        us[a] = u[a * St + i0];
+        fs[a] = f[a * St + i0];
+        js[a] = jt[a * St + i0];
     }
     R Sg[6], Xp[10];
 #pragma unroll
-    for (int k = 0; k < L::NSIG; ++k) Sg[k] = Sig[k * g.N + i0];
+    for (int k = 0; k < L::NSIG; ++k) Sg[k] = Sig[k * St + i0];
 #pragma unroll
-    for (int k = 0; k < L::NXI; ++k) Xp[k] = Xi[k * g.N + i0];
+    for (int k = 0; k < L::NXI; ++k) Xp[k] = Xi[k * St + i0];
 
-    const R gm = R(cf.gamma);
-    const R c0 = R(cf.c0sq);
+    const R gm = R(dm.cf.gamma);
+    const R c0 = R(dm.cf.c0sq);
     const R ic0 = R(1) / c0;
     // n_eq pieces (local weights)
-    const R cs2 = eos_cs2<R>(cf.eos, r);
+    const R cs2 = eos_cs2<R>(dm.cf.eos, r);
     R wl[8];
     shell_weights<Q, R>(cs2, wl);
     const R ics = R(1) / cs2;
@@ -679,18 +835,17 @@ __global__ void k_collide(Geom g, Coef cf, DevScale ds, const SolveInfo* __restr
         bvec[a] = R(0.5) * (R(1) + gm) * ic0 * fs[a] + (gm - R(1)) * ic0 * js[a] - R(0.5) * ic0 * ic0 * v[a];
     const R s0 = -R(0.5) * ic0 * trS;
 
-    // rest velocity (index 0): even part only
-    {
-        const R neq = wl[0] * a0;
-        const R corr = R(cf.Wk[0]) * s0;
-        const R n0 = Codec<S>::dec(A[i0], ds, 0);  // c = 0: pull from r itself
-        B[i0] = Codec<S>::enc(gm * n0 + neq + corr, ds, 0);
-    }
+    // Moving velocities first; the rest population then takes what the
+    // collision invariant sum_i Delta_i = 0 (Sec. VI) leaves for it:
+    // n*_0 = n_0 - sum_{i>0} (n*_i - n_i), with the n*_i as stored.  This is
+    // n_0 + Delta_0 in exact arithmetic; the differences are small, so their
+    // rounding is far below that of the populations themselves.
+    const S* amv = moving_planes(A, St);
+    S* bmv = moving_planes(B, St);
+    R dsum = R(0);
 #pragma unroll
     for (int p = 0; p < L::NPAIR; ++p) {
         const int ip = 2 * p + 1, im = 2 * p + 2;
-        constexpr int dummy = 0;
-        (void)dummy;
         const int cxv = L::cx(ip), cyv = L::cy(ip), czv = L::cz(ip);
         const int k = L::shell(ip);
         const R cx = R(cxv), cy = R(cyv), cz = R(czv);
@@ -714,66 +869,87 @@ __global__ void k_collide(Geom g, Coef cf, DevScale ds, const SolveInfo* __restr
                   R(3) * (Xp[2] * cx * cx * cy + Xp[3] * cx * cy * cy);
         }
         const R bc = bvec[0] * cx + bvec[1] * cy + (D == 3 ? bvec[2] * cz : R(0));
-        const R Wk = R(cf.Wk[k]);
+        const R Wk = R(dm.cf.Wk[k]);
         const R even = wl[k] * (a0 + a2 * uc * uc) + Wk * (kS * cSc + s0);
         const R odd = wl[k] * a1 * uc + Wk * (bc + kX * cXc);
-        const long long sp = nbr(g, x, y, z, -cxv, -cyv, -czv);
-        const long long sm = nbr(g, x, y, z, cxv, cyv, czv);
-        const R np = Codec<S>::dec(A[(size_t)ip * g.N + sp], ds, k);
-        const R nm = Codec<S>::dec(A[(size_t)im * g.N + sm], ds, k);
-        B[(size_t)ip * g.N + i0] = Codec<S>::enc(gm * np + even + odd, ds, k);
-        B[(size_t)im * g.N + i0] = Codec<S>::enc(gm * nm + even - odd, ds, k);
+        const long long sp = o + nbr(g, x, y, z, -cxv, -cyv, -czv);
+        const long long sm = o + nbr(g, x, y, z, cxv, cyv, czv);
+        const R np = Codec<S>::dec(amv[(size_t)(ip - 1) * St + sp], dm.ds, k);
+        const R nm = Codec<S>::dec(amv[(size_t)(im - 1) * St + sm], dm.ds, k);
+        const S ep = Codec<S>::enc(gm * np + even + odd, dm.ds, k);
+        const S em = Codec<S>::enc(gm * nm + even - odd, dm.ds, k);
+        bmv[(size_t)(ip - 1) * St + i0] = ep;
+        bmv[(size_t)(im - 1) * St + i0] = em;
+        dsum += (Codec<S>::dec(ep, dm.ds, k) - np) + (Codec<S>::dec(em, dm.ds, k) - nm);
+    }
+    using T0 = typename RestOf<S>::T;
+    rest_plane(B)[i0] = rest_plane(A)[i0] - T0(dsum);
+}
+
+// Pre-collision populations of the current state as FP64 [Q][S].
+template <int Q, class S>
+__global__ void __launch_bounds__(256) k_export(const Domain* __restrict__ tab,
+                                                const Tile* __restrict__ tiles,
+                                                const S* __restrict__ A, double* __restrict__ out)
+{
+    using L = Lattice<Q>;
+    const Where w = locate(tab, tiles);
+    if (!w.ok) return;
+    const Domain& dm = tab[w.dom];
+    const Geom g = dm.g;
+    const long long o = dm.off, St = g.S;
+    const long long i0 = o + sidx(g, w.x, w.y, w.z);
+    const S* mv = moving_planes(A, St);
+    out[i0] = (double)rest_plane(A)[i0];
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const long long src = o + nbr(g, w.x, w.y, w.z, -L::cx(i), -L::cy(i), -L::cz(i));
+        out[(size_t)i * St + i0] = (double)Codec<S>::dec(mv[(size_t)(i - 1) * St + src], dm.ds, L::shell(i));
     }
 }
 
-// Pre-collision populations of the current state as FP64 [Q][N].
 template <int Q, class S>
-__global__ void k_export(Geom g, DevScale ds, const S* __restrict__ A, double* __restrict__ out)
+__global__ void __launch_bounds__(256) k_import(const Domain* __restrict__ tab,
+                                                const Tile* __restrict__ tiles,
+                                                const double* __restrict__ in, S* __restrict__ A)
 {
     using L = Lattice<Q>;
-    SiteXYZ s = site_of_thread(g);
-    if (!s.ok) return;
-    const long long i0 = sidx(g, s.x, s.y, s.z);
+    const Where w = locate(tab, tiles);
+    if (!w.ok) return;
+    const Domain& dm = tab[w.dom];
+    const Geom g = dm.g;
+    const long long o = dm.off, St = g.S;
+    const long long i0 = o + sidx(g, w.x, w.y, w.z);
+    using RT = decltype(Codec<S>::dec(S(), dm.ds, 0));
+    S* mv = moving_planes(A, St);
+    rest_plane(A)[i0] = (typename RestOf<S>::T)in[i0];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const long long src = nbr(g, s.x, s.y, s.z, -L::cx(i), -L::cy(i), -L::cz(i));
-        out[(size_t)i * g.N + i0] = (double)Codec<S>::dec(A[(size_t)i * g.N + src], ds, L::shell(i));
-    }
-}
-
-template <int Q, class S>
-__global__ void k_import(Geom g, DevScale ds, const double* __restrict__ in, S* __restrict__ A)
-{
-    using L = Lattice<Q>;
-    SiteXYZ s = site_of_thread(g);
-    if (!s.ok) return;
-    const long long i0 = sidx(g, s.x, s.y, s.z);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const long long dst = nbr(g, s.x, s.y, s.z, -L::cx(i), -L::cy(i), -L::cz(i));
-        using RT = decltype(Codec<S>::dec(S(), ds, 0));
-        A[(size_t)i * g.N + dst] = Codec<S>::enc((RT)in[(size_t)i * g.N + i0], ds, L::shell(i));
+    for (int i = 1; i < Q; ++i) {
+        const long long dst = o + nbr(g, w.x, w.y, w.z, -L::cx(i), -L::cy(i), -L::cz(i));
+        mv[(size_t)(i - 1) * St + dst] = Codec<S>::enc((RT)in[(size_t)i * St + i0], dm.ds, L::shell(i));
     }
 }
 
 // Small helpers.
-__global__ void k_reset_ctl(unsigned long long* res, int nres, unsigned long long* jscale,
-                            int* done_at)
+__global__ void k_reset_ctl(unsigned long long* res, long long nres, unsigned long long* jscale,
+                            int* done_at, int ndom, int* nconv)
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (t < nres) res[t] = 0ull;
-    if (t == 0) {
-        *jscale = 0ull;
-        *done_at = -1;
+    if (t < ndom) {
+        jscale[t] = 0ull;
+        done_at[t] = -1;
     }
+    if (t == 0) *nconv = 0;
 }
 
-// Deterministic sum of block partials (one block).
-__global__ void k_sum_partials(const double* __restrict__ partial, long long nblk, double* out)
+// Deterministic sum of block partials [first, last) (one block).
+__global__ void k_sum_partials(const double* __restrict__ partial, long long first, long long last,
+                               double* out)
 {
     __shared__ double red[4][16];
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (long long b = threadIdx.x; b < nblk; b += blockDim.x)
+    for (long long b = first + threadIdx.x; b < last; b += blockDim.x)
 #pragma unroll
         for (int k = 0; k < 4; ++k) acc[k] += partial[4 * b + k];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -785,7 +961,7 @@ __global__ void k_sum_partials(const double* __restrict__ partial, long long nbl
     __syncthreads();
     if (threadIdx.x < 4) {
         double t = 0.0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[threadIdx.x][w];
+        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) t += red[threadIdx.x][q];
         out[threadIdx.x] = t;
     }
 }

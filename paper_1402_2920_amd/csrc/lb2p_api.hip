@@ -1,30 +1,37 @@
 // lb2p_api.hip -- host side of the C ABI declared in include/lb2p.h.
 //
-// A context owns two population buffers (A: read by the next step, B: written
-// by it), the per-site fields of items 1-11 and a few scalars used by the
-// implicit solve's stop rule.  Kernels are instantiated per lattice (D2Q21,
-// D3Q59) and storage form (F64, F32, BF16, F16); F64 computes in FP64, the
-// others in FP32.
+// A context advances one or more independent periodic lattices ("domains")
+// packed into shared buffers: two population buffers (A: read by the next
+// step, B: written by it), the per-site fields of items 1-11, a device table
+// of per-domain constants and two tile lists (per-site kernels and the fused
+// D3Q59 solve pass).  Tiles are dealt to hardware workgroup ids so that each
+// of the 8 XCDs receives a contiguous run of tiles (stencil neighbours then
+// share that XCD's L2).  Kernels are instantiated per lattice (D2Q21, D3Q59)
+// and storage form (F64, F32, BF16, F16); F64 computes in FP64, the others in
+// FP32.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "../../include/lb2p.h"
 #include "kernels.hpp"
+#include "kernels_fused.hpp"
 
 using namespace lb2p;
 
 namespace {
 
 constexpr double kPi = 3.14159265358979323846;
+constexpr int kFusedTX = 32, kFusedTY = 8;
 
-// Positivity windows of the shell weights (Sec. III, App. B), computed at
-// create time from the weight polynomials by bisection.
 template <int Q>
 double min_weight(double s)
 {
@@ -47,6 +54,9 @@ EosParams make_eos(const lb2p_eos& e)
     return p;
 }
 
+// App. B admissibility: weights positive for every c_s^2 the EOS takes, a
+// two-phase region (psi < -1/rho somewhere) and positive bulk viscosity
+// (psi < (2/d)/rho everywhere, Sec. VII).
 template <int Q>
 lb2p_status check_eos(const lb2p_params& p)
 {
@@ -54,14 +64,12 @@ lb2p_status check_eos(const lb2p_params& p)
     if (!(e.rho2 > e.rho1) || !(e.rho1 > 0.0) || !(e.A >= 0.0) || !(e.cs2_rho1 > 0.0))
         return LB2P_EINVAL;
     const int d = Lattice<Q>::D;
-    // weights positive for every c_s^2 the EOS takes: [c1, c1 exp(2 A D/pi)]
     const double lo = e.cs2_rho1, hi = e.cs2_rho1 * std::exp(2.0 * e.A * (e.rho2 - e.rho1) / kPi);
     const int n = 2000;
     for (int k = 0; k <= n; ++k) {
         const double s = lo + (hi - lo) * k / n;
         if (!(min_weight<Q>(s) > 0.0)) return LB2P_EEOS;
     }
-    // two-phase region and positive bulk viscosity, sampled on (rho1, rho3)
     const double rho3 = 2.0 * e.rho2 - e.rho1;
     bool two_phase = false;
     for (int k = 1; k < 20000; ++k) {
@@ -74,39 +82,103 @@ lb2p_status check_eos(const lb2p_params& p)
     return LB2P_OK;
 }
 
+lb2p_status check_params(const lb2p_params& p)
+{
+    if (p.lattice != LB2P_D2Q21 && p.lattice != LB2P_D3Q59) return LB2P_EINVAL;
+    if (p.nx < 8 || p.ny < 8) return LB2P_EINVAL;
+    if (p.lattice == LB2P_D2Q21 && p.nz != 1) return LB2P_EINVAL;
+    if (p.lattice == LB2P_D3Q59 && p.nz < 8) return LB2P_EINVAL;
+    if (p.storage < LB2P_STORE_F64 || p.storage > LB2P_STORE_F16) return LB2P_EINVAL;
+    if (!(p.gamma > -1.0 && p.gamma < 1.0)) return LB2P_EINVAL;
+    if (!(p.kappa >= 0.0) || !(p.tol >= 0.0) || p.max_iter <= 0 || p.fixed_iter < 0)
+        return LB2P_EINVAL;
+    if (p.graph_steps < 0) return LB2P_EINVAL;
+    if (!(p.rho0 > 0.0)) return LB2P_EINVAL;
+    if ((long long)p.nx * p.ny * p.nz > (1LL << 31)) return LB2P_EINVAL;
+    return p.lattice == LB2P_D3Q59 ? check_eos<59>(p) : check_eos<21>(p);
+}
+
+void set_devscale(DevScale& ds, int Q, const EosParams& eos, double rref)
+{
+    const double cs2 = eos_cs2<double>(eos, rref);
+    double w[8] = {0};
+    if (Q == 59) shell_weights<59, double>(cs2, w);
+    else shell_weights<21, double>(cs2, w);
+    for (int k = 0; k < 8; ++k) {
+        const double wk = w[k] > 0 ? w[k] : 1.0;
+        ds.off[k] = (float)(wk * rref);
+        ds.scl[k] = (float)wk;
+        ds.inv[k] = (float)(1.0 / wk);
+    }
+}
+
+// Tile-shape choices remembered per (lattice, storage, domain sizes).
+struct TuneChoice {
+    int bx, by, tz;
+};
+std::map<std::string, TuneChoice>& tune_cache()
+{
+    static std::map<std::string, TuneChoice> m;
+    return m;
+}
+
 }  // namespace
 
 struct lb2p_ctx {
-    lb2p_params prm;
-    int Q = 0, D = 0;
-    Geom g{};
-    Coef cf{};
-    DevScale ds{};
+    lb2p_params prm;             // shared settings (domain 0's record)
+    std::vector<lb2p_params> dprm;
+    int Q = 0, D = 0, ndom = 0;
+    long long S = 0;             // total sites
+    std::vector<Domain> dom;     // host copy of the domain table
+    Domain* dtab = nullptr;      // device domain table
     hipStream_t stream = nullptr;
-    size_t elem = 0;      // bytes per stored population
-    size_t rsize = 0;     // bytes per field element
+    size_t elem = 0;             // bytes per stored moving population
+    size_t pbytes = 0;           // bytes of one population buffer (rest plane + moving planes)
+    size_t rsize = 0;            // bytes per field element
     void* A = nullptr;
     void* B = nullptr;
+    void* A0 = nullptr;          // buffer that was A at creation (graph parity)
     void* fields = nullptr;
     void* rho = nullptr; void* j0 = nullptr; void* f = nullptr; void* j0p = nullptr;
     void* u = nullptr; void* jt0 = nullptr; void* jt1 = nullptr; void* q = nullptr;
     void* X = nullptr; void* T = nullptr; void* Y = nullptr; void* Xi = nullptr; void* Sig = nullptr;
+    // tiles
+    int bx = 64, by = 4, tz = 32;
+    std::vector<Tile> site_host, fused_host;   // launch order
+    Tile* site_tiles = nullptr;
+    Tile* fused_tiles = nullptr;
+    size_t site_cap = 0, fused_cap = 0;
     double* partial = nullptr;
-    long long nblk = 0;
-    void* scratch = nullptr;   // scalars
-    int* flags = nullptr;
+    size_t partial_cap = 0;
+    // stop-rule state
+    int stride = 0;                            // passes per domain in res
+    void* scratch = nullptr;
     unsigned long long* res = nullptr;
     unsigned long long* jscale = nullptr;
     int* done_at = nullptr;
     SolveInfo* info = nullptr;
+    int* flags = nullptr;
+    int* nconv = nullptr;
+    int* ndone = nullptr;
     double* sums = nullptr;
-    void* host = nullptr;      // pinned readback area
-    dim3 block, grid;
+    struct HostScratch {
+        int ndone;
+        int nconv;
+        int flags;
+        int pad;
+        double sums[4];
+    };
+    HostScratch* host = nullptr;               // pinned readback area
     bool initialized = false;
     bool have_prev = false;
     bool sigma_valid = false;
     lb2p_status sticky = LB2P_OK;
     int last_iters = 0;
+    std::vector<SolveInfo> info_host;
+    // graphs of graph_steps fixed-iteration steps, one per buffer parity
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    hipStream_t cap_stream = nullptr;          // capture only (the NULL stream cannot be captured)
+    bool capturing = false;
     // optional per-kernel-class event timing (lb2p_profile_*)
     bool prof = false;
     struct Pending { hipEvent_t a, b; int kid; };
@@ -123,15 +195,6 @@ namespace {
         hipError_t _e = (expr);                        \
         if (_e != hipSuccess) return LB2P_EHIP;        \
     } while (0)
-
-void choose_launch(lb2p_ctx* c)
-{
-    int bx = c->g.nx >= 256 ? 256 : (c->g.nx >= 128 ? 128 : 64);
-    int by = 256 / bx;
-    c->block = dim3(bx, by, 1);
-    c->grid = dim3((c->g.nx + bx - 1) / bx, (c->g.ny + by - 1) / by, c->g.nz);
-    c->nblk = (long long)c->grid.x * c->grid.y * c->grid.z;
-}
 
 hipEvent_t prof_event(lb2p_ctx* c)
 {
@@ -152,14 +215,14 @@ struct ProfScope {
     hipEvent_t a = nullptr;
     ProfScope(lb2p_ctx* cc, int k) : c(cc), kid(k)
     {
-        if (c->prof) {
+        if (c->prof && !c->capturing) {
             a = prof_event(c);
             if (a) (void)hipEventRecord(a, c->stream);
         }
     }
     ~ProfScope()
     {
-        if (c->prof && a) {
+        if (a) {
             hipEvent_t b = prof_event(c);
             if (b) {
                 (void)hipEventRecord(b, c->stream);
@@ -186,97 +249,183 @@ void prof_collect(lb2p_ctx* c)
     c->pending.clear();
 }
 
-struct HostScratch {
-    int done_at;
-    int flags;
-    SolveInfo info;
-    double sums[4];
-    double resid;
-    double jscale;
-};
+// Deal a domain-ordered tile list to workgroup ids: id b runs on XCD b % 8,
+// so XCD k gets the k-th eighth of the list, in order.  Padding tiles
+// (dom = -1) fill the list to a multiple of 8.
+std::vector<Tile> deal_xcd(const std::vector<Tile>& in)
+{
+    const size_t n = (in.size() + 7) / 8 * 8;
+    const size_t per = n / 8;
+    std::vector<Tile> out(n);
+    for (size_t b = 0; b < n; ++b) {
+        const size_t src = (b % 8) * per + b / 8;
+        if (src < in.size()) {
+            out[b] = in[src];
+        } else {
+            Tile t{};
+            t.dom = -1;
+            out[b] = t;
+        }
+    }
+    return out;
+}
+
+void free_graphs(lb2p_ctx* c)
+{
+    for (auto& g : c->graph)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+}
+
+// (Re)build both tile lists for the current block shapes.
+lb2p_status build_tiles(lb2p_ctx* c)
+{
+    std::vector<Tile> site, fused;
+    for (int d = 0; d < c->ndom; ++d) {
+        const Geom& g = c->dom[d].g;
+        for (int z = 0; z < g.nz; ++z)
+            for (int y = 0; y < g.ny; y += c->by)
+                for (int x = 0; x < g.nx; x += c->bx) {
+                    Tile t{};
+                    t.dom = d; t.x0 = x; t.y0 = y; t.z0 = z; t.len = 1;
+                    site.push_back(t);
+                }
+        if (c->D == 3) {
+            const int tz = std::min(c->tz, g.nz);
+            for (int z = 0; z < g.nz; z += tz)
+                for (int y = 0; y < g.ny; y += kFusedTY)
+                    for (int x = 0; x < g.nx; x += kFusedTX) {
+                        Tile t{};
+                        t.dom = d; t.x0 = x; t.y0 = y; t.z0 = z; t.len = std::min(tz, g.nz - z);
+                        fused.push_back(t);
+                    }
+        }
+    }
+    c->site_host = deal_xcd(site);
+    c->fused_host = fused.empty() ? fused : deal_xcd(fused);
+    auto upload = [&](const std::vector<Tile>& h, Tile*& dptr, size_t& cap) -> lb2p_status {
+        if (h.empty()) return LB2P_OK;
+        if (h.size() > cap) {
+            if (dptr) (void)hipFree(dptr);
+            dptr = nullptr;
+            if (hipMalloc((void**)&dptr, h.size() * sizeof(Tile)) != hipSuccess) return LB2P_ENOMEM;
+            cap = h.size();
+        }
+        HIPCHK(hipMemcpyAsync(dptr, h.data(), h.size() * sizeof(Tile), hipMemcpyHostToDevice, c->stream));
+        return LB2P_OK;
+    };
+    lb2p_status st = upload(c->site_host, c->site_tiles, c->site_cap);
+    if (st != LB2P_OK) return st;
+    st = upload(c->fused_host, c->fused_tiles, c->fused_cap);
+    if (st != LB2P_OK) return st;
+    const size_t np = 4 * c->site_host.size();
+    if (np > c->partial_cap) {
+        if (c->partial) (void)hipFree(c->partial);
+        c->partial = nullptr;
+        if (hipMalloc((void**)&c->partial, np * sizeof(double)) != hipSuccess) return LB2P_ENOMEM;
+        c->partial_cap = np;
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    free_graphs(c);
+    return LB2P_OK;
+}
 
 // ---- typed dispatch -------------------------------------------------------
 
 template <int Q, class R, class S>
 struct Impl {
+    static dim3 sgrid(lb2p_ctx* c) { return dim3((unsigned)c->site_host.size()); }
+    static dim3 sblock(lb2p_ctx* c) { return dim3(c->bx, c->by, 1); }
+
     static void launch_init(lb2p_ctx* c)
     {
-        hipLaunchKernelGGL((k_init<Q, R, S>), c->grid, c->block, 0, c->stream, c->g, c->cf, c->ds,
-                           (const R*)c->rho, (const R*)c->u, (S*)c->A);
+        hipLaunchKernelGGL((k_init<Q, R, S>), sgrid(c), sblock(c), 0, c->stream, c->dtab,
+                           c->site_tiles, (const R*)c->rho, (const R*)c->u, (S*)c->A);
     }
 
     static void launch_moments(lb2p_ctx* c, bool write_fields)
     {
-        {
-            ProfScope _ps(c, LB2P_K_MOMENTS);
-            hipLaunchKernelGGL((k_moments<Q, R, S>), c->grid, c->block, 0, c->stream, c->g, c->ds,
-                               (const S*)c->A, write_fields ? (R*)c->rho : (R*)c->X,
-                               write_fields ? (R*)c->j0 : (R*)c->T, c->partial, c->flags);
-        }
+        ProfScope _ps(c, LB2P_K_MOMENTS);
+        hipLaunchKernelGGL((k_moments<Q, R, S>), sgrid(c), sblock(c), 0, c->stream, c->dtab,
+                           c->site_tiles, (const S*)c->A, write_fields ? (R*)c->rho : (R*)c->X,
+                           write_fields ? (R*)c->j0 : (R*)c->T, c->partial, c->flags);
     }
 
-    // Items 1-8; returns false on a HIP error.  iters/converged in c->host.
+    // Items 1-8.  In the default (tolerance) mode the host reads, every
+    // check_every passes, how many domains have met the stop rule.
     static lb2p_status solve(lb2p_ctx* c)
     {
         const lb2p_params& p = c->prm;
         const int max_it = p.fixed_iter > 0 ? p.fixed_iter : p.max_iter;
-        hipLaunchKernelGGL(k_reset_ctl, dim3((max_it + 255) / 256 + 1), dim3(256), 0, c->stream,
-                           c->res, max_it, c->jscale, c->done_at);
+        const long long nres = (long long)c->ndom * c->stride;
+        hipLaunchKernelGGL(k_reset_ctl, dim3((unsigned)((std::max<long long>(nres, c->ndom) + 255) / 256)),
+                           dim3(256), 0, c->stream, c->res, nres, c->jscale, c->done_at, c->ndom,
+                           c->nconv);
         launch_moments(c, true);
-        const R* prev = nullptr;
-        if (p.warm_start && c->have_prev) {
-            // previous final iterate, moved into jt0 (same element, same thread)
-            HostScratch* hs = (HostScratch*)c->host;
-            prev = (const R*)(hs->info.final_buf ? c->jt1 : c->jt0);
-        }
+        IterCtl ic{c->res, c->jscale, c->done_at, c->stride, p.fixed_iter > 0 ? -1.0 : p.tol};
         {
             ProfScope _ps(c, LB2P_K_FORCE);
-            hipLaunchKernelGGL((k_force<Q, R>), c->grid, c->block, 0, c->stream, c->g, c->cf,
-                               (const R*)c->rho, (const R*)c->j0, (R*)c->f, (R*)c->j0p, (R*)c->u,
-                               prev, (R*)c->jt0, c->jscale);
+            const SolveInfo* prev = (p.warm_start && c->have_prev) ? c->info : nullptr;
+            hipLaunchKernelGGL((k_force<Q, R>), sgrid(c), sblock(c), 0, c->stream, c->dtab,
+                               c->site_tiles, ic, (const R*)c->rho, (const R*)c->j0, (R*)c->f,
+                               (R*)c->j0p, (R*)c->u, (const R*)c->jt0, (const R*)c->jt1, prev,
+                               (R*)c->jt0);
         }
-        IterCtl ic{c->res, c->jscale, c->done_at, p.fixed_iter > 0 ? -1.0 : p.tol};
+        const bool fused = Lattice<Q>::D == 3 && !(p.flags & LB2P_FLAG_UNFUSED_SOLVE);
+        const dim3 fblock(kFusedTX + 4, kFusedTY + 4, 1);
+        const dim3 fgrid((unsigned)c->fused_host.size());
         const int every = p.check_every > 0 ? p.check_every : 4;
-        HostScratch* hs = (HostScratch*)c->host;
         int launched = 0;
         for (int it = 0; it < max_it; ++it) {
             R* jold = (R*)((it & 1) ? c->jt1 : c->jt0);
             R* jnew = (R*)((it & 1) ? c->jt0 : c->jt1);
-            {
-                ProfScope _ps(c, LB2P_K_ITER_Q);
-                hipLaunchKernelGGL((k_iter_q<Q, R>), c->grid, c->block, 0, c->stream, c->g, c->cf, ic,
-                                   it, (const R*)c->rho, (const R*)c->u, (R*)c->q);
-            }
-            {
-                ProfScope _ps(c, LB2P_K_ITER_JT);
-                hipLaunchKernelGGL((k_iter_jt<Q, R>), c->grid, c->block, 0, c->stream, c->g, ic, it,
-                                   (const R*)c->rho, (const R*)c->q, (const R*)c->j0p,
-                                   (const R*)jold, jnew, (R*)c->u);
+            if (fused) {
+                ProfScope _ps(c, LB2P_K_ITER_FUSED);
+                hipLaunchKernelGGL((k_iter_fused3<R, kFusedTX, kFusedTY>), fgrid, fblock, 0, c->stream,
+                                   c->dtab, c->fused_tiles, ic, it, (const R*)c->rho,
+                                   (const R*)c->j0p, (const R*)jold, jnew);
+            } else {
+                {
+                    ProfScope _ps(c, LB2P_K_ITER_Q);
+                    hipLaunchKernelGGL((k_iter_q<Q, R>), sgrid(c), sblock(c), 0, c->stream, c->dtab,
+                                       c->site_tiles, ic, it, (const R*)c->rho, (const R*)c->u,
+                                       (R*)c->q);
+                }
+                {
+                    ProfScope _ps(c, LB2P_K_ITER_JT);
+                    hipLaunchKernelGGL((k_iter_jt<Q, R>), sgrid(c), sblock(c), 0, c->stream, c->dtab,
+                                       c->site_tiles, ic, it, (const R*)c->rho, (const R*)c->q,
+                                       (const R*)c->j0p, (const R*)jold, jnew, (R*)c->u);
+                }
             }
             launched = it + 1;
             if (p.fixed_iter <= 0 && (launched % every) == 0 && launched < max_it) {
-                HIPCHK(hipMemcpyAsync(&hs->done_at, c->done_at, sizeof(int), hipMemcpyDeviceToHost,
+                hipLaunchKernelGGL(k_count_done, dim3(1), dim3(256), 0, c->stream, c->done_at, c->ndom,
+                                   c->ndone);
+                HIPCHK(hipMemcpyAsync(&c->host->ndone, c->ndone, sizeof(int), hipMemcpyDeviceToHost,
                                       c->stream));
                 HIPCHK(hipStreamSynchronize(c->stream));
-                if (hs->done_at >= 0) break;
+                if (c->host->ndone >= c->ndom) break;
             }
         }
-        hipLaunchKernelGGL(k_iter_finish, dim3(1), dim3(64), 0, c->stream, ic, launched, c->info);
+        hipLaunchKernelGGL(k_iter_finish, dim3((c->ndom + 255) / 256), dim3(256), 0, c->stream, ic,
+                           launched, c->ndom, c->info, c->nconv);
+        hipLaunchKernelGGL((k_u_final<Q, R>), sgrid(c), sblock(c), 0, c->stream, c->dtab,
+                           c->site_tiles, (const SolveInfo*)c->info, (const R*)c->rho,
+                           (const R*)c->j0p, (const R*)c->jt0, (const R*)c->jt1, (R*)c->u);
         HIPCHK(hipGetLastError());
         if (p.fixed_iter <= 0) {
-            HIPCHK(hipMemcpyAsync(&hs->info, c->info, sizeof(SolveInfo), hipMemcpyDeviceToHost,
+            HIPCHK(hipMemcpyAsync(&c->host->nconv, c->nconv, sizeof(int), hipMemcpyDeviceToHost,
                                   c->stream));
-            HIPCHK(hipMemcpyAsync(&hs->flags, c->flags, sizeof(int), hipMemcpyDeviceToHost,
+            HIPCHK(hipMemcpyAsync(&c->host->flags, c->flags, sizeof(int), hipMemcpyDeviceToHost,
                                   c->stream));
             HIPCHK(hipStreamSynchronize(c->stream));
-            c->last_iters = hs->info.iters;
-            if (!hs->info.converged && c->sticky == LB2P_OK) c->sticky = LB2P_ENOCONV;
-            if (hs->flags) c->sticky = LB2P_ENONFINITE;
+            c->last_iters = launched;
+            if (c->host->nconv > 0 && c->sticky == LB2P_OK) c->sticky = LB2P_ENOCONV;
+            if (c->host->flags) c->sticky = LB2P_ENONFINITE;
         } else {
-            // the final buffer index is known without a readback
-            hs->info.final_buf = max_it & 1;
-            hs->info.iters = max_it;
-            hs->info.converged = 1;
             c->last_iters = max_it;
         }
         c->have_prev = true;
@@ -289,21 +438,21 @@ struct Impl {
         if (st != LB2P_OK) return st;
         {
             ProfScope _ps(c, LB2P_K_CLOSURE1);
-            hipLaunchKernelGGL((k_closure1<Q, R>), c->grid, c->block, 0, c->stream, c->g, c->cf,
-                               (const SolveInfo*)c->info, (const R*)c->rho, (const R*)c->u,
-                               (const R*)c->jt0, (const R*)c->jt1, (R*)c->X, (R*)c->T, (R*)c->Y,
-                               (R*)c->Xi);
+            hipLaunchKernelGGL((k_closure1<Q, R>), sgrid(c), sblock(c), 0, c->stream, c->dtab,
+                               c->site_tiles, (const SolveInfo*)c->info, (const R*)c->rho,
+                               (const R*)c->u, (const R*)c->jt0, (const R*)c->jt1, (R*)c->X, (R*)c->T,
+                               (R*)c->Y, (R*)c->Xi);
         }
         {
             ProfScope _ps(c, LB2P_K_CLOSURE2);
-            hipLaunchKernelGGL((k_closure2<Q, R>), c->grid, c->block, 0, c->stream, c->g, c->cf,
-                               (const R*)c->rho, (const R*)c->u, (const R*)c->X, (const R*)c->T,
-                               (const R*)c->Y, (R*)c->Sig);
+            hipLaunchKernelGGL((k_closure2<Q, R>), sgrid(c), sblock(c), 0, c->stream, c->dtab,
+                               c->site_tiles, (const R*)c->rho, (const R*)c->u, (const R*)c->X,
+                               (const R*)c->T, (const R*)c->Y, (R*)c->Sig);
         }
         {
             ProfScope _ps(c, LB2P_K_COLLIDE);
-            hipLaunchKernelGGL((k_collide<Q, R, S>), c->grid, c->block, 0, c->stream, c->g, c->cf,
-                               c->ds, (const SolveInfo*)c->info, (const S*)c->A, (S*)c->B,
+            hipLaunchKernelGGL((k_collide<Q, R, S>), sgrid(c), sblock(c), 0, c->stream, c->dtab,
+                               c->site_tiles, (const SolveInfo*)c->info, (const S*)c->A, (S*)c->B,
                                (const R*)c->rho, (const R*)c->u, (const R*)c->f, (const R*)c->jt0,
                                (const R*)c->jt1, (const R*)c->Sig, (const R*)c->Xi);
         }
@@ -315,13 +464,13 @@ struct Impl {
 
     static void export_pop(lb2p_ctx* c, double* out)
     {
-        hipLaunchKernelGGL((k_export<Q, S>), c->grid, c->block, 0, c->stream, c->g, c->ds,
+        hipLaunchKernelGGL((k_export<Q, S>), sgrid(c), sblock(c), 0, c->stream, c->dtab, c->site_tiles,
                            (const S*)c->A, out);
     }
     static void import_pop(lb2p_ctx* c, const double* in)
     {
-        hipLaunchKernelGGL((k_import<Q, S>), c->grid, c->block, 0, c->stream, c->g, c->ds, in,
-                           (S*)c->A);
+        hipLaunchKernelGGL((k_import<Q, S>), sgrid(c), sblock(c), 0, c->stream, c->dtab, c->site_tiles,
+                           in, (S*)c->A);
     }
 };
 
@@ -352,10 +501,10 @@ size_t storage_bytes(int storage)
     }
 }
 
-// Copy a field [ncomp][N] of type R to a caller buffer of dtype.
+// Copy a field [ncomp][S] of type R to a caller buffer of dtype.
 lb2p_status copy_out(lb2p_ctx* c, const void* src, int ncomp, void* dst, int dtype, int on_device)
 {
-    const long long n = (long long)ncomp * c->g.N;
+    const long long n = (long long)ncomp * c->S;
     const bool same = (dtype == LB2P_DTYPE_F64) == (c->rsize == 8);
     const size_t out_elem = dtype == LB2P_DTYPE_F64 ? 8 : 4;
     const void* from = src;
@@ -379,10 +528,10 @@ lb2p_status copy_out(lb2p_ctx* c, const void* src, int ncomp, void* dst, int dty
     return LB2P_OK;
 }
 
-// Copy a caller buffer [ncomp][N] of dtype into a field of type R.
+// Copy a caller buffer [ncomp][S] of dtype into a field of type R.
 lb2p_status copy_in(lb2p_ctx* c, const void* src, int ncomp, void* dst, int dtype, int on_device)
 {
-    const long long n = (long long)ncomp * c->g.N;
+    const long long n = (long long)ncomp * c->S;
     const bool same = (dtype == LB2P_DTYPE_F64) == (c->rsize == 8);
     const size_t in_elem = dtype == LB2P_DTYPE_F64 ? 8 : 4;
     if (same) {
@@ -411,18 +560,242 @@ lb2p_status copy_in(lb2p_ctx* c, const void* src, int ncomp, void* dst, int dtyp
 void free_ctx(lb2p_ctx* c)
 {
     if (!c) return;
+    free_graphs(c);
     if (c->A) (void)hipFree(c->A);
     if (c->B) (void)hipFree(c->B);
     if (c->fields) (void)hipFree(c->fields);
     if (c->partial) (void)hipFree(c->partial);
     if (c->scratch) (void)hipFree(c->scratch);
+    if (c->dtab) (void)hipFree(c->dtab);
+    if (c->site_tiles) (void)hipFree(c->site_tiles);
+    if (c->fused_tiles) (void)hipFree(c->fused_tiles);
     if (c->host) (void)hipHostFree(c->host);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (auto& p : c->pending) {
         (void)hipEventDestroy(p.a);
         (void)hipEventDestroy(p.b);
     }
     for (auto e : c->pool) (void)hipEventDestroy(e);
     delete c;
+}
+
+std::string tune_key(const lb2p_ctx* c)
+{
+    std::vector<long long> sz;
+    for (const auto& d : c->dom) sz.push_back(((long long)d.g.nx << 40) | ((long long)d.g.ny << 20) | d.g.nz);
+    std::sort(sz.begin(), sz.end());
+    unsigned long long h = 1469598103934665603ull;
+    for (long long v : sz) {
+        h ^= (unsigned long long)v;
+        h *= 1099511628211ull;
+    }
+    char buf[96];
+    std::snprintf(buf, sizeof(buf), "Q%d-s%d-n%d-%016llx", c->Q, c->prm.storage, c->ndom, h);
+    return buf;
+}
+
+void default_shape(lb2p_ctx* c)
+{
+    int maxnx = 0;
+    for (const auto& d : c->dom) maxnx = std::max(maxnx, d.g.nx);
+    c->bx = maxnx >= 256 ? 256 : (maxnx >= 128 ? 128 : 64);
+    c->by = 256 / c->bx;
+    c->tz = 32;
+    auto it = tune_cache().find(tune_key(c));
+    if (it != tune_cache().end()) {
+        c->bx = it->second.bx;
+        c->by = it->second.by;
+        c->tz = it->second.tz;
+    }
+}
+
+void load_tune_file()
+{
+    static bool loaded = false;
+    if (loaded) return;
+    loaded = true;
+    const char* path = std::getenv("LB2P_TUNE_CACHE");
+    if (!path) return;
+    FILE* fh = std::fopen(path, "r");
+    if (!fh) return;
+    char key[128];
+    int bx, by, tz;
+    while (std::fscanf(fh, "%127s %d %d %d", key, &bx, &by, &tz) == 4)
+        if (bx > 0 && by > 0 && bx * by == 256 && tz > 0) tune_cache()[key] = TuneChoice{bx, by, tz};
+    std::fclose(fh);
+}
+
+lb2p_status create_impl(int ndom, const lb2p_params* pp, void* hip_stream, lb2p_ctx** out)
+{
+    if (!pp || !out || ndom <= 0) return LB2P_EINVAL;
+    *out = nullptr;
+    const lb2p_params& p0 = pp[0];
+    for (int d = 0; d < ndom; ++d) {
+        const lb2p_params& p = pp[d];
+        lb2p_status st = check_params(p);
+        if (st != LB2P_OK) return st;
+        if (p.lattice != p0.lattice || p.storage != p0.storage || p.tol != p0.tol ||
+            p.max_iter != p0.max_iter || p.fixed_iter != p0.fixed_iter ||
+            p.warm_start != p0.warm_start || p.flags != p0.flags || p.graph_steps != p0.graph_steps)
+            return LB2P_EINVAL;
+    }
+    load_tune_file();
+    lb2p_ctx* c = new (std::nothrow) lb2p_ctx;
+    if (!c) return LB2P_ENOMEM;
+    c->prm = p0;
+    c->dprm.assign(pp, pp + ndom);
+    c->Q = p0.lattice;
+    c->D = p0.lattice == LB2P_D3Q59 ? 3 : 2;
+    c->ndom = ndom;
+    c->stream = (hipStream_t)hip_stream;
+    c->elem = storage_bytes(p0.storage);
+    c->rsize = p0.storage == LB2P_STORE_F64 ? 8 : 4;
+    long long off = 0;
+    for (int d = 0; d < ndom; ++d) {
+        const lb2p_params& p = pp[d];
+        Domain dm{};
+        dm.g.nx = p.nx; dm.g.ny = p.ny; dm.g.nz = p.nz;
+        dm.g.N = (long long)p.nx * p.ny * p.nz;
+        dm.off = off;
+        off += dm.g.N;
+        dm.cf.gamma = p.gamma;
+        dm.cf.kappa = p.kappa;
+        dm.cf.eos = make_eos(p.eos);
+        dm.cf.c0sq = eos_cs2<double>(dm.cf.eos, p.rho0);
+        double w[8] = {0};
+        if (c->Q == 59) shell_weights<59, double>(dm.cf.c0sq, w);
+        else shell_weights<21, double>(dm.cf.c0sq, w);
+        const int ns = c->Q == 59 ? 8 : 6;
+        for (int k = 0; k < ns; ++k) {
+            if (!(w[k] > 0.0)) { delete c; return LB2P_EEOS; }
+            dm.cf.Wk[k] = w[k];
+        }
+        set_devscale(dm.ds, c->Q, dm.cf.eos, p.store_rho_ref > 0.0 ? p.store_rho_ref : p.rho0);
+        c->dom.push_back(dm);
+    }
+    c->S = off;
+    if (c->S > (1LL << 31)) { delete c; return LB2P_EINVAL; }
+    for (auto& dm : c->dom) dm.g.S = c->S;
+    c->stride = (p0.fixed_iter > 0 ? p0.fixed_iter : p0.max_iter) + 1;
+
+    const long long S = c->S;
+    const int D = c->D;
+    const int nsig = D == 3 ? 6 : 3, nxi = D == 3 ? 10 : 4;
+    // rho | j0 | f | j0p | u | jt0 | jt1 | q (alias T) | X | Y | Xi | Sig
+    const int ncomp = 1 + 6 * D + nsig + 1 + D + nxi + nsig;
+    {
+        long long mo = 0;
+        switch (p0.storage) {
+            case LB2P_STORE_F64: mo = moving_offset_bytes<double>(S); break;
+            case LB2P_STORE_F32: mo = moving_offset_bytes<float>(S); break;
+            case LB2P_STORE_BF16: mo = moving_offset_bytes<__bf16>(S); break;
+            default: mo = moving_offset_bytes<_Float16>(S); break;
+        }
+        c->pbytes = (size_t)mo + (size_t)(c->Q - 1) * S * c->elem;
+    }
+    hipError_t e = hipMalloc(&c->A, c->pbytes);
+    if (e == hipSuccess) e = hipMalloc(&c->B, c->pbytes);
+    if (e == hipSuccess) e = hipMalloc(&c->fields, (size_t)ncomp * S * c->rsize);
+    if (e == hipSuccess) e = hipMalloc((void**)&c->dtab, ndom * sizeof(Domain));
+    const size_t nres = (size_t)ndom * c->stride;
+    const size_t sbytes = 256 + sizeof(unsigned long long) * nres + (sizeof(unsigned long long) +
+                          sizeof(int) + sizeof(SolveInfo)) * (size_t)ndom + 64;
+    if (e == hipSuccess) e = hipMalloc(&c->scratch, sbytes);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&c->host, sizeof(lb2p_ctx::HostScratch), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        free_ctx(c);
+        (void)hipGetLastError();
+        return LB2P_ENOMEM;
+    }
+    c->A0 = c->A;
+    char* fb = (char*)c->fields;
+    size_t foff = 0;
+    auto take = [&](int nc) { void* ptr = fb + foff * c->rsize; foff += (size_t)nc * S; return ptr; };
+    c->rho = take(1); c->j0 = take(D); c->f = take(D); c->j0p = take(D); c->u = take(D);
+    c->jt0 = take(D); c->jt1 = take(D); c->q = take(nsig); c->T = c->q;
+    c->X = take(1); c->Y = take(D); c->Xi = take(nxi); c->Sig = take(nsig);
+    char* sb = (char*)c->scratch;
+    c->flags = (int*)(sb + 0);
+    c->nconv = (int*)(sb + 4);
+    c->ndone = (int*)(sb + 8);
+    c->sums = (double*)(sb + 64);
+    c->res = (unsigned long long*)(sb + 256);
+    c->jscale = c->res + nres;
+    c->info = (SolveInfo*)(c->jscale + ndom);
+    c->done_at = (int*)(c->info + ndom);
+    std::memset(c->host, 0, sizeof(lb2p_ctx::HostScratch));
+    c->info_host.assign(ndom, SolveInfo{0, 0, 1, 0});
+    if (hipMemcpyAsync(c->dtab, c->dom.data(), ndom * sizeof(Domain), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipMemsetAsync(c->scratch, 0, sbytes, c->stream) != hipSuccess ||
+        hipMemsetAsync(c->fields, 0, (size_t)ncomp * S * c->rsize, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+        free_ctx(c);
+        return LB2P_EHIP;
+    }
+    default_shape(c);
+    lb2p_status st = build_tiles(c);
+    if (st != LB2P_OK) {
+        free_ctx(c);
+        return st;
+    }
+    *out = c;
+    return LB2P_OK;
+}
+
+// nsteps steps: eager launches, or replays of the captured graph (fixed
+// iteration count, graph_steps > 0).
+lb2p_status run_steps(lb2p_ctx* c, int nsteps)
+{
+    const int gs = c->prm.graph_steps > 0 && c->prm.fixed_iter > 0 ? (c->prm.graph_steps + 1) / 2 * 2 : 0;
+    int s = 0;
+    if (gs > 0 && !c->prof) {
+        // a captured step always warm-starts j~ from the previous step; the
+        // first step after lb2p_init has none, so it runs eagerly
+        if (!c->have_prev && nsteps > 0) {
+            lb2p_status st = dispatch(c, [&](auto impl) { return decltype(impl)::step(c); });
+            if (st != LB2P_OK) return st;
+            s = 1;
+        }
+        while (nsteps - s >= gs) {
+            const int par = c->A == c->A0 ? 0 : 1;
+            if (!c->graph[par]) {
+                // capture gs steps (an even count: the buffers end as they
+                // began) on a private stream; the graph runs on c->stream
+                if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+                HIPCHK(hipStreamSynchronize(c->stream));
+                hipStream_t user = c->stream;
+                c->stream = c->cap_stream;
+                hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+                if (e != hipSuccess) {
+                    c->stream = user;
+                    return LB2P_EHIP;
+                }
+                c->capturing = true;
+                lb2p_status st = LB2P_OK;
+                for (int k = 0; k < gs && st == LB2P_OK; ++k)
+                    st = dispatch(c, [&](auto impl) { return decltype(impl)::step(c); });
+                c->capturing = false;
+                hipGraph_t g = nullptr;
+                e = hipStreamEndCapture(c->stream, &g);
+                c->stream = user;
+                if (st != LB2P_OK) {
+                    if (g) (void)hipGraphDestroy(g);
+                    return st;
+                }
+                if (e != hipSuccess) return LB2P_EHIP;
+                e = hipGraphInstantiate(&c->graph[par], g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (e != hipSuccess) return LB2P_EHIP;
+            }
+            HIPCHK(hipGraphLaunch(c->graph[par], c->stream));
+            s += gs;
+        }
+    }
+    for (; s < nsteps; ++s) {
+        lb2p_status st = dispatch(c, [&](auto impl) { return decltype(impl)::step(c); });
+        if (st != LB2P_OK) return st;
+    }
+    return LB2P_OK;
 }
 
 }  // namespace
@@ -473,94 +846,20 @@ lb2p_status lb2p_default_params(int lattice, int nx, int ny, int nz, int storage
     p.warm_start = 1;
     p.check_every = 0;
     p.store_rho_ref = 0.0;
+    p.flags = 0;
+    p.graph_steps = 0;
     *out = p;
     return LB2P_OK;
 }
 
 lb2p_status lb2p_create(const lb2p_params* params, void* hip_stream, lb2p_ctx** out)
 {
-    if (!params || !out) return LB2P_EINVAL;
-    *out = nullptr;
-    const lb2p_params& p = *params;
-    if (p.lattice != LB2P_D2Q21 && p.lattice != LB2P_D3Q59) return LB2P_EINVAL;
-    if (p.nx < 8 || p.ny < 8) return LB2P_EINVAL;
-    if (p.lattice == LB2P_D2Q21 && p.nz != 1) return LB2P_EINVAL;
-    if (p.lattice == LB2P_D3Q59 && p.nz < 8) return LB2P_EINVAL;
-    if (p.storage < LB2P_STORE_F64 || p.storage > LB2P_STORE_F16) return LB2P_EINVAL;
-    if (!(p.gamma > -1.0 && p.gamma < 1.0)) return LB2P_EINVAL;
-    if (!(p.kappa >= 0.0) || !(p.tol >= 0.0) || p.max_iter <= 0 || p.fixed_iter < 0)
-        return LB2P_EINVAL;
-    if (!(p.rho0 > 0.0)) return LB2P_EINVAL;
-    if ((long long)p.nx * p.ny * p.nz > (1LL << 31)) return LB2P_EINVAL;
-    lb2p_status st = p.lattice == LB2P_D3Q59 ? check_eos<59>(p) : check_eos<21>(p);
-    if (st != LB2P_OK) return st;
+    return create_impl(1, params, hip_stream, out);
+}
 
-    lb2p_ctx* c = new (std::nothrow) lb2p_ctx;
-    if (!c) return LB2P_ENOMEM;
-    c->prm = p;
-    c->Q = p.lattice;
-    c->D = p.lattice == LB2P_D3Q59 ? 3 : 2;
-    c->g.nx = p.nx; c->g.ny = p.ny; c->g.nz = p.nz;
-    c->g.N = (long long)p.nx * p.ny * p.nz;
-    c->stream = (hipStream_t)hip_stream;
-    c->cf.gamma = p.gamma;
-    c->cf.kappa = p.kappa;
-    c->cf.eos = make_eos(p.eos);
-    c->cf.c0sq = eos_cs2<double>(c->cf.eos, p.rho0);
-    {
-        double w[8] = {0};
-        if (c->Q == 59) shell_weights<59, double>(c->cf.c0sq, w);
-        else shell_weights<21, double>(c->cf.c0sq, w);
-        const int ns = c->Q == 59 ? 8 : 6;
-        for (int k = 0; k < ns; ++k) {
-            if (!(w[k] > 0.0)) { delete c; return LB2P_EEOS; }
-            c->cf.Wk[k] = w[k];
-        }
-    }
-    c->elem = storage_bytes(p.storage);
-    c->rsize = p.storage == LB2P_STORE_F64 ? 8 : 4;
-    choose_launch(c);
-
-    const long long N = c->g.N;
-    const int D = c->D;
-    const int nsig = D == 3 ? 6 : 3, nxi = D == 3 ? 10 : 4;
-    // rho | j0 | f | j0p | u | jt0 | jt1 | q (alias T) | X | Y | Xi | Sig
-    const int ncomp = 1 + 6 * D + nsig + 1 + D + nxi + nsig;
-    hipError_t e = hipMalloc(&c->A, (size_t)c->Q * N * c->elem);
-    if (e == hipSuccess) e = hipMalloc(&c->B, (size_t)c->Q * N * c->elem);
-    if (e == hipSuccess) e = hipMalloc(&c->fields, (size_t)ncomp * N * c->rsize);
-    if (e == hipSuccess) e = hipMalloc((void**)&c->partial, (size_t)4 * c->nblk * sizeof(double));
-    const int max_it = (p.fixed_iter > 0 ? p.fixed_iter : p.max_iter) + 1;
-    const size_t sbytes = 256 + sizeof(unsigned long long) * (size_t)max_it;
-    if (e == hipSuccess) e = hipMalloc(&c->scratch, sbytes);
-    if (e == hipSuccess) e = hipHostMalloc(&c->host, sizeof(HostScratch), hipHostMallocDefault);
-    if (e != hipSuccess) {
-        free_ctx(c);
-        (void)hipGetLastError();
-        return LB2P_ENOMEM;
-    }
-    char* fb = (char*)c->fields;
-    size_t off = 0;
-    auto take = [&](int nc) { void* ptr = fb + off * c->rsize; off += (size_t)nc * N; return ptr; };
-    c->rho = take(1); c->j0 = take(D); c->f = take(D); c->j0p = take(D); c->u = take(D);
-    c->jt0 = take(D); c->jt1 = take(D); c->q = take(nsig); c->T = c->q;
-    c->X = take(1); c->Y = take(D); c->Xi = take(nxi); c->Sig = take(nsig);
-    char* sb = (char*)c->scratch;
-    c->flags = (int*)(sb + 0);
-    c->done_at = (int*)(sb + 8);
-    c->info = (SolveInfo*)(sb + 16);
-    c->jscale = (unsigned long long*)(sb + 32);
-    c->sums = (double*)(sb + 64);
-    c->res = (unsigned long long*)(sb + 256);
-    std::memset(c->host, 0, sizeof(HostScratch));
-    if (hipMemsetAsync(c->scratch, 0, sbytes, c->stream) != hipSuccess ||
-        hipMemsetAsync(c->fields, 0, (size_t)ncomp * N * c->rsize, c->stream) != hipSuccess ||
-        hipStreamSynchronize(c->stream) != hipSuccess) {
-        free_ctx(c);
-        return LB2P_EHIP;
-    }
-    *out = c;
-    return LB2P_OK;
+lb2p_status lb2p_create_batch(int ndom, const lb2p_params* per_dom, void* hip_stream, lb2p_ctx** out)
+{
+    return create_impl(ndom, per_dom, hip_stream, out);
 }
 
 void lb2p_destroy(lb2p_ctx* ctx)
@@ -578,41 +877,34 @@ lb2p_status lb2p_init(lb2p_ctx* c, const void* rho, const void* u, int dtype, in
     if (st != LB2P_OK) return st;
     st = copy_in(c, u, c->D, c->u, dtype, on_device);
     if (st != LB2P_OK) return st;
-    // deviation storage reference
-    double rref = c->prm.store_rho_ref;
-    if (!(rref > 0.0)) {
-        // mean density of the initial field (host sum in FP64)
-        void* tmp = nullptr;
-        HIPCHK(hipMallocAsync(&tmp, (size_t)c->g.N * sizeof(double), c->stream));
-        const int tb = 256;
-        const long long nb = (c->g.N + tb - 1) / tb;
-        if (c->rsize == 8)
-            HIPCHK(hipMemcpyAsync(tmp, c->rho, c->g.N * 8, hipMemcpyDeviceToDevice, c->stream));
-        else
-            hipLaunchKernelGGL((k_convert<float, double>), dim3((unsigned)nb), dim3(tb), 0,
-                               c->stream, (const float*)c->rho, (double*)tmp, c->g.N);
-        double* hbuf = (double*)std::malloc((size_t)c->g.N * sizeof(double));
-        if (!hbuf) { (void)hipFreeAsync(tmp, c->stream); return LB2P_ENOMEM; }
-        HIPCHK(hipMemcpyAsync(hbuf, tmp, c->g.N * 8, hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(hipFreeAsync(tmp, c->stream));
-        HIPCHK(hipStreamSynchronize(c->stream));
-        double acc = 0.0;
-        for (long long k = 0; k < c->g.N; ++k) acc += hbuf[k];
-        std::free(hbuf);
-        rref = acc / (double)c->g.N;
-    }
-    {
-        const double cs2 = eos_cs2<double>(c->cf.eos, rref);
-        double w[8] = {0};
-        if (c->Q == 59) shell_weights<59, double>(cs2, w);
-        else shell_weights<21, double>(cs2, w);
-        for (int k = 0; k < 8; ++k) {
-            const double wk = w[k] > 0 ? w[k] : 1.0;
-            c->ds.off[k] = (float)(wk * rref);
-            c->ds.scl[k] = (float)wk;
-            c->ds.inv[k] = (float)(1.0 / wk);
+    // deviation-storage reference per domain: the given value, else the
+    // domain's mean initial density (host FP64 sum)
+    bool need_mean = false;
+    for (const auto& p : c->dprm) need_mean |= !(p.store_rho_ref > 0.0);
+    std::vector<double> hrho;
+    if (need_mean) {
+        hrho.resize(c->S);
+        if (c->rsize == 8) {
+            HIPCHK(hipMemcpyAsync(hrho.data(), c->rho, c->S * 8, hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(hipStreamSynchronize(c->stream));
+        } else {
+            std::vector<float> tmp(c->S);
+            HIPCHK(hipMemcpyAsync(tmp.data(), c->rho, c->S * 4, hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(hipStreamSynchronize(c->stream));
+            for (long long k = 0; k < c->S; ++k) hrho[k] = tmp[k];
         }
     }
+    for (int d = 0; d < c->ndom; ++d) {
+        double rref = c->dprm[d].store_rho_ref;
+        if (!(rref > 0.0)) {
+            double acc = 0.0;
+            const Domain& dm = c->dom[d];
+            for (long long k = 0; k < dm.g.N; ++k) acc += hrho[dm.off + k];
+            rref = acc / (double)dm.g.N;
+        }
+        set_devscale(c->dom[d].ds, c->Q, c->dom[d].cf.eos, rref);
+    }
+    HIPCHK(hipMemcpyAsync(c->dtab, c->dom.data(), c->ndom * sizeof(Domain), hipMemcpyHostToDevice, c->stream));
     dispatch(c, [&](auto impl) { decltype(impl)::launch_init(c); });
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemsetAsync(c->flags, 0, sizeof(int), c->stream));
@@ -628,10 +920,8 @@ lb2p_status lb2p_step(lb2p_ctx* c, int nsteps)
 {
     if (!c || nsteps < 0) return LB2P_EINVAL;
     if (!c->initialized) return LB2P_ESTATE;
-    for (int s = 0; s < nsteps; ++s) {
-        lb2p_status st = dispatch(c, [&](auto impl) { return decltype(impl)::step(c); });
-        if (st != LB2P_OK) return st;
-    }
+    lb2p_status st = run_steps(c, nsteps);
+    if (st != LB2P_OK) return st;
     if (c->prm.fixed_iter > 0) HIPCHK(hipGetLastError());
     return c->sticky;
 }
@@ -666,31 +956,63 @@ lb2p_status lb2p_stats_get(lb2p_ctx* c, lb2p_stats* st)
     if (!c->initialized) return LB2P_ESTATE;
     // totals of the current state (item 1 evaluated into spare field space)
     dispatch(c, [&](auto impl) { decltype(impl)::launch_moments(c, false); });
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, c->stream, c->partial, c->nblk,
-                       c->sums);
-    HostScratch* hs = (HostScratch*)c->host;
-    HIPCHK(hipMemcpyAsync(hs->sums, c->sums, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipMemcpyAsync(&hs->flags, c->flags, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipMemcpyAsync(&hs->info, c->info, sizeof(SolveInfo), hipMemcpyDeviceToHost, c->stream));
-    unsigned long long js = 0, rs = 0;
-    HIPCHK(hipMemcpyAsync(&js, c->jscale, sizeof(js), hipMemcpyDeviceToHost, c->stream));
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, c->stream, c->partial, 0LL,
+                       (long long)c->site_host.size(), c->sums);
+    HIPCHK(hipMemcpyAsync(c->host->sums, c->sums, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(&c->host->flags, c->flags, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(c->info_host.data(), c->info, c->ndom * sizeof(SolveInfo),
+                          hipMemcpyDeviceToHost, c->stream));
+    std::vector<unsigned long long> js(c->ndom);
+    HIPCHK(hipMemcpyAsync(js.data(), c->jscale, c->ndom * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                          c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
-    const int it = hs->info.iters;
-    if (it > 0) {
-        HIPCHK(hipMemcpy(&rs, c->res + (it - 1), sizeof(rs), hipMemcpyDeviceToHost));
+    // iteration count and residual: the largest over domains
+    int it = 0;
+    for (const auto& si : c->info_host) it = std::max(it, si.iters);
+    double rmax = 0.0, jmax = 0.0;
+    for (int d = 0; d < c->ndom; ++d) {
+        const int k = c->info_host[d].iters;
+        if (k > 0) {
+            unsigned long long rs = 0;
+            HIPCHK(hipMemcpy(&rs, c->res + (size_t)d * c->stride + (k - 1), sizeof(rs), hipMemcpyDeviceToHost));
+            double rd;
+            std::memcpy(&rd, &rs, sizeof(rd));
+            rmax = std::max(rmax, rd);
+        }
+        double jd;
+        std::memcpy(&jd, &js[d], sizeof(jd));
+        jmax = std::max(jmax, jd);
     }
-    st->mass = hs->sums[0];
-    st->mom[0] = hs->sums[1];
-    st->mom[1] = hs->sums[2];
-    st->mom[2] = c->D == 3 ? hs->sums[3] : 0.0;
+    st->mass = c->host->sums[0];
+    st->mom[0] = c->host->sums[1];
+    st->mom[1] = c->host->sums[2];
+    st->mom[2] = c->D == 3 ? c->host->sums[3] : 0.0;
     st->iters = it;
-    double rd, jd;
-    std::memcpy(&rd, &rs, sizeof(rd));
-    std::memcpy(&jd, &js, sizeof(jd));
-    st->resid = rd;
-    st->jscale = jd;
-    st->nonfinite = hs->flags ? 1 : 0;
-    if (hs->flags) c->sticky = LB2P_ENONFINITE;
+    st->resid = rmax;
+    st->jscale = jmax;
+    st->nonfinite = c->host->flags ? 1 : 0;
+    if (c->host->flags) c->sticky = LB2P_ENONFINITE;
+    return LB2P_OK;
+}
+
+lb2p_status lb2p_domain_totals(lb2p_ctx* c, double* out)
+{
+    if (!c || !out) return LB2P_EINVAL;
+    if (!c->initialized) return LB2P_ESTATE;
+    dispatch(c, [&](auto impl) { decltype(impl)::launch_moments(c, false); });
+    const size_t nb = c->site_host.size();
+    std::vector<double> part(4 * nb);
+    HIPCHK(hipMemcpyAsync(part.data(), c->partial, 4 * nb * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    std::fill(out, out + 4 * c->ndom, 0.0);
+    // deterministic: tiles of a domain in launch order
+    for (size_t b = 0; b < nb; ++b) {
+        const int d = c->site_host[b].dom;
+        if (d < 0) continue;
+        for (int k = 0; k < 4; ++k) out[4 * d + k] += part[4 * b + k];
+    }
+    if (c->D == 2)
+        for (int d = 0; d < c->ndom; ++d) out[4 * d + 3] = 0.0;
     return LB2P_OK;
 }
 
@@ -700,13 +1022,32 @@ lb2p_status lb2p_get_field(lb2p_ctx* c, int field, void* out, int dtype, int on_
     if (!c->initialized) return LB2P_ESTATE;
     if (dtype != LB2P_DTYPE_F64 && dtype != LB2P_DTYPE_F32) return LB2P_EINVAL;
     const int D = c->D;
-    HostScratch* hs = (HostScratch*)c->host;
     switch (field) {
         case LB2P_FIELD_RHO: return copy_out(c, c->rho, 1, out, dtype, on_device);
         case LB2P_FIELD_J0: return copy_out(c, c->j0, D, out, dtype, on_device);
         case LB2P_FIELD_FORCE: return copy_out(c, c->f, D, out, dtype, on_device);
-        case LB2P_FIELD_JTILDE:
-            return copy_out(c, hs->info.final_buf ? c->jt1 : c->jt0, D, out, dtype, on_device);
+        case LB2P_FIELD_JTILDE: {
+            // the final iterate of each domain may sit in either buffer
+            HIPCHK(hipMemcpyAsync(c->info_host.data(), c->info, c->ndom * sizeof(SolveInfo),
+                                  hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(hipStreamSynchronize(c->stream));
+            bool all0 = true, all1 = true;
+            for (const auto& si : c->info_host) {
+                all0 &= si.final_buf == 0;
+                all1 &= si.final_buf == 1;
+            }
+            if (all0 || all1) return copy_out(c, all1 ? c->jt1 : c->jt0, D, out, dtype, on_device);
+            // mixed: gather per domain into the (free) q space
+            const size_t rs = c->rsize;
+            for (int d = 0; d < c->ndom; ++d) {
+                const Domain& dm = c->dom[d];
+                const char* src = (const char*)(c->info_host[d].final_buf ? c->jt1 : c->jt0);
+                for (int a = 0; a < D; ++a)
+                    HIPCHK(hipMemcpyAsync((char*)c->q + (a * c->S + dm.off) * rs, src + (a * c->S + dm.off) * rs,
+                                          dm.g.N * rs, hipMemcpyDeviceToDevice, c->stream));
+            }
+            return copy_out(c, c->q, D, out, dtype, on_device);
+        }
         case LB2P_FIELD_U: return copy_out(c, c->u, D, out, dtype, on_device);
         case LB2P_FIELD_SIGMA:
             if (!c->sigma_valid) return LB2P_ESTATE;
@@ -722,7 +1063,7 @@ lb2p_status lb2p_get_populations(lb2p_ctx* c, double* n_out, int on_device)
 {
     if (!c || !n_out) return LB2P_EINVAL;
     if (!c->initialized) return LB2P_ESTATE;
-    const size_t bytes = (size_t)c->Q * c->g.N * sizeof(double);
+    const size_t bytes = (size_t)c->Q * c->S * sizeof(double);
     double* dst = n_out;
     if (!on_device) HIPCHK(hipMallocAsync((void**)&dst, bytes, c->stream));
     dispatch(c, [&](auto impl) { decltype(impl)::export_pop(c, dst); });
@@ -738,27 +1079,13 @@ lb2p_status lb2p_get_populations(lb2p_ctx* c, double* n_out, int on_device)
 lb2p_status lb2p_set_populations(lb2p_ctx* c, const double* n_in, int on_device)
 {
     if (!c || !n_in) return LB2P_EINVAL;
-    const size_t bytes = (size_t)c->Q * c->g.N * sizeof(double);
+    const size_t bytes = (size_t)c->Q * c->S * sizeof(double);
     const double* src = n_in;
     double* tmp = nullptr;
     if (!on_device) {
         HIPCHK(hipMallocAsync((void**)&tmp, bytes, c->stream));
         HIPCHK(hipMemcpyAsync(tmp, n_in, bytes, hipMemcpyHostToDevice, c->stream));
         src = tmp;
-    }
-    if (!c->initialized) {
-        // deviation storage needs a reference; use rho1-free default: rho0
-        double rref = c->prm.store_rho_ref > 0.0 ? c->prm.store_rho_ref : c->prm.rho0;
-        const double cs2 = eos_cs2<double>(c->cf.eos, rref);
-        double w[8] = {0};
-        if (c->Q == 59) shell_weights<59, double>(cs2, w);
-        else shell_weights<21, double>(cs2, w);
-        for (int k = 0; k < 8; ++k) {
-            const double wk = w[k] > 0 ? w[k] : 1.0;
-            c->ds.off[k] = (float)(wk * rref);
-            c->ds.scl[k] = (float)wk;
-            c->ds.inv[k] = (float)(1.0 / wk);
-        }
     }
     dispatch(c, [&](auto impl) { decltype(impl)::import_pop(c, src); });
     HIPCHK(hipGetLastError());
@@ -769,6 +1096,91 @@ lb2p_status lb2p_set_populations(lb2p_ctx* c, const double* n_in, int on_device)
     c->have_prev = false;
     c->sigma_valid = false;
     c->sticky = LB2P_OK;
+    return LB2P_OK;
+}
+
+lb2p_status lb2p_autotune(lb2p_ctx* c, int steps)
+{
+    if (!c) return LB2P_EINVAL;
+    if (!c->initialized) return LB2P_ESTATE;
+    if (steps <= 0) steps = 2;
+    const size_t pbytes = c->pbytes;
+    void* save = nullptr;
+    if (hipMalloc(&save, pbytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return LB2P_ENOMEM;
+    }
+    HIPCHK(hipMemcpyAsync(save, c->A, pbytes, hipMemcpyDeviceToDevice, c->stream));
+    void* const A_orig = c->A;
+    void* const B_orig = c->B;
+    const lb2p_params keep = c->prm;
+    if (c->prm.fixed_iter <= 0) c->prm.fixed_iter = 4;   // the same work for every candidate
+    c->prm.graph_steps = 0;
+    const bool prof_keep = c->prof;
+    c->prof = false;
+    const int shapes[4][2] = {{64, 4}, {128, 2}, {256, 1}, {32, 8}};
+    const int tzs[4] = {16, 32, 64, 128};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    lb2p_status st = LB2P_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) st = LB2P_EHIP;
+    TuneChoice best{c->bx, c->by, c->tz};
+    float best_ms = 1e30f;
+    for (int si = 0; si < 4 && st == LB2P_OK; ++si)
+        for (int ti = 0; ti < (c->D == 3 ? 4 : 1) && st == LB2P_OK; ++ti) {
+            c->bx = shapes[si][0];
+            c->by = shapes[si][1];
+            c->tz = tzs[ti];
+            st = build_tiles(c);
+            if (st != LB2P_OK) break;
+            // every candidate starts from the same populations
+            c->A = A_orig;
+            c->B = B_orig;
+            if (hipMemcpyAsync(c->A, save, pbytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess) {
+                st = LB2P_EHIP;
+                break;
+            }
+            c->have_prev = false;
+            st = run_steps(c, 1);   // warm-up
+            if (st != LB2P_OK) break;
+            float ms = 0.f;
+            if (hipEventRecord(e0, c->stream) != hipSuccess) { st = LB2P_EHIP; break; }
+            st = run_steps(c, steps);
+            if (st != LB2P_OK) break;
+            if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                st = LB2P_EHIP;
+                break;
+            }
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = TuneChoice{c->bx, c->by, c->tz};
+            }
+        }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    c->prm = keep;
+    c->prof = prof_keep;
+    c->bx = best.bx;
+    c->by = best.by;
+    c->tz = best.tz;
+    c->A = A_orig;
+    c->B = B_orig;
+    if (st == LB2P_OK) st = build_tiles(c);
+    (void)hipMemcpyAsync(c->A, save, pbytes, hipMemcpyDeviceToDevice, c->stream);
+    (void)hipMemsetAsync(c->flags, 0, sizeof(int), c->stream);
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(save);
+    c->have_prev = false;
+    c->sticky = LB2P_OK;
+    if (st != LB2P_OK) return st;
+    const std::string key = tune_key(c);
+    tune_cache()[key] = best;
+    if (const char* path = std::getenv("LB2P_TUNE_CACHE")) {
+        if (FILE* fh = std::fopen(path, "a")) {
+            std::fprintf(fh, "%s %d %d %d\n", key.c_str(), best.bx, best.by, best.tz);
+            std::fclose(fh);
+        }
+    }
     return LB2P_OK;
 }
 

@@ -22,6 +22,7 @@ D2Q21, D3Q59 = 21, 59
 STORE_F64, STORE_F32, STORE_BF16, STORE_F16 = 0, 1, 2, 3
 DTYPE_F64, DTYPE_F32 = 0, 1
 FIELD_RHO, FIELD_J0, FIELD_FORCE, FIELD_JTILDE, FIELD_U, FIELD_SIGMA, FIELD_XI = range(7)
+FLAG_UNFUSED_SOLVE = 1
 STORAGE_NAMES = {"f64": STORE_F64, "f32": STORE_F32, "bf16": STORE_BF16, "f16": STORE_F16}
 
 
@@ -42,7 +43,8 @@ class _Params(ctypes.Structure):
                 ("kappa", ctypes.c_double), ("eos", _Eos), ("rho0", ctypes.c_double),
                 ("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("fixed_iter", ctypes.c_int),
                 ("warm_start", ctypes.c_int), ("check_every", ctypes.c_int),
-                ("store_rho_ref", ctypes.c_double)]
+                ("store_rho_ref", ctypes.c_double), ("flags", ctypes.c_int),
+                ("graph_steps", ctypes.c_int)]
 
 
 class _Stats(ctypes.Structure):
@@ -51,11 +53,13 @@ class _Stats(ctypes.Structure):
 
 
 EXPORTED = [
-    "lb2p_default_params", "lb2p_create", "lb2p_init", "lb2p_step", "lb2p_moments",
+    "lb2p_default_params", "lb2p_create", "lb2p_create_batch", "lb2p_domain_totals",
+    "lb2p_autotune", "lb2p_init", "lb2p_step", "lb2p_moments",
     "lb2p_get_field", "lb2p_get_populations", "lb2p_set_populations", "lb2p_velocities",
     "lb2p_stats_get", "lb2p_profile_enable", "lb2p_profile_read", "lb2p_destroy", "lb2p_strerror",
 ]
-KERNEL_NAMES = ["moments", "force", "iter_q", "iter_jt", "closure1", "closure2", "collide"]
+KERNEL_NAMES = ["moments", "force", "iter_q", "iter_jt", "closure1", "closure2", "collide",
+                "iter_fused"]
 
 _lib = None
 
@@ -66,11 +70,22 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with paper_1402_2920_amd/build.py")
+        # One HIP runtime per process: PyTorch ships its own libamdhip64, and
+        # device pointers and streams it hands over are only valid in that
+        # runtime.  Loading torch first makes the library bind to the same
+        # copy (by soname); loading it second leaves torch without a device.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         vp = ctypes.c_void_p
         pp = ctypes.POINTER(_Params)
         L.lb2p_default_params.argtypes = [ctypes.c_int] * 5 + [pp]
         L.lb2p_create.argtypes = [pp, vp, ctypes.POINTER(vp)]
+        L.lb2p_create_batch.argtypes = [ctypes.c_int, pp, vp, ctypes.POINTER(vp)]
+        L.lb2p_domain_totals.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+        L.lb2p_autotune.argtypes = [vp, ctypes.c_int]
         L.lb2p_init.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int]
         L.lb2p_step.argtypes = [vp, ctypes.c_int]
         L.lb2p_moments.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_Stats)]
@@ -127,13 +142,15 @@ class Params:
     warm_start: int = 1
     check_every: int = 0
     store_rho_ref: float = 0.0
+    flags: int = 0
+    graph_steps: int = 0
 
     def to_c(self) -> _Params:
         tol = self.tol if self.tol is not None else (1e-13 if self.storage == STORE_F64 else 1e-6)
         return _Params(self.lattice, self.nx, self.ny, self.nz, self.storage, self.gamma, self.kappa,
                        _Eos(self.rho1, self.rho2, self.A, self.cs2_rho1), self.rho0, tol,
                        self.max_iter, self.fixed_iter, self.warm_start, self.check_every,
-                       self.store_rho_ref)
+                       self.store_rho_ref, self.flags, self.graph_steps)
 
     @property
     def dim(self) -> int:
@@ -173,21 +190,30 @@ def _ptr(x, dtype_code: int):
 
 
 class Context:
-    """One lattice (``lb2p_create`` ... ``lb2p_destroy``)."""
+    """One lattice (``lb2p_create``), or a batch of independent lattices
+    (``lb2p_create_batch``) when ``params`` is a list; buffers then hold the
+    domains packed in order (``offsets``)."""
 
-    def __init__(self, params: Params, stream=None):
+    def __init__(self, params, stream=None):
+        batch = isinstance(params, (list, tuple))
+        plist = list(params) if batch else [params]
         self.params = params
+        self.domains = plist
         self._ctx = ctypes.c_void_p()
-        prm = params.to_c()
+        arr = (_Params * len(plist))(*[p.to_c() for p in plist])
         handle = None
         if stream is not None:
             handle = ctypes.c_void_p(int(getattr(stream, "cuda_stream", stream)))
-        st = lib().lb2p_create(ctypes.byref(prm), handle, ctypes.byref(self._ctx))
+        if batch:
+            st = lib().lb2p_create_batch(len(plist), arr, handle, ctypes.byref(self._ctx))
+        else:
+            st = lib().lb2p_create(arr, handle, ctypes.byref(self._ctx))
         if st != OK:
-            raise Lb2pError(st, "lb2p_create")
-        self.Q = params.lattice
-        self.dim = params.dim
-        self.N = params.N
+            raise Lb2pError(st, "lb2p_create_batch" if batch else "lb2p_create")
+        self.Q = plist[0].lattice
+        self.dim = plist[0].dim
+        self.N = sum(p.N for p in plist)
+        self.offsets = np.cumsum([0] + [p.N for p in plist])
         self.last_status = OK
 
     def _check(self, st, where, allow=()):
@@ -256,6 +282,12 @@ class Context:
                     "lb2p_get_populations")
         return out
 
+    def populations_into(self, out):
+        """Decoded populations [Q][N] FP64 into a caller buffer (a contiguous
+        torch FP64 device tensor, or a numpy array)."""
+        p, dev = _ptr(out, DTYPE_F64)
+        return self._check(lib().lb2p_get_populations(self._ctx, p, dev), "lb2p_get_populations")
+
     def set_populations(self, n: np.ndarray):
         n = np.ascontiguousarray(n, dtype=np.float64)
         assert n.shape == (self.Q, self.N)
@@ -272,6 +304,16 @@ class Context:
         cnt = (ctypes.c_longlong * n)()
         self._check(lib().lb2p_profile_read(self._ctx, ms, cnt), "lb2p_profile_read")
         return {k: (ms[i], cnt[i]) for i, k in enumerate(KERNEL_NAMES)}
+
+    def domain_totals(self) -> np.ndarray:
+        """[ndom, 4] FP64: mass and momentum (x, y, z) per domain."""
+        out = np.zeros((len(self.domains), 4))
+        self._check(lib().lb2p_domain_totals(self._ctx, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+                    "lb2p_domain_totals")
+        return out
+
+    def autotune(self, steps: int = 2):
+        return self._check(lib().lb2p_autotune(self._ctx, int(steps)), "lb2p_autotune")
 
     def stats(self) -> dict:
         st = _Stats()

@@ -81,3 +81,18 @@ def test_strerror(L):
     for s in range(8):
         assert isinstance(L.strerror(s), str) and L.strerror(s)
     assert L.strerror(99) == "unknown status"
+
+
+def test_batch_rejects_mixed_shared_settings(L):
+    """Domains of one batched context share lattice, storage and iteration
+    settings; a mismatch is refused on the host before any allocation."""
+    a = L.Params(lattice=59, nx=16, ny=16, nz=16, A=0.745, cs2_rho1=0.39, kappa=0.01)
+    b = L.Params(lattice=59, nx=20, ny=12, nz=10, A=0.745, cs2_rho1=0.39, kappa=0.02,
+                 storage=L.STORE_F64)
+    with pytest.raises(L.Lb2pError) as ei:
+        L.Context([a, b])
+    assert ei.value.status == L.EINVAL
+    c = L.Params(lattice=21, nx=16, ny=16, A=0.8, cs2_rho1=0.45, kappa=0.1)
+    with pytest.raises(L.Lb2pError) as ei:
+        L.Context([a, c])
+    assert ei.value.status == L.EINVAL

@@ -1,0 +1,129 @@
+"""GPU parity at full workload sizes, where the oracle cannot run the whole
+lattice.
+
+Windows: with a fixed number k of j~ passes, one step's output at a site
+depends only on sites within R = 14 + 4k of it (pull 4, force stencil 2,
+each pass 4 = two first-derivative stencils, closure 4, the pull that
+exports the populations 4).  The oracle advances a periodic window of side
+W > 2R cut from the same initial fields; its central sites, whose
+dependence cone never meets the window's wrap, must equal the full-size GPU
+result.  Centres are seeded, one sits on a slab wall and on the periodic
+seam of the big lattice.
+
+Long run: the D2Q21 64 x 64 droplet over 1000 steps in FP64 against the
+oracle (both to their own stop rule; the GPU warm-starts j~).
+
+Properties at any size: mass and momentum totals over steps of the
+benchmark's own configuration (FP32, stop rule, warm start).
+"""
+import numpy as np
+import pytest
+
+import lb2p_workloads as W
+from parity_util import match_populations, rel_err
+
+pytestmark = pytest.mark.gpu
+
+K_FIXED = 4
+RADIUS = 14 + 4 * K_FIXED
+WIN = 2 * RADIUS + 12
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1402_2920_amd import lb2p
+    lb2p.lib()
+    return lb2p
+
+
+def _cut(a3, centre, w):
+    """Periodic window of side w centred at `centre` (x, y, z) of a [z][y][x] array."""
+    idx = [(c - w // 2 + np.arange(w)) % n for c, n in zip(centre, a3.shape[::-1])]
+    return a3[np.ix_(idx[2], idx[1], idx[0])], idx
+
+
+def _centres(shape, seed=1402, n=2):
+    rng = np.random.default_rng(seed)
+    cs = [tuple(int(rng.integers(0, s)) for s in shape) for _ in range(n)]
+    cs.append((0, shape[1] - 1, 64 * shape[2] // 256))   # slab wall, periodic seam in x and y
+    return cs
+
+
+@pytest.mark.parametrize("storage,tol", [("STORE_F64", 1e-10), ("STORE_F32", 1e-5)])
+def test_fullsize_windows_match_oracle(orc, L, storage, tol):
+    import torch
+    name = "d3q59_256_slab"
+    entry, shape, rho, u = W.build(name)
+    nx, ny, nz = shape
+    P = L.Params(nx=nx, ny=ny, nz=nz, storage=getattr(L, storage), fixed_iter=K_FIXED, max_iter=200,
+                 warm_start=1, **W.model_kwargs(entry["model"]))
+    Q = P.lattice
+    torch.cuda.set_device(0)
+    nd = torch.empty((Q, nz, ny, nx), dtype=torch.float64, device="cuda:0")
+    with L.Context(P) as ctx:
+        ctx.init(torch.tensor(rho, device="cuda:0"), torch.tensor(u, device="cuda:0").contiguous())
+        ctx.step(1)
+        ctx.populations_into(nd)
+        torch.cuda.synchronize()
+    c_lib = L.velocities(Q)
+    perm = match_populations(c_lib, orc.velocities(Q)[0])
+    rho3 = rho.reshape(nz, ny, nx)
+    u3 = u.reshape(3, nz, ny, nx)
+    inner = slice(RADIUS, WIN - RADIUS)
+    for centre in _centres(shape):
+        rw, idx = _cut(rho3, centre, WIN)
+        uw = np.stack([_cut(u3[a], centre, WIN)[0] for a in range(3)])
+        m = orc.Model(Q=Q, nx=WIN, ny=WIN, nz=WIN, tol=-1.0, max_iter=K_FIXED,
+                      **{k: v for k, v in W.oracle_kwargs(entry["model"]).items() if k != "Q"})
+        n = orc.init(m, rw.ravel(), uw.reshape(3, -1).T.copy())
+        orc.step(m, n, 1)
+        no = n[perm].reshape(Q, WIN, WIN, WIN)[:, inner, inner, inner]
+        it = [torch.as_tensor(i, device="cuda:0") for i in idx]
+        ng = nd.index_select(1, it[2]).index_select(2, it[1]).index_select(3, it[0])
+        ng = ng.cpu().numpy()[:, inner, inner, inner]
+        e = rel_err(ng, no)
+        print(storage, "window at", centre, f"pop rel err {e:.2e}", flush=True)
+        assert e <= tol, (centre, e)
+    del nd
+    torch.cuda.empty_cache()
+
+
+def test_c1_long_run_matches_oracle(orc, L):
+    entry, shape, rho, u = W.build("d2q21_64_droplet")
+    steps = entry["steps"]
+    m = orc.Model(nx=shape[0], ny=shape[1], nz=1, tol=1e-14, max_iter=2000, **W.oracle_kwargs(entry["model"]))
+    n = orc.init(m, rho, u.T.copy())
+    orc.step(m, n, steps)
+    F = orc.fields(m, n)
+    P = L.Params(nx=shape[0], ny=shape[1], nz=1, storage=L.STORE_F64, tol=1e-14, max_iter=2000,
+                 **W.model_kwargs(entry["model"]))
+    with L.Context(P) as ctx:
+        ctx.init(rho, np.ascontiguousarray(u))
+        ctx.step(steps)
+        rg, ug = ctx.moments()
+    er = rel_err(rg, F["rho"])
+    eu = float(np.max(np.sqrt(((ug - F["u"][:, :2].T) ** 2).sum(0))) /
+               np.max(np.sqrt((F["u"][:, :2] ** 2).sum(1))))
+    print(f"C1 {steps} steps: e_rho {er:.2e} e_u {eu:.2e}", flush=True)
+    assert er <= 1e-10 and eu <= 1e-10
+
+
+def test_fullsize_bench_config_conserves(L):
+    """The benchmark's configuration at 256^3: FP64 totals of mass and
+    momentum over 10 steps (FP32 storage; the rest population's mass balance
+    keeps the mass to about 1e-11 per step)."""
+    import torch
+    entry, shape, rho, u = W.build("d3q59_256_slab")
+    P = L.Params(nx=shape[0], ny=shape[1], nz=shape[2], storage=L.STORE_F32, max_iter=200, warm_start=1,
+                 **W.model_kwargs(entry["model"]))
+    torch.cuda.set_device(0)
+    with L.Context(P, stream=torch.cuda.current_stream()) as ctx:
+        ctx.init(torch.tensor(rho, device="cuda:0"), torch.tensor(u, device="cuda:0").contiguous())
+        s0 = ctx.stats()
+        ctx.step(10)
+        s1 = ctx.stats()
+    dm = abs(s1["mass"] - s0["mass"]) / s0["mass"]
+    dj = float(np.max(np.abs(s1["mom"] - s0["mom"]))) / s0["mass"]
+    print(f"256^3 f32 10 steps: mass drift {dm:.2e}, momentum drift {dj:.2e}, iters {s1['iters']}", flush=True)
+    assert not s1["nonfinite"]
+    assert dm <= 1e-9 and dj <= 1e-7

@@ -17,9 +17,13 @@ pytestmark = pytest.mark.gpu
 F64_TOL = 1e-10
 
 CASES = [
-    ("d2q21", 21, (40, 24)),
-    ("d3q59", 59, (20, 12, 10)),
+    ("d2q21", 21, (40, 24), 0),
+    ("d3q59", 59, (20, 12, 10), 0),
+    ("d3q59_unfused", 59, (20, 12, 10), 1),
+    # several 32 x 8 x 32 solve tiles with ragged edges in x and z
+    ("d3q59_tiles", 59, (40, 24, 36), 0),
 ]
+NSTEPS = {"d3q59_tiles": 3}
 
 
 @pytest.fixture(scope="module")
@@ -29,11 +33,12 @@ def L():
     return lb2p
 
 
-@pytest.mark.parametrize("name,lattice,shape", CASES)
-def test_f64_matches_oracle(orc, L, name, lattice, shape):
+@pytest.mark.parametrize("name,lattice,shape,flags", CASES)
+def test_f64_matches_oracle(orc, L, name, lattice, shape, flags):
     rho, u, model = small_case(lattice, shape)
-    ref = oracle_reference(orc, model, rho, u, nsteps_long=10)
-    gpu = gpu_run(L, model, L.STORE_F64, rho, u, nsteps_long=10, tol=1e-14)
+    ns = NSTEPS.get(name, 10)
+    ref = oracle_reference(orc, model, rho, u, nsteps_long=ns)
+    gpu = gpu_run(L, model, L.STORE_F64, rho, u, nsteps_long=ns, tol=1e-14, flags=flags)
     e = compare(orc, ref, gpu)
     print(name, "f64", {k: f"{v:.2e}" for k, v in e.items()}, flush=True)
     for k, v in e.items():
@@ -50,24 +55,47 @@ F32_TOL = dict(rho_t0=1e-5, u_t0=2e-4, j0_t0=2e-4, force_t0=5e-4, jtilde_t0=1e-3
                xi_t0=1e-3, pop_t1=1e-5, rho_tL=1e-5, u_tL=1e-3)
 
 
-@pytest.mark.parametrize("name,lattice,shape", CASES)
-def test_f32_matches_oracle(orc, L, name, lattice, shape):
+@pytest.mark.parametrize("name,lattice,shape,flags", CASES)
+def test_f32_matches_oracle(orc, L, name, lattice, shape, flags):
     rho, u, model = small_case(lattice, shape)
-    ref = oracle_reference(orc, model, rho, u, nsteps_long=10)
-    gpu = gpu_run(L, model, L.STORE_F32, rho, u, nsteps_long=10, tol=1e-7)
+    ns = NSTEPS.get(name, 10)
+    ref = oracle_reference(orc, model, rho, u, nsteps_long=ns)
+    gpu = gpu_run(L, model, L.STORE_F32, rho, u, nsteps_long=ns, tol=1e-7, flags=flags)
     e = compare(orc, ref, gpu)
     print(name, "f32", {k: f"{v:.2e}" for k, v in e.items()}, flush=True)
     for k, v in e.items():
         assert v <= F32_TOL[k], (k, v)
 
 
-@pytest.mark.parametrize("name,lattice,shape", CASES)
-def test_invariants_on_gpu(orc, L, name, lattice, shape):
+@pytest.mark.parametrize("name,lattice,shape,flags", CASES)
+def test_invariants_on_gpu(orc, L, name, lattice, shape, flags):
     """Mass and total momentum are conserved (Sec. VI: the lattice force sums
     to zero on a periodic lattice; j~ is a divergence)."""
     rho, u, model = small_case(lattice, shape)
-    gpu = gpu_run(L, model, L.STORE_F64, rho, u, nsteps_long=10, tol=1e-14)
+    gpu = gpu_run(L, model, L.STORE_F64, rho, u, nsteps_long=10, tol=1e-14, flags=flags)
     s0, sL = gpu["stats0"], gpu["statsL"]
     assert abs(sL["mass"] - s0["mass"]) <= 1e-13 * s0["mass"]
     assert np.max(np.abs(sL["mom"] - s0["mom"])) <= 1e-13 * s0["mass"]
     assert not sL["nonfinite"]
+
+
+@pytest.mark.parametrize("storage", ["STORE_F64", "STORE_F32"])
+def test_fused_and_unfused_solve_agree(orc, L, storage):
+    """The fused D3Q59 pass and the two-sweep pass are the same map: same
+    iteration count from a zero start and the same j~ up to rounding."""
+    rho, u, model = small_case(59, (40, 24, 36))
+    st = getattr(L, storage)
+    out = []
+    for flags in (0, L.FLAG_UNFUSED_SOLVE):
+        P = L.Params(lattice=59, nx=40, ny=24, nz=36, storage=st, gamma=model["gamma"],
+                     kappa=model["kappa"], rho1=model["rho1"], rho2=model["rho2"], A=model["A"],
+                     cs2_rho1=model["cs2_1"], rho0=model["rho0"], max_iter=500, flags=flags,
+                     tol=1e-14 if st == L.STORE_F64 else 1e-6)
+        with L.Context(P) as ctx:
+            ctx.init(rho, u)
+            r, uu = ctx.moments()
+            out.append((ctx.stats()["iters"], ctx.field(L.FIELD_JTILDE), uu))
+    assert out[0][0] == out[1][0]
+    tol = 1e-12 if st == L.STORE_F64 else 1e-5
+    scale = np.abs(out[1][1]).max()
+    assert np.abs(out[0][1] - out[1][1]).max() <= tol * scale
