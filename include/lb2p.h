@@ -51,9 +51,13 @@ typedef enum {
 typedef enum { LB2P_D2Q21 = 21, LB2P_D3Q59 = 59 } lb2p_lattice;
 
 /* Population storage.  F64 computes in FP64; every other form computes in
- * FP32.  BF16/F16 store n_i as deviations from o_i = W_i rho_ref scaled by
- * 1/W_i, where W_i are the rest weights at the reference density rho_ref
- * (lb2p_params.store_rho_ref). */
+ * FP32.  BF16/F16 store the moving populations as deviations from
+ * o_i = W_i rho_ref scaled by 1/W_i, where W_i are the rest weights at the
+ * reference density rho_ref (lb2p_params.store_rho_ref).  In every form the
+ * rest population is held apart at higher precision (FP64 beside F64/F32,
+ * FP32 beside BF16/F16) and set by the collision from the site's mass
+ * balance (sum_i Delta_i = 0, Sec. VI), so the lattice mass is conserved to
+ * the rounding of that plane. */
 typedef enum {
     LB2P_STORE_F64 = 0,
     LB2P_STORE_F32 = 1,
