@@ -30,7 +30,7 @@ HBM_PEAK_GBS = 8000.0
 DEFAULT_WORKLOAD = "d3q59_256_slab"
 
 
-def site_bytes(kernel, Q, D, s, r, warm):
+def site_bytes(kernel, Q, D, s, r, warm, cheb=False):
     """Algorithmic bytes per site of one launch of a kernel class: every
     population or field word the kernel must read or write once (stencil
     neighbours are reuse, not extra traffic).  The rest population is one
@@ -41,21 +41,26 @@ def site_bytes(kernel, Q, D, s, r, warm):
     pops = (Q - 1) * s + t0
     return {
         "moments": pops + (1 + D) * r,
-        "force": (1 + D) * r + (D * r if warm else 0) + 4 * D * r,
-        "iter_q": (1 + D) * r + nsig * r,
-        "iter_jt": (nsig + 1 + 2 * D) * r + 2 * D * r,
+        "force": (1 + D) * r + (D * r if warm else 0) + 4 * D * r + 3 * r,
+        "iter_q": (2 + D) * r + nsig * r,
+        "iter_jt": (nsig + 1 + 2 * D) * r + 2 * D * r + (D * r if cheb else 0),
         "closure1": (1 + 2 * D) * r + (1 + nsig + D + nxi) * r,
         "closure2": (2 + nsig + 2 * D) * r + nsig * r,
         "collide": 2 * pops + (1 + 3 * D + nsig + nxi) * r,
-        # fused pass: read j~, j0', rho, write j~new
-        "iter_fused": (1 + 2 * D) * r + D * r,
+        # fused pass: read j~, j0' and the p, P1, 1/rho planes, write j~new
+        # (Chebyshev: also read x_{k-1})
+        "iter_fused": (3 + 2 * D) * r + D * r + (D * r if cheb else 0),
     }[kernel]
 
 
 STORE_BYTES = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}
 
 
-def run_gpu(workload, storage, steps, warmup, shape=None, profile=True, tol=None):
+SOLVERS = {"fixed_point": 0, "chebyshev": 1}
+
+
+def run_gpu(workload, storage, steps, warmup, shape=None, profile=True, tol=None, solver="fixed_point",
+            autotune=True):
     import torch
     import lb2p_workloads as W
     from paper_1402_2920_amd import lb2p
@@ -63,7 +68,8 @@ def run_gpu(workload, storage, steps, warmup, shape=None, profile=True, tol=None
     d = len(shape)
     st = lb2p.STORAGE_NAMES[storage]
     P = lb2p.Params(nx=shape[0], ny=shape[1], nz=shape[2] if d == 3 else 1, storage=st,
-                    tol=tol, max_iter=200, warm_start=1, **W.model_kwargs(entry["model"]))
+                    tol=tol, max_iter=200, warm_start=1, solver=SOLVERS[solver],
+                    **W.model_kwargs(entry["model"]))
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     dt = torch.float64
@@ -73,6 +79,8 @@ def run_gpu(workload, storage, steps, warmup, shape=None, profile=True, tol=None
     with lb2p.Context(P, stream=stream) as ctx:
         ctx.init(rho_d, u_d)
         del rho_d, u_d
+        if autotune:
+            ctx.autotune(2)
         ctx.step(warmup)
         if profile:
             ctx.profile_enable(True)
@@ -130,7 +138,7 @@ def run_batch(workload, steps, warmup, fixed_iter, graph=True, limit=None, autot
     return out
 
 
-def roofline(res, storage, warm=True):
+def roofline(res, storage, warm=True, cheb=False):
     prof = res["prof"]
     Q, D, N = res["Q"], res["D"], res["N"]
     s = STORE_BYTES[storage]
@@ -139,17 +147,17 @@ def roofline(res, storage, warm=True):
     dom = max(total, key=total.get)
     ms, n = prof[dom]
     avg_s = ms / 1e3 / max(n, 1)
-    bytes_launch = site_bytes(dom, Q, D, s, r, warm) * N
+    bytes_launch = site_bytes(dom, Q, D, s, r, warm, cheb) * N
     achieved = bytes_launch / avg_s / 1e9
     per_kernel = {k: dict(ms_total=round(v[0], 3), launches=v[1],
                           avg_us=round(1e3 * v[0] / max(v[1], 1), 2),
-                          gbs=round(site_bytes(k, Q, D, s, r, warm) * N / (v[0] / 1e3 / max(v[1], 1)) / 1e9, 1)
+                          gbs=round(site_bytes(k, Q, D, s, r, warm, cheb) * N / (v[0] / 1e3 / max(v[1], 1)) / 1e9, 1)
                           if v[1] else None)
                   for k, v in prof.items()}
     traffic = measured_traffic(dom, res)
     return dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                bytes_per_site=site_bytes(dom, Q, D, s, r, warm), launches=n,
+                bytes_per_site=site_bytes(dom, Q, D, s, r, warm, cheb), launches=n,
                 avg_launch_us=round(avg_s * 1e6, 2)), per_kernel
 
 
@@ -230,6 +238,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
     ap.add_argument("--storage", default="f32", choices=list(STORE_BYTES))
+    ap.add_argument("--solver", default="fixed_point", choices=list(SOLVERS),
+                    help="j~ solver: the paper's fixed point, or Chebyshev semi-iteration on the same map")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default block shapes")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-variants", action="store_true", help="skip the BF16/F16 storage lines")
     ap.add_argument("--batch-steps", type=int, default=1000,
@@ -243,10 +254,11 @@ def main():
 
     import lb2p_workloads as W
     entry = W.load_params()[args.workload]
-    res = run_gpu(args.workload, args.storage, args.steps, args.warmup)
+    res = run_gpu(args.workload, args.storage, args.steps, args.warmup, solver=args.solver,
+                  autotune=not args.no_autotune)
     N, K = res["N"], args.steps
     secs = res["seconds"]
-    roof, per_kernel = roofline(res, args.storage)
+    roof, per_kernel = roofline(res, args.storage, cheb=args.solver == "chebyshev")
     shape = res["shape"]
     line = dict(
         metric="MLUPS and % HBM peak, D3Q59 FP32 vs BF16-storage at stated error",
@@ -256,7 +268,8 @@ def main():
         config=dict(workload=f"{args.workload}: D{len(shape)}Q{res['Q']} {'x'.join(map(str, shape))} "
                              f"periodic, {entry['kind']}, {args.storage} populations",
                     sites=N, parallelism="single GPU",
-                    solve="j~ fixed point to the paper's stop rule, tol 1e-6 x max|j0'|, warm start",
+                    solve=("j~ fixed point" if args.solver == "fixed_point" else "Chebyshev semi-iteration")
+                    + " to the paper's stop rule, tol 1e-6 x max|j0'|, warm start",
                     iters_last_step=res["stats"]["iters"]),
         roofline=roof,
         kernels=per_kernel,
@@ -267,12 +280,14 @@ def main():
         line["cpu_baseline"] = cb
     if not args.no_variants and args.storage == "f32":
         var = {}
-        for stg in ("bf16", "f16"):
-            r2 = run_gpu(args.workload, stg, K, args.warmup)
-            rf, _ = roofline(r2, stg)
-            var[stg] = dict(value=round(N * K / r2["seconds"] / 1e6, 2), unit="MLUPS",
-                            ms_per_step=round(1e3 * r2["seconds"] / K, 4), roofline_frac=rf["frac"],
-                            dominant=rf["kernel"])
+        other = "chebyshev" if args.solver == "fixed_point" else "fixed_point"
+        for stg, sol in (("bf16", args.solver), ("f16", args.solver), ("f32", other), ("bf16", other)):
+            r2 = run_gpu(args.workload, stg, K, args.warmup, solver=sol, autotune=not args.no_autotune)
+            rf, _ = roofline(r2, stg, cheb=sol == "chebyshev")
+            var[f"{stg}_{sol}"] = dict(value=round(N * K / r2["seconds"] / 1e6, 2), unit="MLUPS",
+                                       ms_per_step=round(1e3 * r2["seconds"] / K, 4),
+                                       roofline_frac=rf["frac"], dominant=rf["kernel"],
+                                       iters_last_step=r2["stats"]["iters"])
         line["variants"] = var
     if args.batch_steps > 0:
         bw = "d2q21_batch512"

@@ -90,7 +90,9 @@ typedef struct {
 
 typedef struct {
     int lattice;            /* lb2p_lattice                                    */
-    int nx, ny, nz;         /* every side >= 8; nz == 1 for D2Q21              */
+    int nx, ny, nz;         /* every side >= 8; nz == 1 for D2Q21; one field
+                               component of a domain below 4 GiB (fewer than
+                               2^29 sites with F64, 2^30 otherwise)            */
     int storage;            /* lb2p_storage                                    */
     double gamma;           /* BGK parameter, -1 < gamma < 1 (Sec. II)         */
     double kappa;           /* interfacial stiffness >= 0 (Sec. II)            */
@@ -111,7 +113,25 @@ typedef struct {
     int flags;              /* LB2P_FLAG_* (0 = defaults)                      */
     int graph_steps;        /* > 0 with fixed_iter > 0: lb2p_step replays a
                                HIP graph of this many captured steps           */
+    int solver;             /* lb2p_solver: how the j~ fixed point is reached  */
+    double spectral_bound;  /* Chebyshev only: upper bound b < 1 of the
+                               spectrum of the map's linear part (0 = bound
+                               from the EOS, see lb2p_solver)                  */
 } lb2p_params;
+
+/* lb2p_params.solver.  Both reach the fixed point of items 3-8 and stop on
+ * the same rule (max_r |G(j~) - j~| <= tol * max_r |j0'|, Sec. IX).
+ *   LB2P_SOLVER_FIXED_POINT: the paper's iteration j~ <- G(j~).
+ *   LB2P_SOLVER_CHEBYSHEV:   Chebyshev semi-iteration on the same map (the
+ *     faster solvers Sec. IX leaves open).  The linear part of G is similar
+ *     to a symmetric positive semi-definite operator when the bulk viscosity
+ *     is positive, so its spectrum is real in [0, b].  The default b is
+ *     1.05 * (|s|^2_max / 12) * max over (rho1, rho3) of c_s^2 (2 - rho psi),
+ *     with |s|^2_max = d * max_k ((4/3) sin k - (1/6) sin 2k)^2 the largest
+ *     plane-wave symbol of the first-derivative stencil (Sec. IV B).
+ *     lb2p_create returns LB2P_EINVAL when b >= 1 (the map is then not a
+ *     contraction and the semi-iteration does not apply). */
+typedef enum { LB2P_SOLVER_FIXED_POINT = 0, LB2P_SOLVER_CHEBYSHEV = 1 } lb2p_solver;
 
 /* lb2p_params.flags: LB2P_FLAG_UNFUSED_SOLVE runs each pass of the j~
  * iteration as two separate sweeps (items 4 and 5) instead of the fused

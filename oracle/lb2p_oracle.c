@@ -406,7 +406,7 @@ int orc_fields(const orc_params *P, const double *n, double *rho_o, double *j0_o
     double jscale = 0.0;
     for (long k = 0; k < 3 * N; ++k) {
         double ak = fabs(j0p[k]);
-        if (!(ak <= jscale)) jscale = ak;
+        if (!(ak <= jscale) && jscale == jscale) jscale = ak;   /* a NaN, once seen, stays */
     }
     int iters = 0, converged = 0;
     double resid = 0.0;
@@ -417,7 +417,7 @@ int orc_fields(const orc_params *P, const double *n, double *rho_o, double *j0_o
             resid = 0.0;                                            /* item 6    */
             for (long k = 0; k < 3 * N; ++k) {
                 double dk = fabs(jtn[k] - jt[k]);
-                if (!(dk <= resid)) resid = dk;      /* keeps a NaN visible */
+                if (!(dk <= resid) && resid == resid) resid = dk;   /* a NaN, once seen, stays */
             }
             memcpy(jt, jtn, sizeof(double) * 3 * (size_t)N);        /* items 7, 8 */
             if (resid <= P->tol * jscale) { converged = 1; break; }

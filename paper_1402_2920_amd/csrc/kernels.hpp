@@ -35,6 +35,7 @@ struct Coef {
     double c0sq;          // c_s^2(rho0)
     double Wk[8];         // W_k = w_k(c0^2), reference shell weights
     EosParams eos;
+    double cheb_gamma;    // extrapolation 2/(2 - b) of the Chebyshev solver
 };
 
 // Population storage codecs.  Plain forms hold n_i; deviation forms hold
@@ -184,25 +185,73 @@ __device__ __forceinline__ Where locate(const Domain* __restrict__ tab, const Ti
     return w;
 }
 
-// Axis offsets: axis a -> unit vector.
-__device__ __forceinline__ void unit(int a, int& dx, int& dy, int& dz)
+// Neighbours at -2, -1, +1, +2 along each axis of one site, as offsets from
+// its index inside the domain (periodic wrap taken once per thread).  Site
+// indices inside a domain fit 32 bits, and so do the byte offsets of one
+// component plane of a domain (the host limits the domain size), so every
+// access below is a uniform component base plus a 32-bit byte offset.
+struct Nb2 {
+    unsigned i0;
+    int o[3][4];
+};
+
+__device__ __forceinline__ Nb2 make_nb2(const Geom& g, int x, int y, int z)
 {
-    dx = (a == 0);
-    dy = (a == 1);
-    dz = (a == 2);
+    Nb2 nb;
+    nb.i0 = (unsigned)x + (unsigned)g.nx * ((unsigned)y + (unsigned)g.ny * (unsigned)z);
+    const int sx = 1, sy = g.nx, sz = g.nx * g.ny;
+    const int d[4] = {-2, -1, 1, 2};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        nb.o[0][k] = (wrap(x + d[k], g.nx) - x) * sx;
+        nb.o[1][k] = (wrap(y + d[k], g.ny) - y) * sy;
+        nb.o[2][k] = g.nz > 1 ? (wrap(z + d[k], g.nz) - z) * sz : 0;
+    }
+    return nb;
 }
 
-// D1 (Sec. IV B) of one component of an SoA field along axis a.
 template <class R>
-__device__ __forceinline__ R d1_field(const Geom& g, const R* F, int x, int y, int z, int a)
+__device__ __forceinline__ R ldo(const R* base, unsigned i)
 {
-    int dx, dy, dz;
-    unit(a, dx, dy, dz);
-    R m2 = F[nbr(g, x, y, z, -2 * dx, -2 * dy, -2 * dz)];
-    R m1 = F[nbr(g, x, y, z, -dx, -dy, -dz)];
-    R p1 = F[nbr(g, x, y, z, dx, dy, dz)];
-    R p2 = F[nbr(g, x, y, z, 2 * dx, 2 * dy, 2 * dz)];
-    return d1<R>(m2, m1, p1, p2);
+    return *reinterpret_cast<const R*>(reinterpret_cast<const char*>(base) + i * (unsigned)sizeof(R));
+}
+template <class R>
+__device__ __forceinline__ void sto(R* base, unsigned i, R v)
+{
+    *reinterpret_cast<R*>(reinterpret_cast<char*>(base) + i * (unsigned)sizeof(R)) = v;
+}
+
+// Offsets of the pull sources r - c_i (|c_i| components up to 4) from a
+// site's index inside the domain, periodic wrap taken once per axis.
+struct NbP {
+    unsigned i0;
+    int ox[9], oy[9], oz[9];   // index d + 4
+    __device__ __forceinline__ unsigned at(int dx, int dy, int dz) const
+    {
+        return i0 + (unsigned)(ox[dx + 4] + oy[dy + 4] + oz[dz + 4]);
+    }
+};
+
+__device__ __forceinline__ NbP make_nbp(const Geom& g, int x, int y, int z)
+{
+    NbP nb;
+    nb.i0 = (unsigned)x + (unsigned)g.nx * ((unsigned)y + (unsigned)g.ny * (unsigned)z);
+    const int sy = g.nx, sz = g.nx * g.ny;
+#pragma unroll
+    for (int d = -4; d <= 4; ++d) {
+        nb.ox[d + 4] = wrap(x + d, g.nx) - x;
+        nb.oy[d + 4] = (wrap(y + d, g.ny) - y) * sy;
+        nb.oz[d + 4] = g.nz > 1 ? (wrap(z + d, g.nz) - z) * sz : 0;
+    }
+    return nb;
+}
+
+// D1 (Sec. IV B) of one component plane F (domain base) along axis a.
+template <class R>
+__device__ __forceinline__ R d1_nb(const R* F, const Nb2& nb, int a)
+{
+    return d1<R>(ldo(F, nb.i0 + nb.o[a][0]), ldo(F, nb.i0 + nb.o[a][1]), ldo(F, nb.i0 + nb.o[a][2]),
+                 ldo(F, nb.i0 + nb.o[a][3]));
 }
 
 // Symmetric rank-2 component index (xx yy zz xy xz yz / xx yy xy).
@@ -254,16 +303,16 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// Non-negative doubles order like their bit patterns.
-__device__ __forceinline__ void atomic_max_nonneg(unsigned long long* addr, double v)
-{
-    atomicMax(addr, (unsigned long long)__double_as_longlong(v));
-}
-
-// Block-wide max of a non-negative value into *addr (one atomic per block).
-// NaN is mapped to +inf so that it is never lost.  Every thread of the block
+// Block maxima (stop rule of Sec. IX: max|j0'| and the residual of a pass).
+// Each block stores its maximum to a slot of its own; k_reduce_max then
+// reduces each domain's slots.  No two blocks touch one address: tens of
+// thousands of atomics (or coherent loads) on one address serialise across
+// the XCDs.  Slots are in domain order: a launch grid of n blocks (a multiple
+// of 8) runs tile (b % 8) * (n / 8) + b / 8 of the domain-ordered list at
+// workgroup b (the XCD deal), so that is the block's slot.
+// NaN is stored as +inf so that it is never lost.  Every thread of the block
 // must call it.
-__device__ inline void block_max_to(unsigned long long* addr, double v)
+__device__ inline void block_max_part(double* part, double v)
 {
     __shared__ double red[16];
     if (v != v) v = __longlong_as_double(0x7ff0000000000000LL);
@@ -276,7 +325,32 @@ __device__ inline void block_max_to(unsigned long long* addr, double v)
     if (tid == 0) {
         double m = red[0];
         for (int k = 1; k < nw; ++k) m = fmax(m, red[k]);
-        atomic_max_nonneg(addr, m);
+        const unsigned n = gridDim.x, b = blockIdx.x;
+        part[(b % 8u) * (n / 8u) + b / 8u] = m;
+    }
+}
+
+// One block per domain: out[d * stride] = bits of max over part[range[d] ..
+// range[d+1]).  Domains already done (done_at >= 0) are left alone: their
+// blocks skipped the pass and wrote nothing.
+__global__ void __launch_bounds__(256) k_reduce_max(const double* __restrict__ part,
+                                                    const int* __restrict__ range,
+                                                    unsigned long long* __restrict__ out, long long stride,
+                                                    const int* __restrict__ done_at)
+{
+    const int d = blockIdx.x;
+    if (done_at && *((volatile const int*)(done_at + d)) >= 0) return;
+    double m = 0.0;
+    for (int i = range[d] + threadIdx.x; i < range[d + 1]; i += blockDim.x) m = fmax(m, part[i]);
+    m = wave_max(m);
+    __shared__ double red[4];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) red[wid] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = red[0];
+        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) t = fmax(t, red[k]);
+        out[(long long)d * stride] = (unsigned long long)__double_as_longlong(t);
     }
 }
 
@@ -295,30 +369,30 @@ __global__ void __launch_bounds__(256) k_init(const Domain* __restrict__ tab, co
     const Domain& dm = tab[w.dom];
     const Geom g = dm.g;
     const long long o = dm.off, St = g.S;
-    const long long i0 = o + sidx(g, w.x, w.y, w.z);
-    const R r = rho[i0];
+    const NbP nb = make_nbp(g, w.x, w.y, w.z);
+    const unsigned i0 = nb.i0;
+    const R r = ldo(rho + o, i0);
     R uu[3] = {R(0), R(0), R(0)};
 #pragma unroll
-    for (int a = 0; a < L::D; ++a) uu[a] = u[a * St + i0];
+    for (int a = 0; a < L::D; ++a) uu[a] = ldo(u + o + a * St, i0);
     const R cs2 = eos_cs2<R>(dm.cf.eos, r);
     R wl[8];
     shell_weights<Q, R>(cs2, wl);
     const R inv = R(1) / cs2;
     const R a0 = R(1) - (uu[0] * uu[0] + uu[1] * uu[1] + uu[2] * uu[2]) * R(0.5) * inv;
     using T0 = typename RestOf<S>::T;
-    S* mv = moving_planes(A, St);
+    S* const mv = moving_planes(A, St) + o;
     T0 moved = T0(0);
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
         const R uc = uu[0] * R(L::cx(i)) + uu[1] * R(L::cy(i)) + uu[2] * R(L::cz(i));
         const R neq = wl[L::shell(i)] * r * (a0 + uc * inv + R(0.5) * uc * uc * inv * inv);
-        const long long dst = o + nbr(g, w.x, w.y, w.z, -L::cx(i), -L::cy(i), -L::cz(i));
         const S e = Codec<S>::enc(neq, dm.ds, L::shell(i));
-        mv[(size_t)(i - 1) * St + dst] = e;
+        sto(mv + (size_t)(i - 1) * St, nb.at(-L::cx(i), -L::cy(i), -L::cz(i)), e);
         moved += T0(Codec<S>::dec(e, dm.ds, L::shell(i)));
     }
     // rest population: the site's density minus the stored moving ones
-    rest_plane(A)[i0] = T0(r) - moved;
+    sto(rest_plane(A) + o, i0, T0(r) - moved);
 }
 
 // ---------------------------------------------------------------------------
@@ -344,26 +418,27 @@ __global__ void __launch_bounds__(256) k_moments(const Domain* __restrict__ tab,
         const Domain& dm = tab[w.dom];
         const Geom g = dm.g;
         const long long o = dm.off, St = g.S;
-        const long long i0 = o + sidx(g, w.x, w.y, w.z);
+        const NbP nb = make_nbp(g, w.x, w.y, w.z);
+        const unsigned i0 = nb.i0;
         // density accumulated at the rest plane's precision (the conserved sum)
         using T0 = typename RestOf<S>::T;
-        T0 racc = rest_plane(A)[i0];
+        T0 racc = ldo(rest_plane(A) + o, i0);
         R jx = R(0), jy = R(0), jz = R(0);
-        const S* mv = moving_planes(A, St);
+        const S* const mv = moving_planes(A, St) + o;
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
-            const long long src = o + nbr(g, w.x, w.y, w.z, -L::cx(i), -L::cy(i), -L::cz(i));
-            const R v = Codec<S>::dec(mv[(size_t)(i - 1) * St + src], dm.ds, L::shell(i));
+            const R v = Codec<S>::dec(ldo(mv + (size_t)(i - 1) * St, nb.at(-L::cx(i), -L::cy(i), -L::cz(i))),
+                                      dm.ds, L::shell(i));
             racc += T0(v);
             if (L::cx(i)) jx += R(L::cx(i)) * v;
             if (L::cy(i)) jy += R(L::cy(i)) * v;
             if (L::cz(i)) jz += R(L::cz(i)) * v;
         }
         const R r = R(racc);
-        rho[i0] = r;
-        j0[i0] = jx;
-        j0[St + i0] = jy;
-        if (L::D == 3) j0[2 * St + i0] = jz;
+        sto(rho + o, i0, r);
+        sto(j0 + o, i0, jx);
+        sto(j0 + o + St, i0, jy);
+        if (L::D == 3) sto(j0 + o + 2 * St, i0, jz);
         if (!(r > R(0) && r < R(1e30))) atomicOr(flags, 1);
         m[0] = (double)racc; m[1] = jx; m[2] = jy; m[3] = jz;
     }
@@ -401,6 +476,8 @@ struct IterCtl {
     int* done_at;
     int stride;
     double tol;                  // < 0: never stop early (fixed count)
+    const double* omega;         // Chebyshev weights [dom*stride + pass], or null (plain)
+    double* part;                // per-block maxima (block_max_part)
 };
 
 // ---------------------------------------------------------------------------
@@ -415,7 +492,7 @@ __global__ void __launch_bounds__(256) k_force(const Domain* __restrict__ tab,
                                                R* __restrict__ f, R* __restrict__ j0p,
                                                R* __restrict__ u, const R* jt_prevA,
                                                const R* jt_prevB, const SolveInfo* prev_info,
-                                               R* jt0)
+                                               R* jt0, R* __restrict__ pf)
 {
     using L = Lattice<Q>;
     const Where w = locate(tab, tiles);
@@ -423,12 +500,19 @@ __global__ void __launch_bounds__(256) k_force(const Domain* __restrict__ tab,
     double amax = 0.0;
     if (w.ok) {
         const Domain& dm = tab[w.dom];
-        const Geom g = dm.g;
-        const long long o = dm.off, St = g.S;
-        const int x = w.x, y = w.y, z = w.z;
-        const long long i0 = o + sidx(g, x, y, z);
-        const R r = rho[i0];
-        auto RH = [&](int dx, int dy, int dz) { return rho[o + nbr(g, x, y, z, dx, dy, dz)]; };
+        const long long o = dm.off, St = dm.g.S;
+        const Nb2 nb = make_nb2(dm.g, w.x, w.y, w.z);
+        const unsigned i0 = nb.i0;
+        const R* const rh = rho + o;
+        const R r = ldo(rh, i0);
+        // rho at i0 + (dx, dy, dz) with |d| <= 2 along at most two axes
+        auto RH = [&](int dx, int dy, int dz) {
+            int t = 0;
+            if (dx) t += nb.o[0][dx < 0 ? dx + 2 : dx + 1];
+            if (dy) t += nb.o[1][dy < 0 ? dy + 2 : dy + 1];
+            if (dz) t += nb.o[2][dz < 0 ? dz + 2 : dz + 1];
+            return ldo(rh, i0 + (unsigned)t);
+        };
         R fa[3] = {R(0), R(0), R(0)};
         if constexpr (L::D == 3) {
             // (100): tau -3 ; (110): tau 1/2 ; (200): tau 1/4 (Table III)
@@ -455,22 +539,31 @@ __global__ void __launch_bounds__(256) k_force(const Domain* __restrict__ tab,
         }
         const R kr = R(dm.cf.kappa) * r;
         const R inv = R(1) / r;
+        // rho is fixed during the iteration: its EOS terms and 1/rho are
+        // evaluated once here (planes p, P1 = p - rho p', 1/rho)
+        {
+            const EosVal<R> e = eos_all<R>(dm.cf.eos, r);
+            R* const pfo = pf + o;
+            sto(pfo, i0, e.p);
+            sto(pfo + St, i0, e.P1);
+            sto(pfo + 2 * St, i0, inv);
+        }
         // warm start: the previous step's final iterate of this domain
         const R* prev = nullptr;
         if (prev_info) prev = prev_info[w.dom].final_buf ? jt_prevB : jt_prevA;
 #pragma unroll
         for (int a = 0; a < L::D; ++a) {
             const R fv = kr * fa[a];
-            const R jp = j0[a * St + i0] + R(0.5) * fv;
-            const R jt = prev ? prev[a * St + i0] : R(0);
-            f[a * St + i0] = fv;
-            j0p[a * St + i0] = jp;
-            jt0[a * St + i0] = jt;
-            u[a * St + i0] = (jp + jt) * inv;
+            const R jp = ldo(j0 + o + a * St, i0) + R(0.5) * fv;
+            const R jt = prev ? ldo(prev + o + a * St, i0) : R(0);
+            sto(f + o + a * St, i0, fv);
+            sto(j0p + o + a * St, i0, jp);
+            sto(jt0 + o + a * St, i0, jt);
+            sto(u + o + a * St, i0, (jp + jt) * inv);
             amax = fmax(amax, fabs((double)jp));
         }
     }
-    block_max_to(ic.jscale + w.dom, amax);
+    block_max_part(ic.part, amax);
 }
 
 __device__ __forceinline__ bool iter_skip(const IterCtl& c, int dom, int it)
@@ -494,7 +587,7 @@ __device__ __forceinline__ bool iter_skip(const IterCtl& c, int dom, int it)
 template <int Q, class R>
 __global__ void __launch_bounds__(256) k_iter_q(const Domain* __restrict__ tab,
                                                 const Tile* __restrict__ tiles, IterCtl ic, int it,
-                                                const R* __restrict__ rho, const R* __restrict__ u,
+                                                const R* __restrict__ pf, const R* __restrict__ u,
                                                 R* __restrict__ q)
 {
     using L = Lattice<Q>;
@@ -502,65 +595,85 @@ __global__ void __launch_bounds__(256) k_iter_q(const Domain* __restrict__ tab,
     const Where w = locate(tab, tiles);
     if (w.dom < 0 || iter_skip(ic, w.dom, it) || !w.ok) return;
     const Domain& dm = tab[w.dom];
-    const Geom g = dm.g;
-    const long long o = dm.off, St = g.S;
-    const long long i0 = o + sidx(g, w.x, w.y, w.z);
+    const long long o = dm.off, St = dm.g.S;
+    const Nb2 nb = make_nb2(dm.g, w.x, w.y, w.z);
     R G[3][3];
 #pragma unroll
     for (int a = 0; a < D; ++a)
 #pragma unroll
-        for (int b = 0; b < D; ++b) G[a][b] = d1_field<R>(g, u + b * St + o, w.x, w.y, w.z, a);
+        for (int b = 0; b < D; ++b) G[a][b] = d1_nb<R>(u + o + b * St, nb, a);
     R trG = R(0);
 #pragma unroll
     for (int a = 0; a < D; ++a) trG += G[a][a];
-    const EosVal<R> e = eos_all<R>(dm.cf.eos, rho[i0]);
+    const R p = ldo(pf + o, nb.i0), P1 = ldo(pf + o + St, nb.i0);
 #pragma unroll
     for (int a = 0; a < D; ++a)
 #pragma unroll
         for (int b = a; b < D; ++b) {
-            R v = e.p * (G[a][b] + G[b][a]);
-            if (a == b) v += e.P1 * trG;
-            q[sym2<D>(a, b) * St + i0] = v;
+            R v = p * (G[a][b] + G[b][a]);
+            if (a == b) v += P1 * trG;
+            sto(q + o + sym2<D>(a, b) * St, nb.i0, v);
         }
+}
+
+// Next iterate from the map's value g = G(x_k) at one site.  Plain fixed
+// point (Sec. IX): x_{k+1} = g.  Chebyshev semi-iteration on the same map
+// (its linear part is similar to a symmetric positive semi-definite operator,
+// so the spectrum is real in [0, b]): with gamma = 2/(2-b),
+// x_{k+1} = x_{k-1} + omega_k (gamma g + (1-gamma) x_k - x_{k-1}), omega_0 = 1.
+// The stop rule tests |g - x_k| in both cases.
+template <class R>
+__device__ __forceinline__ R next_iterate(R g, R xk, R xkm1, R omega, R gam, bool first)
+{
+    const R y = gam * g + (R(1) - gam) * xk;
+    return first ? y : xkm1 + omega * (y - xkm1);
 }
 
 // ---------------------------------------------------------------------------
 // Item 5: j~new_a = -(1/12) d_b q_ab; item 6 residual; item 3 of the next
-// pass: u = (j0' + j~new)/rho.
+// pass: u = (j0' + j~new)/rho.  With the Chebyshev solver jt_prev holds
+// x_{k-1} and is overwritten in place by x_{k+1} (jt_prev == jt_new).
 // ---------------------------------------------------------------------------
 template <int Q, class R>
 __global__ void __launch_bounds__(256) k_iter_jt(const Domain* __restrict__ tab,
                                                  const Tile* __restrict__ tiles, IterCtl ic, int it,
-                                                 const R* __restrict__ rho, const R* __restrict__ q,
+                                                 const R* __restrict__ pf, const R* __restrict__ q,
                                                  const R* __restrict__ j0p,
                                                  const R* __restrict__ jt_old,
-                                                 R* __restrict__ jt_new, R* __restrict__ u)
+                                                 R* jt_new, R* __restrict__ u)
 {
     using L = Lattice<Q>;
     constexpr int D = L::D;
     const Where w = locate(tab, tiles);
     if (w.dom < 0) return;
     if (*((volatile int*)(ic.done_at + w.dom)) >= 0) return;   // uniform per block
-    double dmax = 0.0;
+    double dmax = 0.0, dsum = 0.0;   // dsum only carries a NaN (fmax drops it)
     if (w.ok) {
         const Domain& dm = tab[w.dom];
-        const Geom g = dm.g;
-        const long long o = dm.off, St = g.S;
-        const long long i0 = o + sidx(g, w.x, w.y, w.z);
-        const R inv = R(1) / rho[i0];
+        const long long o = dm.off, St = dm.g.S;
+        const Nb2 nb = make_nb2(dm.g, w.x, w.y, w.z);
+        const unsigned i0 = nb.i0;
+        const R inv = ldo(pf + o + 2 * St, i0);
+        const bool cheb = ic.omega != nullptr;
+        const R omega = cheb ? R(ic.omega[(long long)w.dom * ic.stride + it]) : R(1);
+        const R gam = cheb ? R(dm.cf.cheb_gamma) : R(1);
 #pragma unroll
         for (int a = 0; a < D; ++a) {
             R acc = R(0);
 #pragma unroll
-            for (int b = 0; b < D; ++b)
-                acc += d1_field<R>(g, q + sym2<D>(a, b) * St + o, w.x, w.y, w.z, b);
-            const R jn = -acc * R(1.0 / 12.0);
-            dmax = fmax(dmax, fabs((double)(jn - jt_old[a * St + i0])));
-            jt_new[a * St + i0] = jn;
-            u[a * St + i0] = (j0p[a * St + i0] + jn) * inv;
+            for (int b = 0; b < D; ++b) acc += d1_nb<R>(q + o + sym2<D>(a, b) * St, nb, b);
+            const R gv = -acc * R(1.0 / 12.0);
+            const R xk = ldo(jt_old + o + a * St, i0);
+            const double d = fabs((double)(gv - xk));
+            dmax = fmax(dmax, d);
+            dsum += d;
+            R xn = gv;
+            if (cheb) xn = next_iterate<R>(gv, xk, it > 0 ? ldo<R>(jt_new + o + a * St, i0) : R(0), omega, gam, it == 0);
+            sto(jt_new + o + a * St, i0, xn);
+            sto(u + o + a * St, i0, (ldo(j0p + o + a * St, i0) + xn) * inv);
         }
     }
-    block_max_to(ic.res + (long long)w.dom * ic.stride + it, dmax);
+    block_max_part(ic.part, dsum == dsum ? dmax : dsum);
 }
 
 // One thread per domain.
@@ -603,7 +716,7 @@ template <int Q, class R>
 __global__ void __launch_bounds__(256) k_closure1(const Domain* __restrict__ tab,
                                                   const Tile* __restrict__ tiles,
                                                   const SolveInfo* __restrict__ info,
-                                                  const R* __restrict__ rho, const R* __restrict__ u,
+                                                  const R* __restrict__ pf, const R* __restrict__ u,
                                                   const R* __restrict__ jtA, const R* __restrict__ jtB,
                                                   R* __restrict__ X, R* __restrict__ T,
                                                   R* __restrict__ Y, R* __restrict__ Xi)
@@ -613,30 +726,27 @@ __global__ void __launch_bounds__(256) k_closure1(const Domain* __restrict__ tab
     const Where w = locate(tab, tiles);
     if (!w.ok) return;
     const Domain& dm = tab[w.dom];
-    const Geom g = dm.g;
-    const long long o = dm.off, St = g.S;
-    const int x = w.x, y = w.y, z = w.z;
-    const long long i0 = o + sidx(g, x, y, z);
-    const R* jt = info[w.dom].final_buf ? jtB : jtA;
+    const long long o = dm.off, St = dm.g.S;
+    const Nb2 nb = make_nb2(dm.g, w.x, w.y, w.z);
+    const unsigned i0 = nb.i0;
+    const R* jt = (info[w.dom].final_buf ? jtB : jtA) + o;
+    const R* const pp = pf + o;            // p
+    const R* const pri = pf + o + 2 * St;  // 1/rho
+    const R* const uo = u + o;
 
     R G[3][3] = {};    // d_a u_b
     R M[3][3][3] = {}; // d_a (p u_b u_g)
-    R Pg[3] = {}, C[3] = {};  // d_a p, d_a (p/rho)
+    R Pg[3] = {}, C[3] = {};  // d_a p, d_a (p/rho) with p/rho = c_s^2
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        int dx, dy, dz;
-        unit(a, dx, dy, dz);
         R pv[4], cv[4], uv[4][3];
-        const int off[4] = {-2, -1, 1, 2};
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const long long t = o + nbr(g, x, y, z, off[k] * dx, off[k] * dy, off[k] * dz);
-            const R rt = rho[t];
-            const R cs2 = eos_cs2<R>(dm.cf.eos, rt);
-            cv[k] = cs2;
-            pv[k] = rt * cs2;
+            const unsigned t = nb.i0 + nb.o[a][k];
+            pv[k] = ldo(pp, t);
+            cv[k] = pv[k] * ldo(pri, t);
 #pragma unroll
-            for (int b = 0; b < D; ++b) uv[k][b] = u[b * St + t];
+            for (int b = 0; b < D; ++b) uv[k][b] = ldo(uo + b * St, t);
         }
         Pg[a] = d1<R>(pv[0], pv[1], pv[2], pv[3]);
         C[a] = d1<R>(cv[0], cv[1], cv[2], cv[3]);
@@ -652,27 +762,25 @@ __global__ void __launch_bounds__(256) k_closure1(const Domain* __restrict__ tab
             }
         }
     }
-    const R r = rho[i0];
-    const EosVal<R> e = eos_all<R>(dm.cf.eos, r);
+    const R ep = ldo(pp, i0), eP1 = ldo(pf + o + St, i0), inv = ldo(pri, i0);
     R us[3] = {R(0), R(0), R(0)};
 #pragma unroll
-    for (int a = 0; a < D; ++a) us[a] = u[a * St + i0];
+    for (int a = 0; a < D; ++a) us[a] = ldo(uo + a * St, i0);
     R trG = R(0);
 #pragma unroll
     for (int a = 0; a < D; ++a) trG += G[a][a];
 
-    X[i0] = e.P1 * trG;
+    sto(X + o, i0, eP1 * trG);
 #pragma unroll
     for (int a = 0; a < D; ++a)
 #pragma unroll
-        for (int c = a; c < D; ++c) T[sym2<D>(a, c) * St + i0] = e.p * (G[a][c] + G[c][a]);
-    const R inv = R(1) / r;
+        for (int c = a; c < D; ++c) sto(T + o + sym2<D>(a, c) * St, i0, ep * (G[a][c] + G[c][a]));
 #pragma unroll
     for (int b = 0; b < D; ++b) {
         R acc = Pg[b] * inv;
 #pragma unroll
         for (int c = 0; c < D; ++c) acc += us[c] * G[c][b];
-        Y[b * St + i0] = acc;
+        sto(Y + o + b * St, i0, acc);
     }
 
     const R gm = R(dm.cf.gamma);
@@ -680,10 +788,10 @@ __global__ void __launch_bounds__(256) k_closure1(const Domain* __restrict__ tab
     const R KJ = (R(1) - gm) * R(dm.cf.c0sq);
     R jts[3] = {R(0), R(0), R(0)};
 #pragma unroll
-    for (int a = 0; a < D; ++a) jts[a] = jt[a * St + i0];
+    for (int a = 0; a < D; ++a) jts[a] = ldo(jt + a * St, i0);
     R V[3];
 #pragma unroll
-    for (int a = 0; a < D; ++a) V[a] = e.p * C[a] + e.P1 * us[a] * trG;
+    for (int a = 0; a < D; ++a) V[a] = ep * C[a] + eP1 * us[a] * trG;
 #pragma unroll
     for (int a = 0; a < D; ++a)
 #pragma unroll
@@ -695,7 +803,7 @@ __global__ void __launch_bounds__(256) k_closure1(const Domain* __restrict__ tab
                 if (a == b) { br += V[c]; dj += jts[c]; }
                 if (a == c) { br += V[b]; dj += jts[b]; }
                 if (b == c) { br += V[a]; dj += jts[a]; }
-                Xi[sym3<D>(a, b, c) * St + i0] = KX * br + KJ * dj;
+                sto(Xi + o + sym3<D>(a, b, c) * St, i0, KX * br + KJ * dj);
             }
 }
 
@@ -715,37 +823,35 @@ __global__ void __launch_bounds__(256) k_closure2(const Domain* __restrict__ tab
     const Where w = locate(tab, tiles);
     if (!w.ok) return;
     const Domain& dm = tab[w.dom];
-    const Geom g = dm.g;
-    const long long o = dm.off, St = g.S;
-    const int x = w.x, y = w.y, z = w.z;
-    const long long i0 = o + sidx(g, x, y, z);
+    const long long o = dm.off, St = dm.g.S;
+    const Nb2 nb = make_nb2(dm.g, w.x, w.y, w.z);
+    const unsigned i0 = nb.i0;
+    const R* const rh = rho + o;
+    const R* const uo = u + o;
     R DX[3] = {}, DT[3] = {}, DY[3][3] = {}, G[3][3] = {};
     R trJ = R(0);
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        DX[a] = d1_field<R>(g, X + o, x, y, z, a);
+        DX[a] = d1_nb<R>(X + o, nb, a);
 #pragma unroll
-        for (int c = 0; c < D; ++c) DT[a] += d1_field<R>(g, T + sym2<D>(a, c) * St + o, x, y, z, c);
+        for (int c = 0; c < D; ++c) DT[a] += d1_nb<R>(T + o + sym2<D>(a, c) * St, nb, c);
 #pragma unroll
-        for (int b = 0; b < D; ++b) DY[a][b] = d1_field<R>(g, Y + b * St + o, x, y, z, a);
-        int dx, dy, dz;
-        unit(a, dx, dy, dz);
+        for (int b = 0; b < D; ++b) DY[a][b] = d1_nb<R>(Y + o + b * St, nb, a);
         R jv[4];
-        const int off[4] = {-2, -1, 1, 2};
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const long long t = o + nbr(g, x, y, z, off[k] * dx, off[k] * dy, off[k] * dz);
-            jv[k] = rho[t] * u[a * St + t];
+            const unsigned t = i0 + nb.o[a][k];
+            jv[k] = ldo(rh, t) * ldo(uo + a * St, t);
         }
         trJ += d1<R>(jv[0], jv[1], jv[2], jv[3]);
 #pragma unroll
-        for (int b = 0; b < D; ++b) G[a][b] = d1_field<R>(g, u + b * St + o, x, y, z, a);
+        for (int b = 0; b < D; ++b) G[a][b] = d1_nb<R>(uo + b * St, nb, a);
     }
-    const R r = rho[i0];
+    const R r = ldo(rh, i0);
     const EosVal<R> e = eos_all<R>(dm.cf.eos, r);
     R us[3] = {R(0), R(0), R(0)};
 #pragma unroll
-    for (int a = 0; a < D; ++a) us[a] = u[a * St + i0];
+    for (int a = 0; a < D; ++a) us[a] = ldo(uo + a * St, i0);
     R trG = R(0), trDY = R(0);
 #pragma unroll
     for (int a = 0; a < D; ++a) { trG += G[a][a]; trDY += DY[a][a]; }
@@ -759,7 +865,7 @@ __global__ void __launch_bounds__(256) k_closure2(const Domain* __restrict__ tab
             const R br1 = us[a] * DX[b] + us[b] * DX[a] + us[b] * DT[a] + us[a] * DT[b];
             R br2 = -e.dp * trJ * (G[a][b] + G[b][a]) - e.p * (DY[a][b] + DY[b][a]);
             if (a == b) br2 += -e.P1 * trDY + e.P2 * trG * trJ;
-            Sig[sym2<D>(a, b) * St + i0] = KS1 * br1 + KS2 * br2;
+            sto(Sig + o + sym2<D>(a, b) * St, i0, KS1 * br1 + KS2 * br2);
         }
 }
 
@@ -785,23 +891,23 @@ __global__ void __launch_bounds__(256) k_collide(const Domain* __restrict__ tab,
     const Domain& dm = tab[w.dom];
     const Geom g = dm.g;
     const long long o = dm.off, St = g.S;
-    const int x = w.x, y = w.y, z = w.z;
-    const long long i0 = o + sidx(g, x, y, z);
-    const R* jt = info[w.dom].final_buf ? jtB : jtA;
+    const NbP nb = make_nbp(g, w.x, w.y, w.z);
+    const unsigned i0 = nb.i0;
+    const R* jt = (info[w.dom].final_buf ? jtB : jtA) + o;
 
-    const R r = rho[i0];
+    const R r = ldo(rho + o, i0);
     R us[3] = {R(0), R(0), R(0)}, fs[3] = {R(0), R(0), R(0)}, js[3] = {R(0), R(0), R(0)};
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        us[a] = u[a * St + i0];
-        fs[a] = f[a * St + i0];
-        js[a] = jt[a * St + i0];
+        us[a] = ldo(u + o + a * St, i0);
+        fs[a] = ldo(f + o + a * St, i0);
+        js[a] = ldo(jt + a * St, i0);
     }
     R Sg[6], Xp[10];
 #pragma unroll
-    for (int k = 0; k < L::NSIG; ++k) Sg[k] = Sig[k * St + i0];
+    for (int k = 0; k < L::NSIG; ++k) Sg[k] = ldo(Sig + o + k * St, i0);
 #pragma unroll
-    for (int k = 0; k < L::NXI; ++k) Xp[k] = Xi[k * St + i0];
+    for (int k = 0; k < L::NXI; ++k) Xp[k] = ldo(Xi + o + k * St, i0);
 
     const R gm = R(dm.cf.gamma);
     const R c0 = R(dm.cf.c0sq);
@@ -840,8 +946,8 @@ __global__ void __launch_bounds__(256) k_collide(const Domain* __restrict__ tab,
     // n*_0 = n_0 - sum_{i>0} (n*_i - n_i), with the n*_i as stored.  This is
     // n_0 + Delta_0 in exact arithmetic; the differences are small, so their
     // rounding is far below that of the populations themselves.
-    const S* amv = moving_planes(A, St);
-    S* bmv = moving_planes(B, St);
+    const S* const amv = moving_planes(A, St) + o;
+    S* const bmv = moving_planes(B, St) + o;
     R dsum = R(0);
 #pragma unroll
     for (int p = 0; p < L::NPAIR; ++p) {
@@ -872,18 +978,16 @@ __global__ void __launch_bounds__(256) k_collide(const Domain* __restrict__ tab,
         const R Wk = R(dm.cf.Wk[k]);
         const R even = wl[k] * (a0 + a2 * uc * uc) + Wk * (kS * cSc + s0);
         const R odd = wl[k] * a1 * uc + Wk * (bc + kX * cXc);
-        const long long sp = o + nbr(g, x, y, z, -cxv, -cyv, -czv);
-        const long long sm = o + nbr(g, x, y, z, cxv, cyv, czv);
-        const R np = Codec<S>::dec(amv[(size_t)(ip - 1) * St + sp], dm.ds, k);
-        const R nm = Codec<S>::dec(amv[(size_t)(im - 1) * St + sm], dm.ds, k);
+        const R np = Codec<S>::dec(ldo(amv + (size_t)(ip - 1) * St, nb.at(-cxv, -cyv, -czv)), dm.ds, k);
+        const R nm = Codec<S>::dec(ldo(amv + (size_t)(im - 1) * St, nb.at(cxv, cyv, czv)), dm.ds, k);
         const S ep = Codec<S>::enc(gm * np + even + odd, dm.ds, k);
         const S em = Codec<S>::enc(gm * nm + even - odd, dm.ds, k);
-        bmv[(size_t)(ip - 1) * St + i0] = ep;
-        bmv[(size_t)(im - 1) * St + i0] = em;
+        sto(bmv + (size_t)(ip - 1) * St, i0, ep);
+        sto(bmv + (size_t)(im - 1) * St, i0, em);
         dsum += (Codec<S>::dec(ep, dm.ds, k) - np) + (Codec<S>::dec(em, dm.ds, k) - nm);
     }
     using T0 = typename RestOf<S>::T;
-    rest_plane(B)[i0] = rest_plane(A)[i0] - T0(dsum);
+    sto(rest_plane(B) + o, i0, ldo(rest_plane(A) + o, i0) - T0(dsum));
 }
 
 // Pre-collision populations of the current state as FP64 [Q][S].
@@ -898,14 +1002,15 @@ __global__ void __launch_bounds__(256) k_export(const Domain* __restrict__ tab,
     const Domain& dm = tab[w.dom];
     const Geom g = dm.g;
     const long long o = dm.off, St = g.S;
-    const long long i0 = o + sidx(g, w.x, w.y, w.z);
-    const S* mv = moving_planes(A, St);
-    out[i0] = (double)rest_plane(A)[i0];
+    const NbP nb = make_nbp(g, w.x, w.y, w.z);
+    const unsigned i0 = nb.i0;
+    const S* const mv = moving_planes(A, St) + o;
+    sto(out + o, i0, (double)ldo(rest_plane(A) + o, i0));
 #pragma unroll
-    for (int i = 1; i < Q; ++i) {
-        const long long src = o + nbr(g, w.x, w.y, w.z, -L::cx(i), -L::cy(i), -L::cz(i));
-        out[(size_t)i * St + i0] = (double)Codec<S>::dec(mv[(size_t)(i - 1) * St + src], dm.ds, L::shell(i));
-    }
+    for (int i = 1; i < Q; ++i)
+        sto(out + o + (size_t)i * St, i0,
+            (double)Codec<S>::dec(ldo(mv + (size_t)(i - 1) * St, nb.at(-L::cx(i), -L::cy(i), -L::cz(i))), dm.ds,
+                                  L::shell(i)));
 }
 
 template <int Q, class S>
@@ -919,15 +1024,15 @@ __global__ void __launch_bounds__(256) k_import(const Domain* __restrict__ tab,
     const Domain& dm = tab[w.dom];
     const Geom g = dm.g;
     const long long o = dm.off, St = g.S;
-    const long long i0 = o + sidx(g, w.x, w.y, w.z);
+    const NbP nb = make_nbp(g, w.x, w.y, w.z);
+    const unsigned i0 = nb.i0;
     using RT = decltype(Codec<S>::dec(S(), dm.ds, 0));
-    S* mv = moving_planes(A, St);
-    rest_plane(A)[i0] = (typename RestOf<S>::T)in[i0];
+    S* const mv = moving_planes(A, St) + o;
+    sto(rest_plane(A) + o, i0, (typename RestOf<S>::T)ldo(in + o, i0));
 #pragma unroll
-    for (int i = 1; i < Q; ++i) {
-        const long long dst = o + nbr(g, w.x, w.y, w.z, -L::cx(i), -L::cy(i), -L::cz(i));
-        mv[(size_t)(i - 1) * St + dst] = Codec<S>::enc((RT)in[(size_t)i * St + i0], dm.ds, L::shell(i));
-    }
+    for (int i = 1; i < Q; ++i)
+        sto(mv + (size_t)(i - 1) * St, nb.at(-L::cx(i), -L::cy(i), -L::cz(i)),
+            Codec<S>::enc((RT)ldo(in + o + (size_t)i * St, i0), dm.ds, L::shell(i)));
 }
 
 // Small helpers.

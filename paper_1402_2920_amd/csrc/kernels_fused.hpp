@@ -7,7 +7,9 @@
 // registers, the last five planes of u at its point (z-derivatives of u) and
 // of q_az (z-derivative in d_b q_ab); LDS holds one u plane (tile + 4-wide
 // frame) and one q plane (tile + 2-wide frame) for the x and y derivatives.
-// Per pass every site reads j~, j0' and rho once from HBM and writes j~new.
+// Per pass every site reads j~, j0' and the per-site planes p, P1, 1/rho
+// (evaluated once per step) once from HBM and writes j~new; the Chebyshev
+// form also reads x_{k-1}, which it overwrites in place.
 #pragma once
 
 #include "kernels.hpp"
@@ -31,34 +33,61 @@ __device__ __forceinline__ int wrapmod(int v, int n)
     return v < 0 ? v + n : v;
 }
 
-template <class R, int TX, int TY>
+// Element i of a component plane: a uniform base plus a 32-bit byte offset
+// (the host keeps one plane of a domain under 4 GiB for this kernel), which
+// lets loads use the scalar-base addressing form instead of 64-bit VALU math.
+template <class R>
+__device__ __forceinline__ R ld(const R* base, unsigned i)
+{
+    return *reinterpret_cast<const R*>(reinterpret_cast<const char*>(base) + i * (unsigned)sizeof(R));
+}
+template <class R>
+__device__ __forceinline__ void st(R* base, unsigned i, R v)
+{
+    *reinterpret_cast<R*>(reinterpret_cast<char*>(base) + i * (unsigned)sizeof(R)) = v;
+}
+
+template <class R, int TX, int TY, bool CHEB>
 __global__ void __launch_bounds__((TX + 4) * (TY + 4))
 k_iter_fused3(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, IterCtl ic, int it,
-              const R* __restrict__ rho, const R* __restrict__ j0p, const R* __restrict__ jt_old,
-              R* __restrict__ jt_new)
+              const R* __restrict__ pf, const R* __restrict__ j0p, const R* __restrict__ jt_old,
+              R* jt_new)
 {
     constexpr int QX = TX + 4, QY = TY + 4;   // q points
     constexpr int UX = TX + 8, UY = TY + 8;   // u points
     constexpr int NFRAME = UX * UY - QX * QY;
     static_assert(NFRAME <= QX * QY, "frame larger than the block");
     __shared__ R su[3][UY][UX];
-    __shared__ R sq[6][QY][QX];
+    __shared__ R sq[5][QY][QX];   // q_xx, q_yy, q_xy, q_xz, q_yz (q_zz is only needed along z)
 
     const Tile tl = tiles[blockIdx.x];
     if (tl.dom < 0 || iter_skip(ic, tl.dom, it)) return;   // uniform per block
     const Domain& dm = tab[tl.dom];
-    const Geom g = dm.g;
-    const int nx = g.nx, ny = g.ny, nz = g.nz;
-    const long long N = g.S;   // component stride
-    const long long plane = (long long)nx * ny;
-    // this domain's part of the packed arrays
-    rho += dm.off; j0p += dm.off; jt_old += dm.off; jt_new += dm.off;
-    const Coef& cf = dm.cf;
+    const int nx = dm.g.nx, ny = dm.g.ny, nz = dm.g.nz;
+    const long long N = dm.g.S;   // component stride
+    const unsigned plane = (unsigned)nx * (unsigned)ny;
+    const R* const pP = pf + dm.off;
+    const R* const pP1 = pP + N;
+    const R* const pRi = pP1 + N;
+    const R* const j0x = j0p + dm.off;
+    const R* const j0y = j0x + N;
+    const R* const j0z = j0y + N;
+    const R* const tx_ = jt_old + dm.off;
+    const R* const ty_ = tx_ + N;
+    const R* const tz_ = ty_ + N;
+    R* const ox = jt_new + dm.off;
+    R* const oy = ox + N;
+    R* const oz = oy + N;
+    R omega = R(1), gam = R(1);
+    if (CHEB) {
+        omega = R(ic.omega[(long long)tl.dom * ic.stride + it]);
+        gam = R(dm.cf.cheb_gamma);
+    }
     const int lx = threadIdx.x, ly = threadIdx.y;
     const int tid = lx + QX * ly;
     const int x0 = tl.x0, y0 = tl.y0, z0 = tl.z0, TZ = tl.len;
     const int gx = wrapmod(x0 + lx - 2, nx), gy = wrapmod(y0 + ly - 2, ny);
-    const long long col = gx + (long long)nx * gy;
+    const unsigned col = (unsigned)gx + (unsigned)nx * (unsigned)gy;
     const bool interior = lx >= 2 && lx < TX + 2 && ly >= 2 && ly < TY + 2;
     const bool owned = interior && (x0 + lx - 2 < nx) && (y0 + ly - 2 < ny);
 
@@ -78,77 +107,77 @@ k_iter_fused3(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, It
             fx = c < 2 ? c : UX - 4 + c;
         }
     }
-    const long long fcol = has_frame
-        ? wrapmod(x0 + fx - 4, nx) + (long long)nx * wrapmod(y0 + fy - 4, ny) : 0;
+    const unsigned fcol = has_frame
+        ? (unsigned)wrapmod(x0 + fx - 4, nx) + (unsigned)nx * (unsigned)wrapmod(y0 + fy - 4, ny) : 0u;
 
+    // Five-plane rings, oldest first; each step shifts them by one.  (Rings
+    // addressed by a compile-time phase avoid the moves but need the loop
+    // unrolled five times, which costs registers and, measured, occupancy
+    // and time.)
     R ur[5][3];        // u at planes lead-4 .. lead
-    R rr[3];           // rho at planes lead-2 .. lead
     R qz[5][3];        // q_xz, q_yz, q_zz at planes c-4 .. c
-    R sd[3][3];        // x,y part of d_b q_ab at planes c-2 .. c
+    R sd[5][3];        // x,y part of d_b q_ab at planes c-4 .. c (c-2 .. c used)
 #pragma unroll
     for (int k = 0; k < 5; ++k)
 #pragma unroll
-        for (int a = 0; a < 3; ++a) { ur[k][a] = R(0); qz[k][a] = R(0); }
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        rr[k] = R(1);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) sd[k][a] = R(0);
-    }
-    double dmax = 0.0;
+        for (int a = 0; a < 3; ++a) { ur[k][a] = R(0); qz[k][a] = R(0); sd[k][a] = R(0); }
+    R dmax = R(0), dsum = R(0);   // dsum only carries a NaN (fmax drops it)
     const R c12 = R(1.0 / 12.0);
 
     // one-plane lookahead: the inputs of step k+1 are loaded while step k
-    // computes (own point at the lead plane, frame point at the centre plane)
-    // (raw values are kept: combining them at load time would make the
-    // compiler wait for the loads right away)
-    R nr = R(1), nj[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
-    R fr = R(1), fj[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
-    R no[3] = {R(0), R(0), R(0)};   // j~ at the output plane of that step
+    // computes (raw values are kept: combining them at load time would make
+    // the compiler wait for the loads right away)
+    R nri = R(1), nj[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};   // own point, lead plane
+    R np = R(0), nP1 = R(0);                                       // own point, centre plane
+    R fri = R(1), fj[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};   // frame point, centre plane
+    R no[3] = {R(0), R(0), R(0)};   // x_k at the output plane of that step
+    R nv[3] = {R(0), R(0), R(0)};   // x_{k-1} there (Chebyshev)
     auto load_step = [&](int k) {
         if (k >= 8 && owned && z0 + k - 8 < nz) {
-            const long long io = col + plane * (z0 + k - 8);
-#pragma unroll
-            for (int a = 0; a < 3; ++a) no[a] = jt_old[a * N + io];
+            const unsigned io = col + plane * (unsigned)(z0 + k - 8);
+            no[0] = ld(tx_, io); no[1] = ld(ty_, io); no[2] = ld(tz_, io);
+            if (CHEB && it > 0) { nv[0] = ld<R>(ox, io); nv[1] = ld<R>(oy, io); nv[2] = ld<R>(oz, io); }
         }
-        const long long i = col + plane * wrap3(z0 - 4 + k, nz);
-        nr = rho[i];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) { nj[a] = j0p[a * N + i]; nj[3 + a] = jt_old[a * N + i]; }
+        const unsigned i = col + plane * (unsigned)wrap3(z0 - 4 + k, nz);
+        nri = ld(pRi, i);
+        nj[0] = ld(j0x, i); nj[1] = ld(j0y, i); nj[2] = ld(j0z, i);
+        nj[3] = ld(tx_, i); nj[4] = ld(ty_, i); nj[5] = ld(tz_, i);
+        const unsigned zc = plane * (unsigned)wrap3(z0 - 6 + k, nz);
+        np = ld(pP, col + zc);
+        nP1 = ld(pP1, col + zc);
         if (has_frame) {
-            const long long f = fcol + plane * wrap3(z0 - 6 + k, nz);
-            fr = rho[f];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) { fj[a] = j0p[a * N + f]; fj[3 + a] = jt_old[a * N + f]; }
+            const unsigned f = fcol + zc;
+            fri = ld(pRi, f);
+            fj[0] = ld(j0x, f); fj[1] = ld(j0y, f); fj[2] = ld(j0z, f);
+            fj[3] = ld(tx_, f); fj[4] = ld(ty_, f); fj[5] = ld(tz_, f);
         }
     };
     load_step(0);
+    const int nsteps = TZ + 8;
 
-    for (int k = 0; k < TZ + 8; ++k) {
+    auto body = [&](int k) {
+        constexpr int s0 = 0, s1 = 1, s2 = 2, s3 = 3, s4 = 4;
         // 1. lead plane at this thread's point: u = (j0' + j~)/rho
-        const R r = nr;
+        const R ri = nri;
         const R cur_j[3] = {nj[0] + nj[3], nj[1] + nj[4], nj[2] + nj[5]};
-        const R cur_fr = fr;
+        const R cur_p = np, cur_P1 = nP1;
+        const R cur_fri = fri;
         const R cur_fj[3] = {fj[0] + fj[3], fj[1] + fj[4], fj[2] + fj[5]};
         const R cur_o[3] = {no[0], no[1], no[2]};
-        if (k + 1 < TZ + 8) load_step(k + 1);
-        {
-            const R inv = R(1) / r;
+        const R cur_v[3] = {nv[0], nv[1], nv[2]};
+        if (k + 1 < nsteps) load_step(k + 1);
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
+        for (int s = 0; s < 4; ++s)
 #pragma unroll
-                for (int a = 0; a < 3; ++a) ur[s][a] = ur[s + 1][a];
+            for (int a = 0; a < 3; ++a) ur[s][a] = ur[s + 1][a];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) ur[4][a] = cur_j[a] * inv;
-            rr[0] = rr[1]; rr[1] = rr[2]; rr[2] = r;
-        }
+        for (int a = 0; a < 3; ++a) ur[s4][a] = cur_j[a] * ri;
         // 2. u plane c = lead-2 into LDS: own point and frame point
 #pragma unroll
-        for (int a = 0; a < 3; ++a) su[a][ly + 2][lx + 2] = ur[2][a];
+        for (int a = 0; a < 3; ++a) su[a][ly + 2][lx + 2] = ur[s2][a];
         if (has_frame) {
-            const R inv = R(1) / cur_fr;
 #pragma unroll
-            for (int a = 0; a < 3; ++a) su[a][fy][fx] = cur_fj[a] * inv;
+            for (int a = 0; a < 3; ++a) su[a][fy][fx] = cur_fj[a] * cur_fri;
         }
         __syncthreads();
         // 3. q at plane c
@@ -160,57 +189,57 @@ k_iter_fused3(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, It
                                 su[b][ly + 2][lx + 4]);
                 G[1][b] = d1<R>(su[b][ly][lx + 2], su[b][ly + 1][lx + 2], su[b][ly + 3][lx + 2],
                                 su[b][ly + 4][lx + 2]);
-                G[2][b] = d1<R>(ur[0][b], ur[1][b], ur[3][b], ur[4][b]);
+                G[2][b] = d1<R>(ur[s0][b], ur[s1][b], ur[s3][b], ur[s4][b]);
             }
-            const R trG = G[0][0] + G[1][1] + G[2][2];
-            const EosVal<R> e = eos_all<R>(cf.eos, rr[0]);
-            const R qxx = e.P1 * trG + R(2) * e.p * G[0][0];
-            const R qyy = e.P1 * trG + R(2) * e.p * G[1][1];
-            const R qzz = e.P1 * trG + R(2) * e.p * G[2][2];
-            const R qxy = e.p * (G[0][1] + G[1][0]);
-            const R qxz = e.p * (G[0][2] + G[2][0]);
-            const R qyz = e.p * (G[1][2] + G[2][1]);
-            sq[0][ly][lx] = qxx; sq[1][ly][lx] = qyy; sq[2][ly][lx] = qzz;
-            sq[3][ly][lx] = qxy; sq[4][ly][lx] = qxz; sq[5][ly][lx] = qyz;
+            const R X = cur_P1 * (G[0][0] + G[1][1] + G[2][2]);
+            const R p2 = R(2) * cur_p;
+            const R qxz = cur_p * (G[0][2] + G[2][0]);
+            const R qyz = cur_p * (G[1][2] + G[2][1]);
+            sq[0][ly][lx] = X + p2 * G[0][0];
+            sq[1][ly][lx] = X + p2 * G[1][1];
+            sq[2][ly][lx] = cur_p * (G[0][1] + G[1][0]);
+            sq[3][ly][lx] = qxz;
+            sq[4][ly][lx] = qyz;
 #pragma unroll
             for (int s = 0; s < 4; ++s)
 #pragma unroll
                 for (int a = 0; a < 3; ++a) qz[s][a] = qz[s + 1][a];
-            qz[4][0] = qxz; qz[4][1] = qyz; qz[4][2] = qzz;
+            qz[s4][0] = qxz; qz[s4][1] = qyz; qz[s4][2] = X + p2 * G[2][2];
         }
         __syncthreads();
         // 4. j~new at plane c-2 = z0 + k - 8
         if (k >= 4 && interior) {
-            // x,y part at plane c: sym2 index of (a, x) and (a, y)
             const int px = lx, py = ly;
-            R S[3];
-            // a = x: d_x q_xx + d_y q_xy ; a = y: d_x q_xy + d_y q_yy ; a = z: d_x q_xz + d_y q_yz
-            S[0] = d1<R>(sq[0][py][px - 2], sq[0][py][px - 1], sq[0][py][px + 1], sq[0][py][px + 2]) +
-                   d1<R>(sq[3][py - 2][px], sq[3][py - 1][px], sq[3][py + 1][px], sq[3][py + 2][px]);
-            S[1] = d1<R>(sq[3][py][px - 2], sq[3][py][px - 1], sq[3][py][px + 1], sq[3][py][px + 2]) +
-                   d1<R>(sq[1][py - 2][px], sq[1][py - 1][px], sq[1][py + 1][px], sq[1][py + 2][px]);
-            S[2] = d1<R>(sq[4][py][px - 2], sq[4][py][px - 1], sq[4][py][px + 1], sq[4][py][px + 2]) +
-                   d1<R>(sq[5][py - 2][px], sq[5][py - 1][px], sq[5][py + 1][px], sq[5][py + 2][px]);
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                sd[0][a] = sd[1][a];
-                sd[1][a] = sd[2][a];
-                sd[2][a] = S[a];
-            }
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) sd[s][a] = sd[s + 1][a];
+            // a = x: d_x q_xx + d_y q_xy ; a = y: d_x q_xy + d_y q_yy ; a = z: d_x q_xz + d_y q_yz
+            sd[s4][0] = d1<R>(sq[0][py][px - 2], sq[0][py][px - 1], sq[0][py][px + 1], sq[0][py][px + 2]) +
+                        d1<R>(sq[2][py - 2][px], sq[2][py - 1][px], sq[2][py + 1][px], sq[2][py + 2][px]);
+            sd[s4][1] = d1<R>(sq[2][py][px - 2], sq[2][py][px - 1], sq[2][py][px + 1], sq[2][py][px + 2]) +
+                        d1<R>(sq[1][py - 2][px], sq[1][py - 1][px], sq[1][py + 1][px], sq[1][py + 2][px]);
+            sd[s4][2] = d1<R>(sq[3][py][px - 2], sq[3][py][px - 1], sq[3][py][px + 1], sq[3][py][px + 2]) +
+                        d1<R>(sq[4][py - 2][px], sq[4][py - 1][px], sq[4][py + 1][px], sq[4][py + 2][px]);
             const int zo = z0 + k - 8;
             if (k >= 8 && owned && zo < z0 + TZ && zo < nz) {
-                const long long i = col + plane * zo;
+                const unsigned i = col + plane * (unsigned)zo;
+                R xn[3];
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    const R dz = d1<R>(qz[0][a], qz[1][a], qz[3][a], qz[4][a]);
-                    const R jn = -(sd[0][a] + dz) * c12;
-                    dmax = fmax(dmax, fabs((double)(jn - cur_o[a])));
-                    jt_new[a * N + i] = jn;
+                    const R dz = d1<R>(qz[s0][a], qz[s1][a], qz[s3][a], qz[s4][a]);
+                    const R gv = -(sd[s2][a] + dz) * c12;
+                    const R d = fabs(gv - cur_o[a]);
+                    dmax = fmax(dmax, d);
+                    dsum += d;
+                    xn[a] = CHEB ? next_iterate<R>(gv, cur_o[a], cur_v[a], omega, gam, it == 0) : gv;
                 }
+                st(ox, i, xn[0]); st(oy, i, xn[1]); st(oz, i, xn[2]);
             }
         }
-    }
-    block_max_to(ic.res + (long long)tl.dom * ic.stride + it, dmax);
+    };
+    for (int k = 0; k < nsteps; ++k) body(k);
+    block_max_part(ic.part, dsum == dsum ? (double)dmax : (double)dsum);
 }
 
 // u = (j0' + j~)/rho for the final iterate (item 8).

@@ -93,6 +93,8 @@ lb2p_status check_params(const lb2p_params& p)
     if (!(p.kappa >= 0.0) || !(p.tol >= 0.0) || p.max_iter <= 0 || p.fixed_iter < 0)
         return LB2P_EINVAL;
     if (p.graph_steps < 0) return LB2P_EINVAL;
+    if (p.solver != LB2P_SOLVER_FIXED_POINT && p.solver != LB2P_SOLVER_CHEBYSHEV) return LB2P_EINVAL;
+    if (!(p.spectral_bound >= 0.0 && p.spectral_bound < 1.0)) return LB2P_EINVAL;
     if (!(p.rho0 > 0.0)) return LB2P_EINVAL;
     if ((long long)p.nx * p.ny * p.nz > (1LL << 31)) return LB2P_EINVAL;
     return p.lattice == LB2P_D3Q59 ? check_eos<59>(p) : check_eos<21>(p);
@@ -110,6 +112,30 @@ void set_devscale(DevScale& ds, int Q, const EosParams& eos, double rref)
         ds.scl[k] = (float)wk;
         ds.inv[k] = (float)(1.0 / wk);
     }
+}
+
+// Upper bound of the spectrum of the j~ map's linear part,
+// M = (1/12) Grad^T C Grad diag(1/rho) with C: G -> P1 tr(G) I + p (G + G^T).
+// For a plane wave its largest eigenvalue is |s|^2 (2p + P1) / (12 rho) =
+// |s|^2 c_s^2 (2 - rho psi) / 12 (longitudinal) or |s|^2 c_s^2 / 12
+// (transverse), |s|^2 <= d * max_k s(k)^2 with s(k) the symbol of the
+// first-derivative stencil (Sec. IV B); 5% margin for non-uniform rho.
+double spectral_bound_from_eos(int D, const EosParams& e, const lb2p_eos& in)
+{
+    double smax = 0.0;
+    for (int k = 0; k <= 4000; ++k) {
+        const double t = kPi * k / 4000.0;
+        const double sv = (4.0 / 3.0) * std::sin(t) - (1.0 / 6.0) * std::sin(2.0 * t);
+        smax = std::fmax(smax, sv * sv);
+    }
+    double m = 0.0;
+    for (int k = 0; k <= 4000; ++k) {
+        const double r = e.rho1 + (e.rho3 - e.rho1) * k / 4000.0;
+        const double psi = (r > e.rho1 && r < e.rho3) ? in.A * std::sin((r - e.rho1) * e.inv_delta_pi) : 0.0;
+        const double cs2 = eos_cs2<double>(e, r);
+        m = std::fmax(m, cs2 * std::fmax(2.0 - r * psi, 1.0));
+    }
+    return 1.05 * D * smax * m / 12.0;
 }
 
 // Tile-shape choices remembered per (lattice, storage, domain sizes).
@@ -142,6 +168,8 @@ struct lb2p_ctx {
     void* rho = nullptr; void* j0 = nullptr; void* f = nullptr; void* j0p = nullptr;
     void* u = nullptr; void* jt0 = nullptr; void* jt1 = nullptr; void* q = nullptr;
     void* X = nullptr; void* T = nullptr; void* Y = nullptr; void* Xi = nullptr; void* Sig = nullptr;
+    void* pf = nullptr;          // p, P1, 1/rho planes (fixed during the j~ solve)
+    double* omega = nullptr;     // Chebyshev weights [ndom][stride], or null
     // tiles
     int bx = 64, by = 4, tz = 32;
     std::vector<Tile> site_host, fused_host;   // launch order
@@ -150,6 +178,10 @@ struct lb2p_ctx {
     size_t site_cap = 0, fused_cap = 0;
     double* partial = nullptr;
     size_t partial_cap = 0;
+    double* pmax = nullptr;                    // per-block maxima
+    size_t pmax_cap = 0;
+    int* site_range = nullptr;                 // [ndom+1] tile ranges per domain (domain order)
+    int* fused_range = nullptr;
     // stop-rule state
     int stride = 0;                            // passes per domain in res
     void* scratch = nullptr;
@@ -283,7 +315,10 @@ void free_graphs(lb2p_ctx* c)
 lb2p_status build_tiles(lb2p_ctx* c)
 {
     std::vector<Tile> site, fused;
+    std::vector<int> srange(c->ndom + 1, 0), frange(c->ndom + 1, 0);
     for (int d = 0; d < c->ndom; ++d) {
+        srange[d] = (int)site.size();
+        frange[d] = (int)fused.size();
         const Geom& g = c->dom[d].g;
         for (int z = 0; z < g.nz; ++z)
             for (int y = 0; y < g.ny; y += c->by)
@@ -303,6 +338,8 @@ lb2p_status build_tiles(lb2p_ctx* c)
                     }
         }
     }
+    srange[c->ndom] = (int)site.size();
+    frange[c->ndom] = (int)fused.size();
     c->site_host = deal_xcd(site);
     c->fused_host = fused.empty() ? fused : deal_xcd(fused);
     auto upload = [&](const std::vector<Tile>& h, Tile*& dptr, size_t& cap) -> lb2p_status {
@@ -327,6 +364,22 @@ lb2p_status build_tiles(lb2p_ctx* c)
         if (hipMalloc((void**)&c->partial, np * sizeof(double)) != hipSuccess) return LB2P_ENOMEM;
         c->partial_cap = np;
     }
+    const size_t nm = std::max(c->site_host.size(), c->fused_host.size());
+    if (nm > c->pmax_cap) {
+        if (c->pmax) (void)hipFree(c->pmax);
+        c->pmax = nullptr;
+        if (hipMalloc((void**)&c->pmax, nm * sizeof(double)) != hipSuccess) return LB2P_ENOMEM;
+        c->pmax_cap = nm;
+    }
+    if (!c->site_range) {
+        if (hipMalloc((void**)&c->site_range, (c->ndom + 1) * sizeof(int)) != hipSuccess ||
+            hipMalloc((void**)&c->fused_range, (c->ndom + 1) * sizeof(int)) != hipSuccess)
+            return LB2P_ENOMEM;
+    }
+    HIPCHK(hipMemcpyAsync(c->site_range, srange.data(), (c->ndom + 1) * sizeof(int), hipMemcpyHostToDevice,
+                          c->stream));
+    HIPCHK(hipMemcpyAsync(c->fused_range, frange.data(), (c->ndom + 1) * sizeof(int), hipMemcpyHostToDevice,
+                          c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     free_graphs(c);
     return LB2P_OK;
@@ -364,14 +417,16 @@ struct Impl {
                            dim3(256), 0, c->stream, c->res, nres, c->jscale, c->done_at, c->ndom,
                            c->nconv);
         launch_moments(c, true);
-        IterCtl ic{c->res, c->jscale, c->done_at, c->stride, p.fixed_iter > 0 ? -1.0 : p.tol};
+        IterCtl ic{c->res, c->jscale, c->done_at, c->stride, p.fixed_iter > 0 ? -1.0 : p.tol, c->omega, c->pmax};
         {
             ProfScope _ps(c, LB2P_K_FORCE);
             const SolveInfo* prev = (p.warm_start && c->have_prev) ? c->info : nullptr;
             hipLaunchKernelGGL((k_force<Q, R>), sgrid(c), sblock(c), 0, c->stream, c->dtab,
                                c->site_tiles, ic, (const R*)c->rho, (const R*)c->j0, (R*)c->f,
                                (R*)c->j0p, (R*)c->u, (const R*)c->jt0, (const R*)c->jt1, prev,
-                               (R*)c->jt0);
+                               (R*)c->jt0, (R*)c->pf);
+            hipLaunchKernelGGL(k_reduce_max, dim3(c->ndom), dim3(256), 0, c->stream, (const double*)c->pmax,
+                               (const int*)c->site_range, c->jscale, 1LL, (const int*)nullptr);
         }
         const bool fused = Lattice<Q>::D == 3 && !(p.flags & LB2P_FLAG_UNFUSED_SOLVE);
         const dim3 fblock(kFusedTX + 4, kFusedTY + 4, 1);
@@ -383,23 +438,31 @@ struct Impl {
             R* jnew = (R*)((it & 1) ? c->jt0 : c->jt1);
             if (fused) {
                 ProfScope _ps(c, LB2P_K_ITER_FUSED);
-                hipLaunchKernelGGL((k_iter_fused3<R, kFusedTX, kFusedTY>), fgrid, fblock, 0, c->stream,
-                                   c->dtab, c->fused_tiles, ic, it, (const R*)c->rho,
-                                   (const R*)c->j0p, (const R*)jold, jnew);
+                if (c->omega)
+                    hipLaunchKernelGGL((k_iter_fused3<R, kFusedTX, kFusedTY, true>), fgrid, fblock, 0,
+                                       c->stream, c->dtab, c->fused_tiles, ic, it, (const R*)c->pf,
+                                       (const R*)c->j0p, (const R*)jold, jnew);
+                else
+                    hipLaunchKernelGGL((k_iter_fused3<R, kFusedTX, kFusedTY, false>), fgrid, fblock, 0,
+                                       c->stream, c->dtab, c->fused_tiles, ic, it, (const R*)c->pf,
+                                       (const R*)c->j0p, (const R*)jold, jnew);
             } else {
                 {
                     ProfScope _ps(c, LB2P_K_ITER_Q);
                     hipLaunchKernelGGL((k_iter_q<Q, R>), sgrid(c), sblock(c), 0, c->stream, c->dtab,
-                                       c->site_tiles, ic, it, (const R*)c->rho, (const R*)c->u,
+                                       c->site_tiles, ic, it, (const R*)c->pf, (const R*)c->u,
                                        (R*)c->q);
                 }
                 {
                     ProfScope _ps(c, LB2P_K_ITER_JT);
                     hipLaunchKernelGGL((k_iter_jt<Q, R>), sgrid(c), sblock(c), 0, c->stream, c->dtab,
-                                       c->site_tiles, ic, it, (const R*)c->rho, (const R*)c->q,
+                                       c->site_tiles, ic, it, (const R*)c->pf, (const R*)c->q,
                                        (const R*)c->j0p, (const R*)jold, jnew, (R*)c->u);
                 }
             }
+            hipLaunchKernelGGL(k_reduce_max, dim3(c->ndom), dim3(256), 0, c->stream, (const double*)c->pmax,
+                               (const int*)(fused ? c->fused_range : c->site_range), c->res + it,
+                               (long long)c->stride, (const int*)c->done_at);
             launched = it + 1;
             if (p.fixed_iter <= 0 && (launched % every) == 0 && launched < max_it) {
                 hipLaunchKernelGGL(k_count_done, dim3(1), dim3(256), 0, c->stream, c->done_at, c->ndom,
@@ -439,7 +502,7 @@ struct Impl {
         {
             ProfScope _ps(c, LB2P_K_CLOSURE1);
             hipLaunchKernelGGL((k_closure1<Q, R>), sgrid(c), sblock(c), 0, c->stream, c->dtab,
-                               c->site_tiles, (const SolveInfo*)c->info, (const R*)c->rho,
+                               c->site_tiles, (const SolveInfo*)c->info, (const R*)c->pf,
                                (const R*)c->u, (const R*)c->jt0, (const R*)c->jt1, (R*)c->X, (R*)c->T,
                                (R*)c->Y, (R*)c->Xi);
         }
@@ -565,8 +628,12 @@ void free_ctx(lb2p_ctx* c)
     if (c->B) (void)hipFree(c->B);
     if (c->fields) (void)hipFree(c->fields);
     if (c->partial) (void)hipFree(c->partial);
+    if (c->pmax) (void)hipFree(c->pmax);
+    if (c->site_range) (void)hipFree(c->site_range);
+    if (c->fused_range) (void)hipFree(c->fused_range);
     if (c->scratch) (void)hipFree(c->scratch);
     if (c->dtab) (void)hipFree(c->dtab);
+    if (c->omega) (void)hipFree(c->omega);
     if (c->site_tiles) (void)hipFree(c->site_tiles);
     if (c->fused_tiles) (void)hipFree(c->fused_tiles);
     if (c->host) (void)hipHostFree(c->host);
@@ -600,7 +667,7 @@ void default_shape(lb2p_ctx* c)
     for (const auto& d : c->dom) maxnx = std::max(maxnx, d.g.nx);
     c->bx = maxnx >= 256 ? 256 : (maxnx >= 128 ? 128 : 64);
     c->by = 256 / c->bx;
-    c->tz = 32;
+    c->tz = 128;
     auto it = tune_cache().find(tune_key(c));
     if (it != tune_cache().end()) {
         c->bx = it->second.bx;
@@ -636,7 +703,8 @@ lb2p_status create_impl(int ndom, const lb2p_params* pp, void* hip_stream, lb2p_
         if (st != LB2P_OK) return st;
         if (p.lattice != p0.lattice || p.storage != p0.storage || p.tol != p0.tol ||
             p.max_iter != p0.max_iter || p.fixed_iter != p0.fixed_iter ||
-            p.warm_start != p0.warm_start || p.flags != p0.flags || p.graph_steps != p0.graph_steps)
+            p.warm_start != p0.warm_start || p.flags != p0.flags || p.graph_steps != p0.graph_steps ||
+            p.solver != p0.solver)
             return LB2P_EINVAL;
     }
     load_tune_file();
@@ -651,11 +719,17 @@ lb2p_status create_impl(int ndom, const lb2p_params* pp, void* hip_stream, lb2p_
     c->elem = storage_bytes(p0.storage);
     c->rsize = p0.storage == LB2P_STORE_F64 ? 8 : 4;
     long long off = 0;
+    std::vector<double> cheb_rho;
     for (int d = 0; d < ndom; ++d) {
         const lb2p_params& p = pp[d];
         Domain dm{};
         dm.g.nx = p.nx; dm.g.ny = p.ny; dm.g.nz = p.nz;
         dm.g.N = (long long)p.nx * p.ny * p.nz;
+        // kernels address one component plane of a domain with 32-bit byte offsets
+        if ((unsigned long long)dm.g.N * (p0.storage == LB2P_STORE_F64 ? 8ull : 4ull) >= (1ull << 32)) {
+            delete c;
+            return LB2P_EINVAL;
+        }
         dm.off = off;
         off += dm.g.N;
         dm.cf.gamma = p.gamma;
@@ -671,6 +745,13 @@ lb2p_status create_impl(int ndom, const lb2p_params* pp, void* hip_stream, lb2p_
             dm.cf.Wk[k] = w[k];
         }
         set_devscale(dm.ds, c->Q, dm.cf.eos, p.store_rho_ref > 0.0 ? p.store_rho_ref : p.rho0);
+        {
+            const double b = p.spectral_bound > 0.0 ? p.spectral_bound
+                                                    : spectral_bound_from_eos(c->D, dm.cf.eos, p.eos);
+            if (p.solver == LB2P_SOLVER_CHEBYSHEV && !(b < 1.0)) { delete c; return LB2P_EINVAL; }
+            dm.cf.cheb_gamma = 2.0 / (2.0 - b);
+            cheb_rho.push_back(b / (2.0 - b));
+        }
         c->dom.push_back(dm);
     }
     c->S = off;
@@ -681,8 +762,8 @@ lb2p_status create_impl(int ndom, const lb2p_params* pp, void* hip_stream, lb2p_
     const long long S = c->S;
     const int D = c->D;
     const int nsig = D == 3 ? 6 : 3, nxi = D == 3 ? 10 : 4;
-    // rho | j0 | f | j0p | u | jt0 | jt1 | q (alias T) | X | Y | Xi | Sig
-    const int ncomp = 1 + 6 * D + nsig + 1 + D + nxi + nsig;
+    // rho | j0 | f | j0p | u | jt0 | jt1 | q (alias T) | X | Y | Xi | Sig | pf (3)
+    const int ncomp = 1 + 6 * D + nsig + 1 + D + nxi + nsig + 3;
     {
         long long mo = 0;
         switch (p0.storage) {
@@ -702,6 +783,8 @@ lb2p_status create_impl(int ndom, const lb2p_params* pp, void* hip_stream, lb2p_
                           sizeof(int) + sizeof(SolveInfo)) * (size_t)ndom + 64;
     if (e == hipSuccess) e = hipMalloc(&c->scratch, sbytes);
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->host, sizeof(lb2p_ctx::HostScratch), hipHostMallocDefault);
+    if (e == hipSuccess && p0.solver == LB2P_SOLVER_CHEBYSHEV)
+        e = hipMalloc((void**)&c->omega, sizeof(double) * nres);
     if (e != hipSuccess) {
         free_ctx(c);
         (void)hipGetLastError();
@@ -713,7 +796,7 @@ lb2p_status create_impl(int ndom, const lb2p_params* pp, void* hip_stream, lb2p_
     auto take = [&](int nc) { void* ptr = fb + foff * c->rsize; foff += (size_t)nc * S; return ptr; };
     c->rho = take(1); c->j0 = take(D); c->f = take(D); c->j0p = take(D); c->u = take(D);
     c->jt0 = take(D); c->jt1 = take(D); c->q = take(nsig); c->T = c->q;
-    c->X = take(1); c->Y = take(D); c->Xi = take(nxi); c->Sig = take(nsig);
+    c->X = take(1); c->Y = take(D); c->Xi = take(nxi); c->Sig = take(nsig); c->pf = take(3);
     char* sb = (char*)c->scratch;
     c->flags = (int*)(sb + 0);
     c->nconv = (int*)(sb + 4);
@@ -725,7 +808,21 @@ lb2p_status create_impl(int ndom, const lb2p_params* pp, void* hip_stream, lb2p_
     c->done_at = (int*)(c->info + ndom);
     std::memset(c->host, 0, sizeof(lb2p_ctx::HostScratch));
     c->info_host.assign(ndom, SolveInfo{0, 0, 1, 0});
-    if (hipMemcpyAsync(c->dtab, c->dom.data(), ndom * sizeof(Domain), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+    std::vector<double> om;
+    if (c->omega) {
+        // Chebyshev weights per domain: omega_0 = 1, omega_1 = 1/(1 - r^2/2),
+        // omega_m = 1/(1 - r^2 omega_{m-1}/4), r = b/(2-b) (Golub-Varga)
+        om.resize(nres);
+        for (int d = 0; d < ndom; ++d) {
+            const double r2 = cheb_rho[d] * cheb_rho[d];
+            double* w = om.data() + (size_t)d * c->stride;
+            for (int m = 0; m < c->stride; ++m)
+                w[m] = m == 0 ? 1.0 : (m == 1 ? 1.0 / (1.0 - 0.5 * r2) : 1.0 / (1.0 - 0.25 * r2 * w[m - 1]));
+        }
+    }
+    if ((c->omega && hipMemcpyAsync(c->omega, om.data(), sizeof(double) * nres, hipMemcpyHostToDevice,
+                                    c->stream) != hipSuccess) ||
+        hipMemcpyAsync(c->dtab, c->dom.data(), ndom * sizeof(Domain), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
         hipMemsetAsync(c->scratch, 0, sbytes, c->stream) != hipSuccess ||
         hipMemsetAsync(c->fields, 0, (size_t)ncomp * S * c->rsize, c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess) {
@@ -848,6 +945,8 @@ lb2p_status lb2p_default_params(int lattice, int nx, int ny, int nz, int storage
     p.store_rho_ref = 0.0;
     p.flags = 0;
     p.graph_steps = 0;
+    p.solver = LB2P_SOLVER_FIXED_POINT;
+    p.spectral_bound = 0.0;
     *out = p;
     return LB2P_OK;
 }

@@ -96,3 +96,13 @@ def test_batch_rejects_mixed_shared_settings(L):
     with pytest.raises(L.Lb2pError) as ei:
         L.Context([a, c])
     assert ei.value.status == L.EINVAL
+
+
+def test_solver_settings_validated(L):
+    base = dict(lattice=59, nx=16, ny=16, nz=16, A=0.745, cs2_rho1=0.39, kappa=0.01)
+    assert L.create_status(L.Params(**base, solver=2)) == L.EINVAL
+    assert L.create_status(L.Params(**base, solver=1, spectral_bound=1.0)) == L.EINVAL
+    assert L.create_status(L.Params(**base, solver=1, spectral_bound=-0.1)) == L.EINVAL
+    # an EOS whose plane-wave bound reaches 1: the semi-iteration does not apply
+    hot = dict(base, A=0.9, cs2_rho1=0.8)
+    assert L.create_status(L.Params(**hot, solver=1)) in (L.EINVAL, L.EEOS)

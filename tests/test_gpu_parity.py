@@ -16,12 +16,17 @@ pytestmark = pytest.mark.gpu
 
 F64_TOL = 1e-10
 
+CHEB = dict(solver=1)
 CASES = [
-    ("d2q21", 21, (40, 24), 0),
-    ("d3q59", 59, (20, 12, 10), 0),
-    ("d3q59_unfused", 59, (20, 12, 10), 1),
-    # several 32 x 8 x 32 solve tiles with ragged edges in x and z
-    ("d3q59_tiles", 59, (40, 24, 36), 0),
+    ("d2q21", 21, (40, 24), {}),
+    ("d3q59", 59, (20, 12, 10), {}),
+    ("d3q59_unfused", 59, (20, 12, 10), dict(flags=1)),
+    # several 32 x 8 x 64 solve tiles with ragged edges in x and z
+    ("d3q59_tiles", 59, (40, 24, 72), {}),
+    # the Chebyshev solver reaches the same fixed point (same stop rule)
+    ("d2q21_cheb", 21, (40, 24), CHEB),
+    ("d3q59_cheb", 59, (20, 12, 10), CHEB),
+    ("d3q59_cheb_unfused", 59, (20, 12, 10), dict(CHEB, flags=1)),
 ]
 NSTEPS = {"d3q59_tiles": 3}
 
@@ -33,12 +38,12 @@ def L():
     return lb2p
 
 
-@pytest.mark.parametrize("name,lattice,shape,flags", CASES)
-def test_f64_matches_oracle(orc, L, name, lattice, shape, flags):
+@pytest.mark.parametrize("name,lattice,shape,extra", CASES)
+def test_f64_matches_oracle(orc, L, name, lattice, shape, extra):
     rho, u, model = small_case(lattice, shape)
     ns = NSTEPS.get(name, 10)
     ref = oracle_reference(orc, model, rho, u, nsteps_long=ns)
-    gpu = gpu_run(L, model, L.STORE_F64, rho, u, nsteps_long=ns, tol=1e-14, flags=flags)
+    gpu = gpu_run(L, model, L.STORE_F64, rho, u, nsteps_long=ns, tol=1e-14, **extra)
     e = compare(orc, ref, gpu)
     print(name, "f64", {k: f"{v:.2e}" for k, v in e.items()}, flush=True)
     for k, v in e.items():
@@ -55,24 +60,24 @@ F32_TOL = dict(rho_t0=1e-5, u_t0=2e-4, j0_t0=2e-4, force_t0=5e-4, jtilde_t0=1e-3
                xi_t0=1e-3, pop_t1=1e-5, rho_tL=1e-5, u_tL=1e-3)
 
 
-@pytest.mark.parametrize("name,lattice,shape,flags", CASES)
-def test_f32_matches_oracle(orc, L, name, lattice, shape, flags):
+@pytest.mark.parametrize("name,lattice,shape,extra", CASES)
+def test_f32_matches_oracle(orc, L, name, lattice, shape, extra):
     rho, u, model = small_case(lattice, shape)
     ns = NSTEPS.get(name, 10)
     ref = oracle_reference(orc, model, rho, u, nsteps_long=ns)
-    gpu = gpu_run(L, model, L.STORE_F32, rho, u, nsteps_long=ns, tol=1e-7, flags=flags)
+    gpu = gpu_run(L, model, L.STORE_F32, rho, u, nsteps_long=ns, tol=1e-7, **extra)
     e = compare(orc, ref, gpu)
     print(name, "f32", {k: f"{v:.2e}" for k, v in e.items()}, flush=True)
     for k, v in e.items():
         assert v <= F32_TOL[k], (k, v)
 
 
-@pytest.mark.parametrize("name,lattice,shape,flags", CASES)
-def test_invariants_on_gpu(orc, L, name, lattice, shape, flags):
+@pytest.mark.parametrize("name,lattice,shape,extra", CASES)
+def test_invariants_on_gpu(orc, L, name, lattice, shape, extra):
     """Mass and total momentum are conserved (Sec. VI: the lattice force sums
     to zero on a periodic lattice; j~ is a divergence)."""
     rho, u, model = small_case(lattice, shape)
-    gpu = gpu_run(L, model, L.STORE_F64, rho, u, nsteps_long=10, tol=1e-14, flags=flags)
+    gpu = gpu_run(L, model, L.STORE_F64, rho, u, nsteps_long=10, tol=1e-14, **extra)
     s0, sL = gpu["stats0"], gpu["statsL"]
     assert abs(sL["mass"] - s0["mass"]) <= 1e-13 * s0["mass"]
     assert np.max(np.abs(sL["mom"] - s0["mom"])) <= 1e-13 * s0["mass"]
@@ -99,3 +104,25 @@ def test_fused_and_unfused_solve_agree(orc, L, storage):
     tol = 1e-12 if st == L.STORE_F64 else 1e-5
     scale = np.abs(out[1][1]).max()
     assert np.abs(out[0][1] - out[1][1]).max() <= tol * scale
+
+
+@pytest.mark.parametrize("lattice,shape", [(21, (40, 24)), (59, (40, 24, 36))])
+def test_chebyshev_needs_fewer_passes(L, lattice, shape):
+    """From a zero start on the same state, the Chebyshev semi-iteration
+    reaches the stop rule in well under half the passes of the plain
+    fixed point, and both land on the same j~ within the tolerance."""
+    rho, u, model = small_case(lattice, shape)
+    out = {}
+    for solver in (0, 1):
+        P = L.Params(lattice=lattice, nx=shape[0], ny=shape[1], nz=shape[2] if len(shape) == 3 else 1,
+                     storage=L.STORE_F64, gamma=model["gamma"], kappa=model["kappa"], rho1=model["rho1"],
+                     rho2=model["rho2"], A=model["A"], cs2_rho1=model["cs2_1"], rho0=model["rho0"],
+                     tol=1e-12, max_iter=500, solver=solver)
+        with L.Context(P) as ctx:
+            ctx.init(rho, u)
+            ctx.moments()
+            out[solver] = (ctx.stats()["iters"], ctx.field(L.FIELD_JTILDE))
+    print("passes: fixed point", out[0][0], "chebyshev", out[1][0], flush=True)
+    assert out[1][0] * 2 < out[0][0]
+    scale = np.abs(out[0][1]).max()
+    assert np.abs(out[0][1] - out[1][1]).max() <= 1e-10 * scale
