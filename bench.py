@@ -44,7 +44,7 @@ def site_bytes(kernel, Q, D, s, r, warm, cheb=False):
         "force": (1 + D) * r + (D * r if warm else 0) + 4 * D * r + 3 * r,
         "iter_q": (2 + D) * r + nsig * r,
         "iter_jt": (nsig + 1 + 2 * D) * r + 2 * D * r + (D * r if cheb else 0),
-        "closure1": (1 + 2 * D) * r + (1 + nsig + D + nxi) * r,
+        "closure1": (3 + 2 * D) * r + (1 + nsig + D + nxi) * r,
         "closure2": (2 + nsig + 2 * D) * r + nsig * r,
         "collide": 2 * pops + (1 + 3 * D + nsig + nxi) * r,
         # fused pass: read j~, j0' and the p, P1, 1/rho planes, write j~new

@@ -320,22 +320,36 @@ lb2p_status build_tiles(lb2p_ctx* c)
         srange[d] = (int)site.size();
         frange[d] = (int)fused.size();
         const Geom& g = c->dom[d].g;
-        for (int z = 0; z < g.nz; ++z)
-            for (int y = 0; y < g.ny; y += c->by)
-                for (int x = 0; x < g.nx; x += c->bx) {
-                    Tile t{};
-                    t.dom = d; t.x0 = x; t.y0 = y; t.z0 = z; t.len = 1;
-                    site.push_back(t);
-                }
+        // A large 3D domain is cut into 8 slabs of rows, each swept through
+        // every z: after the XCD deal each XCD owns one slab, so the planes a
+        // z-stencil revisits (z +- 2) are a slab's share of a plane and stay
+        // in that XCD's L2.  Small domains stay whole (one XCD each).
+        const int rows = (g.ny + c->by - 1) / c->by;
+        const int frows = (g.ny + kFusedTY - 1) / kFusedTY;
+        const bool slabs = c->D == 3 && (long long)rows * g.nz * ((g.nx + c->bx - 1) / c->bx) >= 4096;
+        const int nslab = slabs ? 8 : 1;
+        for (int sl = 0; sl < nslab; ++sl) {
+            const int r0 = (int)((long long)rows * sl / nslab), r1 = (int)((long long)rows * (sl + 1) / nslab);
+            for (int z = 0; z < g.nz; ++z)
+                for (int r = r0; r < r1; ++r)
+                    for (int x = 0; x < g.nx; x += c->bx) {
+                        Tile t{};
+                        t.dom = d; t.x0 = x; t.y0 = r * c->by; t.z0 = z; t.len = 1;
+                        site.push_back(t);
+                    }
+        }
         if (c->D == 3) {
             const int tz = std::min(c->tz, g.nz);
-            for (int z = 0; z < g.nz; z += tz)
-                for (int y = 0; y < g.ny; y += kFusedTY)
-                    for (int x = 0; x < g.nx; x += kFusedTX) {
-                        Tile t{};
-                        t.dom = d; t.x0 = x; t.y0 = y; t.z0 = z; t.len = std::min(tz, g.nz - z);
-                        fused.push_back(t);
-                    }
+            for (int sl = 0; sl < nslab; ++sl) {
+                const int r0 = (int)((long long)frows * sl / nslab), r1 = (int)((long long)frows * (sl + 1) / nslab);
+                for (int z = 0; z < g.nz; z += tz)
+                    for (int r = r0; r < r1; ++r)
+                        for (int x = 0; x < g.nx; x += kFusedTX) {
+                            Tile t{};
+                            t.dom = d; t.x0 = x; t.y0 = r * kFusedTY; t.z0 = z; t.len = std::min(tz, g.nz - z);
+                            fused.push_back(t);
+                        }
+            }
         }
     }
     srange[c->ndom] = (int)site.size();
