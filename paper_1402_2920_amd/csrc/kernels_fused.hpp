@@ -7,9 +7,11 @@
 // registers, the last five planes of u at its point (z-derivatives of u) and
 // of q_az (z-derivative in d_b q_ab); LDS holds one u plane (tile + 4-wide
 // frame) and one q plane (tile + 2-wide frame) for the x and y derivatives.
-// Per pass every site reads j~, j0' and the per-site planes p, P1, 1/rho
-// (evaluated once per step) once from HBM and writes j~new; the Chebyshev
-// form also reads x_{k-1}, which it overwrites in place.
+// Per pass every site reads u (at the q and frame points), p and P1 (at the
+// q points; both evaluated once per step) and, at its own point, j~, j0' and
+// 1/rho, and writes j~new and the next pass's u = (j0' + j~new)/rho (u is
+// double-buffered like j~); the Chebyshev form also reads x_{k-1}, which it
+// overwrites in place.
 #pragma once
 
 #include "kernels.hpp"
@@ -51,7 +53,7 @@ template <class R, int TX, int TY, bool CHEB>
 __global__ void __launch_bounds__((TX + 4) * (TY + 4))
 k_iter_fused3(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, IterCtl ic, int it,
               const R* __restrict__ pf, const R* __restrict__ j0p, const R* __restrict__ jt_old,
-              R* jt_new)
+              const R* __restrict__ u_old, R* jt_new, R* __restrict__ u_new)
 {
     constexpr int QX = TX + 4, QY = TY + 4;   // q points
     constexpr int UX = TX + 8, UY = TY + 8;   // u points
@@ -75,9 +77,15 @@ k_iter_fused3(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, It
     const R* const tx_ = jt_old + dm.off;
     const R* const ty_ = tx_ + N;
     const R* const tz_ = ty_ + N;
+    const R* const ux = u_old + dm.off;
+    const R* const uy = ux + N;
+    const R* const uz = uy + N;
     R* const ox = jt_new + dm.off;
     R* const oy = ox + N;
     R* const oz = oy + N;
+    R* const vx = u_new + dm.off;
+    R* const vy = vx + N;
+    R* const vz = vy + N;
     R omega = R(1), gam = R(1);
     if (CHEB) {
         omega = R(ic.omega[(long long)tl.dom * ic.stride + it]);
@@ -110,74 +118,75 @@ k_iter_fused3(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, It
     const unsigned fcol = has_frame
         ? (unsigned)wrapmod(x0 + fx - 4, nx) + (unsigned)nx * (unsigned)wrapmod(y0 + fy - 4, ny) : 0u;
 
-    // Five-plane rings, oldest first; each step shifts them by one.  (Rings
+    // Plane rings, oldest first; each step shifts them by one.  (Rings
     // addressed by a compile-time phase avoid the moves but need the loop
     // unrolled five times, which costs registers and, measured, occupancy
     // and time.)
     R ur[5][3];        // u at planes lead-4 .. lead
     R qz[5][3];        // q_xz, q_yz, q_zz at planes c-4 .. c
-    R sd[5][3];        // x,y part of d_b q_ab at planes c-4 .. c (c-2 .. c used)
+    R sd[3][3];        // x,y part of d_b q_ab at planes c-2 .. c
 #pragma unroll
     for (int k = 0; k < 5; ++k)
 #pragma unroll
-        for (int a = 0; a < 3; ++a) { ur[k][a] = R(0); qz[k][a] = R(0); sd[k][a] = R(0); }
+        for (int a = 0; a < 3; ++a) { ur[k][a] = R(0); qz[k][a] = R(0); }
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) sd[k][a] = R(0);
     R dmax = R(0), dsum = R(0);   // dsum only carries a NaN (fmax drops it)
     const R c12 = R(1.0 / 12.0);
 
     // one-plane lookahead: the inputs of step k+1 are loaded while step k
-    // computes (raw values are kept: combining them at load time would make
-    // the compiler wait for the loads right away)
-    R nri = R(1), nj[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};   // own point, lead plane
-    R np = R(0), nP1 = R(0);                                       // own point, centre plane
-    R fri = R(1), fj[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};   // frame point, centre plane
-    R no[3] = {R(0), R(0), R(0)};   // x_k at the output plane of that step
-    R nv[3] = {R(0), R(0), R(0)};   // x_{k-1} there (Chebyshev)
+    // computes
+    R nu[3] = {R(0), R(0), R(0)};                 // u, own point, lead plane
+    R np = R(0), nP1 = R(0);                      // p, P1, own point, centre plane
+    R fu[3] = {R(0), R(0), R(0)};                 // u, frame point, centre plane
+    R no[3] = {R(0), R(0), R(0)};                 // x_k, own point, output plane
+    R nv[3] = {R(0), R(0), R(0)};                 // x_{k-1} there (Chebyshev)
+    R nj[3] = {R(0), R(0), R(0)}, nri = R(0);     // j0' and 1/rho there
     auto load_step = [&](int k) {
         if (k >= 8 && owned && z0 + k - 8 < nz) {
             const unsigned io = col + plane * (unsigned)(z0 + k - 8);
             no[0] = ld(tx_, io); no[1] = ld(ty_, io); no[2] = ld(tz_, io);
+            nj[0] = ld(j0x, io); nj[1] = ld(j0y, io); nj[2] = ld(j0z, io);
+            nri = ld(pRi, io);
             if (CHEB && it > 0) { nv[0] = ld<R>(ox, io); nv[1] = ld<R>(oy, io); nv[2] = ld<R>(oz, io); }
         }
         const unsigned i = col + plane * (unsigned)wrap3(z0 - 4 + k, nz);
-        nri = ld(pRi, i);
-        nj[0] = ld(j0x, i); nj[1] = ld(j0y, i); nj[2] = ld(j0z, i);
-        nj[3] = ld(tx_, i); nj[4] = ld(ty_, i); nj[5] = ld(tz_, i);
+        nu[0] = ld(ux, i); nu[1] = ld(uy, i); nu[2] = ld(uz, i);
         const unsigned zc = plane * (unsigned)wrap3(z0 - 6 + k, nz);
         np = ld(pP, col + zc);
         nP1 = ld(pP1, col + zc);
         if (has_frame) {
             const unsigned f = fcol + zc;
-            fri = ld(pRi, f);
-            fj[0] = ld(j0x, f); fj[1] = ld(j0y, f); fj[2] = ld(j0z, f);
-            fj[3] = ld(tx_, f); fj[4] = ld(ty_, f); fj[5] = ld(tz_, f);
+            fu[0] = ld(ux, f); fu[1] = ld(uy, f); fu[2] = ld(uz, f);
         }
     };
     load_step(0);
     const int nsteps = TZ + 8;
 
-    auto body = [&](int k) {
-        constexpr int s0 = 0, s1 = 1, s2 = 2, s3 = 3, s4 = 4;
-        // 1. lead plane at this thread's point: u = (j0' + j~)/rho
-        const R ri = nri;
-        const R cur_j[3] = {nj[0] + nj[3], nj[1] + nj[4], nj[2] + nj[5]};
+    for (int k = 0; k < nsteps; ++k) {
+        const R cur_u[3] = {nu[0], nu[1], nu[2]};
         const R cur_p = np, cur_P1 = nP1;
-        const R cur_fri = fri;
-        const R cur_fj[3] = {fj[0] + fj[3], fj[1] + fj[4], fj[2] + fj[5]};
+        const R cur_fu[3] = {fu[0], fu[1], fu[2]};
         const R cur_o[3] = {no[0], no[1], no[2]};
         const R cur_v[3] = {nv[0], nv[1], nv[2]};
+        const R cur_j[3] = {nj[0], nj[1], nj[2]};
+        const R cur_ri = nri;
         if (k + 1 < nsteps) load_step(k + 1);
+        // 1. lead plane of the u ring at this thread's point
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
             for (int a = 0; a < 3; ++a) ur[s][a] = ur[s + 1][a];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) ur[s4][a] = cur_j[a] * ri;
+        for (int a = 0; a < 3; ++a) ur[4][a] = cur_u[a];
         // 2. u plane c = lead-2 into LDS: own point and frame point
 #pragma unroll
-        for (int a = 0; a < 3; ++a) su[a][ly + 2][lx + 2] = ur[s2][a];
+        for (int a = 0; a < 3; ++a) su[a][ly + 2][lx + 2] = ur[2][a];
         if (has_frame) {
 #pragma unroll
-            for (int a = 0; a < 3; ++a) su[a][fy][fx] = cur_fj[a] * cur_fri;
+            for (int a = 0; a < 3; ++a) su[a][fy][fx] = cur_fu[a];
         }
         __syncthreads();
         // 3. q at plane c
@@ -189,7 +198,7 @@ k_iter_fused3(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, It
                                 su[b][ly + 2][lx + 4]);
                 G[1][b] = d1<R>(su[b][ly][lx + 2], su[b][ly + 1][lx + 2], su[b][ly + 3][lx + 2],
                                 su[b][ly + 4][lx + 2]);
-                G[2][b] = d1<R>(ur[s0][b], ur[s1][b], ur[s3][b], ur[s4][b]);
+                G[2][b] = d1<R>(ur[0][b], ur[1][b], ur[3][b], ur[4][b]);
             }
             const R X = cur_P1 * (G[0][0] + G[1][1] + G[2][2]);
             const R p2 = R(2) * cur_p;
@@ -204,41 +213,42 @@ k_iter_fused3(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, It
             for (int s = 0; s < 4; ++s)
 #pragma unroll
                 for (int a = 0; a < 3; ++a) qz[s][a] = qz[s + 1][a];
-            qz[s4][0] = qxz; qz[s4][1] = qyz; qz[s4][2] = X + p2 * G[2][2];
+            qz[4][0] = qxz; qz[4][1] = qyz; qz[4][2] = X + p2 * G[2][2];
         }
         __syncthreads();
-        // 4. j~new at plane c-2 = z0 + k - 8
+        // 4. the next iterate at plane c-2 = z0 + k - 8
         if (k >= 4 && interior) {
             const int px = lx, py = ly;
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
-#pragma unroll
-                for (int a = 0; a < 3; ++a) sd[s][a] = sd[s + 1][a];
+            for (int a = 0; a < 3; ++a) { sd[0][a] = sd[1][a]; sd[1][a] = sd[2][a]; }
             // a = x: d_x q_xx + d_y q_xy ; a = y: d_x q_xy + d_y q_yy ; a = z: d_x q_xz + d_y q_yz
-            sd[s4][0] = d1<R>(sq[0][py][px - 2], sq[0][py][px - 1], sq[0][py][px + 1], sq[0][py][px + 2]) +
-                        d1<R>(sq[2][py - 2][px], sq[2][py - 1][px], sq[2][py + 1][px], sq[2][py + 2][px]);
-            sd[s4][1] = d1<R>(sq[2][py][px - 2], sq[2][py][px - 1], sq[2][py][px + 1], sq[2][py][px + 2]) +
-                        d1<R>(sq[1][py - 2][px], sq[1][py - 1][px], sq[1][py + 1][px], sq[1][py + 2][px]);
-            sd[s4][2] = d1<R>(sq[3][py][px - 2], sq[3][py][px - 1], sq[3][py][px + 1], sq[3][py][px + 2]) +
-                        d1<R>(sq[4][py - 2][px], sq[4][py - 1][px], sq[4][py + 1][px], sq[4][py + 2][px]);
+            sd[2][0] = d1<R>(sq[0][py][px - 2], sq[0][py][px - 1], sq[0][py][px + 1], sq[0][py][px + 2]) +
+                       d1<R>(sq[2][py - 2][px], sq[2][py - 1][px], sq[2][py + 1][px], sq[2][py + 2][px]);
+            sd[2][1] = d1<R>(sq[2][py][px - 2], sq[2][py][px - 1], sq[2][py][px + 1], sq[2][py][px + 2]) +
+                       d1<R>(sq[1][py - 2][px], sq[1][py - 1][px], sq[1][py + 1][px], sq[1][py + 2][px]);
+            sd[2][2] = d1<R>(sq[3][py][px - 2], sq[3][py][px - 1], sq[3][py][px + 1], sq[3][py][px + 2]) +
+                       d1<R>(sq[4][py - 2][px], sq[4][py - 1][px], sq[4][py + 1][px], sq[4][py + 2][px]);
             const int zo = z0 + k - 8;
             if (k >= 8 && owned && zo < z0 + TZ && zo < nz) {
                 const unsigned i = col + plane * (unsigned)zo;
                 R xn[3];
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    const R dz = d1<R>(qz[s0][a], qz[s1][a], qz[s3][a], qz[s4][a]);
-                    const R gv = -(sd[s2][a] + dz) * c12;
+                    const R dz = d1<R>(qz[0][a], qz[1][a], qz[3][a], qz[4][a]);
+                    const R gv = -(sd[0][a] + dz) * c12;
                     const R d = fabs(gv - cur_o[a]);
                     dmax = fmax(dmax, d);
                     dsum += d;
                     xn[a] = CHEB ? next_iterate<R>(gv, cur_o[a], cur_v[a], omega, gam, it == 0) : gv;
                 }
                 st(ox, i, xn[0]); st(oy, i, xn[1]); st(oz, i, xn[2]);
+                // item 3 of the next pass: u = (j0' + j~)/rho
+                st(vx, i, (cur_j[0] + xn[0]) * cur_ri);
+                st(vy, i, (cur_j[1] + xn[1]) * cur_ri);
+                st(vz, i, (cur_j[2] + xn[2]) * cur_ri);
             }
         }
-    };
-    for (int k = 0; k < nsteps; ++k) body(k);
+    }
     block_max_part(ic.part, dsum == dsum ? (double)dmax : (double)dsum);
 }
 

@@ -169,6 +169,7 @@ struct lb2p_ctx {
     void* u = nullptr; void* jt0 = nullptr; void* jt1 = nullptr; void* q = nullptr;
     void* X = nullptr; void* T = nullptr; void* Y = nullptr; void* Xi = nullptr; void* Sig = nullptr;
     void* pf = nullptr;          // p, P1, 1/rho planes (fixed during the j~ solve)
+    void* u1 = nullptr;          // second u buffer of the fused solve passes
     double* omega = nullptr;     // Chebyshev weights [ndom][stride], or null
     // tiles
     int bx = 64, by = 4, tz = 32;
@@ -450,16 +451,18 @@ struct Impl {
         for (int it = 0; it < max_it; ++it) {
             R* jold = (R*)((it & 1) ? c->jt1 : c->jt0);
             R* jnew = (R*)((it & 1) ? c->jt0 : c->jt1);
+            R* uold = (R*)((it & 1) ? c->u1 : c->u);
+            R* unew = (R*)((it & 1) ? c->u : c->u1);
             if (fused) {
                 ProfScope _ps(c, LB2P_K_ITER_FUSED);
                 if (c->omega)
                     hipLaunchKernelGGL((k_iter_fused3<R, kFusedTX, kFusedTY, true>), fgrid, fblock, 0,
                                        c->stream, c->dtab, c->fused_tiles, ic, it, (const R*)c->pf,
-                                       (const R*)c->j0p, (const R*)jold, jnew);
+                                       (const R*)c->j0p, (const R*)jold, (const R*)uold, jnew, unew);
                 else
                     hipLaunchKernelGGL((k_iter_fused3<R, kFusedTX, kFusedTY, false>), fgrid, fblock, 0,
                                        c->stream, c->dtab, c->fused_tiles, ic, it, (const R*)c->pf,
-                                       (const R*)c->j0p, (const R*)jold, jnew);
+                                       (const R*)c->j0p, (const R*)jold, (const R*)uold, jnew, unew);
             } else {
                 {
                     ProfScope _ps(c, LB2P_K_ITER_Q);
@@ -776,8 +779,8 @@ lb2p_status create_impl(int ndom, const lb2p_params* pp, void* hip_stream, lb2p_
     const long long S = c->S;
     const int D = c->D;
     const int nsig = D == 3 ? 6 : 3, nxi = D == 3 ? 10 : 4;
-    // rho | j0 | f | j0p | u | jt0 | jt1 | q (alias T) | X | Y | Xi | Sig | pf (3)
-    const int ncomp = 1 + 6 * D + nsig + 1 + D + nxi + nsig + 3;
+    // rho | j0 | f | j0p | u | jt0 | jt1 | q (alias T) | X | Y | Xi | Sig | pf (3) | u1
+    const int ncomp = 1 + 6 * D + nsig + 1 + D + nxi + nsig + 3 + D;
     {
         long long mo = 0;
         switch (p0.storage) {
@@ -810,7 +813,7 @@ lb2p_status create_impl(int ndom, const lb2p_params* pp, void* hip_stream, lb2p_
     auto take = [&](int nc) { void* ptr = fb + foff * c->rsize; foff += (size_t)nc * S; return ptr; };
     c->rho = take(1); c->j0 = take(D); c->f = take(D); c->j0p = take(D); c->u = take(D);
     c->jt0 = take(D); c->jt1 = take(D); c->q = take(nsig); c->T = c->q;
-    c->X = take(1); c->Y = take(D); c->Xi = take(nxi); c->Sig = take(nsig); c->pf = take(3);
+    c->X = take(1); c->Y = take(D); c->Xi = take(nxi); c->Sig = take(nsig); c->pf = take(3); c->u1 = take(D);
     char* sb = (char*)c->scratch;
     c->flags = (int*)(sb + 0);
     c->nconv = (int*)(sb + 4);
