@@ -60,7 +60,7 @@ SOLVERS = {"fixed_point": 0, "chebyshev": 1}
 
 
 def run_gpu(workload, storage, steps, warmup, shape=None, profile=True, tol=None, solver="fixed_point",
-            autotune=True):
+            autotune=True, warm_start=1):
     import torch
     import lb2p_workloads as W
     from paper_1402_2920_amd import lb2p
@@ -68,7 +68,7 @@ def run_gpu(workload, storage, steps, warmup, shape=None, profile=True, tol=None
     d = len(shape)
     st = lb2p.STORAGE_NAMES[storage]
     P = lb2p.Params(nx=shape[0], ny=shape[1], nz=shape[2] if d == 3 else 1, storage=st,
-                    tol=tol, max_iter=200, warm_start=1, solver=SOLVERS[solver],
+                    tol=tol, max_iter=200, warm_start=warm_start, solver=SOLVERS[solver],
                     **W.model_kwargs(entry["model"]))
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
@@ -241,6 +241,8 @@ def main():
     ap.add_argument("--solver", default="fixed_point", choices=list(SOLVERS),
                     help="j~ solver: the paper's fixed point, or Chebyshev semi-iteration on the same map")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default block shapes")
+    ap.add_argument("--warm-start", type=int, default=2, choices=(0, 1, 2),
+                    help="start of the j~ iteration: zero, previous step, extrapolated from two steps")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-variants", action="store_true", help="skip the BF16/F16 storage lines")
     ap.add_argument("--batch-steps", type=int, default=1000,
@@ -255,7 +257,7 @@ def main():
     import lb2p_workloads as W
     entry = W.load_params()[args.workload]
     res = run_gpu(args.workload, args.storage, args.steps, args.warmup, solver=args.solver,
-                  autotune=not args.no_autotune)
+                  autotune=not args.no_autotune, warm_start=args.warm_start)
     N, K = res["N"], args.steps
     secs = res["seconds"]
     roof, per_kernel = roofline(res, args.storage, cheb=args.solver == "chebyshev")
@@ -269,7 +271,8 @@ def main():
                              f"periodic, {entry['kind']}, {args.storage} populations",
                     sites=N, parallelism="single GPU",
                     solve=("j~ fixed point" if args.solver == "fixed_point" else "Chebyshev semi-iteration")
-                    + " to the paper's stop rule, tol 1e-6 x max|j0'|, warm start",
+                    + " to the paper's stop rule, tol 1e-6 x max|j0'|, "
+                    + ["zero start", "warm start", "extrapolated warm start"][args.warm_start],
                     iters_last_step=res["stats"]["iters"]),
         roofline=roof,
         kernels=per_kernel,
@@ -282,7 +285,8 @@ def main():
         var = {}
         other = "chebyshev" if args.solver == "fixed_point" else "fixed_point"
         for stg, sol in (("bf16", args.solver), ("f16", args.solver), ("f32", other), ("bf16", other)):
-            r2 = run_gpu(args.workload, stg, K, args.warmup, solver=sol, autotune=not args.no_autotune)
+            r2 = run_gpu(args.workload, stg, K, args.warmup, solver=sol, autotune=not args.no_autotune,
+                         warm_start=args.warm_start)
             rf, _ = roofline(r2, stg, cheb=sol == "chebyshev")
             var[f"{stg}_{sol}"] = dict(value=round(N * K / r2["seconds"] / 1e6, 2), unit="MLUPS",
                                        ms_per_step=round(1e3 * r2["seconds"] / K, 4),

@@ -104,8 +104,11 @@ typedef struct {
     int max_iter;           /* iteration cap (> 0)                             */
     int fixed_iter;         /* > 0: exactly this many iterations, no test and
                                no host synchronisation inside lb2p_step        */
-    int warm_start;         /* != 0: start from the previous step's j~ (Sec. IX
-                               allows zero or the previous value)              */
+    int warm_start;         /* start of the j~ iteration: 0 zero, 1 the previous
+                               step's j~ (Sec. IX allows both), 2 the linear
+                               extrapolation 2 j~(t-1) - j~(t-2) (the previous
+                               value until two steps exist); the fixed point
+                               and the stop rule do not depend on it           */
     int check_every;        /* convergence readback granularity in iterations
                                (0 = library default)                          */
     double store_rho_ref;   /* reference density of BF16/F16 deviation storage

@@ -492,7 +492,7 @@ __global__ void __launch_bounds__(256) k_force(const Domain* __restrict__ tab,
                                                R* __restrict__ f, R* __restrict__ j0p,
                                                R* __restrict__ u, const R* jt_prevA,
                                                const R* jt_prevB, const SolveInfo* prev_info,
-                                               R* jt0, R* __restrict__ pf)
+                                               R* jt0, R* __restrict__ pf, R* hist, int extrap)
 {
     using L = Lattice<Q>;
     const Where w = locate(tab, tiles);
@@ -548,14 +548,22 @@ __global__ void __launch_bounds__(256) k_force(const Domain* __restrict__ tab,
             sto(pfo + St, i0, e.P1);
             sto(pfo + 2 * St, i0, inv);
         }
-        // warm start: the previous step's final iterate of this domain
+        // start of the iteration (Sec. IX allows zero or the previous step's
+        // value): zero, the previous step's final iterate y1, or the linear
+        // extrapolation 2 y1 - y2 from the two previous steps (extrap = 1);
+        // hist keeps y1 for the next step (hist != null)
         const R* prev = nullptr;
         if (prev_info) prev = prev_info[w.dom].final_buf ? jt_prevB : jt_prevA;
 #pragma unroll
         for (int a = 0; a < L::D; ++a) {
             const R fv = kr * fa[a];
             const R jp = ldo(j0 + o + a * St, i0) + R(0.5) * fv;
-            const R jt = prev ? ldo(prev + o + a * St, i0) : R(0);
+            R jt = prev ? ldo(prev + o + a * St, i0) : R(0);
+            if (hist) {
+                const R y2 = ldo(hist + o + a * St, i0);
+                sto(hist + o + a * St, i0, jt);
+                if (extrap) jt = R(2) * jt - y2;
+            }
             sto(f + o + a * St, i0, fv);
             sto(j0p + o + a * St, i0, jp);
             sto(jt0 + o + a * St, i0, jt);

@@ -94,6 +94,7 @@ lb2p_status check_params(const lb2p_params& p)
         return LB2P_EINVAL;
     if (p.graph_steps < 0) return LB2P_EINVAL;
     if (p.solver != LB2P_SOLVER_FIXED_POINT && p.solver != LB2P_SOLVER_CHEBYSHEV) return LB2P_EINVAL;
+    if (p.warm_start < 0 || p.warm_start > 2) return LB2P_EINVAL;
     if (!(p.spectral_bound >= 0.0 && p.spectral_bound < 1.0)) return LB2P_EINVAL;
     if (!(p.rho0 > 0.0)) return LB2P_EINVAL;
     if ((long long)p.nx * p.ny * p.nz > (1LL << 31)) return LB2P_EINVAL;
@@ -204,6 +205,8 @@ struct lb2p_ctx {
     HostScratch* host = nullptr;               // pinned readback area
     bool initialized = false;
     bool have_prev = false;
+    int nprev = 0;               // solves since init whose j~ can start the next one
+    void* jhist = nullptr;       // previous step's final j~ (extrapolated warm start)
     bool sigma_valid = false;
     lb2p_status sticky = LB2P_OK;
     int last_iters = 0;
@@ -423,7 +426,9 @@ struct Impl {
 
     // Items 1-8.  In the default (tolerance) mode the host reads, every
     // check_every passes, how many domains have met the stop rule.
-    static lb2p_status solve(lb2p_ctx* c)
+    // advance: the solve belongs to a time step (lb2p_step), not to a
+    // re-evaluation of the same state (lb2p_moments)
+    static lb2p_status solve(lb2p_ctx* c, bool advance = true)
     {
         const lb2p_params& p = c->prm;
         const int max_it = p.fixed_iter > 0 ? p.fixed_iter : p.max_iter;
@@ -436,10 +441,14 @@ struct Impl {
         {
             ProfScope _ps(c, LB2P_K_FORCE);
             const SolveInfo* prev = (p.warm_start && c->have_prev) ? c->info : nullptr;
+            // warm_start 2: keep the history only for solves that advance
+            // time; extrapolate once two previous steps exist
+            R* hist = (p.warm_start == 2 && advance && prev) ? (R*)c->jhist : nullptr;
+            const int extrap = (hist && c->nprev >= 2) ? 1 : 0;
             hipLaunchKernelGGL((k_force<Q, R>), sgrid(c), sblock(c), 0, c->stream, c->dtab,
                                c->site_tiles, ic, (const R*)c->rho, (const R*)c->j0, (R*)c->f,
                                (R*)c->j0p, (R*)c->u, (const R*)c->jt0, (const R*)c->jt1, prev,
-                               (R*)c->jt0, (R*)c->pf);
+                               (R*)c->jt0, (R*)c->pf, hist, extrap);
             hipLaunchKernelGGL(k_reduce_max, dim3(c->ndom), dim3(256), 0, c->stream, (const double*)c->pmax,
                                (const int*)c->site_range, c->jscale, 1LL, (const int*)nullptr);
         }
@@ -509,6 +518,7 @@ struct Impl {
             c->last_iters = max_it;
         }
         c->have_prev = true;
+        if (advance) c->nprev = std::min(c->nprev + 1, 2);
         return LB2P_OK;
     }
 
@@ -651,6 +661,7 @@ void free_ctx(lb2p_ctx* c)
     if (c->scratch) (void)hipFree(c->scratch);
     if (c->dtab) (void)hipFree(c->dtab);
     if (c->omega) (void)hipFree(c->omega);
+    if (c->jhist) (void)hipFree(c->jhist);
     if (c->site_tiles) (void)hipFree(c->site_tiles);
     if (c->fused_tiles) (void)hipFree(c->fused_tiles);
     if (c->host) (void)hipHostFree(c->host);
@@ -802,6 +813,10 @@ lb2p_status create_impl(int ndom, const lb2p_params* pp, void* hip_stream, lb2p_
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->host, sizeof(lb2p_ctx::HostScratch), hipHostMallocDefault);
     if (e == hipSuccess && p0.solver == LB2P_SOLVER_CHEBYSHEV)
         e = hipMalloc((void**)&c->omega, sizeof(double) * nres);
+    if (e == hipSuccess && p0.warm_start == 2) {
+        e = hipMalloc(&c->jhist, (size_t)D * S * c->rsize);
+        if (e == hipSuccess) e = hipMemsetAsync(c->jhist, 0, (size_t)D * S * c->rsize, c->stream);
+    }
     if (e != hipSuccess) {
         free_ctx(c);
         (void)hipGetLastError();
@@ -863,12 +878,12 @@ lb2p_status run_steps(lb2p_ctx* c, int nsteps)
     const int gs = c->prm.graph_steps > 0 && c->prm.fixed_iter > 0 ? (c->prm.graph_steps + 1) / 2 * 2 : 0;
     int s = 0;
     if (gs > 0 && !c->prof) {
-        // a captured step always warm-starts j~ from the previous step; the
-        // first step after lb2p_init has none, so it runs eagerly
-        if (!c->have_prev && nsteps > 0) {
+        // a captured step warm-starts j~ from the previous step(s); the first
+        // steps after lb2p_init have none, so they run eagerly
+        while (s < nsteps && (!c->have_prev || (c->prm.warm_start == 2 && c->nprev < 2))) {
             lb2p_status st = dispatch(c, [&](auto impl) { return decltype(impl)::step(c); });
             if (st != LB2P_OK) return st;
-            s = 1;
+            ++s;
         }
         while (nsteps - s >= gs) {
             const int par = c->A == c->A0 ? 0 : 1;
@@ -1027,6 +1042,7 @@ lb2p_status lb2p_init(lb2p_ctx* c, const void* rho, const void* u, int dtype, in
     HIPCHK(hipStreamSynchronize(c->stream));
     c->initialized = true;
     c->have_prev = false;
+    c->nprev = 0;
     c->sigma_valid = false;
     c->sticky = LB2P_OK;
     return LB2P_OK;
@@ -1048,7 +1064,7 @@ lb2p_status lb2p_moments(lb2p_ctx* c, void* rho_out, void* u_out, int dtype, int
     if (!c) return LB2P_EINVAL;
     if (!c->initialized) return LB2P_ESTATE;
     if (dtype != LB2P_DTYPE_F64 && dtype != LB2P_DTYPE_F32) return LB2P_EINVAL;
-    lb2p_status s = dispatch(c, [&](auto impl) { return decltype(impl)::solve(c); });
+    lb2p_status s = dispatch(c, [&](auto impl) { return decltype(impl)::solve(c, false); });
     if (s != LB2P_OK) return s;
     c->sigma_valid = false;
     if (rho_out) {
@@ -1210,6 +1226,7 @@ lb2p_status lb2p_set_populations(lb2p_ctx* c, const double* n_in, int on_device)
     HIPCHK(hipStreamSynchronize(c->stream));
     c->initialized = true;
     c->have_prev = false;
+    c->nprev = 0;
     c->sigma_valid = false;
     c->sticky = LB2P_OK;
     return LB2P_OK;
@@ -1256,6 +1273,7 @@ lb2p_status lb2p_autotune(lb2p_ctx* c, int steps)
                 break;
             }
             c->have_prev = false;
+            c->nprev = 0;
             st = run_steps(c, 1);   // warm-up
             if (st != LB2P_OK) break;
             float ms = 0.f;
@@ -1287,6 +1305,7 @@ lb2p_status lb2p_autotune(lb2p_ctx* c, int steps)
     (void)hipStreamSynchronize(c->stream);
     (void)hipFree(save);
     c->have_prev = false;
+    c->nprev = 0;
     c->sticky = LB2P_OK;
     if (st != LB2P_OK) return st;
     const std::string key = tune_key(c);
