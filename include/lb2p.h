@@ -109,8 +109,10 @@ typedef struct {
                                extrapolation 2 j~(t-1) - j~(t-2) (the previous
                                value until two steps exist); the fixed point
                                and the stop rule do not depend on it           */
-    int check_every;        /* convergence readback granularity in iterations
-                               (0 = library default)                          */
+    int check_every;        /* tolerance mode: the host reads the number of
+                               converged domains first one pass before the
+                               previous solve's pass count, then every
+                               check_every passes (0 = every pass)            */
     double store_rho_ref;   /* reference density of BF16/F16 deviation storage
                                (<= 0: mean of the density given to lb2p_init) */
     int flags;              /* LB2P_FLAG_* (0 = defaults)                      */
@@ -198,8 +200,8 @@ lb2p_status lb2p_init(lb2p_ctx *ctx, const void *rho, const void *u, int dtype, 
 
 /* Advance nsteps >= 0 time steps (Supplemental items 1-12 each).
  * Asynchronous on the context's stream when fixed_iter > 0; otherwise the
- * iteration's convergence test reads one flag back every check_every
- * iterations.  Returns ENOCONV if any step's solve hit max_iter.
+ * host reads the convergence count back during each solve (check_every).
+ * Returns ENOCONV if any step's solve hit max_iter.
  * Errors: ESTATE (no init), ENOCONV, EHIP. */
 lb2p_status lb2p_step(lb2p_ctx *ctx, int nsteps);
 

@@ -703,14 +703,26 @@ __global__ void k_iter_finish(IterCtl ic, int launched, int ndom, SolveInfo* inf
     if (!(d >= 0 || ic.tol < 0.0)) atomicAdd(nconv, 1);
 }
 
-// Number of domains whose stop rule has held (for the host's early exit).
-__global__ void k_count_done(const int* __restrict__ done_at, int ndom, int* out)
+// After `launched` passes: apply the stop rule to the last pass of every
+// domain still iterating (as the next pass would) and count the domains whose
+// rule has held, for the host's early exit.
+__global__ void k_check_done(IterCtl ic, int launched, int ndom, int* out)
 {
     __shared__ int cnt;
     if (threadIdx.x == 0) cnt = 0;
     __syncthreads();
-    for (int d = threadIdx.x; d < ndom; d += blockDim.x)
-        if (done_at[d] >= 0) atomicAdd(&cnt, 1);
+    for (int d = threadIdx.x; d < ndom; d += blockDim.x) {
+        int da = ic.done_at[d];
+        if (da < 0 && launched > 0) {
+            const double r = __longlong_as_double((long long)ic.res[(long long)d * ic.stride + launched - 1]);
+            const double thr = ic.tol * __longlong_as_double((long long)ic.jscale[d]);
+            if (r <= thr) {
+                da = launched;
+                ic.done_at[d] = da;
+            }
+        }
+        if (da >= 0) atomicAdd(&cnt, 1);
+    }
     __syncthreads();
     if (threadIdx.x == 0) *out = cnt;
 }

@@ -424,8 +424,9 @@ struct Impl {
                            write_fields ? (R*)c->j0 : (R*)c->T, c->partial, c->flags);
     }
 
-    // Items 1-8.  In the default (tolerance) mode the host reads, every
-    // check_every passes, how many domains have met the stop rule.
+    // Items 1-8.  In the default (tolerance) mode the host reads how many
+    // domains have met the stop rule: first one pass before the previous
+    // solve's pass count, then every check_every passes (default 1).
     // advance: the solve belongs to a time step (lb2p_step), not to a
     // re-evaluation of the same state (lb2p_moments)
     static lb2p_status solve(lb2p_ctx* c, bool advance = true)
@@ -455,7 +456,8 @@ struct Impl {
         const bool fused = Lattice<Q>::D == 3 && !(p.flags & LB2P_FLAG_UNFUSED_SOLVE);
         const dim3 fblock(kFusedTX + 4, kFusedTY + 4, 1);
         const dim3 fgrid((unsigned)c->fused_host.size());
-        const int every = p.check_every > 0 ? p.check_every : 4;
+        const int every = p.check_every > 0 ? p.check_every : 1;
+        int next_check = std::max(1, c->last_iters - 1);
         int launched = 0;
         for (int it = 0; it < max_it; ++it) {
             R* jold = (R*)((it & 1) ? c->jt1 : c->jt0);
@@ -490,8 +492,9 @@ struct Impl {
                                (const int*)(fused ? c->fused_range : c->site_range), c->res + it,
                                (long long)c->stride, (const int*)c->done_at);
             launched = it + 1;
-            if (p.fixed_iter <= 0 && (launched % every) == 0 && launched < max_it) {
-                hipLaunchKernelGGL(k_count_done, dim3(1), dim3(256), 0, c->stream, c->done_at, c->ndom,
+            if (p.fixed_iter <= 0 && launched >= next_check && launched < max_it) {
+                next_check = launched + every;
+                hipLaunchKernelGGL(k_check_done, dim3(1), dim3(256), 0, c->stream, ic, launched, c->ndom,
                                    c->ndone);
                 HIPCHK(hipMemcpyAsync(&c->host->ndone, c->ndone, sizeof(int), hipMemcpyDeviceToHost,
                                       c->stream));
