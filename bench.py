@@ -41,7 +41,8 @@ def site_bytes(kernel, Q, D, s, r, warm, cheb=False):
     pops = (Q - 1) * s + t0
     return {
         "moments": pops + (1 + D) * r,
-        "force": (1 + D) * r + (D * r if warm else 0) + 4 * D * r + 3 * r,
+        # warm: 0 zero start, 1 previous j~, 2 extrapolated (history read and written)
+        "force": (1 + D) * r + (D * r if warm else 0) + (2 * D * r if warm == 2 else 0) + 4 * D * r + 3 * r,
         "iter_q": (2 + D) * r + nsig * r,
         "iter_jt": (nsig + 1 + 2 * D) * r + 2 * D * r + (D * r if cheb else 0),
         "closure1": (3 + 2 * D) * r + (1 + nsig + D + nxi) * r,
@@ -138,7 +139,7 @@ def run_batch(workload, steps, warmup, fixed_iter, graph=True, limit=None, autot
     return out
 
 
-def roofline(res, storage, warm=True, cheb=False):
+def roofline(res, storage, warm=2, cheb=False):
     prof = res["prof"]
     Q, D, N = res["Q"], res["D"], res["N"]
     s = STORE_BYTES[storage]
@@ -260,7 +261,7 @@ def main():
                   autotune=not args.no_autotune, warm_start=args.warm_start)
     N, K = res["N"], args.steps
     secs = res["seconds"]
-    roof, per_kernel = roofline(res, args.storage, cheb=args.solver == "chebyshev")
+    roof, per_kernel = roofline(res, args.storage, warm=args.warm_start, cheb=args.solver == "chebyshev")
     shape = res["shape"]
     line = dict(
         metric="MLUPS and % HBM peak, D3Q59 FP32 vs BF16-storage at stated error",
@@ -287,7 +288,7 @@ def main():
         for stg, sol in (("bf16", args.solver), ("f16", args.solver), ("f32", other), ("bf16", other)):
             r2 = run_gpu(args.workload, stg, K, args.warmup, solver=sol, autotune=not args.no_autotune,
                          warm_start=args.warm_start)
-            rf, _ = roofline(r2, stg, cheb=sol == "chebyshev")
+            rf, _ = roofline(r2, stg, warm=args.warm_start, cheb=sol == "chebyshev")
             var[f"{stg}_{sol}"] = dict(value=round(N * K / r2["seconds"] / 1e6, 2), unit="MLUPS",
                                        ms_per_step=round(1e3 * r2["seconds"] / K, 4),
                                        roofline_frac=rf["frac"], dominant=rf["kernel"],
@@ -296,7 +297,7 @@ def main():
     if args.batch_steps > 0:
         bw = "d2q21_batch512"
         bres = run_batch(bw, args.batch_steps, args.warmup, args.batch_iters)
-        broof, _ = roofline(bres, "f32")
+        broof, _ = roofline(bres, "f32", warm=1)
         bN = bres["N"]
         line["batched"] = dict(
             workload=f"{bw}: {bres['ndom']} periodic D2Q21 domains, sides 32..256, one droplet each, "
