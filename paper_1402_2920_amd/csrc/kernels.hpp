@@ -38,12 +38,18 @@ struct Coef {
     double cheb_gamma;    // extrapolation 2/(2 - b) of the Chebyshev solver
 };
 
-// Population storage codecs.  Plain forms hold n_i; deviation forms hold
-// (n_i - off_k) / scl_k with per-shell constants.
+// Population storage codecs.  Plain forms hold n_i.  The BF16/FP16 forms
+// hold (n_i - o_i) / W_k, the deviation from the rest equilibrium of the site
+// that wrote the value, o_i = w_k(c_s^2(rho)) rho (Sec. III weights at that
+// site's density; the (rho, c_s^2) pair is stored beside the populations),
+// scaled per shell by the reference weight W_k.  What remains is the
+// velocity and non-equilibrium part, small next to W_k, which BF16/FP16
+// resolve far better than the populations themselves.
 struct DevScale {
-    float off[8];
-    float scl[8];
-    float inv[8];
+    float off[8];    // w_k(c_s^2(rho_ref)) rho_ref: offsets of the reference state
+    float scl[8];    // W_k
+    float inv[8];    // 1 / W_k
+    float rref, sref;   // rho_ref and c_s^2(rho_ref) (states without a local record)
 };
 
 struct Domain {
@@ -65,34 +71,38 @@ struct Codec;
 
 template <>
 struct Codec<double> {
-    __device__ static inline double dec(double v, const DevScale&, int) { return v; }
-    __device__ static inline double enc(double v, const DevScale&, int) { return v; }
+    static constexpr bool kLocal = false;
+    __device__ static inline double dec(double v, const DevScale&, int, float) { return v; }
+    __device__ static inline double enc(double v, const DevScale&, int, float) { return v; }
 };
 template <>
 struct Codec<float> {
-    __device__ static inline float dec(float v, const DevScale&, int) { return v; }
-    __device__ static inline float enc(float v, const DevScale&, int) { return v; }
+    static constexpr bool kLocal = false;
+    __device__ static inline float dec(float v, const DevScale&, int, float) { return v; }
+    __device__ static inline float enc(float v, const DevScale&, int, float) { return v; }
 };
 template <>
 struct Codec<_Float16> {
-    __device__ static inline float dec(_Float16 v, const DevScale& s, int k)
+    static constexpr bool kLocal = true;
+    __device__ static inline float dec(_Float16 v, const DevScale& s, int k, float off)
     {
-        return fmaf(static_cast<float>(v), s.scl[k], s.off[k]);
+        return fmaf(static_cast<float>(v), s.scl[k], off);
     }
-    __device__ static inline _Float16 enc(float v, const DevScale& s, int k)
+    __device__ static inline _Float16 enc(float v, const DevScale& s, int k, float off)
     {
-        return static_cast<_Float16>((v - s.off[k]) * s.inv[k]);
+        return static_cast<_Float16>((v - off) * s.inv[k]);
     }
 };
 template <>
 struct Codec<__bf16> {
-    __device__ static inline float dec(__bf16 v, const DevScale& s, int k)
+    static constexpr bool kLocal = true;
+    __device__ static inline float dec(__bf16 v, const DevScale& s, int k, float off)
     {
-        return fmaf(static_cast<float>(v), s.scl[k], s.off[k]);
+        return fmaf(static_cast<float>(v), s.scl[k], off);
     }
-    __device__ static inline __bf16 enc(float v, const DevScale& s, int k)
+    __device__ static inline __bf16 enc(float v, const DevScale& s, int k, float off)
     {
-        return static_cast<__bf16>((v - s.off[k]) * s.inv[k]);
+        return static_cast<__bf16>((v - off) * s.inv[k]);
     }
 };
 
@@ -117,9 +127,37 @@ struct RestOf<_Float16> {
 };
 
 template <class S>
-__host__ __device__ inline long long moving_offset_bytes(long long St)
+__host__ __device__ inline long long eq_offset_bytes(long long St)
 {
     return (St * (long long)sizeof(typename RestOf<S>::T) + 255) / 256 * 256;
+}
+// After the rest plane: for BF16/FP16 the (rho, c_s^2) record of the site
+// that wrote each value (float2 [S]), then the moving planes.
+template <class S>
+__host__ __device__ inline long long moving_offset_bytes(long long St)
+{
+    return eq_offset_bytes<S>(St) + (Codec<S>::kLocal ? (St * 8 + 255) / 256 * 256 : 0);
+}
+template <class S>
+__device__ inline float2* eq_plane(S* A, long long St)
+{
+    return reinterpret_cast<float2*>(reinterpret_cast<char*>(A) + eq_offset_bytes<S>(St));
+}
+template <class S>
+__device__ inline const float2* eq_plane(const S* A, long long St)
+{
+    return reinterpret_cast<const float2*>(reinterpret_cast<const char*>(A) + eq_offset_bytes<S>(St));
+}
+
+// Offset of a value of shell k written by a site with record e = (rho, c_s^2)
+// (k is a constant once the velocity loops are unrolled, and the other
+// shells fold away).
+template <int Q>
+__device__ __forceinline__ float rest_offset(int k, float2 e)
+{
+    float w[8];
+    shell_weights<Q, float>(e.y, w);
+    return w[k] * e.x;
 }
 
 template <class S>
@@ -382,14 +420,22 @@ __global__ void __launch_bounds__(256) k_init(const Domain* __restrict__ tab, co
     const R a0 = R(1) - (uu[0] * uu[0] + uu[1] * uu[1] + uu[2] * uu[2]) * R(0.5) * inv;
     using T0 = typename RestOf<S>::T;
     S* const mv = moving_planes(A, St) + o;
+    if constexpr (Codec<S>::kLocal) sto(eq_plane(A, St) + o, i0, make_float2(float(r), float(cs2)));
     T0 moved = T0(0);
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
         const R uc = uu[0] * R(L::cx(i)) + uu[1] * R(L::cy(i)) + uu[2] * R(L::cz(i));
         const R neq = wl[L::shell(i)] * r * (a0 + uc * inv + R(0.5) * uc * uc * inv * inv);
-        const S e = Codec<S>::enc(neq, dm.ds, L::shell(i));
-        sto(mv + (size_t)(i - 1) * St, nb.at(-L::cx(i), -L::cy(i), -L::cz(i)), e);
-        moved += T0(Codec<S>::dec(e, dm.ds, L::shell(i)));
+        const unsigned slot = nb.at(-L::cx(i), -L::cy(i), -L::cz(i));
+        float off = 0.f;
+        if constexpr (Codec<S>::kLocal) {
+            // the record the slot's own thread writes: its density and c_s^2
+            const float rs = float(ldo(rho + o, slot));
+            off = rest_offset<Q>(L::shell(i), make_float2(rs, float(eos_cs2<R>(dm.cf.eos, R(rs)))));
+        }
+        const S e = Codec<S>::enc(neq, dm.ds, L::shell(i), off);
+        sto(mv + (size_t)(i - 1) * St, slot, e);
+        moved += T0(Codec<S>::dec(e, dm.ds, L::shell(i), off));
     }
     // rest population: the site's density minus the stored moving ones
     sto(rest_plane(A) + o, i0, T0(r) - moved);
@@ -425,10 +471,13 @@ __global__ void __launch_bounds__(256) k_moments(const Domain* __restrict__ tab,
         T0 racc = ldo(rest_plane(A) + o, i0);
         R jx = R(0), jy = R(0), jz = R(0);
         const S* const mv = moving_planes(A, St) + o;
+        const float2* const eqa = eq_plane(A, St) + o;
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
-            const R v = Codec<S>::dec(ldo(mv + (size_t)(i - 1) * St, nb.at(-L::cx(i), -L::cy(i), -L::cz(i))),
-                                      dm.ds, L::shell(i));
+            const unsigned src = nb.at(-L::cx(i), -L::cy(i), -L::cz(i));
+            float off = 0.f;
+            if constexpr (Codec<S>::kLocal) off = rest_offset<Q>(L::shell(i), ldo(eqa, src));
+            const R v = Codec<S>::dec(ldo(mv + (size_t)(i - 1) * St, src), dm.ds, L::shell(i), off);
             racc += T0(v);
             if (L::cx(i)) jx += R(L::cx(i)) * v;
             if (L::cy(i)) jy += R(L::cy(i)) * v;
@@ -968,6 +1017,14 @@ __global__ void __launch_bounds__(256) k_collide(const Domain* __restrict__ tab,
     // rounding is far below that of the populations themselves.
     const S* const amv = moving_planes(A, St) + o;
     S* const bmv = moving_planes(B, St) + o;
+    const float2* const eqa = eq_plane(A, St) + o;
+    // this site's record for the values it writes: rest offsets w_k(c_s^2) rho
+    float ownoff[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if constexpr (Codec<S>::kLocal) {
+        sto(eq_plane(B, St) + o, i0, make_float2(float(r), float(cs2)));
+#pragma unroll
+        for (int k = 1; k < L::NSHELL; ++k) ownoff[k] = rest_offset<Q>(k, make_float2(float(r), float(cs2)));
+    }
     R dsum = R(0);
 #pragma unroll
     for (int p = 0; p < L::NPAIR; ++p) {
@@ -998,13 +1055,19 @@ __global__ void __launch_bounds__(256) k_collide(const Domain* __restrict__ tab,
         const R Wk = R(dm.cf.Wk[k]);
         const R even = wl[k] * (a0 + a2 * uc * uc) + Wk * (kS * cSc + s0);
         const R odd = wl[k] * a1 * uc + Wk * (bc + kX * cXc);
-        const R np = Codec<S>::dec(ldo(amv + (size_t)(ip - 1) * St, nb.at(-cxv, -cyv, -czv)), dm.ds, k);
-        const R nm = Codec<S>::dec(ldo(amv + (size_t)(im - 1) * St, nb.at(cxv, cyv, czv)), dm.ds, k);
-        const S ep = Codec<S>::enc(gm * np + even + odd, dm.ds, k);
-        const S em = Codec<S>::enc(gm * nm + even - odd, dm.ds, k);
+        const unsigned sp = nb.at(-cxv, -cyv, -czv), sm = nb.at(cxv, cyv, czv);
+        float offp = 0.f, offm = 0.f;
+        if constexpr (Codec<S>::kLocal) {
+            offp = rest_offset<Q>(k, ldo(eqa, sp));
+            offm = rest_offset<Q>(k, ldo(eqa, sm));
+        }
+        const R np = Codec<S>::dec(ldo(amv + (size_t)(ip - 1) * St, sp), dm.ds, k, offp);
+        const R nm = Codec<S>::dec(ldo(amv + (size_t)(im - 1) * St, sm), dm.ds, k, offm);
+        const S ep = Codec<S>::enc(gm * np + even + odd, dm.ds, k, ownoff[k]);
+        const S em = Codec<S>::enc(gm * nm + even - odd, dm.ds, k, ownoff[k]);
         sto(bmv + (size_t)(ip - 1) * St, i0, ep);
         sto(bmv + (size_t)(im - 1) * St, i0, em);
-        dsum += (Codec<S>::dec(ep, dm.ds, k) - np) + (Codec<S>::dec(em, dm.ds, k) - nm);
+        dsum += (Codec<S>::dec(ep, dm.ds, k, ownoff[k]) - np) + (Codec<S>::dec(em, dm.ds, k, ownoff[k]) - nm);
     }
     using T0 = typename RestOf<S>::T;
     sto(rest_plane(B) + o, i0, ldo(rest_plane(A) + o, i0) - T0(dsum));
@@ -1025,12 +1088,16 @@ __global__ void __launch_bounds__(256) k_export(const Domain* __restrict__ tab,
     const NbP nb = make_nbp(g, w.x, w.y, w.z);
     const unsigned i0 = nb.i0;
     const S* const mv = moving_planes(A, St) + o;
+    const float2* const eqa = eq_plane(A, St) + o;
     sto(out + o, i0, (double)ldo(rest_plane(A) + o, i0));
 #pragma unroll
-    for (int i = 1; i < Q; ++i)
-        sto(out + o + (size_t)i * St, i0,
-            (double)Codec<S>::dec(ldo(mv + (size_t)(i - 1) * St, nb.at(-L::cx(i), -L::cy(i), -L::cz(i))), dm.ds,
-                                  L::shell(i)));
+    for (int i = 1; i < Q; ++i) {
+        const unsigned src = nb.at(-L::cx(i), -L::cy(i), -L::cz(i));
+        float off = 0.f;
+        if constexpr (Codec<S>::kLocal) off = rest_offset<Q>(L::shell(i), ldo(eqa, src));
+        sto(out + o + (size_t)i * St, i0, (double)Codec<S>::dec(ldo(mv + (size_t)(i - 1) * St, src), dm.ds,
+                                                                L::shell(i), off));
+    }
 }
 
 template <int Q, class S>
@@ -1046,13 +1113,20 @@ __global__ void __launch_bounds__(256) k_import(const Domain* __restrict__ tab,
     const long long o = dm.off, St = g.S;
     const NbP nb = make_nbp(g, w.x, w.y, w.z);
     const unsigned i0 = nb.i0;
-    using RT = decltype(Codec<S>::dec(S(), dm.ds, 0));
+    using RT = decltype(Codec<S>::dec(S(), dm.ds, 0, 0.f));
     S* const mv = moving_planes(A, St) + o;
     sto(rest_plane(A) + o, i0, (typename RestOf<S>::T)ldo(in + o, i0));
+    // no density is at hand for the slots: every record is the reference
+    // state's, until the first collision writes local ones
+    const float2 eref = make_float2(dm.ds.rref, dm.ds.sref);
+    if constexpr (Codec<S>::kLocal) sto(eq_plane(A, St) + o, i0, eref);
 #pragma unroll
-    for (int i = 1; i < Q; ++i)
+    for (int i = 1; i < Q; ++i) {
+        float off = 0.f;
+        if constexpr (Codec<S>::kLocal) off = rest_offset<Q>(L::shell(i), eref);
         sto(mv + (size_t)(i - 1) * St, nb.at(-L::cx(i), -L::cy(i), -L::cz(i)),
-            Codec<S>::enc((RT)ldo(in + o + (size_t)i * St, i0), dm.ds, L::shell(i)));
+            Codec<S>::enc((RT)ldo(in + o + (size_t)i * St, i0), dm.ds, L::shell(i), off));
+    }
 }
 
 // Small helpers.

@@ -136,6 +136,15 @@ __host__ __device__ inline void shell_weights(R s, R* w)
     }
 }
 
+// Weight of one shell K >= 1 (the other shells fold away when inlined).
+template <int Q, int K, class R>
+__host__ __device__ inline R shell_weight(R s)
+{
+    R w[8];
+    shell_weights<Q, R>(s, w);
+    return w[K];
+}
+
 // Equation of state of App. B, the quantities of Supplemental item 1.
 struct EosParams {
     double rho1, rho3, inv_delta_pi;   // pi/(rho2-rho1)

@@ -104,6 +104,8 @@ lb2p_status check_params(const lb2p_params& p)
 void set_devscale(DevScale& ds, int Q, const EosParams& eos, double rref)
 {
     const double cs2 = eos_cs2<double>(eos, rref);
+    ds.rref = (float)rref;
+    ds.sref = (float)cs2;
     double w[8] = {0};
     if (Q == 59) shell_weights<59, double>(cs2, w);
     else shell_weights<21, double>(cs2, w);

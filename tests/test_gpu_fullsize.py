@@ -127,3 +127,41 @@ def test_fullsize_bench_config_conserves(L):
     print(f"256^3 f32 10 steps: mass drift {dm:.2e}, momentum drift {dj:.2e}, iters {s1['iters']}", flush=True)
     assert not s1["nonfinite"]
     assert dm <= 1e-9 and dj <= 1e-7
+
+
+LONG_RUNS = [
+    # (workload, storage, steps)
+    ("d3q59_128_droplet", "STORE_F32", 1000),
+    ("d3q59_256_slab", "STORE_F32", 2000),
+    ("d3q59_256_slab", "STORE_BF16", 2000),
+    ("d3q59_512_two_droplets", "STORE_F32", 100),
+]
+
+
+@pytest.mark.parametrize("name,storage,steps", LONG_RUNS)
+def test_workload_runs_stay_bounded(L, name, storage, steps):
+    """The workloads' own step counts at full size, in the benchmark's
+    configuration (tolerance stop rule, extrapolated warm start): no
+    non-finite value, the flow velocity stays small (|u| < 0.05) and the
+    mass is conserved (rest-plane balance)."""
+    import torch
+    entry, shape, rho, u = W.build(name)
+    P = L.Params(nx=shape[0], ny=shape[1], nz=shape[2], storage=getattr(L, storage), max_iter=300,
+                 warm_start=2, **W.model_kwargs(entry["model"]))
+    torch.cuda.set_device(0)
+    with L.Context(P, stream=torch.cuda.current_stream()) as ctx:
+        ctx.init(torch.tensor(rho, device="cuda:0"), torch.tensor(u, device="cuda:0").contiguous())
+        del rho, u
+        s0 = ctx.stats()
+        ctx.step(steps)
+        s1 = ctx.stats()
+        ud = torch.empty((3, ctx.N), dtype=torch.float32, device="cuda:0")
+        rd = torch.empty(ctx.N, dtype=torch.float32, device="cuda:0")
+        ctx.moments_into(rd, ud)
+        umax = float(ud.square().sum(0).sqrt().max())
+        del ud, rd
+    dm = abs(s1["mass"] - s0["mass"]) / s0["mass"]
+    print(f"{name} {storage} {steps} steps: max|u| {umax:.2e}, mass drift {dm:.2e}, passes {s1['iters']}", flush=True)
+    assert not s1["nonfinite"]
+    assert umax < 0.05
+    assert dm <= (1e-9 if storage == "STORE_F32" else 1e-6)
