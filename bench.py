@@ -30,24 +30,29 @@ HBM_PEAK_GBS = 8000.0
 DEFAULT_WORKLOAD = "d3q59_256_slab"
 
 
-def site_bytes(kernel, Q, D, s, r, warm, cheb=False):
+def site_bytes(kernel, Q, D, s, r, warm, cheb=False, pull=False):
     """Algorithmic bytes per site of one launch of a kernel class: every
     population or field word the kernel must read or write once (stencil
     neighbours are reuse, not extra traffic).  The rest population is one
-    plane of t0 bytes (FP64 beside FP64/FP32 storage, FP32 beside BF16/FP16)."""
+    plane of t0 bytes (FP64 beside FP64/FP32 storage, FP32 beside BF16/FP16);
+    BF16/FP16 storage adds a 2-byte density record per site.  The moments
+    kernel writes the exact pulled mass (FP64), which the collision reads in
+    place of the pulled populations when gamma = 0 (pull=False); with
+    gamma != 0 the collision pulls the populations again."""
     nsig = 6 if D == 3 else 3
     nxi = 10 if D == 3 else 4
     t0 = 8 if s >= 4 else 4
-    pops = (Q - 1) * s + t0
+    rec = 2 if s == 2 else 0
+    pops = (Q - 1) * s + t0 + rec
     return {
-        "moments": pops + (1 + D) * r,
+        "moments": pops + (1 + D) * r + 8,
         # warm: 0 zero start, 1 previous j~, 2 extrapolated (history read and written)
         "force": (1 + D) * r + (D * r if warm else 0) + (2 * D * r if warm == 2 else 0) + 4 * D * r + 3 * r,
         "iter_q": (2 + D) * r + nsig * r,
         "iter_jt": (nsig + 1 + 2 * D) * r + 2 * D * r + (D * r if cheb else 0),
         "closure1": (3 + 2 * D) * r + (1 + nsig + D + nxi) * r,
         "closure2": (2 + nsig + 2 * D) * r + nsig * r,
-        "collide": 2 * pops + (1 + 3 * D + nsig + nxi) * r,
+        "collide": (2 * pops if pull else pops + 8) + (1 + 3 * D + nsig + nxi) * r,
         # fused pass: read u, p, P1 and (own site) j~, j0', 1/rho; write j~new
         # and the next pass's u (Chebyshev: also read x_{k-1})
         "iter_fused": (3 + 3 * D) * r + 2 * D * r + (D * r if cheb else 0),
@@ -93,7 +98,7 @@ def run_gpu(workload, storage, steps, warmup, shape=None, profile=True, tol=None
         prof = ctx.profile_read() if profile else None
         stats = ctx.stats()
         out.update(seconds=t1 - t0, prof=prof, stats=stats, N=P.N, Q=P.lattice, D=d, shape=shape,
-                   params=P)
+                   params=P, pull=P.gamma != 0.0)
     return out
 
 
@@ -135,6 +140,7 @@ def run_batch(workload, steps, warmup, fixed_iter, graph=True, limit=None, autot
         prof = ctx.profile_read()
         ctx.profile_enable(False)
         out.update(seconds=t1 - t0, prof=prof, stats=st, N=ctx.N, Q=21, D=2, ndom=len(doms),
+                   pull=any(p.gamma != 0.0 for p in plist),
                    mass_drift=float(np.max(np.abs(tot[:, 0] - tot0[:, 0]) / tot0[:, 0])))
     return out
 
@@ -144,21 +150,22 @@ def roofline(res, storage, warm=2, cheb=False):
     Q, D, N = res["Q"], res["D"], res["N"]
     s = STORE_BYTES[storage]
     r = 8 if storage == "f64" else 4
+    pull = res.get("pull", False)
     total = {k: v[0] for k, v in prof.items()}
     dom = max(total, key=total.get)
     ms, n = prof[dom]
     avg_s = ms / 1e3 / max(n, 1)
-    bytes_launch = site_bytes(dom, Q, D, s, r, warm, cheb) * N
+    bytes_launch = site_bytes(dom, Q, D, s, r, warm, cheb, pull) * N
     achieved = bytes_launch / avg_s / 1e9
     per_kernel = {k: dict(ms_total=round(v[0], 3), launches=v[1],
                           avg_us=round(1e3 * v[0] / max(v[1], 1), 2),
-                          gbs=round(site_bytes(k, Q, D, s, r, warm, cheb) * N / (v[0] / 1e3 / max(v[1], 1)) / 1e9, 1)
+                          gbs=round(site_bytes(k, Q, D, s, r, warm, cheb, pull) * N / (v[0] / 1e3 / max(v[1], 1)) / 1e9, 1)
                           if v[1] else None)
                   for k, v in prof.items()}
     traffic = measured_traffic(dom, res)
     return dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                bytes_per_site=site_bytes(dom, Q, D, s, r, warm, cheb), launches=n,
+                bytes_per_site=site_bytes(dom, Q, D, s, r, warm, cheb, pull), launches=n,
                 avg_launch_us=round(avg_s * 1e6, 2)), per_kernel
 
 

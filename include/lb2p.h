@@ -90,9 +90,9 @@ typedef struct {
 
 typedef struct {
     int lattice;            /* lb2p_lattice                                    */
-    int nx, ny, nz;         /* every side >= 8; nz == 1 for D2Q21; one field
-                               component of a domain below 4 GiB (fewer than
-                               2^29 sites with F64, 2^30 otherwise)            */
+    int nx, ny, nz;         /* every side >= 8; nz == 1 for D2Q21; fewer
+                               than 2^29 sites per domain (its FP64 mass
+                               plane stays below 4 GiB)                        */
     int storage;            /* lb2p_storage                                    */
     double gamma;           /* BGK parameter, -1 < gamma < 1 (Sec. II)         */
     double kappa;           /* interfacial stiffness >= 0 (Sec. II)            */

@@ -18,6 +18,9 @@ FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-adds fused only within one expression, as written: every
+    # rounding follows from the source, the same in every instantiation
+    "-ffp-contract=on",
     "-Wall", "-Wno-unused-function",
 ]
 

@@ -40,16 +40,20 @@ struct Coef {
 
 // Population storage codecs.  Plain forms hold n_i.  The BF16/FP16 forms
 // hold (n_i - o_i) / W_k, the deviation from the rest equilibrium of the site
-// that wrote the value, o_i = w_k(c_s^2(rho)) rho (Sec. III weights at that
-// site's density; the (rho, c_s^2) pair is stored beside the populations),
-// scaled per shell by the reference weight W_k.  What remains is the
-// velocity and non-equilibrium part, small next to W_k, which BF16/FP16
-// resolve far better than the populations themselves.
+// that wrote the value, scaled per shell by the reference weight W_k.  That
+// site keeps a record of its density, rec = fp16(rho - rho_ref), beside the
+// populations, and o_i = P_k(rec) with P_k a cubic fitted on the host to
+// w_k(c_s^2(rho)) rho (Sec. III weights) over the domain's density range.
+// Writer and reader evaluate the same P_k on the same record, so the
+// offsets agree exactly; the fit only decides how small the stored
+// deviation is.  What remains is the velocity and non-equilibrium part,
+// small next to W_k, which BF16/FP16 resolve far better than n_i itself.
 struct DevScale {
-    float off[8];    // w_k(c_s^2(rho_ref)) rho_ref: offsets of the reference state
-    float scl[8];    // W_k
-    float inv[8];    // 1 / W_k
-    float rref, sref;   // rho_ref and c_s^2(rho_ref) (states without a local record)
+    float off[8];       // w_k(c_s^2(rho_ref)) rho_ref
+    float scl[8];       // W_k
+    float inv[8];       // 1 / W_k
+    float rref;         // rho_ref
+    float pc[8][4];     // P_k(d) = pc[k][0] + d (pc[k][1] + d (pc[k][2] + d pc[k][3]))
 };
 
 struct Domain {
@@ -131,33 +135,22 @@ __host__ __device__ inline long long eq_offset_bytes(long long St)
 {
     return (St * (long long)sizeof(typename RestOf<S>::T) + 255) / 256 * 256;
 }
-// After the rest plane: for BF16/FP16 the (rho, c_s^2) record of the site
-// that wrote each value (float2 [S]), then the moving planes.
+// After the rest plane: for BF16/FP16 the density record of the site that
+// wrote each value (fp16 [S]), then the moving planes.
 template <class S>
 __host__ __device__ inline long long moving_offset_bytes(long long St)
 {
-    return eq_offset_bytes<S>(St) + (Codec<S>::kLocal ? (St * 8 + 255) / 256 * 256 : 0);
+    return eq_offset_bytes<S>(St) + (Codec<S>::kLocal ? (St * 2 + 255) / 256 * 256 : 0);
 }
 template <class S>
-__device__ inline float2* eq_plane(S* A, long long St)
+__device__ inline _Float16* eq_plane(S* A, long long St)
 {
-    return reinterpret_cast<float2*>(reinterpret_cast<char*>(A) + eq_offset_bytes<S>(St));
+    return reinterpret_cast<_Float16*>(reinterpret_cast<char*>(A) + eq_offset_bytes<S>(St));
 }
 template <class S>
-__device__ inline const float2* eq_plane(const S* A, long long St)
+__device__ inline const _Float16* eq_plane(const S* A, long long St)
 {
-    return reinterpret_cast<const float2*>(reinterpret_cast<const char*>(A) + eq_offset_bytes<S>(St));
-}
-
-// Offset of a value of shell k written by a site with record e = (rho, c_s^2)
-// (k is a constant once the velocity loops are unrolled, and the other
-// shells fold away).
-template <int Q>
-__device__ __forceinline__ float rest_offset(int k, float2 e)
-{
-    float w[8];
-    shell_weights<Q, float>(e.y, w);
-    return w[k] * e.x;
+    return reinterpret_cast<const _Float16*>(reinterpret_cast<const char*>(A) + eq_offset_bytes<S>(St));
 }
 
 template <class S>
@@ -180,6 +173,17 @@ template <class S>
 __device__ inline const S* moving_planes(const S* A, long long St)
 {
     return reinterpret_cast<const S*>(reinterpret_cast<const char*>(A) + moving_offset_bytes<S>(St));
+}
+
+// Density record of a site and the offset of a value of shell k it wrote.
+__device__ __forceinline__ _Float16 density_record(const DevScale& ds, float rho)
+{
+    return static_cast<_Float16>(rho - ds.rref);
+}
+__device__ __forceinline__ float rest_offset(const DevScale& ds, int k, _Float16 rec)
+{
+    const float d = static_cast<float>(rec);
+    return fmaf(d, fmaf(d, fmaf(d, ds.pc[k][3], ds.pc[k][2]), ds.pc[k][1]), ds.pc[k][0]);
 }
 
 __device__ __forceinline__ int wrap(int v, int n)
@@ -420,7 +424,7 @@ __global__ void __launch_bounds__(256) k_init(const Domain* __restrict__ tab, co
     const R a0 = R(1) - (uu[0] * uu[0] + uu[1] * uu[1] + uu[2] * uu[2]) * R(0.5) * inv;
     using T0 = typename RestOf<S>::T;
     S* const mv = moving_planes(A, St) + o;
-    if constexpr (Codec<S>::kLocal) sto(eq_plane(A, St) + o, i0, make_float2(float(r), float(cs2)));
+    if constexpr (Codec<S>::kLocal) sto(eq_plane(A, St) + o, i0, density_record(dm.ds, float(r)));
     T0 moved = T0(0);
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
@@ -428,11 +432,8 @@ __global__ void __launch_bounds__(256) k_init(const Domain* __restrict__ tab, co
         const R neq = wl[L::shell(i)] * r * (a0 + uc * inv + R(0.5) * uc * uc * inv * inv);
         const unsigned slot = nb.at(-L::cx(i), -L::cy(i), -L::cz(i));
         float off = 0.f;
-        if constexpr (Codec<S>::kLocal) {
-            // the record the slot's own thread writes: its density and c_s^2
-            const float rs = float(ldo(rho + o, slot));
-            off = rest_offset<Q>(L::shell(i), make_float2(rs, float(eos_cs2<R>(dm.cf.eos, R(rs)))));
-        }
+        if constexpr (Codec<S>::kLocal)   // the record the slot's own thread writes
+            off = rest_offset(dm.ds, L::shell(i), density_record(dm.ds, float(ldo(rho + o, slot))));
         const S e = Codec<S>::enc(neq, dm.ds, L::shell(i), off);
         sto(mv + (size_t)(i - 1) * St, slot, e);
         moved += T0(Codec<S>::dec(e, dm.ds, L::shell(i), off));
@@ -450,7 +451,7 @@ __global__ void __launch_bounds__(256) k_moments(const Domain* __restrict__ tab,
                                                  const Tile* __restrict__ tiles,
                                                  const S* __restrict__ A, R* __restrict__ rho,
                                                  R* __restrict__ j0, double* __restrict__ partial,
-                                                 int* __restrict__ flags)
+                                                 int* __restrict__ flags, double* __restrict__ mass)
 {
     using L = Lattice<Q>;
     const Where w = locate(tab, tiles);
@@ -466,30 +467,31 @@ __global__ void __launch_bounds__(256) k_moments(const Domain* __restrict__ tab,
         const long long o = dm.off, St = g.S;
         const NbP nb = make_nbp(g, w.x, w.y, w.z);
         const unsigned i0 = nb.i0;
-        // density accumulated at the rest plane's precision (the conserved sum)
-        using T0 = typename RestOf<S>::T;
-        T0 racc = ldo(rest_plane(A) + o, i0);
+        // density accumulated in FP64: the exact sum of the stored values (the
+        // conserved mass), kept for the collision's mass balance
+        double racc = (double)ldo(rest_plane(A) + o, i0);
         R jx = R(0), jy = R(0), jz = R(0);
         const S* const mv = moving_planes(A, St) + o;
-        const float2* const eqa = eq_plane(A, St) + o;
+        const _Float16* const eqa = eq_plane(A, St) + o;
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
             const unsigned src = nb.at(-L::cx(i), -L::cy(i), -L::cz(i));
             float off = 0.f;
-            if constexpr (Codec<S>::kLocal) off = rest_offset<Q>(L::shell(i), ldo(eqa, src));
+            if constexpr (Codec<S>::kLocal) off = rest_offset(dm.ds, L::shell(i), ldo(eqa, src));
             const R v = Codec<S>::dec(ldo(mv + (size_t)(i - 1) * St, src), dm.ds, L::shell(i), off);
-            racc += T0(v);
+            racc += (double)v;
             if (L::cx(i)) jx += R(L::cx(i)) * v;
             if (L::cy(i)) jy += R(L::cy(i)) * v;
             if (L::cz(i)) jz += R(L::cz(i)) * v;
         }
         const R r = R(racc);
+        sto(mass + o, i0, racc);
         sto(rho + o, i0, r);
         sto(j0 + o, i0, jx);
         sto(j0 + o + St, i0, jy);
         if (L::D == 3) sto(j0 + o + 2 * St, i0, jz);
         if (!(r > R(0) && r < R(1e30))) atomicOr(flags, 1);
-        m[0] = (double)racc; m[1] = jx; m[2] = jy; m[3] = jz;
+        m[0] = racc; m[1] = jx; m[2] = jy; m[3] = jz;
     }
     __shared__ double red[4][16];
     const int tid = threadIdx.x + blockDim.x * threadIdx.y;
@@ -943,7 +945,7 @@ __global__ void __launch_bounds__(256) k_closure2(const Domain* __restrict__ tab
 // Delta^bulk + Delta^int + Delta^corr and store n*_i(r) in the other buffer.
 // Velocities come in antipodal pairs; each pair shares its even part.
 // ---------------------------------------------------------------------------
-template <int Q, class R, class S>
+template <int Q, class R, class S, bool ANY_PULL>
 __global__ void __launch_bounds__(256) k_collide(const Domain* __restrict__ tab,
                                                  const Tile* __restrict__ tiles,
                                                  const SolveInfo* __restrict__ info,
@@ -951,8 +953,11 @@ __global__ void __launch_bounds__(256) k_collide(const Domain* __restrict__ tab,
                                                  const R* __restrict__ rho, const R* __restrict__ u,
                                                  const R* __restrict__ f, const R* __restrict__ jtA,
                                                  const R* __restrict__ jtB, const R* __restrict__ Sig,
-                                                 const R* __restrict__ Xi)
+                                                 const R* __restrict__ Xi, const double* __restrict__ mass)
 {
+    // multiply-adds fused only as written in each expression, so that both
+    // instantiations round a gamma = 0 site identically
+#pragma clang fp contract(on)
     using L = Lattice<Q>;
     constexpr int D = L::D;
     const Where w = locate(tab, tiles);
@@ -1011,21 +1016,30 @@ __global__ void __launch_bounds__(256) k_collide(const Domain* __restrict__ tab,
     const R s0 = -R(0.5) * ic0 * trS;
 
     // Moving velocities first; the rest population then takes what the
-    // collision invariant sum_i Delta_i = 0 (Sec. VI) leaves for it:
-    // n*_0 = n_0 - sum_{i>0} (n*_i - n_i), with the n*_i as stored.  This is
-    // n_0 + Delta_0 in exact arithmetic; the differences are small, so their
-    // rounding is far below that of the populations themselves.
+    // collision invariant sum_i Delta_i = 0 (Sec. VI) leaves for it,
+    // n*_0 = n_0 + sum_{i>0} n_i - sum_{i>0} n*_i with the n*_i as stored, so
+    // the site's mass is kept to the rounding of the rest plane.  With
+    // gamma = 0 the bulk operator relaxes fully: n*_i = n_eq_i + Delta^int_i
+    // + Delta^corr_i does not depend on n_i, the pulled populations are not
+    // read at all, and the mass balance uses the exact pulled mass of item 1.
+    // Otherwise n_i is pulled and n*_0 = n_0 - sum_{i>0} (n*_i - n_i) (small
+    // differences, rounded far below the populations themselves).
+    // uniform per block; instantiated without the pulling path when no
+    // domain of the launch has gamma != 0
+    const bool pull = ANY_PULL && dm.cf.gamma != 0.0;
     const S* const amv = moving_planes(A, St) + o;
     S* const bmv = moving_planes(B, St) + o;
-    const float2* const eqa = eq_plane(A, St) + o;
-    // this site's record for the values it writes: rest offsets w_k(c_s^2) rho
+    const _Float16* const eqa = eq_plane(A, St) + o;
+    // this site's record for the values it writes, and their rest offsets
     float ownoff[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if constexpr (Codec<S>::kLocal) {
-        sto(eq_plane(B, St) + o, i0, make_float2(float(r), float(cs2)));
+        const _Float16 rec = density_record(dm.ds, float(r));
+        sto(eq_plane(B, St) + o, i0, rec);
 #pragma unroll
-        for (int k = 1; k < L::NSHELL; ++k) ownoff[k] = rest_offset<Q>(k, make_float2(float(r), float(cs2)));
+        for (int k = 1; k < L::NSHELL; ++k) ownoff[k] = rest_offset(dm.ds, k, rec);
     }
-    R dsum = R(0);
+    R dsum = R(0);        // pull: sum of (n*_i - n_i)
+    double moved = 0.0;   // no pull: sum of n*_i (exact in FP64)
 #pragma unroll
     for (int p = 0; p < L::NPAIR; ++p) {
         const int ip = 2 * p + 1, im = 2 * p + 2;
@@ -1055,22 +1069,32 @@ __global__ void __launch_bounds__(256) k_collide(const Domain* __restrict__ tab,
         const R Wk = R(dm.cf.Wk[k]);
         const R even = wl[k] * (a0 + a2 * uc * uc) + Wk * (kS * cSc + s0);
         const R odd = wl[k] * a1 * uc + Wk * (bc + kX * cXc);
-        const unsigned sp = nb.at(-cxv, -cyv, -czv), sm = nb.at(cxv, cyv, czv);
-        float offp = 0.f, offm = 0.f;
-        if constexpr (Codec<S>::kLocal) {
-            offp = rest_offset<Q>(k, ldo(eqa, sp));
-            offm = rest_offset<Q>(k, ldo(eqa, sm));
+        R np = R(0), nm = R(0);
+        if (pull) {
+            const unsigned sp = nb.at(-cxv, -cyv, -czv), sm = nb.at(cxv, cyv, czv);
+            float offp = 0.f, offm = 0.f;
+            if constexpr (Codec<S>::kLocal) {
+                offp = rest_offset(dm.ds, k, ldo(eqa, sp));
+                offm = rest_offset(dm.ds, k, ldo(eqa, sm));
+            }
+            np = Codec<S>::dec(ldo(amv + (size_t)(ip - 1) * St, sp), dm.ds, k, offp);
+            nm = Codec<S>::dec(ldo(amv + (size_t)(im - 1) * St, sm), dm.ds, k, offm);
         }
-        const R np = Codec<S>::dec(ldo(amv + (size_t)(ip - 1) * St, sp), dm.ds, k, offp);
-        const R nm = Codec<S>::dec(ldo(amv + (size_t)(im - 1) * St, sm), dm.ds, k, offm);
         const S ep = Codec<S>::enc(gm * np + even + odd, dm.ds, k, ownoff[k]);
         const S em = Codec<S>::enc(gm * nm + even - odd, dm.ds, k, ownoff[k]);
         sto(bmv + (size_t)(ip - 1) * St, i0, ep);
         sto(bmv + (size_t)(im - 1) * St, i0, em);
-        dsum += (Codec<S>::dec(ep, dm.ds, k, ownoff[k]) - np) + (Codec<S>::dec(em, dm.ds, k, ownoff[k]) - nm);
+        const R dp = Codec<S>::dec(ep, dm.ds, k, ownoff[k]), dmm = Codec<S>::dec(em, dm.ds, k, ownoff[k]);
+        if (pull)
+            dsum += (dp - np) + (dmm - nm);
+        else
+            moved += (double)dp + (double)dmm;
     }
     using T0 = typename RestOf<S>::T;
-    sto(rest_plane(B) + o, i0, ldo(rest_plane(A) + o, i0) - T0(dsum));
+    if (pull)
+        sto(rest_plane(B) + o, i0, ldo(rest_plane(A) + o, i0) - T0(dsum));
+    else
+        sto(rest_plane(B) + o, i0, T0(ldo(mass + o, i0) - moved));
 }
 
 // Pre-collision populations of the current state as FP64 [Q][S].
@@ -1088,13 +1112,13 @@ __global__ void __launch_bounds__(256) k_export(const Domain* __restrict__ tab,
     const NbP nb = make_nbp(g, w.x, w.y, w.z);
     const unsigned i0 = nb.i0;
     const S* const mv = moving_planes(A, St) + o;
-    const float2* const eqa = eq_plane(A, St) + o;
+    const _Float16* const eqa = eq_plane(A, St) + o;
     sto(out + o, i0, (double)ldo(rest_plane(A) + o, i0));
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
         const unsigned src = nb.at(-L::cx(i), -L::cy(i), -L::cz(i));
         float off = 0.f;
-        if constexpr (Codec<S>::kLocal) off = rest_offset<Q>(L::shell(i), ldo(eqa, src));
+        if constexpr (Codec<S>::kLocal) off = rest_offset(dm.ds, L::shell(i), ldo(eqa, src));
         sto(out + o + (size_t)i * St, i0, (double)Codec<S>::dec(ldo(mv + (size_t)(i - 1) * St, src), dm.ds,
                                                                 L::shell(i), off));
     }
@@ -1117,13 +1141,13 @@ __global__ void __launch_bounds__(256) k_import(const Domain* __restrict__ tab,
     S* const mv = moving_planes(A, St) + o;
     sto(rest_plane(A) + o, i0, (typename RestOf<S>::T)ldo(in + o, i0));
     // no density is at hand for the slots: every record is the reference
-    // state's, until the first collision writes local ones
-    const float2 eref = make_float2(dm.ds.rref, dm.ds.sref);
+    // density's, until the first collision writes local ones
+    const _Float16 eref = density_record(dm.ds, dm.ds.rref);
     if constexpr (Codec<S>::kLocal) sto(eq_plane(A, St) + o, i0, eref);
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
         float off = 0.f;
-        if constexpr (Codec<S>::kLocal) off = rest_offset<Q>(L::shell(i), eref);
+        if constexpr (Codec<S>::kLocal) off = rest_offset(dm.ds, L::shell(i), eref);
         sto(mv + (size_t)(i - 1) * St, nb.at(-L::cx(i), -L::cy(i), -L::cz(i)),
             Codec<S>::enc((RT)ldo(in + o + (size_t)i * St, i0), dm.ds, L::shell(i), off));
     }

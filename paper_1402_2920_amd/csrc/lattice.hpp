@@ -115,24 +115,27 @@ template <> struct Lattice<21> {
 template <int Q, class R>
 __host__ __device__ inline void shell_weights(R s, R* w)
 {
+    // The polynomials of Tables I and II with every constant divisor folded
+    // into a reciprocal coefficient (a division by a constant is not a
+    // multiplication in IEEE arithmetic and costs a full divide sequence).
     if constexpr (Q == 59) {
-        const R base = s * (R(8) / R(45) - s / R(3) + s * s / R(6));
+        const R base = s * (R(8.0 / 45.0) - s * R(1.0 / 3.0) + s * s * R(1.0 / 6.0));
         w[1] = R(2) * base;
         w[2] = base;
-        w[3] = s / R(12) * (R(-16) / R(15) + R(4) * s - R(2.5) * s * s);
-        w[4] = s / R(96) * (R(-24) / R(5) + R(17) * s - R(9) * s * s);
-        w[5] = s / R(192) * (R(-8) / R(15) + s + s * s);
-        w[6] = s / R(192) * (R(4) / R(15) - s + s * s);
-        w[7] = s / R(384) * (R(4) / R(15) - s + s * s);
+        w[3] = s * R(1.0 / 12.0) * (R(-16.0 / 15.0) + R(4) * s - R(2.5) * s * s);
+        w[4] = s * R(1.0 / 96.0) * (R(-24.0 / 5.0) + R(17) * s - R(9) * s * s);
+        w[5] = s * R(1.0 / 192.0) * (R(-8.0 / 15.0) + s + s * s);
+        w[6] = s * R(1.0 / 192.0) * (R(4.0 / 15.0) - s + s * s);
+        w[7] = s * R(1.0 / 384.0) * (R(4.0 / 15.0) - s + s * s);
         w[0] = R(1) - (R(6) * w[1] + R(12) * w[2] + R(8) * w[3] + R(6) * w[4] +
                        R(12) * w[5] + R(8) * w[6] + R(6) * w[7]);
     } else {
-        w[0] = R(1) - R(22.5) * s * (R(7) / R(60) - R(7) / R(48) * s + s * s / R(16));
-        w[1] = s / R(3) * (R(32) / R(15) - R(4) * s + R(2) * s * s);
-        w[2] = s * (s / R(3) - s * s / R(4));
-        w[3] = s * (R(-1) / R(18) + R(3) / R(16) * s - s * s / R(12));
-        w[4] = s / R(96) * (R(-0.5) * s + R(1.5) * s * s);
-        w[5] = s / R(384) * (R(4) / R(15) - s + s * s);
+        w[0] = R(1) - R(22.5) * s * (R(7.0 / 60.0) - R(7.0 / 48.0) * s + s * s * R(1.0 / 16.0));
+        w[1] = s * R(1.0 / 3.0) * (R(32.0 / 15.0) - R(4) * s + R(2) * s * s);
+        w[2] = s * (s * R(1.0 / 3.0) - s * s * R(0.25));
+        w[3] = s * (R(-1.0 / 18.0) + R(3.0 / 16.0) * s - s * s * R(1.0 / 12.0));
+        w[4] = s * R(1.0 / 96.0) * (R(-0.5) * s + R(1.5) * s * s);
+        w[5] = s * R(1.0 / 384.0) * (R(4.0 / 15.0) - s + s * s);
     }
 }
 

@@ -101,11 +101,12 @@ lb2p_status check_params(const lb2p_params& p)
     return p.lattice == LB2P_D3Q59 ? check_eos<59>(p) : check_eos<21>(p);
 }
 
-void set_devscale(DevScale& ds, int Q, const EosParams& eos, double rref)
+// Reduced-storage scales of a domain: W_k at rho_ref, and the cubics P_k
+// fitted (least squares, 201 points) to w_k(c_s^2(rho)) rho over [lo, hi].
+void set_devscale(DevScale& ds, int Q, const EosParams& eos, double rref, double lo, double hi)
 {
     const double cs2 = eos_cs2<double>(eos, rref);
     ds.rref = (float)rref;
-    ds.sref = (float)cs2;
     double w[8] = {0};
     if (Q == 59) shell_weights<59, double>(cs2, w);
     else shell_weights<21, double>(cs2, w);
@@ -114,6 +115,41 @@ void set_devscale(DevScale& ds, int Q, const EosParams& eos, double rref)
         ds.off[k] = (float)(wk * rref);
         ds.scl[k] = (float)wk;
         ds.inv[k] = (float)(1.0 / wk);
+        for (int j = 0; j < 4; ++j) ds.pc[k][j] = 0.f;
+    }
+    const int nshell = Q == 59 ? 8 : 6;
+    const double h = std::fmax(std::fmax(rref - lo, hi - rref), 1e-3);   // fit in t = d / h
+    for (int k = 1; k < nshell; ++k) {
+        double ata[4][5] = {};
+        for (int m = 0; m <= 200; ++m) {
+            const double t = -1.0 + m / 100.0, r = rref + h * t;
+            double wr[8] = {0};
+            if (Q == 59) shell_weights<59, double>(eos_cs2<double>(eos, r), wr);
+            else shell_weights<21, double>(eos_cs2<double>(eos, r), wr);
+            const double f = wr[k] * r;
+            const double pw[4] = {1.0, t, t * t, t * t * t};
+            for (int a = 0; a < 4; ++a) {
+                for (int b = 0; b < 4; ++b) ata[a][b] += pw[a] * pw[b];
+                ata[a][4] += pw[a] * f;
+            }
+        }
+        // Gaussian elimination with partial pivoting on the 4x4 normal equations
+        for (int col = 0; col < 4; ++col) {
+            int piv = col;
+            for (int r = col + 1; r < 4; ++r)
+                if (std::fabs(ata[r][col]) > std::fabs(ata[piv][col])) piv = r;
+            for (int c2 = 0; c2 < 5; ++c2) std::swap(ata[col][c2], ata[piv][c2]);
+            for (int r = 0; r < 4; ++r) {
+                if (r == col) continue;
+                const double fct = ata[r][col] / ata[col][col];
+                for (int c2 = col; c2 < 5; ++c2) ata[r][c2] -= fct * ata[col][c2];
+            }
+        }
+        double hj = 1.0;
+        for (int j = 0; j < 4; ++j) {
+            ds.pc[k][j] = (float)(ata[j][4] / ata[j][j] / hj);
+            hj *= h;
+        }
     }
 }
 
@@ -172,6 +208,8 @@ struct lb2p_ctx {
     void* u = nullptr; void* jt0 = nullptr; void* jt1 = nullptr; void* q = nullptr;
     void* X = nullptr; void* T = nullptr; void* Y = nullptr; void* Xi = nullptr; void* Sig = nullptr;
     void* pf = nullptr;          // p, P1, 1/rho planes (fixed during the j~ solve)
+    double* mass = nullptr;      // exact pulled mass per site (item 1, FP64)
+    bool any_pull = false;       // some domain has gamma != 0 (collision pulls n_i)
     void* u1 = nullptr;          // second u buffer of the fused solve passes
     double* omega = nullptr;     // Chebyshev weights [ndom][stride], or null
     // tiles
@@ -423,7 +461,7 @@ struct Impl {
         ProfScope _ps(c, LB2P_K_MOMENTS);
         hipLaunchKernelGGL((k_moments<Q, R, S>), sgrid(c), sblock(c), 0, c->stream, c->dtab,
                            c->site_tiles, (const S*)c->A, write_fields ? (R*)c->rho : (R*)c->X,
-                           write_fields ? (R*)c->j0 : (R*)c->T, c->partial, c->flags);
+                           write_fields ? (R*)c->j0 : (R*)c->T, c->partial, c->flags, c->mass);
     }
 
     // Items 1-8.  In the default (tolerance) mode the host reads how many
@@ -546,10 +584,11 @@ struct Impl {
         }
         {
             ProfScope _ps(c, LB2P_K_COLLIDE);
-            hipLaunchKernelGGL((k_collide<Q, R, S>), sgrid(c), sblock(c), 0, c->stream, c->dtab,
+            auto kc = c->any_pull ? k_collide<Q, R, S, true> : k_collide<Q, R, S, false>;
+            hipLaunchKernelGGL(kc, sgrid(c), sblock(c), 0, c->stream, c->dtab,
                                c->site_tiles, (const SolveInfo*)c->info, (const S*)c->A, (S*)c->B,
                                (const R*)c->rho, (const R*)c->u, (const R*)c->f, (const R*)c->jt0,
-                               (const R*)c->jt1, (const R*)c->Sig, (const R*)c->Xi);
+                               (const R*)c->jt1, (const R*)c->Sig, (const R*)c->Xi, (const double*)c->mass);
         }
         HIPCHK(hipGetLastError());
         std::swap(c->A, c->B);
@@ -667,6 +706,7 @@ void free_ctx(lb2p_ctx* c)
     if (c->dtab) (void)hipFree(c->dtab);
     if (c->omega) (void)hipFree(c->omega);
     if (c->jhist) (void)hipFree(c->jhist);
+    if (c->mass) (void)hipFree(c->mass);
     if (c->site_tiles) (void)hipFree(c->site_tiles);
     if (c->fused_tiles) (void)hipFree(c->fused_tiles);
     if (c->host) (void)hipHostFree(c->host);
@@ -758,14 +798,16 @@ lb2p_status create_impl(int ndom, const lb2p_params* pp, void* hip_stream, lb2p_
         Domain dm{};
         dm.g.nx = p.nx; dm.g.ny = p.ny; dm.g.nz = p.nz;
         dm.g.N = (long long)p.nx * p.ny * p.nz;
-        // kernels address one component plane of a domain with 32-bit byte offsets
-        if ((unsigned long long)dm.g.N * (p0.storage == LB2P_STORE_F64 ? 8ull : 4ull) >= (1ull << 32)) {
+        // kernels address one component plane of a domain with 32-bit byte
+        // offsets; the widest plane is the FP64 mass
+        if ((unsigned long long)dm.g.N * 8ull >= (1ull << 32)) {
             delete c;
             return LB2P_EINVAL;
         }
         dm.off = off;
         off += dm.g.N;
         dm.cf.gamma = p.gamma;
+        if (p.gamma != 0.0) c->any_pull = true;
         dm.cf.kappa = p.kappa;
         dm.cf.eos = make_eos(p.eos);
         dm.cf.c0sq = eos_cs2<double>(dm.cf.eos, p.rho0);
@@ -777,7 +819,10 @@ lb2p_status create_impl(int ndom, const lb2p_params* pp, void* hip_stream, lb2p_
             if (!(w[k] > 0.0)) { delete c; return LB2P_EEOS; }
             dm.cf.Wk[k] = w[k];
         }
-        set_devscale(dm.ds, c->Q, dm.cf.eos, p.store_rho_ref > 0.0 ? p.store_rho_ref : p.rho0);
+        {
+            const double r0 = p.store_rho_ref > 0.0 ? p.store_rho_ref : p.rho0;
+            set_devscale(dm.ds, c->Q, dm.cf.eos, r0, 0.75 * r0, 1.25 * r0);
+        }
         {
             const double b = p.spectral_bound > 0.0 ? p.spectral_bound
                                                     : spectral_bound_from_eos(c->D, dm.cf.eos, p.eos);
@@ -818,6 +863,7 @@ lb2p_status create_impl(int ndom, const lb2p_params* pp, void* hip_stream, lb2p_
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->host, sizeof(lb2p_ctx::HostScratch), hipHostMallocDefault);
     if (e == hipSuccess && p0.solver == LB2P_SOLVER_CHEBYSHEV)
         e = hipMalloc((void**)&c->omega, sizeof(double) * nres);
+    if (e == hipSuccess) e = hipMalloc((void**)&c->mass, sizeof(double) * (size_t)S);
     if (e == hipSuccess && p0.warm_start == 2) {
         e = hipMalloc(&c->jhist, (size_t)D * S * c->rsize);
         if (e == hipSuccess) e = hipMemsetAsync(c->jhist, 0, (size_t)D * S * c->rsize, c->stream);
@@ -1015,10 +1061,13 @@ lb2p_status lb2p_init(lb2p_ctx* c, const void* rho, const void* u, int dtype, in
     if (st != LB2P_OK) return st;
     // deviation-storage reference per domain: the given value, else the
     // domain's mean initial density (host FP64 sum)
-    bool need_mean = false;
-    for (const auto& p : c->dprm) need_mean |= !(p.store_rho_ref > 0.0);
+    // the density range of every domain (for the reduced-storage offsets)
+    // and, where no reference density is given, its mean
+    const bool need_rho = c->prm.storage == LB2P_STORE_BF16 || c->prm.storage == LB2P_STORE_F16 ||
+                          std::any_of(c->dprm.begin(), c->dprm.end(),
+                                      [](const lb2p_params& p) { return !(p.store_rho_ref > 0.0); });
     std::vector<double> hrho;
-    if (need_mean) {
+    if (need_rho) {
         hrho.resize(c->S);
         if (c->rsize == 8) {
             HIPCHK(hipMemcpyAsync(hrho.data(), c->rho, c->S * 8, hipMemcpyDeviceToHost, c->stream));
@@ -1032,13 +1081,22 @@ lb2p_status lb2p_init(lb2p_ctx* c, const void* rho, const void* u, int dtype, in
     }
     for (int d = 0; d < c->ndom; ++d) {
         double rref = c->dprm[d].store_rho_ref;
-        if (!(rref > 0.0)) {
-            double acc = 0.0;
+        double lo = 0.75 * rref, hi = 1.25 * rref;
+        if (need_rho) {
+            double acc = 0.0, mn = 1e300, mx = -1e300;
             const Domain& dm = c->dom[d];
-            for (long long k = 0; k < dm.g.N; ++k) acc += hrho[dm.off + k];
-            rref = acc / (double)dm.g.N;
+            for (long long k = 0; k < dm.g.N; ++k) {
+                const double v = hrho[dm.off + k];
+                acc += v;
+                mn = std::fmin(mn, v);
+                mx = std::fmax(mx, v);
+            }
+            if (!(rref > 0.0)) rref = acc / (double)dm.g.N;
+            const double pad = 0.05 + 0.25 * (mx - mn);
+            lo = mn - pad;
+            hi = mx + pad;
         }
-        set_devscale(c->dom[d].ds, c->Q, c->dom[d].cf.eos, rref);
+        set_devscale(c->dom[d].ds, c->Q, c->dom[d].cf.eos, rref, lo, hi);
     }
     HIPCHK(hipMemcpyAsync(c->dtab, c->dom.data(), c->ndom * sizeof(Domain), hipMemcpyHostToDevice, c->stream));
     dispatch(c, [&](auto impl) { decltype(impl)::launch_init(c); });
