@@ -53,9 +53,9 @@ def site_bytes(kernel, Q, D, s, r, warm, cheb=False, pull=False):
         "closure1": (3 + 2 * D) * r + (1 + nsig + D + nxi) * r,
         "closure2": (2 + nsig + 2 * D) * r + nsig * r,
         "collide": (2 * pops if pull else pops + 8) + (1 + 3 * D + nsig + nxi) * r,
-        # fused pass: read u, p, P1 and (own site) j~, j0', 1/rho; write j~new
-        # and the next pass's u (Chebyshev: also read x_{k-1})
-        "iter_fused": (3 + 3 * D) * r + 2 * D * r + (D * r if cheb else 0),
+        # fused pass (velocity form): read u, p, P1 and (own site) j0', rho;
+        # write the next u (Chebyshev: also read u_{k-1})
+        "iter_fused": (3 + 2 * D) * r + D * r + (D * r if cheb else 0),
     }[kernel]
 
 

@@ -1,17 +1,25 @@
 // kernels_fused.hpp -- one kernel per pass of the correction-current
-// iteration (Supplemental items 3-6) for D3Q59.
+// iteration (Supplemental items 3-6) for D3Q59, carried in velocity form.
+//
+// The pass maps u_k = (j0' + x_k)/rho to u_{k+1} = (j0' + G(x_k))/rho, where
+// G(x) = -(1/12) d_b q_ab depends on x only through u (item 4 builds q from
+// u).  This is the iteration of items 3-6 with the iterate stored as u: the
+// map x -> u is affine with fixed j0' and rho, and both the plain and the
+// Chebyshev update are affine combinations of iterates, so the sequence is
+// the same up to rounding.  The stop rule's |G(x_k) - x_k| is evaluated as
+// |G + j0' - rho u_k|, and the final x = rho u - j0' is formed once after
+// the last pass.  Each pass then reads u (stencil), p and P1 (stencil; both
+// evaluated once per step) and, at its own point, j0' and rho, and writes
+// the next u (the Chebyshev form also reads u_{k-1}, which it overwrites in
+// place).
 //
 // A block owns a TX x TY tile of an xy plane and marches through TZ planes of
 // z.  Its threads are the (TX+4) x (TY+4) points where q is needed (the tile
 // and a 2-wide frame for the outer first derivative).  Each thread keeps, in
-// registers, the last five planes of u at its point (z-derivatives of u) and
-// of q_az (z-derivative in d_b q_ab); LDS holds one u plane (tile + 4-wide
-// frame) and one q plane (tile + 2-wide frame) for the x and y derivatives.
-// Per pass every site reads u (at the q and frame points), p and P1 (at the
-// q points; both evaluated once per step) and, at its own point, j~, j0' and
-// 1/rho, and writes j~new and the next pass's u = (j0' + j~new)/rho (u is
-// double-buffered like j~); the Chebyshev form also reads x_{k-1}, which it
-// overwrites in place.
+// registers, the last five planes of u at its point (z-derivatives of u, and
+// u_k at the output plane) and of q_az (z-derivative in d_b q_ab); LDS holds
+// one u plane (tile + 4-wide frame) and one q plane (tile + 2-wide frame)
+// for the x and y derivatives.
 #pragma once
 
 #include "kernels.hpp"
@@ -52,8 +60,8 @@ __device__ __forceinline__ void st(R* base, unsigned i, R v)
 template <class R, int TX, int TY, bool CHEB>
 __global__ void __launch_bounds__((TX + 4) * (TY + 4))
 k_iter_fused3(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, IterCtl ic, int it,
-              const R* __restrict__ pf, const R* __restrict__ j0p, const R* __restrict__ jt_old,
-              const R* __restrict__ u_old, R* jt_new, R* __restrict__ u_new)
+              const R* __restrict__ pf, const R* __restrict__ rho, const R* __restrict__ j0p,
+              const R* __restrict__ u_old, R* u_new)
 {
     constexpr int QX = TX + 4, QY = TY + 4;   // q points
     constexpr int UX = TX + 8, UY = TY + 8;   // u points
@@ -70,19 +78,13 @@ k_iter_fused3(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, It
     const unsigned plane = (unsigned)nx * (unsigned)ny;
     const R* const pP = pf + dm.off;
     const R* const pP1 = pP + N;
-    const R* const pRi = pP1 + N;
+    const R* const pRho = rho + dm.off;
     const R* const j0x = j0p + dm.off;
     const R* const j0y = j0x + N;
     const R* const j0z = j0y + N;
-    const R* const tx_ = jt_old + dm.off;
-    const R* const ty_ = tx_ + N;
-    const R* const tz_ = ty_ + N;
     const R* const ux = u_old + dm.off;
     const R* const uy = ux + N;
     const R* const uz = uy + N;
-    R* const ox = jt_new + dm.off;
-    R* const oy = ox + N;
-    R* const oz = oy + N;
     R* const vx = u_new + dm.off;
     R* const vy = vx + N;
     R* const vz = vy + N;
@@ -122,7 +124,7 @@ k_iter_fused3(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, It
     // addressed by a compile-time phase avoid the moves but need the loop
     // unrolled five times, which costs registers and, measured, occupancy
     // and time.)
-    R ur[5][3];        // u at planes lead-4 .. lead
+    R ur[5][3];        // u at planes lead-4 .. lead (lead-4 is the output plane)
     R qz[5][3];        // q_xz, q_yz, q_zz at planes c-4 .. c
     R sd[3][3];        // x,y part of d_b q_ab at planes c-2 .. c
 #pragma unroll
@@ -141,16 +143,14 @@ k_iter_fused3(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, It
     R nu[3] = {R(0), R(0), R(0)};                 // u, own point, lead plane
     R np = R(0), nP1 = R(0);                      // p, P1, own point, centre plane
     R fu[3] = {R(0), R(0), R(0)};                 // u, frame point, centre plane
-    R no[3] = {R(0), R(0), R(0)};                 // x_k, own point, output plane
-    R nv[3] = {R(0), R(0), R(0)};                 // x_{k-1} there (Chebyshev)
-    R nj[3] = {R(0), R(0), R(0)}, nri = R(0);     // j0' and 1/rho there
+    R nv[3] = {R(0), R(0), R(0)};                 // u_{k-1}, own point, output plane (Chebyshev)
+    R nj[3] = {R(0), R(0), R(0)}, nrho = R(1);    // j0' and rho there
     auto load_step = [&](int k) {
         if (k >= 8 && owned && z0 + k - 8 < nz) {
             const unsigned io = col + plane * (unsigned)(z0 + k - 8);
-            no[0] = ld(tx_, io); no[1] = ld(ty_, io); no[2] = ld(tz_, io);
             nj[0] = ld(j0x, io); nj[1] = ld(j0y, io); nj[2] = ld(j0z, io);
-            nri = ld(pRi, io);
-            if (CHEB && it > 0) { nv[0] = ld<R>(ox, io); nv[1] = ld<R>(oy, io); nv[2] = ld<R>(oz, io); }
+            nrho = ld(pRho, io);
+            if (CHEB && it > 0) { nv[0] = ld<R>(vx, io); nv[1] = ld<R>(vy, io); nv[2] = ld<R>(vz, io); }
         }
         const unsigned i = col + plane * (unsigned)wrap3(z0 - 4 + k, nz);
         nu[0] = ld(ux, i); nu[1] = ld(uy, i); nu[2] = ld(uz, i);
@@ -169,10 +169,9 @@ k_iter_fused3(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, It
         const R cur_u[3] = {nu[0], nu[1], nu[2]};
         const R cur_p = np, cur_P1 = nP1;
         const R cur_fu[3] = {fu[0], fu[1], fu[2]};
-        const R cur_o[3] = {no[0], no[1], no[2]};
         const R cur_v[3] = {nv[0], nv[1], nv[2]};
         const R cur_j[3] = {nj[0], nj[1], nj[2]};
-        const R cur_ri = nri;
+        const R cur_rho = nrho;
         if (k + 1 < nsteps) load_step(k + 1);
         // 1. lead plane of the u ring at this thread's point
 #pragma unroll
@@ -231,21 +230,21 @@ k_iter_fused3(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, It
             const int zo = z0 + k - 8;
             if (k >= 8 && owned && zo < z0 + TZ && zo < nz) {
                 const unsigned i = col + plane * (unsigned)zo;
-                R xn[3];
+                const R ri = R(1) / cur_rho;
+                R un[3];
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
                     const R dz = d1<R>(qz[0][a], qz[1][a], qz[3][a], qz[4][a]);
-                    const R gv = -(sd[0][a] + dz) * c12;
-                    const R d = fabs(gv - cur_o[a]);
+                    const R gv = -(sd[0][a] + dz) * c12;          // G(x_k)_a
+                    // item 6: |G(x_k) - x_k| with x_k = rho u_k - j0'
+                    const R d = fabs(gv + cur_j[a] - cur_rho * ur[0][a]);
                     dmax = fmax(dmax, d);
                     dsum += d;
-                    xn[a] = CHEB ? next_iterate<R>(gv, cur_o[a], cur_v[a], omega, gam, it == 0) : gv;
+                    // item 3 of the next pass: u = (j0' + G)/rho
+                    const R gu = (cur_j[a] + gv) * ri;
+                    un[a] = CHEB ? next_iterate<R>(gu, ur[0][a], cur_v[a], omega, gam, it == 0) : gu;
                 }
-                st(ox, i, xn[0]); st(oy, i, xn[1]); st(oz, i, xn[2]);
-                // item 3 of the next pass: u = (j0' + j~)/rho
-                st(vx, i, (cur_j[0] + xn[0]) * cur_ri);
-                st(vy, i, (cur_j[1] + xn[1]) * cur_ri);
-                st(vz, i, (cur_j[2] + xn[2]) * cur_ri);
+                st(vx, i, un[0]); st(vy, i, un[1]); st(vz, i, un[2]);
             }
         }
     }
@@ -271,6 +270,35 @@ __global__ void __launch_bounds__(256) k_u_final(const Domain* __restrict__ tab,
     const R inv = R(1) / rho[i0];
 #pragma unroll
     for (int a = 0; a < L::D; ++a) u[a * St + i0] = (j0p[a * St + i0] + jt[a * St + i0]) * inv;
+}
+
+// The velocity-form solve ends with u_final in u (even pass count) or u1
+// (odd): x = rho u - j0' (the correction current of items 7-12) goes to the
+// j~ buffer the pass count selects, as in the current form, and u_final to u.
+template <int Q, class R>
+__global__ void __launch_bounds__(256) k_jt_final(const Domain* __restrict__ tab,
+                                                  const Tile* __restrict__ tiles,
+                                                  const SolveInfo* __restrict__ info,
+                                                  const R* __restrict__ rho, const R* __restrict__ j0p,
+                                                  R* __restrict__ u0, const R* __restrict__ u1,
+                                                  R* __restrict__ jtA, R* __restrict__ jtB)
+{
+    using L = Lattice<Q>;
+    const Where w = locate(tab, tiles);
+    if (!w.ok) return;
+    const Domain& dm = tab[w.dom];
+    const long long St = dm.g.S;
+    const long long i0 = dm.off + sidx(dm.g, w.x, w.y, w.z);
+    const bool odd = info[w.dom].final_buf != 0;   // uniform per block
+    const R* uf = odd ? u1 : u0;
+    R* jt = odd ? jtB : jtA;
+    const R r = rho[i0];
+#pragma unroll
+    for (int a = 0; a < L::D; ++a) {
+        const R v = uf[a * St + i0];
+        jt[a * St + i0] = r * v - j0p[a * St + i0];
+        if (odd) u0[a * St + i0] = v;
+    }
 }
 
 }  // namespace lb2p

@@ -509,11 +509,11 @@ struct Impl {
                 if (c->omega)
                     hipLaunchKernelGGL((k_iter_fused3<R, kFusedTX, kFusedTY, true>), fgrid, fblock, 0,
                                        c->stream, c->dtab, c->fused_tiles, ic, it, (const R*)c->pf,
-                                       (const R*)c->j0p, (const R*)jold, (const R*)uold, jnew, unew);
+                                       (const R*)c->rho, (const R*)c->j0p, (const R*)uold, unew);
                 else
                     hipLaunchKernelGGL((k_iter_fused3<R, kFusedTX, kFusedTY, false>), fgrid, fblock, 0,
                                        c->stream, c->dtab, c->fused_tiles, ic, it, (const R*)c->pf,
-                                       (const R*)c->j0p, (const R*)jold, (const R*)uold, jnew, unew);
+                                       (const R*)c->rho, (const R*)c->j0p, (const R*)uold, unew);
             } else {
                 {
                     ProfScope _ps(c, LB2P_K_ITER_Q);
@@ -544,9 +544,14 @@ struct Impl {
         }
         hipLaunchKernelGGL(k_iter_finish, dim3((c->ndom + 255) / 256), dim3(256), 0, c->stream, ic,
                            launched, c->ndom, c->info, c->nconv);
-        hipLaunchKernelGGL((k_u_final<Q, R>), sgrid(c), sblock(c), 0, c->stream, c->dtab,
-                           c->site_tiles, (const SolveInfo*)c->info, (const R*)c->rho,
-                           (const R*)c->j0p, (const R*)c->jt0, (const R*)c->jt1, (R*)c->u);
+        if (fused)
+            hipLaunchKernelGGL((k_jt_final<Q, R>), sgrid(c), sblock(c), 0, c->stream, c->dtab,
+                               c->site_tiles, (const SolveInfo*)c->info, (const R*)c->rho,
+                               (const R*)c->j0p, (R*)c->u, (const R*)c->u1, (R*)c->jt0, (R*)c->jt1);
+        else
+            hipLaunchKernelGGL((k_u_final<Q, R>), sgrid(c), sblock(c), 0, c->stream, c->dtab,
+                               c->site_tiles, (const SolveInfo*)c->info, (const R*)c->rho,
+                               (const R*)c->j0p, (const R*)c->jt0, (const R*)c->jt1, (R*)c->u);
         HIPCHK(hipGetLastError());
         if (p.fixed_iter <= 0) {
             HIPCHK(hipMemcpyAsync(&c->host->nconv, c->nconv, sizeof(int), hipMemcpyDeviceToHost,
