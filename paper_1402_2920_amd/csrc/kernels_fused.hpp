@@ -43,22 +43,59 @@ __device__ __forceinline__ int wrapmod(int v, int n)
     return v < 0 ? v + n : v;
 }
 
-// Element i of a component plane: a uniform base plus a 32-bit byte offset
-// (the host keeps one plane of a domain under 4 GiB for this kernel), which
-// lets loads use the scalar-base addressing form instead of 64-bit VALU math.
-template <class R>
-__device__ __forceinline__ R ld(const R* base, unsigned i)
+// One component plane of a domain as a raw buffer resource (stride 0, the
+// plane's byte size as its range).  A load at an offset at or past the range
+// returns 0 and a store there is dropped by the hardware's range check, so
+// every lane can issue every load and store of a step: a lane with nothing to
+// read or write passes the offset `range` itself.  With no load or store
+// under a branch, the compiler counts outstanding memory operations exactly
+// and can wait for one step's loads while the next step's are still in
+// flight.  (Planes stay below 4 GiB: the host limits a domain to fewer than
+// 2^29 sites.)
+struct PlaneBuf {
+    __amdgpu_buffer_rsrc_t rs;
+    unsigned range;
+};
+__device__ __forceinline__ PlaneBuf plane_buf(const void* base, unsigned bytes)
 {
-    return *reinterpret_cast<const R*>(reinterpret_cast<const char*>(base) + i * (unsigned)sizeof(R));
+    // dword 3 of the resource: 32-bit data format (the gfx9 raw-buffer value)
+    return PlaneBuf{__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000),
+                    bytes};
 }
 template <class R>
-__device__ __forceinline__ void st(R* base, unsigned i, R v)
+__device__ __forceinline__ R bload(const PlaneBuf& b, unsigned off)
 {
-    *reinterpret_cast<R*>(reinterpret_cast<char*>(base) + i * (unsigned)sizeof(R)) = v;
+    if constexpr (sizeof(R) == 4) {
+        return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b32(b.rs, (int)off, 0, 0));
+    } else {
+        typedef unsigned u2 __attribute__((ext_vector_type(2)));
+        return __builtin_bit_cast(R, (u2)__builtin_amdgcn_raw_buffer_load_b64(b.rs, (int)off, 0, 0));
+    }
+}
+template <class R>
+__device__ __forceinline__ void bstore(const PlaneBuf& b, unsigned off, R v)
+{
+    if constexpr (sizeof(R) == 4) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), b.rs, (int)off, 0, 0);
+    } else {
+        typedef unsigned u2 __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), b.rs, (int)off, 0, 0);
+    }
 }
 
+// Inputs of one z step, loaded two steps ahead.
+template <class R>
+struct StepIn {
+    R u[3];      // u, own point, lead plane
+    R p, P1;     // p, P1, own point, centre plane
+    R fu[3];     // u, frame point, centre plane
+    R j[3];      // j0', own point, output plane
+    R rho;       // rho there
+    R v[3];      // u_{k-1} there (Chebyshev)
+};
+
 template <class R, int TX, int TY, bool CHEB>
-__global__ void __launch_bounds__((TX + 4) * (TY + 4))
+__global__ void __launch_bounds__((TX + 4) * (TY + 4)) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 1)))
 k_iter_fused3(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, IterCtl ic, int it,
               const R* __restrict__ pf, const R* __restrict__ rho, const R* __restrict__ j0p,
               const R* __restrict__ u_old, R* u_new)
@@ -76,30 +113,50 @@ k_iter_fused3(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, It
     const int nx = dm.g.nx, ny = dm.g.ny, nz = dm.g.nz;
     const long long N = dm.g.S;   // component stride
     const unsigned plane = (unsigned)nx * (unsigned)ny;
-    const R* const pP = pf + dm.off;
-    const R* const pP1 = pP + N;
-    const R* const pRho = rho + dm.off;
-    const R* const j0x = j0p + dm.off;
-    const R* const j0y = j0x + N;
-    const R* const j0z = j0y + N;
-    const R* const ux = u_old + dm.off;
-    const R* const uy = ux + N;
-    const R* const uz = uy + N;
-    R* const vx = u_new + dm.off;
-    R* const vy = vx + N;
-    R* const vz = vy + N;
+    const unsigned bytes = (unsigned)dm.g.N * (unsigned)sizeof(R);
+    const PlaneBuf bP = plane_buf(pf + dm.off, bytes);
+    const PlaneBuf bP1 = plane_buf(pf + dm.off + N, bytes);
+    const PlaneBuf bRho = plane_buf(rho + dm.off, bytes);
+    const PlaneBuf bJ[3] = {plane_buf(j0p + dm.off, bytes), plane_buf(j0p + dm.off + N, bytes),
+                            plane_buf(j0p + dm.off + 2 * N, bytes)};
+    const PlaneBuf bU[3] = {plane_buf(u_old + dm.off, bytes), plane_buf(u_old + dm.off + N, bytes),
+                            plane_buf(u_old + dm.off + 2 * N, bytes)};
+    const PlaneBuf bV[3] = {plane_buf(u_new + dm.off, bytes), plane_buf(u_new + dm.off + N, bytes),
+                            plane_buf(u_new + dm.off + 2 * N, bytes)};
+    const unsigned OUT = bytes;   // an offset outside every plane
     R omega = R(1), gam = R(1);
     if (CHEB) {
         omega = R(ic.omega[(long long)tl.dom * ic.stride + it]);
         gam = R(dm.cf.cheb_gamma);
     }
-    const int lx = threadIdx.x, ly = threadIdx.y;
-    const int tid = lx + QX * ly;
+    // q point (qx, qy) of this thread in the QX x QY region: the TX x TY
+    // tile points first (whole wavefronts when TX * TY is a multiple of 64,
+    // so the output step is uniform per wavefront and a wavefront reads whole
+    // rows), then the 2-wide frame around them
+    static_assert((TX * TY) % 64 == 0, "tile points must fill whole wavefronts");
+    const int tid = threadIdx.x + QX * threadIdx.y;
+    int qx, qy;
+    // uniform per wavefront (the compiler then branches on it)
+    const bool interior = __builtin_amdgcn_readfirstlane(tid >> 6) < (TX * TY) / 64;
+    if (interior) {
+        qx = 2 + tid % TX; qy = 2 + tid / TX;
+    } else {
+        const int e = tid - TX * TY;
+        if (e < 2 * QX) {                    // two rows at the bottom
+            qy = e / QX; qx = e % QX;
+        } else if (e < 4 * QX) {             // two rows at the top
+            qy = QY - 4 + e / QX; qx = e % QX;
+        } else {                             // two columns left, two right
+            const int t = e - 4 * QX;
+            const int c = t % 4;
+            qy = 2 + t / 4;
+            qx = c < 2 ? c : QX - 4 + c;
+        }
+    }
     const int x0 = tl.x0, y0 = tl.y0, z0 = tl.z0, TZ = tl.len;
-    const int gx = wrapmod(x0 + lx - 2, nx), gy = wrapmod(y0 + ly - 2, ny);
+    const int gx = wrapmod(x0 + qx - 2, nx), gy = wrapmod(y0 + qy - 2, ny);
     const unsigned col = (unsigned)gx + (unsigned)nx * (unsigned)gy;
-    const bool interior = lx >= 2 && lx < TX + 2 && ly >= 2 && ly < TY + 2;
-    const bool owned = interior && (x0 + lx - 2 < nx) && (y0 + ly - 2 < ny);
+    const bool owned = interior && (x0 + qx - 2 < nx) && (y0 + qy - 2 < ny);
 
     // this thread's u-frame point (outer 2-wide ring of the UX x UY region)
     int fx = 0, fy = 0;
@@ -138,86 +195,98 @@ k_iter_fused3(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, It
     R dmax = R(0), dsum = R(0);   // dsum only carries a NaN (fmax drops it)
     const R c12 = R(1.0 / 12.0);
 
-    // one-plane lookahead: the inputs of step k+1 are loaded while step k
-    // computes
-    R nu[3] = {R(0), R(0), R(0)};                 // u, own point, lead plane
-    R np = R(0), nP1 = R(0);                      // p, P1, own point, centre plane
-    R fu[3] = {R(0), R(0), R(0)};                 // u, frame point, centre plane
-    R nv[3] = {R(0), R(0), R(0)};                 // u_{k-1}, own point, output plane (Chebyshev)
-    R nj[3] = {R(0), R(0), R(0)}, nrho = R(1);    // j0' and rho there
-    auto load_step = [&](int k) {
-        if (k >= 8 && owned && z0 + k - 8 < nz) {
-            const unsigned io = col + plane * (unsigned)(z0 + k - 8);
-            nj[0] = ld(j0x, io); nj[1] = ld(j0y, io); nj[2] = ld(j0z, io);
-            nrho = ld(pRho, io);
-            if (CHEB && it > 0) { nv[0] = ld<R>(vx, io); nv[1] = ld<R>(vy, io); nv[2] = ld<R>(vz, io); }
-        }
-        const unsigned i = col + plane * (unsigned)wrap3(z0 - 4 + k, nz);
-        nu[0] = ld(ux, i); nu[1] = ld(uy, i); nu[2] = ld(uz, i);
-        const unsigned zc = plane * (unsigned)wrap3(z0 - 6 + k, nz);
-        np = ld(pP, col + zc);
-        nP1 = ld(pP1, col + zc);
-        if (has_frame) {
-            const unsigned f = fcol + zc;
-            fu[0] = ld(ux, f); fu[1] = ld(uy, f); fu[2] = ld(uz, f);
+    // Step k: lead plane z0-4+k, centre plane c = z0-6+k, output plane
+    // z0-8+k (written for 8 <= k < TZ+8).  Steps run in pairs, so one past
+    // the end may run with its output dropped; every plane index stays in
+    // [z0-6, z0+TZ+6) and is wrapped.
+    const int nsteps = TZ + 8;
+    auto out_plane = [&](int k) -> bool { return k >= 8 && k < nsteps && z0 + k - 8 < nz; };
+    // Loaders of the inputs of step k, one per group of fields.
+    auto load_own = [&](int k, StepIn<R>& in) {
+        const bool own = owned && out_plane(k);
+        const unsigned io = own ? (col + plane * (unsigned)(z0 + k - 8)) * (unsigned)sizeof(R) : OUT;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) in.j[a] = bload<R>(bJ[a], io);
+        in.rho = bload<R>(bRho, io);
+        if (CHEB) {
+            const unsigned iv = it > 0 ? io : OUT;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) in.v[a] = bload<R>(bV[a], iv);
         }
     };
-    load_step(0);
-    const int nsteps = TZ + 8;
+    auto load_lead = [&](int k, StepIn<R>& in) {
+        const unsigned il = (col + plane * (unsigned)wrap3(z0 - 4 + k, nz)) * (unsigned)sizeof(R);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) in.u[a] = bload<R>(bU[a], il);
+    };
+    auto load_frame = [&](int k, StepIn<R>& in) {
+        const unsigned zc = plane * (unsigned)wrap3(z0 - 6 + k, nz);
+        const unsigned ifr = has_frame ? (fcol + zc) * (unsigned)sizeof(R) : OUT;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) in.fu[a] = bload<R>(bU[a], ifr);
+    };
+    auto load_pp = [&](int k, StepIn<R>& in) {
+        const unsigned ic_ = (col + plane * (unsigned)wrap3(z0 - 6 + k, nz)) * (unsigned)sizeof(R);
+        in.p = bload<R>(bP, ic_);
+        in.P1 = bload<R>(bP1, ic_);
+    };
 
-    for (int k = 0; k < nsteps; ++k) {
-        const R cur_u[3] = {nu[0], nu[1], nu[2]};
-        const R cur_p = np, cur_P1 = nP1;
-        const R cur_fu[3] = {fu[0], fu[1], fu[2]};
-        const R cur_v[3] = {nv[0], nv[1], nv[2]};
-        const R cur_j[3] = {nj[0], nj[1], nj[2]};
-        const R cur_rho = nrho;
-        if (k + 1 < nsteps) load_step(k + 1);
+    // Step k reads its inputs from `in` and refills each group, right after
+    // its last use, with the inputs of step k+2 (the same phase two steps
+    // later): every load has two steps to complete, in two register sets.
+    auto run_step = [&](int k, StepIn<R>& in) {
         // 1. lead plane of the u ring at this thread's point
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
             for (int a = 0; a < 3; ++a) ur[s][a] = ur[s + 1][a];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) ur[4][a] = cur_u[a];
+        for (int a = 0; a < 3; ++a) ur[4][a] = in.u[a];
+        load_lead(k + 2, in);
         // 2. u plane c = lead-2 into LDS: own point and frame point
 #pragma unroll
-        for (int a = 0; a < 3; ++a) su[a][ly + 2][lx + 2] = ur[2][a];
+        for (int a = 0; a < 3; ++a) su[a][qy + 2][qx + 2] = ur[2][a];
         if (has_frame) {
 #pragma unroll
-            for (int a = 0; a < 3; ++a) su[a][fy][fx] = cur_fu[a];
+            for (int a = 0; a < 3; ++a) su[a][fy][fx] = in.fu[a];
         }
+        load_frame(k + 2, in);
         __syncthreads();
         // 3. q at plane c
         if (k >= 4) {
             R G[3][3];   // G[a][b] = d_a u_b
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
-                G[0][b] = d1<R>(su[b][ly + 2][lx], su[b][ly + 2][lx + 1], su[b][ly + 2][lx + 3],
-                                su[b][ly + 2][lx + 4]);
-                G[1][b] = d1<R>(su[b][ly][lx + 2], su[b][ly + 1][lx + 2], su[b][ly + 3][lx + 2],
-                                su[b][ly + 4][lx + 2]);
+                G[0][b] = d1<R>(su[b][qy + 2][qx], su[b][qy + 2][qx + 1], su[b][qy + 2][qx + 3],
+                                su[b][qy + 2][qx + 4]);
+                G[1][b] = d1<R>(su[b][qy][qx + 2], su[b][qy + 1][qx + 2], su[b][qy + 3][qx + 2],
+                                su[b][qy + 4][qx + 2]);
                 G[2][b] = d1<R>(ur[0][b], ur[1][b], ur[3][b], ur[4][b]);
             }
-            const R X = cur_P1 * (G[0][0] + G[1][1] + G[2][2]);
-            const R p2 = R(2) * cur_p;
-            const R qxz = cur_p * (G[0][2] + G[2][0]);
-            const R qyz = cur_p * (G[1][2] + G[2][1]);
-            sq[0][ly][lx] = X + p2 * G[0][0];
-            sq[1][ly][lx] = X + p2 * G[1][1];
-            sq[2][ly][lx] = cur_p * (G[0][1] + G[1][0]);
-            sq[3][ly][lx] = qxz;
-            sq[4][ly][lx] = qyz;
+            const R X = in.P1 * (G[0][0] + G[1][1] + G[2][2]);
+            const R p2 = R(2) * in.p;
+            const R qxz = in.p * (G[0][2] + G[2][0]);
+            const R qyz = in.p * (G[1][2] + G[2][1]);
+            sq[0][qy][qx] = X + p2 * G[0][0];
+            sq[1][qy][qx] = X + p2 * G[1][1];
+            sq[2][qy][qx] = in.p * (G[0][1] + G[1][0]);
+            sq[3][qy][qx] = qxz;
+            sq[4][qy][qx] = qyz;
+            if (interior) {   // d_z q_az is only taken at tile points
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
+                for (int s = 0; s < 4; ++s)
 #pragma unroll
-                for (int a = 0; a < 3; ++a) qz[s][a] = qz[s + 1][a];
-            qz[4][0] = qxz; qz[4][1] = qyz; qz[4][2] = X + p2 * G[2][2];
+                    for (int a = 0; a < 3; ++a) qz[s][a] = qz[s + 1][a];
+                qz[4][0] = qxz; qz[4][1] = qyz; qz[4][2] = X + p2 * G[2][2];
+            }
         }
+        load_pp(k + 2, in);
         __syncthreads();
-        // 4. the next iterate at plane c-2 = z0 + k - 8
+        // 4. the next iterate at the output plane z0 + k - 8
+        R un[3] = {R(0), R(0), R(0)};
+        const bool out = owned && out_plane(k);
         if (k >= 4 && interior) {
-            const int px = lx, py = ly;
+            const int px = qx, py = qy;
 #pragma unroll
             for (int a = 0; a < 3; ++a) { sd[0][a] = sd[1][a]; sd[1][a] = sd[2][a]; }
             // a = x: d_x q_xx + d_y q_xy ; a = y: d_x q_xy + d_y q_yy ; a = z: d_x q_xz + d_y q_yz
@@ -227,26 +296,35 @@ k_iter_fused3(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, It
                        d1<R>(sq[1][py - 2][px], sq[1][py - 1][px], sq[1][py + 1][px], sq[1][py + 2][px]);
             sd[2][2] = d1<R>(sq[3][py][px - 2], sq[3][py][px - 1], sq[3][py][px + 1], sq[3][py][px + 2]) +
                        d1<R>(sq[4][py - 2][px], sq[4][py - 1][px], sq[4][py + 1][px], sq[4][py + 2][px]);
-            const int zo = z0 + k - 8;
-            if (k >= 8 && owned && zo < z0 + TZ && zo < nz) {
-                const unsigned i = col + plane * (unsigned)zo;
-                const R ri = R(1) / cur_rho;
-                R un[3];
+            if (out) {
+                const R ri = R(1) / in.rho;
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
                     const R dz = d1<R>(qz[0][a], qz[1][a], qz[3][a], qz[4][a]);
                     const R gv = -(sd[0][a] + dz) * c12;          // G(x_k)_a
                     // item 6: |G(x_k) - x_k| with x_k = rho u_k - j0'
-                    const R d = fabs(gv + cur_j[a] - cur_rho * ur[0][a]);
+                    const R d = fabs(gv + in.j[a] - in.rho * ur[0][a]);
                     dmax = fmax(dmax, d);
                     dsum += d;
                     // item 3 of the next pass: u = (j0' + G)/rho
-                    const R gu = (cur_j[a] + gv) * ri;
-                    un[a] = CHEB ? next_iterate<R>(gu, ur[0][a], cur_v[a], omega, gam, it == 0) : gu;
+                    const R gu = (in.j[a] + gv) * ri;
+                    un[a] = CHEB ? next_iterate<R>(gu, ur[0][a], in.v[a], omega, gam, it == 0) : gu;
                 }
-                st(vx, i, un[0]); st(vy, i, un[1]); st(vz, i, un[2]);
             }
         }
+        // every lane stores; lanes without an output point write nowhere
+        const unsigned io = out ? (col + plane * (unsigned)(z0 + k - 8)) * (unsigned)sizeof(R) : OUT;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) bstore<R>(bV[a], io, un[a]);
+        load_own(k + 2, in);
+    };
+
+    StepIn<R> A, B;
+    load_lead(0, A); load_frame(0, A); load_pp(0, A); load_own(0, A);
+    load_lead(1, B); load_frame(1, B); load_pp(1, B); load_own(1, B);
+    for (int k = 0; k < nsteps; k += 2) {
+        run_step(k, A);
+        run_step(k + 1, B);
     }
     block_max_part(ic.part, dsum == dsum ? (double)dmax : (double)dsum);
 }
