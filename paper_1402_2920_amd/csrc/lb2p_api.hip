@@ -30,7 +30,13 @@ using namespace lb2p;
 namespace {
 
 constexpr double kPi = 3.14159265358979323846;
-constexpr int kFusedTX = 32, kFusedTY = 8;
+// Tile of the fused D3Q59 solve pass: 64 x 8 points for FP32 fields (one
+// thread per q point, 68 x 12 threads), 32 x 8 for FP64 fields, whose
+// registers would not fit four wavefronts per SIMD in the wider block.
+template <class R>
+constexpr int fused_tx() { return sizeof(R) == 4 ? 64 : 32; }
+constexpr int kFusedTY = 8;
+int fused_tx_of(size_t rsize) { return rsize == 4 ? fused_tx<float>() : fused_tx<double>(); }
 
 template <int Q>
 double min_weight(double s)
@@ -388,7 +394,7 @@ lb2p_status build_tiles(lb2p_ctx* c)
                 const int r0 = (int)((long long)frows * sl / nslab), r1 = (int)((long long)frows * (sl + 1) / nslab);
                 for (int z = 0; z < g.nz; z += tz)
                     for (int r = r0; r < r1; ++r)
-                        for (int x = 0; x < g.nx; x += kFusedTX) {
+                        for (int x = 0; x < g.nx; x += fused_tx_of(c->rsize)) {
                             Tile t{};
                             t.dom = d; t.x0 = x; t.y0 = r * kFusedTY; t.z0 = z; t.len = std::min(tz, g.nz - z);
                             fused.push_back(t);
@@ -494,6 +500,7 @@ struct Impl {
                                (const int*)c->site_range, c->jscale, 1LL, (const int*)nullptr);
         }
         const bool fused = Lattice<Q>::D == 3 && !(p.flags & LB2P_FLAG_UNFUSED_SOLVE);
+        constexpr int kFusedTX = fused_tx<R>();
         const dim3 fblock(kFusedTX + 4, kFusedTY + 4, 1);
         const dim3 fgrid((unsigned)c->fused_host.size());
         const int every = p.check_every > 0 ? p.check_every : 1;

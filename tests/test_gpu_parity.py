@@ -21,14 +21,16 @@ CASES = [
     ("d2q21", 21, (40, 24), {}),
     ("d3q59", 59, (20, 12, 10), {}),
     ("d3q59_unfused", 59, (20, 12, 10), dict(flags=1)),
-    # several 32 x 8 x 64 solve tiles with ragged edges in x and z
+    # several solve tiles (64 x 8 for FP32 fields, 32 x 8 for FP64) with
+    # ragged edges in x and y; a tile wider than the grid
     ("d3q59_tiles", 59, (40, 24, 72), {}),
+    ("d3q59_tiles_wide", 59, (72, 20, 40), {}),
     # the Chebyshev solver reaches the same fixed point (same stop rule)
     ("d2q21_cheb", 21, (40, 24), CHEB),
     ("d3q59_cheb", 59, (20, 12, 10), CHEB),
     ("d3q59_cheb_unfused", 59, (20, 12, 10), dict(CHEB, flags=1)),
 ]
-NSTEPS = {"d3q59_tiles": 3}
+NSTEPS = {"d3q59_tiles": 3, "d3q59_tiles_wide": 3}
 
 
 @pytest.fixture(scope="module")
