@@ -755,12 +755,13 @@ __global__ void k_iter_finish(IterCtl ic, int launched, int ndom, SolveInfo* inf
 }
 
 // After `launched` passes: apply the stop rule to the last pass of every
-// domain still iterating (as the next pass would) and count the domains whose
-// rule has held, for the host's early exit.
+// domain still iterating (as the next pass would), and report for the host's
+// early exit the number of domains whose rule has held (out[0]) and the
+// largest pass count at which it held (out[1]).
 __global__ void k_check_done(IterCtl ic, int launched, int ndom, int* out)
 {
-    __shared__ int cnt;
-    if (threadIdx.x == 0) cnt = 0;
+    __shared__ int cnt, last;
+    if (threadIdx.x == 0) { cnt = 0; last = 0; }
     __syncthreads();
     for (int d = threadIdx.x; d < ndom; d += blockDim.x) {
         int da = ic.done_at[d];
@@ -772,10 +773,13 @@ __global__ void k_check_done(IterCtl ic, int launched, int ndom, int* out)
                 ic.done_at[d] = da;
             }
         }
-        if (da >= 0) atomicAdd(&cnt, 1);
+        if (da >= 0) {
+            atomicAdd(&cnt, 1);
+            atomicMax(&last, da);
+        }
     }
     __syncthreads();
-    if (threadIdx.x == 0) *out = cnt;
+    if (threadIdx.x == 0) { out[0] = cnt; out[1] = last; }
 }
 
 // ---------------------------------------------------------------------------
@@ -1163,7 +1167,7 @@ __global__ void k_reset_ctl(unsigned long long* res, long long nres, unsigned lo
         jscale[t] = 0ull;
         done_at[t] = -1;
     }
-    if (t == 0) *nconv = 0;
+    if (t == 0 && nconv) *nconv = 0;
 }
 
 // Deterministic sum of block partials [first, last) (one block).

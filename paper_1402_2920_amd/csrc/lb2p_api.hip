@@ -242,13 +242,14 @@ struct lb2p_ctx {
     int* ndone = nullptr;
     double* sums = nullptr;
     struct HostScratch {
-        int ndone;
+        int ndone;       // domains whose stop rule has held
+        int ndone_last;  // the largest pass count at which it held
         int nconv;
         int flags;
-        int pad;
         double sums[4];
     };
     HostScratch* host = nullptr;               // pinned readback area
+    bool status_pending = false;               // tolerance-mode status not yet read
     bool initialized = false;
     bool have_prev = false;
     int nprev = 0;               // solves since init whose j~ can start the next one
@@ -471,8 +472,13 @@ struct Impl {
     }
 
     // Items 1-8.  In the default (tolerance) mode the host reads how many
-    // domains have met the stop rule: first one pass before the previous
-    // solve's pass count, then every check_every passes (default 1).
+    // domains have met the stop rule: first one pass after the previous
+    // solve's pass count, then every check_every passes (default 1).  Passes
+    // launched after a domain met the rule exit at once (the stop rule is
+    // evaluated on the device), so a generous first check costs a few
+    // microseconds where an early one costs a host round trip.  The count of
+    // domains that hit max_iter and the non-finite flag are read once per
+    // lb2p_step / lb2p_moments call (read_status).
     // advance: the solve belongs to a time step (lb2p_step), not to a
     // re-evaluation of the same state (lb2p_moments)
     static lb2p_status solve(lb2p_ctx* c, bool advance = true)
@@ -482,7 +488,7 @@ struct Impl {
         const long long nres = (long long)c->ndom * c->stride;
         hipLaunchKernelGGL(k_reset_ctl, dim3((unsigned)((std::max<long long>(nres, c->ndom) + 255) / 256)),
                            dim3(256), 0, c->stream, c->res, nres, c->jscale, c->done_at, c->ndom,
-                           c->nconv);
+                           (int*)nullptr);
         launch_moments(c, true);
         IterCtl ic{c->res, c->jscale, c->done_at, c->stride, p.fixed_iter > 0 ? -1.0 : p.tol, c->omega, c->pmax};
         {
@@ -504,7 +510,8 @@ struct Impl {
         const dim3 fblock(kFusedTX + 4, kFusedTY + 4, 1);
         const dim3 fgrid((unsigned)c->fused_host.size());
         const int every = p.check_every > 0 ? p.check_every : 1;
-        int next_check = std::max(1, c->last_iters - 1);
+        int next_check = std::max(1, c->last_iters + 1);
+        int last_done = -1;
         int launched = 0;
         for (int it = 0; it < max_it; ++it) {
             R* jold = (R*)((it & 1) ? c->jt1 : c->jt0);
@@ -543,10 +550,13 @@ struct Impl {
                 next_check = launched + every;
                 hipLaunchKernelGGL(k_check_done, dim3(1), dim3(256), 0, c->stream, ic, launched, c->ndom,
                                    c->ndone);
-                HIPCHK(hipMemcpyAsync(&c->host->ndone, c->ndone, sizeof(int), hipMemcpyDeviceToHost,
+                HIPCHK(hipMemcpyAsync(&c->host->ndone, c->ndone, 2 * sizeof(int), hipMemcpyDeviceToHost,
                                       c->stream));
                 HIPCHK(hipStreamSynchronize(c->stream));
-                if (c->host->ndone >= c->ndom) break;
+                if (c->host->ndone >= c->ndom) {
+                    last_done = c->host->ndone_last;
+                    break;
+                }
             }
         }
         hipLaunchKernelGGL(k_iter_finish, dim3((c->ndom + 255) / 256), dim3(256), 0, c->stream, ic,
@@ -561,14 +571,8 @@ struct Impl {
                                (const R*)c->j0p, (const R*)c->jt0, (const R*)c->jt1, (R*)c->u);
         HIPCHK(hipGetLastError());
         if (p.fixed_iter <= 0) {
-            HIPCHK(hipMemcpyAsync(&c->host->nconv, c->nconv, sizeof(int), hipMemcpyDeviceToHost,
-                                  c->stream));
-            HIPCHK(hipMemcpyAsync(&c->host->flags, c->flags, sizeof(int), hipMemcpyDeviceToHost,
-                                  c->stream));
-            HIPCHK(hipStreamSynchronize(c->stream));
-            c->last_iters = launched;
-            if (c->host->nconv > 0 && c->sticky == LB2P_OK) c->sticky = LB2P_ENOCONV;
-            if (c->host->flags) c->sticky = LB2P_ENONFINITE;
+            c->last_iters = last_done >= 0 ? last_done : launched;
+            c->status_pending = true;
         } else {
             c->last_iters = max_it;
         }
@@ -895,7 +899,7 @@ lb2p_status create_impl(int ndom, const lb2p_params* pp, void* hip_stream, lb2p_
     char* sb = (char*)c->scratch;
     c->flags = (int*)(sb + 0);
     c->nconv = (int*)(sb + 4);
-    c->ndone = (int*)(sb + 8);
+    c->ndone = (int*)(sb + 8);   // two ints
     c->sums = (double*)(sb + 64);
     c->res = (unsigned long long*)(sb + 256);
     c->jscale = c->res + nres;
@@ -936,6 +940,22 @@ lb2p_status create_impl(int ndom, const lb2p_params* pp, void* hip_stream, lb2p_
 
 // nsteps steps: eager launches, or replays of the captured graph (fixed
 // iteration count, graph_steps > 0).
+// Tolerance mode: the domains that hit max_iter (counted on the device over
+// the steps since the last read) and the non-finite flag, read with one
+// synchronisation per call.
+lb2p_status read_status(lb2p_ctx* c)
+{
+    if (!c->status_pending) return LB2P_OK;
+    c->status_pending = false;
+    HIPCHK(hipMemcpyAsync(&c->host->nconv, c->nconv, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(&c->host->flags, c->flags, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemsetAsync(c->nconv, 0, sizeof(int), c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (c->host->nconv > 0 && c->sticky == LB2P_OK) c->sticky = LB2P_ENOCONV;
+    if (c->host->flags) c->sticky = LB2P_ENONFINITE;
+    return LB2P_OK;
+}
+
 lb2p_status run_steps(lb2p_ctx* c, int nsteps)
 {
     const int gs = c->prm.graph_steps > 0 && c->prm.fixed_iter > 0 ? (c->prm.graph_steps + 1) / 2 * 2 : 0;
@@ -1114,6 +1134,8 @@ lb2p_status lb2p_init(lb2p_ctx* c, const void* rho, const void* u, int dtype, in
     dispatch(c, [&](auto impl) { decltype(impl)::launch_init(c); });
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemsetAsync(c->flags, 0, sizeof(int), c->stream));
+    HIPCHK(hipMemsetAsync(c->nconv, 0, sizeof(int), c->stream));
+    c->status_pending = false;
     HIPCHK(hipStreamSynchronize(c->stream));
     c->initialized = true;
     c->have_prev = false;
@@ -1130,6 +1152,8 @@ lb2p_status lb2p_step(lb2p_ctx* c, int nsteps)
     lb2p_status st = run_steps(c, nsteps);
     if (st != LB2P_OK) return st;
     if (c->prm.fixed_iter > 0) HIPCHK(hipGetLastError());
+    st = read_status(c);
+    if (st != LB2P_OK) return st;
     return c->sticky;
 }
 
@@ -1140,6 +1164,8 @@ lb2p_status lb2p_moments(lb2p_ctx* c, void* rho_out, void* u_out, int dtype, int
     if (!c->initialized) return LB2P_ESTATE;
     if (dtype != LB2P_DTYPE_F64 && dtype != LB2P_DTYPE_F32) return LB2P_EINVAL;
     lb2p_status s = dispatch(c, [&](auto impl) { return decltype(impl)::solve(c, false); });
+    if (s != LB2P_OK) return s;
+    s = read_status(c);
     if (s != LB2P_OK) return s;
     c->sigma_valid = false;
     if (rho_out) {
@@ -1298,6 +1324,8 @@ lb2p_status lb2p_set_populations(lb2p_ctx* c, const double* n_in, int on_device)
     HIPCHK(hipGetLastError());
     if (tmp) HIPCHK(hipFreeAsync(tmp, c->stream));
     HIPCHK(hipMemsetAsync(c->flags, 0, sizeof(int), c->stream));
+    HIPCHK(hipMemsetAsync(c->nconv, 0, sizeof(int), c->stream));
+    c->status_pending = false;
     HIPCHK(hipStreamSynchronize(c->stream));
     c->initialized = true;
     c->have_prev = false;
@@ -1377,6 +1405,8 @@ lb2p_status lb2p_autotune(lb2p_ctx* c, int steps)
     if (st == LB2P_OK) st = build_tiles(c);
     (void)hipMemcpyAsync(c->A, save, pbytes, hipMemcpyDeviceToDevice, c->stream);
     (void)hipMemsetAsync(c->flags, 0, sizeof(int), c->stream);
+    (void)hipMemsetAsync(c->nconv, 0, sizeof(int), c->stream);
+    c->status_pending = false;
     (void)hipStreamSynchronize(c->stream);
     (void)hipFree(save);
     c->have_prev = false;
