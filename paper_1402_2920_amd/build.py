@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liblb2p.so")
 SOURCES = [os.path.join(CSRC, "lb2p_api.hip")]
-HEADERS = [os.path.join(CSRC, f) for f in ("kernels.hpp", "kernels_fused.hpp", "lattice.hpp")] + [
+HEADERS = [os.path.join(CSRC, f) for f in ("kernels.hpp", "kernels_fused.hpp", "kernels_closure.hpp", "lattice.hpp")] + [
     os.path.join(ROOT, "include", "lb2p.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

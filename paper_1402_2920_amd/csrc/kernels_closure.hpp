@@ -1,0 +1,228 @@
+// kernels_closure.hpp -- the second closure kernel (item 11: Sigma from the
+// derivatives of the level-1 fields X, T, Y) for D3Q59 as a z-march.
+//
+// A block owns a TX x TY tile of an xy plane (one thread per tile point) and
+// marches through TZ planes of z, like the fused solve pass.  Each thread
+// keeps, in registers, five planes (c-2 .. c+2) of the eleven fields whose z
+// derivative is taken at its point; one plane of the fourteen fields with x or
+// y derivatives (tile + 2-wide frame) sits in LDS.  Every input word is then
+// read once per launch (plus the frame), where a per-site kernel issues four
+// neighbour loads per field and direction, about 150 loads per site.
+#pragma once
+
+#include "kernels_fused.hpp"
+
+namespace lb2p {
+
+// Inputs of one z step.
+template <class R>
+struct C2In {
+    R lead[11];   // own point, lead plane c+2: X, Txz, Tyz, Tzz, Yx, Yy, Yz, rho, ux, uy, uz
+    R own[3];     // own point, centre plane: Txx, Txy, Tyy (no z derivative)
+    R fr[13];     // frame point, centre plane: X, Txx, Txy, Tyy, Txz, Tyz, Yx, Yy, Yz, rho, ux, uy, uz
+};
+
+template <class R, int TX, int TY>
+__global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 2 : 1)))
+k_closure2_zm(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, const R* __restrict__ rho,
+              const R* __restrict__ u, const R* __restrict__ X, const R* __restrict__ T,
+              const R* __restrict__ Y, R* __restrict__ Sig)
+{
+    constexpr int UX = TX + 4, UY = TY + 4;   // tile + 2-wide frame
+    constexpr int NFRAME = UX * UY - TX * TY;
+    static_assert(NFRAME <= TX * TY, "frame larger than the block");
+    // planar fields: X, Txx, Txy, Tyy, Txz, Tyz, Yx, Yy, Yz, rho ux, rho uy, ux, uy, uz
+    __shared__ R sl[14][UY][UX];
+
+    const Tile tl = tiles[blockIdx.x];
+    if (tl.dom < 0) return;   // uniform per block
+    const Domain& dm = tab[tl.dom];
+    const int nx = dm.g.nx, ny = dm.g.ny, nz = dm.g.nz;
+    const long long N = dm.g.S;
+    const unsigned plane = (unsigned)nx * (unsigned)ny;
+    const unsigned bytes = (unsigned)dm.g.N * (unsigned)sizeof(R);
+    const unsigned OUT = bytes;
+    const long long o = dm.off;
+    const PlaneBuf bX = plane_buf(X + o, bytes);
+    // T and Sigma components: xx yy zz xy xz yz
+    const PlaneBuf bT[6] = {plane_buf(T + o, bytes), plane_buf(T + o + N, bytes), plane_buf(T + o + 2 * N, bytes),
+                            plane_buf(T + o + 3 * N, bytes), plane_buf(T + o + 4 * N, bytes),
+                            plane_buf(T + o + 5 * N, bytes)};
+    const PlaneBuf bY[3] = {plane_buf(Y + o, bytes), plane_buf(Y + o + N, bytes), plane_buf(Y + o + 2 * N, bytes)};
+    const PlaneBuf bR = plane_buf(rho + o, bytes);
+    const PlaneBuf bU[3] = {plane_buf(u + o, bytes), plane_buf(u + o + N, bytes), plane_buf(u + o + 2 * N, bytes)};
+    const PlaneBuf bS[6] = {plane_buf(Sig + o, bytes), plane_buf(Sig + o + N, bytes),
+                            plane_buf(Sig + o + 2 * N, bytes), plane_buf(Sig + o + 3 * N, bytes),
+                            plane_buf(Sig + o + 4 * N, bytes), plane_buf(Sig + o + 5 * N, bytes)};
+
+    const int lx = threadIdx.x, ly = threadIdx.y;
+    const int tid = lx + TX * ly;
+    const int x0 = tl.x0, y0 = tl.y0, z0 = tl.z0, TZ = tl.len;
+    const unsigned col = (unsigned)wrapmod(x0 + lx, nx) + (unsigned)nx * (unsigned)wrapmod(y0 + ly, ny);
+    const bool owned = (x0 + lx < nx) && (y0 + ly < ny);
+
+    // this thread's frame point (2-wide ring of the UX x UY region)
+    int fx = 0, fy = 0;
+    const bool has_frame = tid < NFRAME;
+    if (has_frame) {
+        if (tid < 2 * UX) {                  // two rows at the bottom
+            fy = tid / UX; fx = tid % UX;
+        } else if (tid < 4 * UX) {           // two rows at the top
+            const int t = tid - 2 * UX;
+            fy = UY - 2 + t / UX; fx = t % UX;
+        } else {                             // two columns left, two right
+            const int t = tid - 4 * UX;
+            const int c = t % 4;
+            fy = 2 + t / 4;
+            fx = c < 2 ? c : UX - 4 + c;
+        }
+    }
+    const unsigned fcol = has_frame
+        ? (unsigned)wrapmod(x0 + fx - 2, nx) + (unsigned)nx * (unsigned)wrapmod(y0 + fy - 2, ny) : 0u;
+
+    // Step k: lead plane z0-2+k, centre plane c = z0-4+k, output at c for
+    // 4 <= k < TZ+4.  The ring holds planes c-2 .. c+2 after the shift.
+    const int nsteps = TZ + 4;
+    auto load_lead = [&](int k, C2In<R>& in) {
+        const unsigned i = k < nsteps ? (col + plane * (unsigned)wrap3(z0 - 2 + k, nz)) * (unsigned)sizeof(R) : OUT;
+        in.lead[0] = bload<R>(bX, i);
+        in.lead[1] = bload<R>(bT[4], i);
+        in.lead[2] = bload<R>(bT[5], i);
+        in.lead[3] = bload<R>(bT[2], i);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) in.lead[4 + b] = bload<R>(bY[b], i);
+        in.lead[7] = bload<R>(bR, i);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) in.lead[8 + b] = bload<R>(bU[b], i);
+    };
+    auto load_centre = [&](int k, C2In<R>& in) {
+        const bool live = k >= 4 && k < nsteps;   // LDS is read from step 4 on
+        const unsigned zc = plane * (unsigned)wrap3(z0 - 4 + k, nz);
+        const unsigned i = live ? (col + zc) * (unsigned)sizeof(R) : OUT;
+        in.own[0] = bload<R>(bT[0], i);
+        in.own[1] = bload<R>(bT[3], i);
+        in.own[2] = bload<R>(bT[1], i);
+        const unsigned f = live && has_frame ? (fcol + zc) * (unsigned)sizeof(R) : OUT;
+        in.fr[0] = bload<R>(bX, f);
+        in.fr[1] = bload<R>(bT[0], f);
+        in.fr[2] = bload<R>(bT[3], f);
+        in.fr[3] = bload<R>(bT[1], f);
+        in.fr[4] = bload<R>(bT[4], f);
+        in.fr[5] = bload<R>(bT[5], f);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) in.fr[6 + b] = bload<R>(bY[b], f);
+        in.fr[9] = bload<R>(bR, f);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) in.fr[10 + b] = bload<R>(bU[b], f);
+    };
+
+    R rg[5][11];
+#pragma unroll
+    for (int s = 0; s < 5; ++s)
+#pragma unroll
+        for (int f = 0; f < 11; ++f) rg[s][f] = R(0);
+
+    const R gm = R(dm.cf.gamma);
+    const R KS1 = R(-0.25) * (gm + R(1)) * (gm + R(1)) / (gm - R(1));
+    const R KS2 = (gm * gm + R(4) * gm + R(1)) / (R(6) * (gm - R(1)));
+
+    C2In<R> in;
+    load_lead(0, in);
+    for (int k = 0; k < nsteps; ++k) {
+        // centre-plane inputs of this step (the lead plane was loaded one step
+        // ahead; holding these across a step as well costs registers that
+        // would spill)
+        load_centre(k, in);
+        // 1. ring shift; the lead plane comes in
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int f = 0; f < 11; ++f) rg[s][f] = rg[s + 1][f];
+#pragma unroll
+        for (int f = 0; f < 11; ++f) rg[4][f] = in.lead[f];
+        load_lead(k + 1, in);
+        // 2. the centre plane into LDS: own point and frame point
+        {
+            const int py = ly + 2, px = lx + 2;
+            sl[0][py][px] = rg[2][0];
+            sl[1][py][px] = in.own[0];
+            sl[2][py][px] = in.own[1];
+            sl[3][py][px] = in.own[2];
+            sl[4][py][px] = rg[2][1];
+            sl[5][py][px] = rg[2][2];
+            sl[6][py][px] = rg[2][4];
+            sl[7][py][px] = rg[2][5];
+            sl[8][py][px] = rg[2][6];
+            sl[9][py][px] = rg[2][7] * rg[2][8];
+            sl[10][py][px] = rg[2][7] * rg[2][9];
+            sl[11][py][px] = rg[2][8];
+            sl[12][py][px] = rg[2][9];
+            sl[13][py][px] = rg[2][10];
+        }
+        if (has_frame) {
+#pragma unroll
+            for (int f = 0; f < 9; ++f) sl[f][fy][fx] = in.fr[f];
+            sl[9][fy][fx] = in.fr[9] * in.fr[10];
+            sl[10][fy][fx] = in.fr[9] * in.fr[11];
+#pragma unroll
+            for (int b = 0; b < 3; ++b) sl[11 + b][fy][fx] = in.fr[10 + b];
+        }
+        __syncthreads();
+        // 3. Sigma at the centre plane (item 11)
+        const bool out = owned && k >= 4 && z0 + k - 4 < nz;
+        R sg[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+        if (k >= 4) {
+            const int py = ly + 2, px = lx + 2;
+            auto dx = [&](int f) {
+                return d1<R>(sl[f][py][px - 2], sl[f][py][px - 1], sl[f][py][px + 1], sl[f][py][px + 2]);
+            };
+            auto dy = [&](int f) {
+                return d1<R>(sl[f][py - 2][px], sl[f][py - 1][px], sl[f][py + 1][px], sl[f][py + 2][px]);
+            };
+            auto dz = [&](int f) { return d1<R>(rg[0][f], rg[1][f], rg[3][f], rg[4][f]); };
+            const R DX[3] = {dx(0), dy(0), dz(0)};
+            R DT[3];
+            DT[0] = dx(1) + dy(2) + dz(1);
+            DT[1] = dx(2) + dy(3) + dz(2);
+            DT[2] = dx(4) + dy(5) + dz(3);
+            R DY[3][3];   // DY[a][b] = d_a Y_b
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                DY[0][b] = dx(6 + b);
+                DY[1][b] = dy(6 + b);
+                DY[2][b] = dz(4 + b);
+            }
+            const R trJ = dx(9) + dy(10) +
+                          d1<R>(rg[0][7] * rg[0][10], rg[1][7] * rg[1][10], rg[3][7] * rg[3][10],
+                                rg[4][7] * rg[4][10]);
+            R G[3][3];    // G[a][b] = d_a u_b
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                G[0][b] = dx(11 + b);
+                G[1][b] = dy(11 + b);
+                G[2][b] = dz(8 + b);
+            }
+            const R r = rg[2][7];
+            const EosVal<R> e = eos_all<R>(dm.cf.eos, r);
+            const R us[3] = {rg[2][8], rg[2][9], rg[2][10]};
+            const R trG = G[0][0] + G[1][1] + G[2][2];
+            const R trDY = DY[0][0] + DY[1][1] + DY[2][2];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = a; b < 3; ++b) {
+                    const R br1 = us[a] * DX[b] + us[b] * DX[a] + us[b] * DT[a] + us[a] * DT[b];
+                    R br2 = -e.dp * trJ * (G[a][b] + G[b][a]) - e.p * (DY[a][b] + DY[b][a]);
+                    if (a == b) br2 += -e.P1 * trDY + e.P2 * trG * trJ;
+                    sg[sym2<3>(a, b)] = KS1 * br1 + KS2 * br2;
+                }
+        }
+        // every lane stores; lanes without an output point write nowhere
+        const unsigned io = out ? (col + plane * (unsigned)(z0 + k - 4)) * (unsigned)sizeof(R) : OUT;
+#pragma unroll
+        for (int s = 0; s < 6; ++s) bstore<R>(bS[s], io, sg[s]);
+        __syncthreads();
+    }
+}
+
+}  // namespace lb2p

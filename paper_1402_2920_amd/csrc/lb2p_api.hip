@@ -24,6 +24,7 @@
 #include "../../include/lb2p.h"
 #include "kernels.hpp"
 #include "kernels_fused.hpp"
+#include "kernels_closure.hpp"
 
 using namespace lb2p;
 
@@ -594,9 +595,17 @@ struct Impl {
         }
         {
             ProfScope _ps(c, LB2P_K_CLOSURE2);
-            hipLaunchKernelGGL((k_closure2<Q, R>), sgrid(c), sblock(c), 0, c->stream, c->dtab,
-                               c->site_tiles, (const R*)c->rho, (const R*)c->u, (const R*)c->X,
-                               (const R*)c->T, (const R*)c->Y, (R*)c->Sig);
+            if constexpr (Lattice<Q>::D == 3) {
+                constexpr int TX = fused_tx<R>();
+                hipLaunchKernelGGL((k_closure2_zm<R, TX, kFusedTY>), dim3((unsigned)c->fused_host.size()),
+                                   dim3(TX, kFusedTY, 1), 0, c->stream, c->dtab, c->fused_tiles,
+                                   (const R*)c->rho, (const R*)c->u, (const R*)c->X, (const R*)c->T,
+                                   (const R*)c->Y, (R*)c->Sig);
+            } else {
+                hipLaunchKernelGGL((k_closure2<Q, R>), sgrid(c), sblock(c), 0, c->stream, c->dtab,
+                                   c->site_tiles, (const R*)c->rho, (const R*)c->u, (const R*)c->X,
+                                   (const R*)c->T, (const R*)c->Y, (R*)c->Sig);
+            }
         }
         {
             ProfScope _ps(c, LB2P_K_COLLIDE);
