@@ -617,7 +617,7 @@ __global__ void __launch_bounds__(256) k_force(const Domain* __restrict__ tab,
             }
             sto(f + o + a * St, i0, fv);
             sto(j0p + o + a * St, i0, jp);
-            sto(jt0 + o + a * St, i0, jt);
+            if (jt0) sto(jt0 + o + a * St, i0, jt);   // the velocity-form solve needs only u
             sto(u + o + a * St, i0, (jp + jt) * inv);
             amax = fmax(amax, fabs((double)jp));
         }

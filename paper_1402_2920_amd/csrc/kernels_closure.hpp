@@ -1,13 +1,15 @@
-// kernels_closure.hpp -- the second closure kernel (item 11: Sigma from the
-// derivatives of the level-1 fields X, T, Y) for D3Q59 as a z-march.
+// kernels_closure.hpp -- the closure kernels (items 9-11) for D3Q59 as
+// z-marches: k_closure1_zm (the level-1 fields X, T, Y and Xi' from first
+// derivatives of u, p and per-site products) and k_closure2_zm (Sigma from the
+// derivatives of X, T, Y).
 //
 // A block owns a TX x TY tile of an xy plane (one thread per tile point) and
 // marches through TZ planes of z, like the fused solve pass.  Each thread
-// keeps, in registers, five planes (c-2 .. c+2) of the eleven fields whose z
-// derivative is taken at its point; one plane of the fourteen fields with x or
-// y derivatives (tile + 2-wide frame) sits in LDS.  Every input word is then
+// keeps, in registers, five planes (c-2 .. c+2) of the fields whose z
+// derivative is taken at its point; one plane of the fields with x or y
+// derivatives (tile + 2-wide frame) sits in LDS.  Every input word is then
 // read once per launch (plus the frame), where a per-site kernel issues four
-// neighbour loads per field and direction, about 150 loads per site.
+// neighbour loads per field and direction (70 to 150 loads per site).
 #pragma once
 
 #include "kernels_fused.hpp"
@@ -221,6 +223,221 @@ k_closure2_zm(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, co
         const unsigned io = out ? (col + plane * (unsigned)(z0 + k - 4)) * (unsigned)sizeof(R) : OUT;
 #pragma unroll
         for (int s = 0; s < 6; ++s) bstore<R>(bS[s], io, sg[s]);
+        __syncthreads();
+    }
+}
+
+// Items 9-10 and the Xi' part of item 11: per site X = P1 d_g u_g,
+// T_ag = p (d_a u_g + d_g u_a), Y_b = rho^-1 d_b p + u_g d_g u_b and Xi'
+// from d_a (p u_b u_g), d_a (p/rho) and j~ (the same arithmetic as the
+// per-site k_closure1).
+template <class R>
+struct C1In {
+    R lead[5];    // own point, lead plane c+2: ux, uy, uz, p, 1/rho
+    R own[4];     // own point, centre plane: P1, j~ (3)
+    R fr[5];      // frame point, centre plane: ux, uy, uz, p, 1/rho
+};
+
+template <class R, int TX, int TY>
+__global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 2 : 1)))
+k_closure1_zm(const Domain* __restrict__ tab, const Tile* __restrict__ tiles,
+              const SolveInfo* __restrict__ info, const R* __restrict__ pf, const R* __restrict__ u,
+              const R* __restrict__ jtA, const R* __restrict__ jtB, R* __restrict__ X, R* __restrict__ T,
+              R* __restrict__ Y, R* __restrict__ Xi)
+{
+    constexpr int UX = TX + 4, UY = TY + 4;   // tile + 2-wide frame
+    constexpr int NFRAME = UX * UY - TX * TY;
+    static_assert(NFRAME <= TX * TY, "frame larger than the block");
+    // planar fields: ux, uy, uz, p, p/rho, then p u_b u_c for (b,c) = xx xy xz yy yz zz
+    __shared__ R sl[11][UY][UX];
+
+    const Tile tl = tiles[blockIdx.x];
+    if (tl.dom < 0) return;   // uniform per block
+    const Domain& dm = tab[tl.dom];
+    const int nx = dm.g.nx, ny = dm.g.ny, nz = dm.g.nz;
+    const long long N = dm.g.S;
+    const unsigned plane = (unsigned)nx * (unsigned)ny;
+    const unsigned bytes = (unsigned)dm.g.N * (unsigned)sizeof(R);
+    const unsigned OUT = bytes;
+    const long long o = dm.off;
+    const R* jt = info[tl.dom].final_buf ? jtB : jtA;
+    const PlaneBuf bU[3] = {plane_buf(u + o, bytes), plane_buf(u + o + N, bytes), plane_buf(u + o + 2 * N, bytes)};
+    const PlaneBuf bP = plane_buf(pf + o, bytes);
+    const PlaneBuf bP1 = plane_buf(pf + o + N, bytes);
+    const PlaneBuf bRi = plane_buf(pf + o + 2 * N, bytes);
+    const PlaneBuf bJ[3] = {plane_buf(jt + o, bytes), plane_buf(jt + o + N, bytes), plane_buf(jt + o + 2 * N, bytes)};
+    const PlaneBuf bX = plane_buf(X + o, bytes);
+    const PlaneBuf bT[6] = {plane_buf(T + o, bytes), plane_buf(T + o + N, bytes), plane_buf(T + o + 2 * N, bytes),
+                            plane_buf(T + o + 3 * N, bytes), plane_buf(T + o + 4 * N, bytes),
+                            plane_buf(T + o + 5 * N, bytes)};
+    const PlaneBuf bY[3] = {plane_buf(Y + o, bytes), plane_buf(Y + o + N, bytes), plane_buf(Y + o + 2 * N, bytes)};
+    PlaneBuf bXi[10];
+#pragma unroll
+    for (int s = 0; s < 10; ++s) bXi[s] = plane_buf(Xi + o + s * N, bytes);
+
+    const int lx = threadIdx.x, ly = threadIdx.y;
+    const int tid = lx + TX * ly;
+    const int x0 = tl.x0, y0 = tl.y0, z0 = tl.z0, TZ = tl.len;
+    const unsigned col = (unsigned)wrapmod(x0 + lx, nx) + (unsigned)nx * (unsigned)wrapmod(y0 + ly, ny);
+    const bool owned = (x0 + lx < nx) && (y0 + ly < ny);
+
+    int fx = 0, fy = 0;
+    const bool has_frame = tid < NFRAME;
+    if (has_frame) {
+        if (tid < 2 * UX) {
+            fy = tid / UX; fx = tid % UX;
+        } else if (tid < 4 * UX) {
+            const int t = tid - 2 * UX;
+            fy = UY - 2 + t / UX; fx = t % UX;
+        } else {
+            const int t = tid - 4 * UX;
+            const int c = t % 4;
+            fy = 2 + t / 4;
+            fx = c < 2 ? c : UX - 4 + c;
+        }
+    }
+    const unsigned fcol = has_frame
+        ? (unsigned)wrapmod(x0 + fx - 2, nx) + (unsigned)nx * (unsigned)wrapmod(y0 + fy - 2, ny) : 0u;
+
+    const int nsteps = TZ + 4;
+    auto load_lead = [&](int k, C1In<R>& in) {
+        const unsigned i = k < nsteps ? (col + plane * (unsigned)wrap3(z0 - 2 + k, nz)) * (unsigned)sizeof(R) : OUT;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) in.lead[b] = bload<R>(bU[b], i);
+        in.lead[3] = bload<R>(bP, i);
+        in.lead[4] = bload<R>(bRi, i);
+    };
+    auto load_centre = [&](int k, C1In<R>& in) {
+        const bool live = k >= 4 && k < nsteps;
+        const unsigned zc = plane * (unsigned)wrap3(z0 - 4 + k, nz);
+        const unsigned i = live ? (col + zc) * (unsigned)sizeof(R) : OUT;
+        in.own[0] = bload<R>(bP1, i);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) in.own[1 + b] = bload<R>(bJ[b], i);
+        const unsigned f = live && has_frame ? (fcol + zc) * (unsigned)sizeof(R) : OUT;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) in.fr[b] = bload<R>(bU[b], f);
+        in.fr[3] = bload<R>(bP, f);
+        in.fr[4] = bload<R>(bRi, f);
+    };
+    // planar LDS fields of one point
+    auto put = [&](int py, int px, R ux, R uy, R uz, R p, R ri) {
+        sl[0][py][px] = ux;
+        sl[1][py][px] = uy;
+        sl[2][py][px] = uz;
+        sl[3][py][px] = p;
+        sl[4][py][px] = p * ri;
+        sl[5][py][px] = p * ux * ux;
+        sl[6][py][px] = p * ux * uy;
+        sl[7][py][px] = p * ux * uz;
+        sl[8][py][px] = p * uy * uy;
+        sl[9][py][px] = p * uy * uz;
+        sl[10][py][px] = p * uz * uz;
+    };
+
+    R rg[5][5];   // ux, uy, uz, p, 1/rho at planes c-2 .. c+2
+#pragma unroll
+    for (int s = 0; s < 5; ++s)
+#pragma unroll
+        for (int f = 0; f < 5; ++f) rg[s][f] = R(0);
+
+    const R gm = R(dm.cf.gamma);
+    const R KX = (gm * gm + R(4) * gm + R(1)) / (R(3) * (gm + R(1)));
+    const R KJ = (R(1) - gm) * R(dm.cf.c0sq);
+
+    C1In<R> in;
+    load_lead(0, in);
+    for (int k = 0; k < nsteps; ++k) {
+        load_centre(k, in);
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int f = 0; f < 5; ++f) rg[s][f] = rg[s + 1][f];
+#pragma unroll
+        for (int f = 0; f < 5; ++f) rg[4][f] = in.lead[f];
+        load_lead(k + 1, in);
+        put(ly + 2, lx + 2, rg[2][0], rg[2][1], rg[2][2], rg[2][3], rg[2][4]);
+        if (has_frame) put(fy, fx, in.fr[0], in.fr[1], in.fr[2], in.fr[3], in.fr[4]);
+        __syncthreads();
+        const bool out = owned && k >= 4 && z0 + k - 4 < nz;
+        R oX = R(0), oT[6] = {}, oY[3] = {}, oXi[10] = {};
+        if (k >= 4) {
+            const int py = ly + 2, px = lx + 2;
+            auto dxl = [&](int f) {
+                return d1<R>(sl[f][py][px - 2], sl[f][py][px - 1], sl[f][py][px + 1], sl[f][py][px + 2]);
+            };
+            auto dyl = [&](int f) {
+                return d1<R>(sl[f][py - 2][px], sl[f][py - 1][px], sl[f][py + 1][px], sl[f][py + 2][px]);
+            };
+            // z derivatives from the ring; products formed per plane (items 9-10)
+            auto dzr = [&](int f) { return d1<R>(rg[0][f], rg[1][f], rg[3][f], rg[4][f]); };
+            auto dzm = [&](int b, int c) {
+                return d1<R>(rg[0][3] * rg[0][b] * rg[0][c], rg[1][3] * rg[1][b] * rg[1][c],
+                             rg[3][3] * rg[3][b] * rg[3][c], rg[4][3] * rg[4][b] * rg[4][c]);
+            };
+            R G[3][3];      // d_a u_b
+            R M[3][3][3];   // d_a (p u_b u_c)
+            R Pg[3], C[3];  // d_a p, d_a (p/rho)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                G[0][b] = dxl(b);
+                G[1][b] = dyl(b);
+                G[2][b] = dzr(b);
+            }
+            Pg[0] = dxl(3); Pg[1] = dyl(3); Pg[2] = dzr(3);
+            C[0] = dxl(4); C[1] = dyl(4);
+            C[2] = d1<R>(rg[0][3] * rg[0][4], rg[1][3] * rg[1][4], rg[3][3] * rg[3][4], rg[4][3] * rg[4][4]);
+            constexpr int PI[3][3] = {{5, 6, 7}, {6, 8, 9}, {7, 9, 10}};
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+#pragma unroll
+                for (int c = b; c < 3; ++c) {
+                    const R mx = dxl(PI[b][c]), my = dyl(PI[b][c]), mz = dzm(b, c);
+                    M[0][b][c] = mx; M[0][c][b] = mx;
+                    M[1][b][c] = my; M[1][c][b] = my;
+                    M[2][b][c] = mz; M[2][c][b] = mz;
+                }
+            const R ep = rg[2][3], inv = rg[2][4], eP1 = in.own[0];
+            const R us[3] = {rg[2][0], rg[2][1], rg[2][2]};
+            const R trG = G[0][0] + G[1][1] + G[2][2];
+            oX = eP1 * trG;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int c = a; c < 3; ++c) oT[sym2<3>(a, c)] = ep * (G[a][c] + G[c][a]);
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                R acc = Pg[b] * inv;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) acc += us[c] * G[c][b];
+                oY[b] = acc;
+            }
+            const R jts[3] = {in.own[1], in.own[2], in.own[3]};
+            R V[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) V[a] = ep * C[a] + eP1 * us[a] * trG;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = a; b < 3; ++b)
+#pragma unroll
+                    for (int c = b; c < 3; ++c) {
+                        R br = M[c][a][b] + M[b][a][c] + M[a][b][c];
+                        R dj = R(0);
+                        if (a == b) { br += V[c]; dj += jts[c]; }
+                        if (a == c) { br += V[b]; dj += jts[b]; }
+                        if (b == c) { br += V[a]; dj += jts[a]; }
+                        oXi[sym3<3>(a, b, c)] = KX * br + KJ * dj;
+                    }
+        }
+        const unsigned io = out ? (col + plane * (unsigned)(z0 + k - 4)) * (unsigned)sizeof(R) : OUT;
+        bstore<R>(bX, io, oX);
+#pragma unroll
+        for (int s = 0; s < 6; ++s) bstore<R>(bT[s], io, oT[s]);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) bstore<R>(bY[b], io, oY[b]);
+#pragma unroll
+        for (int s = 0; s < 10; ++s) bstore<R>(bXi[s], io, oXi[s]);
         __syncthreads();
     }
 }

@@ -499,10 +499,13 @@ struct Impl {
             // time; extrapolate once two previous steps exist
             R* hist = (p.warm_start == 2 && advance && prev) ? (R*)c->jhist : nullptr;
             const int extrap = (hist && c->nprev >= 2) ? 1 : 0;
+            // the fused (velocity-form) solve starts from u alone and forms
+            // j~ after its last pass, so x_0 is not stored for it
+            const bool fused_solve = Lattice<Q>::D == 3 && !(p.flags & LB2P_FLAG_UNFUSED_SOLVE);
             hipLaunchKernelGGL((k_force<Q, R>), sgrid(c), sblock(c), 0, c->stream, c->dtab,
                                c->site_tiles, ic, (const R*)c->rho, (const R*)c->j0, (R*)c->f,
                                (R*)c->j0p, (R*)c->u, (const R*)c->jt0, (const R*)c->jt1, prev,
-                               (R*)c->jt0, (R*)c->pf, hist, extrap);
+                               fused_solve ? (R*)nullptr : (R*)c->jt0, (R*)c->pf, hist, extrap);
             hipLaunchKernelGGL(k_reduce_max, dim3(c->ndom), dim3(256), 0, c->stream, (const double*)c->pmax,
                                (const int*)c->site_range, c->jscale, 1LL, (const int*)nullptr);
         }
@@ -588,10 +591,19 @@ struct Impl {
         if (st != LB2P_OK) return st;
         {
             ProfScope _ps(c, LB2P_K_CLOSURE1);
-            hipLaunchKernelGGL((k_closure1<Q, R>), sgrid(c), sblock(c), 0, c->stream, c->dtab,
-                               c->site_tiles, (const SolveInfo*)c->info, (const R*)c->pf,
-                               (const R*)c->u, (const R*)c->jt0, (const R*)c->jt1, (R*)c->X, (R*)c->T,
-                               (R*)c->Y, (R*)c->Xi);
+            if constexpr (Lattice<Q>::D == 3) {
+                constexpr int TX = fused_tx<R>();
+                hipLaunchKernelGGL((k_closure1_zm<R, TX, kFusedTY>), dim3((unsigned)c->fused_host.size()),
+                                   dim3(TX, kFusedTY, 1), 0, c->stream, c->dtab, c->fused_tiles,
+                                   (const SolveInfo*)c->info, (const R*)c->pf, (const R*)c->u,
+                                   (const R*)c->jt0, (const R*)c->jt1, (R*)c->X, (R*)c->T, (R*)c->Y,
+                                   (R*)c->Xi);
+            } else {
+                hipLaunchKernelGGL((k_closure1<Q, R>), sgrid(c), sblock(c), 0, c->stream, c->dtab,
+                                   c->site_tiles, (const SolveInfo*)c->info, (const R*)c->pf,
+                                   (const R*)c->u, (const R*)c->jt0, (const R*)c->jt1, (R*)c->X,
+                                   (R*)c->T, (R*)c->Y, (R*)c->Xi);
+            }
         }
         {
             ProfScope _ps(c, LB2P_K_CLOSURE2);
