@@ -257,8 +257,10 @@ def main():
     ap.add_argument("--solver", default="fixed_point", choices=list(SOLVERS),
                     help="j~ solver: the paper's fixed point, or Chebyshev semi-iteration on the same map")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default block shapes")
-    ap.add_argument("--warm-start", type=int, default=2, choices=(0, 1, 2),
-                    help="start of the j~ iteration: zero, previous step, extrapolated from two steps")
+    ap.add_argument("--warm-start", type=int, default=None, choices=(0, 1, 2),
+                    help="start of the j~ iteration: zero, previous step, extrapolated from two steps "
+                         "(default: extrapolated for FP32/FP64 storage, previous step for BF16/FP16, whose "
+                         "rounding noise the extrapolation amplifies)")
     ap.add_argument("--settle", type=int, default=200,
                     help="steps run before warm-up and timing: the relaxation of the synthetic start, whose "
                          "solves need more passes than the rest of the run")
@@ -275,11 +277,13 @@ def main():
 
     import lb2p_workloads as W
     entry = W.load_params()[args.workload]
+    warm_of = lambda stg: args.warm_start if args.warm_start is not None else (2 if STORE_BYTES[stg] >= 4 else 1)
+    args_warm = warm_of(args.storage)
     res = run_gpu(args.workload, args.storage, args.steps, args.warmup, solver=args.solver,
-                  autotune=not args.no_autotune, warm_start=args.warm_start, settle=args.settle)
+                  autotune=not args.no_autotune, warm_start=args_warm, settle=args.settle)
     N, K = res["N"], args.steps
     secs = res["seconds"]
-    roof, per_kernel = roofline(res, args.storage, warm=args.warm_start, cheb=args.solver == "chebyshev")
+    roof, per_kernel = roofline(res, args.storage, warm=args_warm, cheb=args.solver == "chebyshev")
     shape = res["shape"]
     line = dict(
         metric="MLUPS and % HBM peak, D3Q59 FP32 vs BF16-storage at stated error",
@@ -291,7 +295,7 @@ def main():
                     sites=N, parallelism="single GPU",
                     solve=("j~ fixed point" if args.solver == "fixed_point" else "Chebyshev semi-iteration")
                     + " to the paper's stop rule, tol 1e-6 x max|j0'|, "
-                    + ["zero start", "warm start", "extrapolated warm start"][args.warm_start],
+                    + ["zero start", "warm start", "extrapolated warm start"][args_warm],
                     iters_last_step=res["stats"]["iters"],
                     timed_after_step=args.settle + args.warmup),
         roofline=roof,
@@ -306,12 +310,12 @@ def main():
         other = "chebyshev" if args.solver == "fixed_point" else "fixed_point"
         for stg, sol in (("bf16", args.solver), ("f16", args.solver), ("f32", other), ("bf16", other)):
             r2 = run_gpu(args.workload, stg, K, args.warmup, solver=sol, autotune=not args.no_autotune,
-                         warm_start=args.warm_start, settle=args.settle)
-            rf, _ = roofline(r2, stg, warm=args.warm_start, cheb=sol == "chebyshev")
+                         warm_start=warm_of(stg), settle=args.settle)
+            rf, _ = roofline(r2, stg, warm=warm_of(stg), cheb=sol == "chebyshev")
             var[f"{stg}_{sol}"] = dict(value=round(N * K / r2["seconds"] / 1e6, 2), unit="MLUPS",
                                        ms_per_step=round(1e3 * r2["seconds"] / K, 4),
                                        roofline_frac=rf["frac"], dominant=rf["kernel"],
-                                       iters_last_step=r2["stats"]["iters"])
+                                       iters_last_step=r2["stats"]["iters"], warm_start=warm_of(stg))
         line["variants"] = var
     if args.batch_steps > 0:
         bw = "d2q21_batch512"
