@@ -51,7 +51,7 @@ def site_bytes(kernel, Q, D, s, r, warm, cheb=False, pull=False):
         "moments": pops + (1 + D) * r + 8,
         # warm: 0 zero start, 1 previous j~, 2 extrapolated (history read and
         # written); writes f, j0', u (and the start j~ for the 2D solve)
-        "force": (1 + D) * r + (D * r if warm else 0) + (2 * D * r if warm == 2 else 0)
+        "force": (1 + D) * r + (D * r if warm else 0) + (2 * D * r * (warm - 1) if warm >= 2 else 0)
                  + (3 if D == 3 else 4) * D * r + 3 * r,
         "iter_q": (2 + D) * r + nsig * r,
         "iter_jt": (nsig + 1 + 2 * D) * r + 2 * D * r + (D * r if cheb else 0),
@@ -257,10 +257,11 @@ def main():
     ap.add_argument("--solver", default="fixed_point", choices=list(SOLVERS),
                     help="j~ solver: the paper's fixed point, or Chebyshev semi-iteration on the same map")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default block shapes")
-    ap.add_argument("--warm-start", type=int, default=None, choices=(0, 1, 2),
-                    help="start of the j~ iteration: zero, previous step, extrapolated from two steps "
-                         "(default: extrapolated for FP32/FP64 storage, previous step for BF16/FP16, whose "
-                         "rounding noise the extrapolation amplifies)")
+    ap.add_argument("--warm-start", type=int, default=1, choices=(0, 1, 2, 3),
+                    help="start of the j~ iteration: zero, previous step, extrapolated linearly from two "
+                         "steps or quadratically from three (after the initial transient the previous step's "
+                         "j~ needs the fewest passes on these workloads: extrapolation amplifies the "
+                         "step-to-step fluctuation of j~)")
     ap.add_argument("--settle", type=int, default=200,
                     help="steps run before warm-up and timing: the relaxation of the synthetic start, whose "
                          "solves need more passes than the rest of the run")
@@ -277,7 +278,7 @@ def main():
 
     import lb2p_workloads as W
     entry = W.load_params()[args.workload]
-    warm_of = lambda stg: args.warm_start if args.warm_start is not None else (2 if STORE_BYTES[stg] >= 4 else 1)
+    warm_of = lambda stg: args.warm_start
     args_warm = warm_of(args.storage)
     res = run_gpu(args.workload, args.storage, args.steps, args.warmup, solver=args.solver,
                   autotune=not args.no_autotune, warm_start=args_warm, settle=args.settle)
@@ -295,7 +296,7 @@ def main():
                     sites=N, parallelism="single GPU",
                     solve=("j~ fixed point" if args.solver == "fixed_point" else "Chebyshev semi-iteration")
                     + " to the paper's stop rule, tol 1e-6 x max|j0'|, "
-                    + ["zero start", "warm start", "extrapolated warm start"][args_warm],
+                    + ["zero start", "warm start", "extrapolated warm start", "quadratic warm start"][args_warm],
                     iters_last_step=res["stats"]["iters"],
                     timed_after_step=args.settle + args.warmup),
         roofline=roof,

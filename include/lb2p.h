@@ -106,9 +106,11 @@ typedef struct {
                                no host synchronisation inside lb2p_step        */
     int warm_start;         /* start of the j~ iteration: 0 zero, 1 the previous
                                step's j~ (Sec. IX allows both), 2 the linear
-                               extrapolation 2 j~(t-1) - j~(t-2) (the previous
-                               value until two steps exist); the fixed point
-                               and the stop rule do not depend on it           */
+                               extrapolation 2 j~(t-1) - j~(t-2), 3 the
+                               quadratic one j~(t-3) + 3 (j~(t-1) - j~(t-2))
+                               (lower orders until enough steps exist); the
+                               fixed point and the stop rule do not depend
+                               on it                                           */
     int check_every;        /* tolerance mode: the host reads the number of
                                converged domains first one pass before the
                                previous solve's pass count, then every

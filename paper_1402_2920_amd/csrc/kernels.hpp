@@ -543,7 +543,7 @@ __global__ void __launch_bounds__(256) k_force(const Domain* __restrict__ tab,
                                                R* __restrict__ f, R* __restrict__ j0p,
                                                R* __restrict__ u, const R* jt_prevA,
                                                const R* jt_prevB, const SolveInfo* prev_info,
-                                               R* jt0, R* __restrict__ pf, R* hist, int extrap)
+                                               R* jt0, R* __restrict__ pf, R* hist, R* hist2, int order)
 {
     using L = Lattice<Q>;
     const Where w = locate(tab, tiles);
@@ -600,9 +600,10 @@ __global__ void __launch_bounds__(256) k_force(const Domain* __restrict__ tab,
             sto(pfo + 2 * St, i0, inv);
         }
         // start of the iteration (Sec. IX allows zero or the previous step's
-        // value): zero, the previous step's final iterate y1, or the linear
-        // extrapolation 2 y1 - y2 from the two previous steps (extrap = 1);
-        // hist keeps y1 for the next step (hist != null)
+        // value): zero, the previous step's final iterate y1, or the
+        // extrapolation from the previous steps: linear 2 y1 - y2 (order 1)
+        // or quadratic y3 + 3 (y1 - y2) (order 2); hist keeps y1 and hist2
+        // y2 for the next step (when non-null)
         const R* prev = nullptr;
         if (prev_info) prev = prev_info[w.dom].final_buf ? jt_prevB : jt_prevA;
 #pragma unroll
@@ -611,9 +612,18 @@ __global__ void __launch_bounds__(256) k_force(const Domain* __restrict__ tab,
             const R jp = ldo(j0 + o + a * St, i0) + R(0.5) * fv;
             R jt = prev ? ldo(prev + o + a * St, i0) : R(0);
             if (hist) {
+                const R y1 = jt;
                 const R y2 = ldo(hist + o + a * St, i0);
-                sto(hist + o + a * St, i0, jt);
-                if (extrap) jt = R(2) * jt - y2;
+                sto(hist + o + a * St, i0, y1);
+                R y3 = R(0);
+                if (hist2) {
+                    y3 = ldo(hist2 + o + a * St, i0);
+                    sto(hist2 + o + a * St, i0, y2);
+                }
+                if (order == 2)
+                    jt = y3 + R(3) * (y1 - y2);
+                else if (order == 1)
+                    jt = R(2) * y1 - y2;
             }
             sto(f + o + a * St, i0, fv);
             sto(j0p + o + a * St, i0, jp);

@@ -101,7 +101,7 @@ lb2p_status check_params(const lb2p_params& p)
         return LB2P_EINVAL;
     if (p.graph_steps < 0) return LB2P_EINVAL;
     if (p.solver != LB2P_SOLVER_FIXED_POINT && p.solver != LB2P_SOLVER_CHEBYSHEV) return LB2P_EINVAL;
-    if (p.warm_start < 0 || p.warm_start > 2) return LB2P_EINVAL;
+    if (p.warm_start < 0 || p.warm_start > 3) return LB2P_EINVAL;
     if (!(p.spectral_bound >= 0.0 && p.spectral_bound < 1.0)) return LB2P_EINVAL;
     if (!(p.rho0 > 0.0)) return LB2P_EINVAL;
     if ((long long)p.nx * p.ny * p.nz > (1LL << 31)) return LB2P_EINVAL;
@@ -254,7 +254,8 @@ struct lb2p_ctx {
     bool initialized = false;
     bool have_prev = false;
     int nprev = 0;               // solves since init whose j~ can start the next one
-    void* jhist = nullptr;       // previous step's final j~ (extrapolated warm start)
+    void* jhist = nullptr;       // final j~ of the steps before the previous one (extrapolated
+                                 // warm start: j~(t-2), then j~(t-3) for the quadratic form)
     bool sigma_valid = false;
     lb2p_status sticky = LB2P_OK;
     int last_iters = 0;
@@ -495,17 +496,19 @@ struct Impl {
         {
             ProfScope _ps(c, LB2P_K_FORCE);
             const SolveInfo* prev = (p.warm_start && c->have_prev) ? c->info : nullptr;
-            // warm_start 2: keep the history only for solves that advance
-            // time; extrapolate once two previous steps exist
-            R* hist = (p.warm_start == 2 && advance && prev) ? (R*)c->jhist : nullptr;
-            const int extrap = (hist && c->nprev >= 2) ? 1 : 0;
+            // warm_start 2/3: keep the history only for solves that advance
+            // time; extrapolate linearly once two previous steps exist and
+            // quadratically (warm_start 3) once three do
+            R* hist = (p.warm_start >= 2 && advance && prev) ? (R*)c->jhist : nullptr;
+            R* hist2 = (hist && p.warm_start == 3) ? (R*)c->jhist + (size_t)c->D * c->S : nullptr;
+            const int order = !hist ? 0 : std::min(c->nprev, p.warm_start) - 1;
             // the fused (velocity-form) solve starts from u alone and forms
             // j~ after its last pass, so x_0 is not stored for it
             const bool fused_solve = Lattice<Q>::D == 3 && !(p.flags & LB2P_FLAG_UNFUSED_SOLVE);
             hipLaunchKernelGGL((k_force<Q, R>), sgrid(c), sblock(c), 0, c->stream, c->dtab,
                                c->site_tiles, ic, (const R*)c->rho, (const R*)c->j0, (R*)c->f,
                                (R*)c->j0p, (R*)c->u, (const R*)c->jt0, (const R*)c->jt1, prev,
-                               fused_solve ? (R*)nullptr : (R*)c->jt0, (R*)c->pf, hist, extrap);
+                               fused_solve ? (R*)nullptr : (R*)c->jt0, (R*)c->pf, hist, hist2, order);
             hipLaunchKernelGGL(k_reduce_max, dim3(c->ndom), dim3(256), 0, c->stream, (const double*)c->pmax,
                                (const int*)c->site_range, c->jscale, 1LL, (const int*)nullptr);
         }
@@ -581,7 +584,7 @@ struct Impl {
             c->last_iters = max_it;
         }
         c->have_prev = true;
-        if (advance) c->nprev = std::min(c->nprev + 1, 2);
+        if (advance) c->nprev = std::min(c->nprev + 1, 3);
         return LB2P_OK;
     }
 
@@ -901,9 +904,10 @@ lb2p_status create_impl(int ndom, const lb2p_params* pp, void* hip_stream, lb2p_
     if (e == hipSuccess && p0.solver == LB2P_SOLVER_CHEBYSHEV)
         e = hipMalloc((void**)&c->omega, sizeof(double) * nres);
     if (e == hipSuccess) e = hipMalloc((void**)&c->mass, sizeof(double) * (size_t)S);
-    if (e == hipSuccess && p0.warm_start == 2) {
-        e = hipMalloc(&c->jhist, (size_t)D * S * c->rsize);
-        if (e == hipSuccess) e = hipMemsetAsync(c->jhist, 0, (size_t)D * S * c->rsize, c->stream);
+    if (e == hipSuccess && p0.warm_start >= 2) {
+        const size_t hb = (size_t)(p0.warm_start - 1) * D * S * c->rsize;
+        e = hipMalloc(&c->jhist, hb);
+        if (e == hipSuccess) e = hipMemsetAsync(c->jhist, 0, hb, c->stream);
     }
     if (e != hipSuccess) {
         free_ctx(c);
@@ -984,7 +988,7 @@ lb2p_status run_steps(lb2p_ctx* c, int nsteps)
     if (gs > 0 && !c->prof) {
         // a captured step warm-starts j~ from the previous step(s); the first
         // steps after lb2p_init have none, so they run eagerly
-        while (s < nsteps && (!c->have_prev || (c->prm.warm_start == 2 && c->nprev < 2))) {
+        while (s < nsteps && (!c->have_prev || (c->prm.warm_start >= 2 && c->nprev < c->prm.warm_start))) {
             lb2p_status st = dispatch(c, [&](auto impl) { return decltype(impl)::step(c); });
             if (st != LB2P_OK) return st;
             ++s;

@@ -130,7 +130,7 @@ def test_chebyshev_needs_fewer_passes(L, lattice, shape):
     assert np.abs(out[0][1] - out[1][1]).max() <= 1e-10 * scale
 
 
-@pytest.mark.parametrize("warm", [0, 2])
+@pytest.mark.parametrize("warm", [0, 2, 3])
 def test_warm_start_forms_reach_the_same_fixed_point(orc, L, warm):
     """Zero start and the extrapolated warm start change only the first
     iterate: over 10 steps both stay on the oracle (FP64, 1e-10)."""
