@@ -49,10 +49,10 @@ def site_bytes(kernel, Q, D, s, r, warm, cheb=False, pull=False):
     pops = (Q - 1) * s + t0 + rec
     return {
         "moments": pops + (1 + D) * r + 8,
-        # warm: 0 zero start, 1 previous j~, 2 extrapolated (history read and
-        # written); writes f, j0', u (and the start j~ for the 2D solve)
+        # warm: 0 zero start, 1 previous j~, 2/3 extrapolated (history read
+        # and written); writes f, j0', u and p, P1, 1/rho
         "force": (1 + D) * r + (D * r if warm else 0) + (2 * D * r * (warm - 1) if warm >= 2 else 0)
-                 + (3 if D == 3 else 4) * D * r + 3 * r,
+                 + 3 * D * r + 3 * r,
         "iter_q": (2 + D) * r + nsig * r,
         "iter_jt": (nsig + 1 + 2 * D) * r + 2 * D * r + (D * r if cheb else 0),
         "closure1": (3 + 2 * D) * r + (1 + nsig + D + nxi) * r,

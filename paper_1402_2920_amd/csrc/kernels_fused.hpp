@@ -329,6 +329,149 @@ k_iter_fused3(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, It
     block_max_part(ic.part, dsum == dsum ? (double)dmax : (double)dsum);
 }
 
+// One pass of the correction-current iteration for D2Q21 (items 3-6), in the
+// velocity form of the 3D pass: u_{k+1} = (j0' + G)/rho with G = -(1/12)
+// d_b q_ab and q built from u_k.  A block owns a TX x TY tile; its threads
+// are the (TX+4) x (TY+4) points where q is needed, the tile's points first
+// (whole wavefronts) and the 2-wide frame after them.  u of the tile and a
+// 4-wide frame goes to LDS, then q, then the tile's wavefronts take the
+// divergence.  Reads u (stencil), p, P1 (stencil), j0' and rho at the tile
+// points; writes the next u (Chebyshev: also reads u_{k-1}, overwritten in
+// place).
+template <class R, int TX, int TY, bool CHEB>
+__global__ void __launch_bounds__((TX + 4) * (TY + 4))
+k_iter_fused2(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, IterCtl ic, int it,
+              const R* __restrict__ pf, const R* __restrict__ rho, const R* __restrict__ j0p,
+              const R* __restrict__ u_old, R* u_new)
+{
+    constexpr int QX = TX + 4, QY = TY + 4;   // q points
+    constexpr int UX = TX + 8, UY = TY + 8;   // u points
+    constexpr int NFRAME = UX * UY - QX * QY;
+    static_assert(NFRAME <= QX * QY, "frame larger than the block");
+    static_assert((TX * TY) % 64 == 0, "tile points must fill whole wavefronts");
+    __shared__ R su[2][UY][UX];
+    __shared__ R sq[3][QY][QX];   // q_xx, q_yy, q_xy
+
+    const Tile tl = tiles[blockIdx.x];
+    if (tl.dom < 0 || iter_skip(ic, tl.dom, it)) return;   // uniform per block
+    const Domain& dm = tab[tl.dom];
+    const int nx = dm.g.nx, ny = dm.g.ny;
+    const long long N = dm.g.S;
+    const unsigned bytes = (unsigned)dm.g.N * (unsigned)sizeof(R);
+    const unsigned OUT = bytes;
+    const long long o = dm.off;
+    const PlaneBuf bP = plane_buf(pf + o, bytes);
+    const PlaneBuf bP1 = plane_buf(pf + o + N, bytes);
+    const PlaneBuf bRho = plane_buf(rho + o, bytes);
+    const PlaneBuf bJ[2] = {plane_buf(j0p + o, bytes), plane_buf(j0p + o + N, bytes)};
+    const PlaneBuf bU[2] = {plane_buf(u_old + o, bytes), plane_buf(u_old + o + N, bytes)};
+    const PlaneBuf bV[2] = {plane_buf(u_new + o, bytes), plane_buf(u_new + o + N, bytes)};
+    R omega = R(1), gam = R(1);
+    if (CHEB) {
+        omega = R(ic.omega[(long long)tl.dom * ic.stride + it]);
+        gam = R(dm.cf.cheb_gamma);
+    }
+
+    const int tid = threadIdx.x + QX * threadIdx.y;
+    int qx, qy;
+    const bool interior = __builtin_amdgcn_readfirstlane(tid >> 6) < (TX * TY) / 64;
+    if (interior) {
+        qx = 2 + tid % TX; qy = 2 + tid / TX;
+    } else {
+        const int e = tid - TX * TY;
+        if (e < 2 * QX) {
+            qy = e / QX; qx = e % QX;
+        } else if (e < 4 * QX) {
+            qy = QY - 4 + e / QX; qx = e % QX;
+        } else {
+            const int t = e - 4 * QX;
+            const int c = t % 4;
+            qy = 2 + t / 4;
+            qx = c < 2 ? c : QX - 4 + c;
+        }
+    }
+    const int x0 = tl.x0, y0 = tl.y0;
+    const unsigned col = (unsigned)wrapmod(x0 + qx - 2, nx) + (unsigned)nx * (unsigned)wrapmod(y0 + qy - 2, ny);
+    const bool owned = interior && (x0 + qx - 2 < nx) && (y0 + qy - 2 < ny);
+    // this thread's u-frame point (outer 2-wide ring of the UX x UY region)
+    int fx = 0, fy = 0;
+    const bool has_frame = tid < NFRAME;
+    if (has_frame) {
+        if (tid < 2 * UX) {
+            fy = tid / UX; fx = tid % UX;
+        } else if (tid < 4 * UX) {
+            const int t = tid - 2 * UX;
+            fy = UY - 2 + t / UX; fx = t % UX;
+        } else {
+            const int t = tid - 4 * UX;
+            const int c = t % 4;
+            fy = 2 + t / 4;
+            fx = c < 2 ? c : UX - 4 + c;
+        }
+    }
+    const unsigned fcol = has_frame
+        ? (unsigned)wrapmod(x0 + fx - 4, nx) + (unsigned)nx * (unsigned)wrapmod(y0 + fy - 4, ny) : 0u;
+
+    // every lane issues every load; lanes with nothing to read use OUT
+    const unsigned ic_ = col * (unsigned)sizeof(R);
+    const unsigned io = owned ? ic_ : OUT;
+    const unsigned ifr = has_frame ? fcol * (unsigned)sizeof(R) : OUT;
+    R uq[2], fu[2], jj[2], vv[2] = {R(0), R(0)};
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        uq[a] = bload<R>(bU[a], ic_);
+        fu[a] = bload<R>(bU[a], ifr);
+        jj[a] = bload<R>(bJ[a], io);
+        if (CHEB) vv[a] = bload<R>(bV[a], it > 0 ? io : OUT);
+    }
+    const R pq = bload<R>(bP, ic_), P1q = bload<R>(bP1, ic_);
+    const R rr = bload<R>(bRho, io);
+#pragma unroll
+    for (int a = 0; a < 2; ++a) su[a][qy + 2][qx + 2] = uq[a];
+    if (has_frame) {
+#pragma unroll
+        for (int a = 0; a < 2; ++a) su[a][fy][fx] = fu[a];
+    }
+    __syncthreads();
+    {
+        R G[2][2];   // G[a][b] = d_a u_b
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            G[0][b] = d1<R>(su[b][qy + 2][qx], su[b][qy + 2][qx + 1], su[b][qy + 2][qx + 3], su[b][qy + 2][qx + 4]);
+            G[1][b] = d1<R>(su[b][qy][qx + 2], su[b][qy + 1][qx + 2], su[b][qy + 3][qx + 2], su[b][qy + 4][qx + 2]);
+        }
+        const R X = P1q * (G[0][0] + G[1][1]);
+        const R p2 = R(2) * pq;
+        sq[0][qy][qx] = X + p2 * G[0][0];
+        sq[1][qy][qx] = X + p2 * G[1][1];
+        sq[2][qy][qx] = pq * (G[0][1] + G[1][0]);
+    }
+    __syncthreads();
+    R dmax = R(0), dsum = R(0);   // dsum only carries a NaN (fmax drops it)
+    R un[2] = {R(0), R(0)};
+    if (interior && owned) {
+        const int px = qx, py = qy;
+        const R sd[2] = {
+            d1<R>(sq[0][py][px - 2], sq[0][py][px - 1], sq[0][py][px + 1], sq[0][py][px + 2]) +
+                d1<R>(sq[2][py - 2][px], sq[2][py - 1][px], sq[2][py + 1][px], sq[2][py + 2][px]),
+            d1<R>(sq[2][py][px - 2], sq[2][py][px - 1], sq[2][py][px + 1], sq[2][py][px + 2]) +
+                d1<R>(sq[1][py - 2][px], sq[1][py - 1][px], sq[1][py + 1][px], sq[1][py + 2][px])};
+        const R ri = R(1) / rr;
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const R gv = -sd[a] * R(1.0 / 12.0);               // G(x_k)_a
+            const R d = fabs(gv + jj[a] - rr * uq[a]);          // |G(x_k) - x_k|, x_k = rho u_k - j0'
+            dmax = fmax(dmax, d);
+            dsum += d;
+            const R gu = (jj[a] + gv) * ri;
+            un[a] = CHEB ? next_iterate<R>(gu, uq[a], vv[a], omega, gam, it == 0) : gu;
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a) bstore<R>(bV[a], io, un[a]);
+    block_max_part(ic.part, dsum == dsum ? (double)dmax : (double)dsum);
+}
+
 // u = (j0' + j~)/rho for the final iterate (item 8).
 template <int Q, class R>
 __global__ void __launch_bounds__(256) k_u_final(const Domain* __restrict__ tab,

@@ -37,6 +37,7 @@ constexpr double kPi = 3.14159265358979323846;
 template <class R>
 constexpr int fused_tx() { return sizeof(R) == 4 ? 64 : 32; }
 constexpr int kFusedTY = 8;
+constexpr int kFused2TX = 32, kFused2TY = 24;   // 2D solve pass: 32 x 24 tiles (36 x 28 threads)
 int fused_tx_of(size_t rsize) { return rsize == 4 ? fused_tx<float>() : fused_tx<double>(); }
 
 template <int Q>
@@ -391,7 +392,15 @@ lb2p_status build_tiles(lb2p_ctx* c)
                         site.push_back(t);
                     }
         }
-        if (c->D == 3) {
+        if (c->D == 2) {
+            // the 2D fused solve pass: kFused2TX x kFused2TY tiles, no z
+            for (int y = 0; y < g.ny; y += kFused2TY)
+                for (int x = 0; x < g.nx; x += kFused2TX) {
+                    Tile t{};
+                    t.dom = d; t.x0 = x; t.y0 = y; t.z0 = 0; t.len = 1;
+                    fused.push_back(t);
+                }
+        } else {
             const int tz = std::min(c->tz, g.nz);
             for (int sl = 0; sl < nslab; ++sl) {
                 const int r0 = (int)((long long)frows * sl / nslab), r1 = (int)((long long)frows * (sl + 1) / nslab);
@@ -504,7 +513,7 @@ struct Impl {
             const int order = !hist ? 0 : std::min(c->nprev, p.warm_start) - 1;
             // the fused (velocity-form) solve starts from u alone and forms
             // j~ after its last pass, so x_0 is not stored for it
-            const bool fused_solve = Lattice<Q>::D == 3 && !(p.flags & LB2P_FLAG_UNFUSED_SOLVE);
+            const bool fused_solve = !(p.flags & LB2P_FLAG_UNFUSED_SOLVE);
             hipLaunchKernelGGL((k_force<Q, R>), sgrid(c), sblock(c), 0, c->stream, c->dtab,
                                c->site_tiles, ic, (const R*)c->rho, (const R*)c->j0, (R*)c->f,
                                (R*)c->j0p, (R*)c->u, (const R*)c->jt0, (const R*)c->jt1, prev,
@@ -512,9 +521,10 @@ struct Impl {
             hipLaunchKernelGGL(k_reduce_max, dim3(c->ndom), dim3(256), 0, c->stream, (const double*)c->pmax,
                                (const int*)c->site_range, c->jscale, 1LL, (const int*)nullptr);
         }
-        const bool fused = Lattice<Q>::D == 3 && !(p.flags & LB2P_FLAG_UNFUSED_SOLVE);
-        constexpr int kFusedTX = fused_tx<R>();
-        const dim3 fblock(kFusedTX + 4, kFusedTY + 4, 1);
+        const bool fused = !(p.flags & LB2P_FLAG_UNFUSED_SOLVE);
+        constexpr int kFusedTX = Lattice<Q>::D == 3 ? fused_tx<R>() : kFused2TX;
+        constexpr int kTY = Lattice<Q>::D == 3 ? kFusedTY : kFused2TY;
+        const dim3 fblock(kFusedTX + 4, kTY + 4, 1);
         const dim3 fgrid((unsigned)c->fused_host.size());
         const int every = p.check_every > 0 ? p.check_every : 1;
         int next_check = std::max(1, c->last_iters + 1);
@@ -526,15 +536,27 @@ struct Impl {
             R* uold = (R*)((it & 1) ? c->u1 : c->u);
             R* unew = (R*)((it & 1) ? c->u : c->u1);
             if (fused) {
-                ProfScope _ps(c, LB2P_K_ITER_FUSED);
-                if (c->omega)
-                    hipLaunchKernelGGL((k_iter_fused3<R, kFusedTX, kFusedTY, true>), fgrid, fblock, 0,
-                                       c->stream, c->dtab, c->fused_tiles, ic, it, (const R*)c->pf,
-                                       (const R*)c->rho, (const R*)c->j0p, (const R*)uold, unew);
-                else
-                    hipLaunchKernelGGL((k_iter_fused3<R, kFusedTX, kFusedTY, false>), fgrid, fblock, 0,
-                                       c->stream, c->dtab, c->fused_tiles, ic, it, (const R*)c->pf,
-                                       (const R*)c->rho, (const R*)c->j0p, (const R*)uold, unew);
+                if constexpr (Lattice<Q>::D == 2) {
+                    ProfScope _ps(c, LB2P_K_ITER_FUSED);
+                    if (c->omega)
+                        hipLaunchKernelGGL((k_iter_fused2<R, kFusedTX, kTY, true>), fgrid, fblock, 0,
+                                           c->stream, c->dtab, c->fused_tiles, ic, it, (const R*)c->pf,
+                                           (const R*)c->rho, (const R*)c->j0p, (const R*)uold, unew);
+                    else
+                        hipLaunchKernelGGL((k_iter_fused2<R, kFusedTX, kTY, false>), fgrid, fblock, 0,
+                                           c->stream, c->dtab, c->fused_tiles, ic, it, (const R*)c->pf,
+                                           (const R*)c->rho, (const R*)c->j0p, (const R*)uold, unew);
+                } else {
+                    ProfScope _ps(c, LB2P_K_ITER_FUSED);
+                    if (c->omega)
+                        hipLaunchKernelGGL((k_iter_fused3<R, kFusedTX, kFusedTY, true>), fgrid, fblock, 0,
+                                           c->stream, c->dtab, c->fused_tiles, ic, it, (const R*)c->pf,
+                                           (const R*)c->rho, (const R*)c->j0p, (const R*)uold, unew);
+                    else
+                        hipLaunchKernelGGL((k_iter_fused3<R, kFusedTX, kFusedTY, false>), fgrid, fblock, 0,
+                                           c->stream, c->dtab, c->fused_tiles, ic, it, (const R*)c->pf,
+                                           (const R*)c->rho, (const R*)c->j0p, (const R*)uold, unew);
+                }
             } else {
                 {
                     ProfScope _ps(c, LB2P_K_ITER_Q);

@@ -21,6 +21,7 @@ CASES = [
     ("d2q21", 21, (40, 24), {}),
     ("d3q59", 59, (20, 12, 10), {}),
     ("d3q59_unfused", 59, (20, 12, 10), dict(flags=1)),
+    ("d2q21_unfused", 21, (40, 24), dict(flags=1)),
     # several solve tiles (64 x 8 for FP32 fields, 32 x 8 for FP64) with
     # ragged edges in x and y; a tile wider than the grid
     ("d3q59_tiles", 59, (40, 24, 72), {}),
@@ -87,14 +88,17 @@ def test_invariants_on_gpu(orc, L, name, lattice, shape, extra):
 
 
 @pytest.mark.parametrize("storage", ["STORE_F64", "STORE_F32"])
-def test_fused_and_unfused_solve_agree(orc, L, storage):
-    """The fused D3Q59 pass and the two-sweep pass are the same map: same
-    iteration count from a zero start and the same j~ up to rounding."""
-    rho, u, model = small_case(59, (40, 24, 36))
+@pytest.mark.parametrize("lattice,shape", [(21, (72, 20)), (59, (40, 24, 36))])
+def test_fused_and_unfused_solve_agree(orc, L, storage, lattice, shape):
+    """The fused pass (velocity form, one kernel per pass) and the two-sweep
+    pass (j~ form) are the same map: same iteration count from a zero start
+    and the same j~ up to rounding."""
+    rho, u, model = small_case(lattice, shape)
     st = getattr(L, storage)
     out = []
     for flags in (0, L.FLAG_UNFUSED_SOLVE):
-        P = L.Params(lattice=59, nx=40, ny=24, nz=36, storage=st, gamma=model["gamma"],
+        P = L.Params(lattice=lattice, nx=shape[0], ny=shape[1], nz=shape[2] if len(shape) == 3 else 1,
+                     storage=st, gamma=model["gamma"],
                      kappa=model["kappa"], rho1=model["rho1"], rho2=model["rho2"], A=model["A"],
                      cs2_rho1=model["cs2_1"], rho0=model["rho0"], max_iter=500, flags=flags,
                      tol=1e-14 if st == L.STORE_F64 else 1e-6)
