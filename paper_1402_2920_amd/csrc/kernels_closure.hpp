@@ -25,7 +25,7 @@ struct C2In {
 };
 
 template <class R, int TX, int TY>
-__global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 2 : 1)))
+__global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 1)))
 k_closure2_zm(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, const R* __restrict__ rho,
               const R* __restrict__ u, const R* __restrict__ X, const R* __restrict__ T,
               const R* __restrict__ Y, R* __restrict__ Sig)
@@ -182,11 +182,17 @@ k_closure2_zm(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, co
                 return d1<R>(sl[f][py - 2][px], sl[f][py - 1][px], sl[f][py + 1][px], sl[f][py + 2][px]);
             };
             auto dz = [&](int f) { return d1<R>(rg[0][f], rg[1][f], rg[3][f], rg[4][f]); };
+            // (groups of derivatives are kept apart, so that the LDS reads
+            // of one group are not all hoisted ahead and held in registers)
+            const R r = rg[2][7];
+            const EosVal<R> e = eos_all<R>(dm.cf.eos, r);
+            __builtin_amdgcn_sched_barrier(0);
             const R DX[3] = {dx(0), dy(0), dz(0)};
             R DT[3];
             DT[0] = dx(1) + dy(2) + dz(1);
             DT[1] = dx(2) + dy(3) + dz(2);
             DT[2] = dx(4) + dy(5) + dz(3);
+            __builtin_amdgcn_sched_barrier(0);
             R DY[3][3];   // DY[a][b] = d_a Y_b
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
@@ -194,6 +200,7 @@ k_closure2_zm(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, co
                 DY[1][b] = dy(6 + b);
                 DY[2][b] = dz(4 + b);
             }
+            __builtin_amdgcn_sched_barrier(0);
             const R trJ = dx(9) + dy(10) +
                           d1<R>(rg[0][7] * rg[0][10], rg[1][7] * rg[1][10], rg[3][7] * rg[3][10],
                                 rg[4][7] * rg[4][10]);
@@ -204,8 +211,7 @@ k_closure2_zm(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, co
                 G[1][b] = dy(11 + b);
                 G[2][b] = dz(8 + b);
             }
-            const R r = rg[2][7];
-            const EosVal<R> e = eos_all<R>(dm.cf.eos, r);
+            __builtin_amdgcn_sched_barrier(0);
             const R us[3] = {rg[2][8], rg[2][9], rg[2][10]};
             const R trG = G[0][0] + G[1][1] + G[2][2];
             const R trDY = DY[0][0] + DY[1][1] + DY[2][2];

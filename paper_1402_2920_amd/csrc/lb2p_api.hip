@@ -37,6 +37,7 @@ constexpr double kPi = 3.14159265358979323846;
 template <class R>
 constexpr int fused_tx() { return sizeof(R) == 4 ? 64 : 32; }
 constexpr int kFusedTY = 8;
+constexpr int kClosTZ = 32;     // z chunk of the 3D closure kernels
 constexpr int kFused2TX = 32, kFused2TY = 24;   // 2D solve pass: 32 x 24 tiles (36 x 28 threads)
 int fused_tx_of(size_t rsize) { return rsize == 4 ? fused_tx<float>() : fused_tx<double>(); }
 
@@ -223,9 +224,11 @@ struct lb2p_ctx {
     // tiles
     int bx = 64, by = 4, tz = 32;
     std::vector<Tile> site_host, fused_host;   // launch order
+    std::vector<Tile> clos_host;               // 3D closure z-march (shorter z chunks)
     Tile* site_tiles = nullptr;
     Tile* fused_tiles = nullptr;
-    size_t site_cap = 0, fused_cap = 0;
+    Tile* clos_tiles = nullptr;
+    size_t site_cap = 0, fused_cap = 0, clos_cap = 0;
     double* partial = nullptr;
     size_t partial_cap = 0;
     double* pmax = nullptr;                    // per-block maxima
@@ -368,7 +371,7 @@ void free_graphs(lb2p_ctx* c)
 // (Re)build both tile lists for the current block shapes.
 lb2p_status build_tiles(lb2p_ctx* c)
 {
-    std::vector<Tile> site, fused;
+    std::vector<Tile> site, fused, clos;
     std::vector<int> srange(c->ndom + 1, 0), frange(c->ndom + 1, 0);
     for (int d = 0; d < c->ndom; ++d) {
         srange[d] = (int)site.size();
@@ -401,16 +404,24 @@ lb2p_status build_tiles(lb2p_ctx* c)
                     fused.push_back(t);
                 }
         } else {
-            const int tz = std::min(c->tz, g.nz);
-            for (int sl = 0; sl < nslab; ++sl) {
-                const int r0 = (int)((long long)frows * sl / nslab), r1 = (int)((long long)frows * (sl + 1) / nslab);
-                for (int z = 0; z < g.nz; z += tz)
-                    for (int r = r0; r < r1; ++r)
-                        for (int x = 0; x < g.nx; x += fused_tx_of(c->rsize)) {
-                            Tile t{};
-                            t.dom = d; t.x0 = x; t.y0 = r * kFusedTY; t.z0 = z; t.len = std::min(tz, g.nz - z);
-                            fused.push_back(t);
-                        }
+            // the solve pass marches tz planes; the closure kernels, which
+            // have registers for two blocks per CU, march kClosTZ (more
+            // blocks in flight)
+            for (int pass = 0; pass < 2; ++pass) {
+                const int tz = std::min(pass == 0 ? c->tz : kClosTZ, g.nz);
+                std::vector<Tile>& lst = pass == 0 ? fused : clos;
+                for (int sl = 0; sl < nslab; ++sl) {
+                    const int r0 = (int)((long long)frows * sl / nslab),
+                              r1 = (int)((long long)frows * (sl + 1) / nslab);
+                    for (int z = 0; z < g.nz; z += tz)
+                        for (int r = r0; r < r1; ++r)
+                            for (int x = 0; x < g.nx; x += fused_tx_of(c->rsize)) {
+                                Tile t{};
+                                t.dom = d; t.x0 = x; t.y0 = r * kFusedTY; t.z0 = z;
+                                t.len = std::min(tz, g.nz - z);
+                                lst.push_back(t);
+                            }
+                }
             }
         }
     }
@@ -418,6 +429,7 @@ lb2p_status build_tiles(lb2p_ctx* c)
     frange[c->ndom] = (int)fused.size();
     c->site_host = deal_xcd(site);
     c->fused_host = fused.empty() ? fused : deal_xcd(fused);
+    c->clos_host = clos.empty() ? clos : deal_xcd(clos);
     auto upload = [&](const std::vector<Tile>& h, Tile*& dptr, size_t& cap) -> lb2p_status {
         if (h.empty()) return LB2P_OK;
         if (h.size() > cap) {
@@ -432,6 +444,8 @@ lb2p_status build_tiles(lb2p_ctx* c)
     lb2p_status st = upload(c->site_host, c->site_tiles, c->site_cap);
     if (st != LB2P_OK) return st;
     st = upload(c->fused_host, c->fused_tiles, c->fused_cap);
+    if (st != LB2P_OK) return st;
+    st = upload(c->clos_host, c->clos_tiles, c->clos_cap);
     if (st != LB2P_OK) return st;
     const size_t np = 4 * c->site_host.size();
     if (np > c->partial_cap) {
@@ -618,8 +632,8 @@ struct Impl {
             ProfScope _ps(c, LB2P_K_CLOSURE1);
             if constexpr (Lattice<Q>::D == 3) {
                 constexpr int TX = fused_tx<R>();
-                hipLaunchKernelGGL((k_closure1_zm<R, TX, kFusedTY>), dim3((unsigned)c->fused_host.size()),
-                                   dim3(TX, kFusedTY, 1), 0, c->stream, c->dtab, c->fused_tiles,
+                hipLaunchKernelGGL((k_closure1_zm<R, TX, kFusedTY>), dim3((unsigned)c->clos_host.size()),
+                                   dim3(TX, kFusedTY, 1), 0, c->stream, c->dtab, c->clos_tiles,
                                    (const SolveInfo*)c->info, (const R*)c->pf, (const R*)c->u,
                                    (const R*)c->jt0, (const R*)c->jt1, (R*)c->X, (R*)c->T, (R*)c->Y,
                                    (R*)c->Xi);
@@ -634,8 +648,8 @@ struct Impl {
             ProfScope _ps(c, LB2P_K_CLOSURE2);
             if constexpr (Lattice<Q>::D == 3) {
                 constexpr int TX = fused_tx<R>();
-                hipLaunchKernelGGL((k_closure2_zm<R, TX, kFusedTY>), dim3((unsigned)c->fused_host.size()),
-                                   dim3(TX, kFusedTY, 1), 0, c->stream, c->dtab, c->fused_tiles,
+                hipLaunchKernelGGL((k_closure2_zm<R, TX, kFusedTY>), dim3((unsigned)c->clos_host.size()),
+                                   dim3(TX, kFusedTY, 1), 0, c->stream, c->dtab, c->clos_tiles,
                                    (const R*)c->rho, (const R*)c->u, (const R*)c->X, (const R*)c->T,
                                    (const R*)c->Y, (R*)c->Sig);
             } else {
@@ -771,6 +785,7 @@ void free_ctx(lb2p_ctx* c)
     if (c->mass) (void)hipFree(c->mass);
     if (c->site_tiles) (void)hipFree(c->site_tiles);
     if (c->fused_tiles) (void)hipFree(c->fused_tiles);
+    if (c->clos_tiles) (void)hipFree(c->clos_tiles);
     if (c->host) (void)hipHostFree(c->host);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (auto& p : c->pending) {
