@@ -448,4 +448,153 @@ k_closure1_zm(const Domain* __restrict__ tab, const Tile* __restrict__ tiles,
     }
 }
 
+// Item 2 for D3Q59 as a z-march: f = kappa rho (sum over the force stencil of
+// Table III of tau_i d_i rho(r + d_i)), j0' = j0 + f/2, the per-step planes p,
+// P1 = p - rho p', 1/rho, and the start of the iteration (the same arithmetic
+// as the per-site k_force).  The stencil reaches (+-1, 0, 0), (+-1, +-1, 0)
+// and (+-2, 0, 0) and their permutations, so three planes of rho (c-1, c,
+// c+1, tile + 2-wide frame) sit in LDS and the column's rho at c-2 .. c+2 in
+// registers.
+template <class R, int TX, int TY>
+__global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 1)))
+k_force_zm(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, IterCtl ic,
+           const R* __restrict__ rho, const R* __restrict__ j0, R* __restrict__ f, R* __restrict__ j0p,
+           R* __restrict__ u, const R* jt_prevA, const R* jt_prevB, const SolveInfo* prev_info, R* jt0,
+           R* __restrict__ pf, R* hist, R* hist2, int order)
+{
+    constexpr int UX = TX + 4, UY = TY + 4;
+    constexpr int NFRAME = UX * UY - TX * TY;
+    static_assert(NFRAME <= TX * TY, "frame larger than the block");
+    __shared__ R sr[3][UY][UX];   // rho at planes (slot = plane mod 3)
+
+    const Tile tl = tiles[blockIdx.x];
+    double amax = 0.0;
+    if (tl.dom >= 0) {
+        const Domain& dm = tab[tl.dom];
+        const int nx = dm.g.nx, ny = dm.g.ny, nz = dm.g.nz;
+        const long long N = dm.g.S;
+        const unsigned plane = (unsigned)nx * (unsigned)ny;
+        const unsigned bytes = (unsigned)dm.g.N * (unsigned)sizeof(R);
+        const unsigned OUT = bytes;
+        const long long o = dm.off;
+        const PlaneBuf bR = plane_buf(rho + o, bytes);
+        const R* prev = nullptr;
+        if (prev_info) prev = prev_info[tl.dom].final_buf ? jt_prevB : jt_prevA;
+
+        const int lx = threadIdx.x, ly = threadIdx.y;
+        const int tid = lx + TX * ly;
+        const int x0 = tl.x0, y0 = tl.y0, z0 = tl.z0, TZ = tl.len;
+        const unsigned col = (unsigned)wrapmod(x0 + lx, nx) + (unsigned)nx * (unsigned)wrapmod(y0 + ly, ny);
+        const bool owned = (x0 + lx < nx) && (y0 + ly < ny);
+        int fx = 0, fy = 0;
+        const bool has_frame = tid < NFRAME;
+        if (has_frame) {
+            if (tid < 2 * UX) {
+                fy = tid / UX; fx = tid % UX;
+            } else if (tid < 4 * UX) {
+                const int t = tid - 2 * UX;
+                fy = UY - 2 + t / UX; fx = t % UX;
+            } else {
+                const int t = tid - 4 * UX;
+                const int c = t % 4;
+                fy = 2 + t / 4;
+                fx = c < 2 ? c : UX - 4 + c;
+            }
+        }
+        const unsigned fcol = has_frame
+            ? (unsigned)wrapmod(x0 + fx - 2, nx) + (unsigned)nx * (unsigned)wrapmod(y0 + fy - 2, ny) : 0u;
+
+        // Step k: the column's lead plane z0-2+k enters the ring, plane
+        // c+1 = z0-3+k enters LDS, output at c = z0-4+k for 4 <= k < TZ+4.
+        const int nsteps = TZ + 4;
+        auto lead_off = [&](int k) {
+            return k < nsteps ? (col + plane * (unsigned)wrap3(z0 - 2 + k, nz)) * (unsigned)sizeof(R) : OUT;
+        };
+        auto frame_off = [&](int k) {
+            return has_frame && k >= 2 && k < nsteps
+                ? (fcol + plane * (unsigned)wrap3(z0 - 3 + k, nz)) * (unsigned)sizeof(R) : OUT;
+        };
+        R rg[5] = {R(0), R(0), R(0), R(0), R(0)};   // the column's rho at c-2 .. c+2
+        R nlead = bload<R>(bR, lead_off(0));
+        R nfr = bload<R>(bR, frame_off(0));
+        const R kap = R(dm.cf.kappa);
+        for (int k = 0; k < nsteps; ++k) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) rg[s] = rg[s + 1];
+            rg[4] = nlead;
+            const R fr = nfr;
+            nlead = bload<R>(bR, lead_off(k + 1));
+            nfr = bload<R>(bR, frame_off(k + 1));
+            // plane c+1 = z0-3+k into its LDS slot
+            const int slot = (k + 3) % 3;   // (z0 - 3 + k) mod 3 relative to z0: slots follow k
+            sr[slot][ly + 2][lx + 2] = rg[3];
+            if (has_frame) sr[slot][fy][fx] = fr;
+            __syncthreads();
+            const int zc = z0 + k - 4;
+            if (k >= 4 && owned && zc < nz) {
+                const int sc = (k + 2) % 3, sm = (k + 1) % 3, sp = slot;   // planes c, c-1, c+1
+                const int py = ly + 2, px = lx + 2;
+                auto RH = [&](int dx, int dy, int dz) -> R {
+                    if (dz == 0) return sr[sc][py + dy][px + dx];
+                    if (dz == 1) return (dx == 0 && dy == 0) ? rg[3] : sr[sp][py + dy][px + dx];
+                    if (dz == -1) return (dx == 0 && dy == 0) ? rg[1] : sr[sm][py + dy][px + dx];
+                    return dz == 2 ? rg[4] : rg[0];
+                };
+                R fa[3];
+                // (100): tau -3 ; (110): tau 1/2 ; (200): tau 1/4 (Table III)
+                fa[0] = R(-3) * (RH(1, 0, 0) - RH(-1, 0, 0)) +
+                        R(0.5) * (RH(1, 1, 0) + RH(1, -1, 0) + RH(1, 0, 1) + RH(1, 0, -1) -
+                                  RH(-1, 1, 0) - RH(-1, -1, 0) - RH(-1, 0, 1) - RH(-1, 0, -1)) +
+                        R(0.5) * (RH(2, 0, 0) - RH(-2, 0, 0));
+                fa[1] = R(-3) * (RH(0, 1, 0) - RH(0, -1, 0)) +
+                        R(0.5) * (RH(1, 1, 0) + RH(-1, 1, 0) + RH(0, 1, 1) + RH(0, 1, -1) -
+                                  RH(1, -1, 0) - RH(-1, -1, 0) - RH(0, -1, 1) - RH(0, -1, -1)) +
+                        R(0.5) * (RH(0, 2, 0) - RH(0, -2, 0));
+                fa[2] = R(-3) * (RH(0, 0, 1) - RH(0, 0, -1)) +
+                        R(0.5) * (RH(1, 0, 1) + RH(-1, 0, 1) + RH(0, 1, 1) + RH(0, -1, 1) -
+                                  RH(1, 0, -1) - RH(-1, 0, -1) - RH(0, 1, -1) - RH(0, -1, -1)) +
+                        R(0.5) * (RH(0, 0, 2) - RH(0, 0, -2));
+                const R r = rg[2];
+                const R kr = kap * r;
+                const R inv = R(1) / r;
+                const long long i0 = o + col + (long long)plane * zc;
+                {
+                    const EosVal<R> e = eos_all<R>(dm.cf.eos, r);
+                    pf[i0] = e.p;
+                    pf[i0 + N] = e.P1;
+                    pf[i0 + 2 * N] = inv;
+                }
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const long long ia = i0 + a * N;
+                    const R fv = kr * fa[a];
+                    const R jp = j0[ia] + R(0.5) * fv;
+                    R jt = prev ? prev[ia] : R(0);
+                    if (hist) {
+                        const R y1 = jt;
+                        const R y2 = hist[ia];
+                        hist[ia] = y1;
+                        R y3 = R(0);
+                        if (hist2) {
+                            y3 = hist2[ia];
+                            hist2[ia] = y2;
+                        }
+                        if (order == 2)
+                            jt = y3 + R(3) * (y1 - y2);
+                        else if (order == 1)
+                            jt = R(2) * y1 - y2;
+                    }
+                    f[ia] = fv;
+                    j0p[ia] = jp;
+                    if (jt0) jt0[ia] = jt;
+                    u[ia] = (jp + jt) * inv;
+                    amax = fmax(amax, fabs((double)jp));
+                }
+            }
+            __syncthreads();
+        }
+    }
+    block_max_part(ic.part, amax);
+}
+
 }  // namespace lb2p

@@ -235,6 +235,7 @@ struct lb2p_ctx {
     size_t pmax_cap = 0;
     int* site_range = nullptr;                 // [ndom+1] tile ranges per domain (domain order)
     int* fused_range = nullptr;
+    int* clos_range = nullptr;
     // stop-rule state
     int stride = 0;                            // passes per domain in res
     void* scratch = nullptr;
@@ -372,10 +373,11 @@ void free_graphs(lb2p_ctx* c)
 lb2p_status build_tiles(lb2p_ctx* c)
 {
     std::vector<Tile> site, fused, clos;
-    std::vector<int> srange(c->ndom + 1, 0), frange(c->ndom + 1, 0);
+    std::vector<int> srange(c->ndom + 1, 0), frange(c->ndom + 1, 0), crange(c->ndom + 1, 0);
     for (int d = 0; d < c->ndom; ++d) {
         srange[d] = (int)site.size();
         frange[d] = (int)fused.size();
+        crange[d] = (int)clos.size();
         const Geom& g = c->dom[d].g;
         // A large 3D domain is cut into 8 slabs of rows, each swept through
         // every z: after the XCD deal each XCD owns one slab, so the planes a
@@ -427,6 +429,7 @@ lb2p_status build_tiles(lb2p_ctx* c)
     }
     srange[c->ndom] = (int)site.size();
     frange[c->ndom] = (int)fused.size();
+    crange[c->ndom] = (int)clos.size();
     c->site_host = deal_xcd(site);
     c->fused_host = fused.empty() ? fused : deal_xcd(fused);
     c->clos_host = clos.empty() ? clos : deal_xcd(clos);
@@ -454,7 +457,7 @@ lb2p_status build_tiles(lb2p_ctx* c)
         if (hipMalloc((void**)&c->partial, np * sizeof(double)) != hipSuccess) return LB2P_ENOMEM;
         c->partial_cap = np;
     }
-    const size_t nm = std::max(c->site_host.size(), c->fused_host.size());
+    const size_t nm = std::max({c->site_host.size(), c->fused_host.size(), c->clos_host.size()});
     if (nm > c->pmax_cap) {
         if (c->pmax) (void)hipFree(c->pmax);
         c->pmax = nullptr;
@@ -463,12 +466,15 @@ lb2p_status build_tiles(lb2p_ctx* c)
     }
     if (!c->site_range) {
         if (hipMalloc((void**)&c->site_range, (c->ndom + 1) * sizeof(int)) != hipSuccess ||
-            hipMalloc((void**)&c->fused_range, (c->ndom + 1) * sizeof(int)) != hipSuccess)
+            hipMalloc((void**)&c->fused_range, (c->ndom + 1) * sizeof(int)) != hipSuccess ||
+            hipMalloc((void**)&c->clos_range, (c->ndom + 1) * sizeof(int)) != hipSuccess)
             return LB2P_ENOMEM;
     }
     HIPCHK(hipMemcpyAsync(c->site_range, srange.data(), (c->ndom + 1) * sizeof(int), hipMemcpyHostToDevice,
                           c->stream));
     HIPCHK(hipMemcpyAsync(c->fused_range, frange.data(), (c->ndom + 1) * sizeof(int), hipMemcpyHostToDevice,
+                          c->stream));
+    HIPCHK(hipMemcpyAsync(c->clos_range, crange.data(), (c->ndom + 1) * sizeof(int), hipMemcpyHostToDevice,
                           c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     free_graphs(c);
@@ -528,12 +534,23 @@ struct Impl {
             // the fused (velocity-form) solve starts from u alone and forms
             // j~ after its last pass, so x_0 is not stored for it
             const bool fused_solve = !(p.flags & LB2P_FLAG_UNFUSED_SOLVE);
-            hipLaunchKernelGGL((k_force<Q, R>), sgrid(c), sblock(c), 0, c->stream, c->dtab,
-                               c->site_tiles, ic, (const R*)c->rho, (const R*)c->j0, (R*)c->f,
-                               (R*)c->j0p, (R*)c->u, (const R*)c->jt0, (const R*)c->jt1, prev,
-                               fused_solve ? (R*)nullptr : (R*)c->jt0, (R*)c->pf, hist, hist2, order);
+            R* const jstart = fused_solve ? (R*)nullptr : (R*)c->jt0;
+            if constexpr (Lattice<Q>::D == 3) {
+                constexpr int TX = fused_tx<R>();
+                hipLaunchKernelGGL((k_force_zm<R, TX, kFusedTY>), dim3((unsigned)c->clos_host.size()),
+                                   dim3(TX, kFusedTY, 1), 0, c->stream, c->dtab, c->clos_tiles, ic,
+                                   (const R*)c->rho, (const R*)c->j0, (R*)c->f, (R*)c->j0p, (R*)c->u,
+                                   (const R*)c->jt0, (const R*)c->jt1, prev, jstart, (R*)c->pf, hist, hist2,
+                                   order);
+            } else {
+                hipLaunchKernelGGL((k_force<Q, R>), sgrid(c), sblock(c), 0, c->stream, c->dtab,
+                                   c->site_tiles, ic, (const R*)c->rho, (const R*)c->j0, (R*)c->f,
+                                   (R*)c->j0p, (R*)c->u, (const R*)c->jt0, (const R*)c->jt1, prev, jstart,
+                                   (R*)c->pf, hist, hist2, order);
+            }
             hipLaunchKernelGGL(k_reduce_max, dim3(c->ndom), dim3(256), 0, c->stream, (const double*)c->pmax,
-                               (const int*)c->site_range, c->jscale, 1LL, (const int*)nullptr);
+                               (const int*)(Lattice<Q>::D == 3 ? c->clos_range : c->site_range), c->jscale,
+                               1LL, (const int*)nullptr);
         }
         const bool fused = !(p.flags & LB2P_FLAG_UNFUSED_SOLVE);
         constexpr int kFusedTX = Lattice<Q>::D == 3 ? fused_tx<R>() : kFused2TX;
@@ -778,6 +795,7 @@ void free_ctx(lb2p_ctx* c)
     if (c->pmax) (void)hipFree(c->pmax);
     if (c->site_range) (void)hipFree(c->site_range);
     if (c->fused_range) (void)hipFree(c->fused_range);
+    if (c->clos_range) (void)hipFree(c->clos_range);
     if (c->scratch) (void)hipFree(c->scratch);
     if (c->dtab) (void)hipFree(c->dtab);
     if (c->omega) (void)hipFree(c->omega);
