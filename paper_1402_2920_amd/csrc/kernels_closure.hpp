@@ -240,17 +240,22 @@ k_closure2_zm(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, co
 template <class R>
 struct C1In {
     R lead[5];    // own point, lead plane c+2: ux, uy, uz, p, 1/rho
-    R own[4];     // own point, centre plane: P1, j~ (3)
+    R own[5];     // own point, centre plane: P1, then rho and j0' (form) or j~
     R fr[5];      // frame point, centre plane: ux, uy, uz, p, 1/rho
 };
 
 template <class R, int TX, int TY>
-__global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 2 : 1)))
+__global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 1)))
 k_closure1_zm(const Domain* __restrict__ tab, const Tile* __restrict__ tiles,
-              const SolveInfo* __restrict__ info, const R* __restrict__ pf, const R* __restrict__ u,
-              const R* __restrict__ jtA, const R* __restrict__ jtB, R* __restrict__ X, R* __restrict__ T,
-              R* __restrict__ Y, R* __restrict__ Xi)
+              const SolveInfo* __restrict__ info, const R* __restrict__ pf, const R* __restrict__ rho,
+              const R* __restrict__ j0p, R* u0, const R* u1, R* jtA, R* jtB, R* __restrict__ X,
+              R* __restrict__ T, R* __restrict__ Y, R* __restrict__ Xi, int form)
 {
+    // form = 1 (after a velocity-form solve): the final iterate is u in u0
+    // or u1 (by the pass count); j~ = rho u - j0' is formed here at each site
+    // (item 7) and stored in the j~ buffer the pass count selects, and u is
+    // copied to u0 when it ended in u1.  form = 0: u0 and that j~ buffer
+    // already hold the final values.
     constexpr int UX = TX + 4, UY = TY + 4;   // tile + 2-wide frame
     constexpr int NFRAME = UX * UY - TX * TY;
     static_assert(NFRAME <= TX * TY, "frame larger than the block");
@@ -266,12 +271,18 @@ k_closure1_zm(const Domain* __restrict__ tab, const Tile* __restrict__ tiles,
     const unsigned bytes = (unsigned)dm.g.N * (unsigned)sizeof(R);
     const unsigned OUT = bytes;
     const long long o = dm.off;
-    const R* jt = info[tl.dom].final_buf ? jtB : jtA;
+    const bool odd = info[tl.dom].final_buf != 0;   // uniform per block
+    R* const jt = odd ? jtB : jtA;
+    const R* const u = (form && odd) ? u1 : u0;
     const PlaneBuf bU[3] = {plane_buf(u + o, bytes), plane_buf(u + o + N, bytes), plane_buf(u + o + 2 * N, bytes)};
     const PlaneBuf bP = plane_buf(pf + o, bytes);
     const PlaneBuf bP1 = plane_buf(pf + o + N, bytes);
     const PlaneBuf bRi = plane_buf(pf + o + 2 * N, bytes);
     const PlaneBuf bJ[3] = {plane_buf(jt + o, bytes), plane_buf(jt + o + N, bytes), plane_buf(jt + o + 2 * N, bytes)};
+    const PlaneBuf bRho = plane_buf(rho + o, bytes);
+    const PlaneBuf bJ0[3] = {plane_buf(j0p + o, bytes), plane_buf(j0p + o + N, bytes),
+                             plane_buf(j0p + o + 2 * N, bytes)};
+    const PlaneBuf bU0[3] = {plane_buf(u0 + o, bytes), plane_buf(u0 + o + N, bytes), plane_buf(u0 + o + 2 * N, bytes)};
     const PlaneBuf bX = plane_buf(X + o, bytes);
     const PlaneBuf bT[6] = {plane_buf(T + o, bytes), plane_buf(T + o + N, bytes), plane_buf(T + o + 2 * N, bytes),
                             plane_buf(T + o + 3 * N, bytes), plane_buf(T + o + 4 * N, bytes),
@@ -318,8 +329,15 @@ k_closure1_zm(const Domain* __restrict__ tab, const Tile* __restrict__ tiles,
         const unsigned zc = plane * (unsigned)wrap3(z0 - 4 + k, nz);
         const unsigned i = live ? (col + zc) * (unsigned)sizeof(R) : OUT;
         in.own[0] = bload<R>(bP1, i);
+        if (form) {
+            in.own[1] = bload<R>(bRho, i);
 #pragma unroll
-        for (int b = 0; b < 3; ++b) in.own[1 + b] = bload<R>(bJ[b], i);
+            for (int b = 0; b < 3; ++b) in.own[2 + b] = bload<R>(bJ0[b], i);
+        } else {
+#pragma unroll
+            for (int b = 0; b < 3; ++b) in.own[1 + b] = bload<R>(bJ[b], i);
+            in.own[4] = R(0);
+        }
         const unsigned f = live && has_frame ? (fcol + zc) * (unsigned)sizeof(R) : OUT;
 #pragma unroll
         for (int b = 0; b < 3; ++b) in.fr[b] = bload<R>(bU[b], f);
@@ -366,7 +384,7 @@ k_closure1_zm(const Domain* __restrict__ tab, const Tile* __restrict__ tiles,
         if (has_frame) put(fy, fx, in.fr[0], in.fr[1], in.fr[2], in.fr[3], in.fr[4]);
         __syncthreads();
         const bool out = owned && k >= 4 && z0 + k - 4 < nz;
-        R oX = R(0), oT[6] = {}, oY[3] = {}, oXi[10] = {};
+        R oX = R(0), oT[6] = {}, oY[3] = {}, oXi[10] = {}, oJ[3] = {};
         if (k >= 4) {
             const int py = ly + 2, px = lx + 2;
             auto dxl = [&](int f) {
@@ -418,7 +436,13 @@ k_closure1_zm(const Domain* __restrict__ tab, const Tile* __restrict__ tiles,
                 for (int c = 0; c < 3; ++c) acc += us[c] * G[c][b];
                 oY[b] = acc;
             }
-            const R jts[3] = {in.own[1], in.own[2], in.own[3]};
+            R jts[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                // item 7: j~ = j - j0' with j = rho u
+                jts[a] = form ? in.own[1] * us[a] - in.own[2 + a] : in.own[1 + a];
+                oJ[a] = jts[a];
+            }
             R V[3];
 #pragma unroll
             for (int a = 0; a < 3; ++a) V[a] = ep * C[a] + eP1 * us[a] * trG;
@@ -444,6 +468,14 @@ k_closure1_zm(const Domain* __restrict__ tab, const Tile* __restrict__ tiles,
         for (int b = 0; b < 3; ++b) bstore<R>(bY[b], io, oY[b]);
 #pragma unroll
         for (int s = 0; s < 10; ++s) bstore<R>(bXi[s], io, oXi[s]);
+        {
+            const unsigned ij = form ? io : OUT, iu = (form && odd) ? io : OUT;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                bstore<R>(bJ[a], ij, oJ[a]);
+                bstore<R>(bU0[a], iu, rg[2][a]);
+            }
+        }
         __syncthreads();
     }
 }

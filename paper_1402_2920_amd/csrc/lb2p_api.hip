@@ -512,7 +512,10 @@ struct Impl {
     // lb2p_step / lb2p_moments call (read_status).
     // advance: the solve belongs to a time step (lb2p_step), not to a
     // re-evaluation of the same state (lb2p_moments)
-    static lb2p_status solve(lb2p_ctx* c, bool advance = true)
+    // form_final: store j~ = rho u - j0' (and u) after a velocity-form
+    // solve; a 3D time step leaves that to k_closure1_zm, which reads the
+    // same words anyway.
+    static lb2p_status solve(lb2p_ctx* c, bool advance = true, bool form_final = true)
     {
         const lb2p_params& p = c->prm;
         const int max_it = p.fixed_iter > 0 ? p.fixed_iter : p.max_iter;
@@ -621,11 +624,11 @@ struct Impl {
         }
         hipLaunchKernelGGL(k_iter_finish, dim3((c->ndom + 255) / 256), dim3(256), 0, c->stream, ic,
                            launched, c->ndom, c->info, c->nconv);
-        if (fused)
+        if (fused && form_final)
             hipLaunchKernelGGL((k_jt_final<Q, R>), sgrid(c), sblock(c), 0, c->stream, c->dtab,
                                c->site_tiles, (const SolveInfo*)c->info, (const R*)c->rho,
                                (const R*)c->j0p, (R*)c->u, (const R*)c->u1, (R*)c->jt0, (R*)c->jt1);
-        else
+        else if (!fused)
             hipLaunchKernelGGL((k_u_final<Q, R>), sgrid(c), sblock(c), 0, c->stream, c->dtab,
                                c->site_tiles, (const SolveInfo*)c->info, (const R*)c->rho,
                                (const R*)c->j0p, (const R*)c->jt0, (const R*)c->jt1, (R*)c->u);
@@ -643,7 +646,10 @@ struct Impl {
 
     static lb2p_status step(lb2p_ctx* c)
     {
-        lb2p_status st = solve(c);
+        // 3D fused solve: k_closure1_zm forms the final j~ and u
+        const bool closure_forms =
+            Lattice<Q>::D == 3 && !(c->prm.flags & LB2P_FLAG_UNFUSED_SOLVE);
+        lb2p_status st = solve(c, true, !closure_forms);
         if (st != LB2P_OK) return st;
         {
             ProfScope _ps(c, LB2P_K_CLOSURE1);
@@ -651,9 +657,9 @@ struct Impl {
                 constexpr int TX = fused_tx<R>();
                 hipLaunchKernelGGL((k_closure1_zm<R, TX, kFusedTY>), dim3((unsigned)c->clos_host.size()),
                                    dim3(TX, kFusedTY, 1), 0, c->stream, c->dtab, c->clos_tiles,
-                                   (const SolveInfo*)c->info, (const R*)c->pf, (const R*)c->u,
-                                   (const R*)c->jt0, (const R*)c->jt1, (R*)c->X, (R*)c->T, (R*)c->Y,
-                                   (R*)c->Xi);
+                                   (const SolveInfo*)c->info, (const R*)c->pf, (const R*)c->rho,
+                                   (const R*)c->j0p, (R*)c->u, (const R*)c->u1, (R*)c->jt0, (R*)c->jt1,
+                                   (R*)c->X, (R*)c->T, (R*)c->Y, (R*)c->Xi, closure_forms ? 1 : 0);
             } else {
                 hipLaunchKernelGGL((k_closure1<Q, R>), sgrid(c), sblock(c), 0, c->stream, c->dtab,
                                    c->site_tiles, (const SolveInfo*)c->info, (const R*)c->pf,
