@@ -331,26 +331,26 @@ k_iter_fused3(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, It
 
 // One pass of the correction-current iteration for D2Q21 (items 3-6), in the
 // velocity form of the 3D pass: u_{k+1} = (j0' + G)/rho with G = -(1/12)
-// d_b q_ab and q built from u_k.  A block owns a TX x TY tile; its threads
-// are the (TX+4) x (TY+4) points where q is needed, the tile's points first
-// (whole wavefronts) and the 2-wide frame after them.  u of the tile and a
-// 4-wide frame goes to LDS, then q, then the tile's wavefronts take the
-// divergence.  Reads u (stencil), p, P1 (stencil), j0' and rho at the tile
-// points; writes the next u (Chebyshev: also reads u_{k-1}, overwritten in
-// place).
-template <class R, int TX, int TY, bool CHEB>
-__global__ void __launch_bounds__((TX + 4) * (TY + 4))
+// d_b q_ab and q built from u_k.  A block owns a TX-wide column strip of
+// tl.len rows and marches along y in chunks of CH rows.  Rows of u (strip +
+// 4-wide frame) and of q (strip + 2-wide frame) pass through LDS rings
+// indexed by the row number, so each u and q row is loaded or computed once
+// per strip: per chunk the threads load the next CH rows of u, compute the
+// next CH rows of q, then the strip's wavefronts take the divergence for the
+// chunk's CH output rows.  Threads: one per q point of a chunk, (TX+4) x CH,
+// the strip's TX x CH points first (whole wavefronts).
+template <class R, int TX, int CH, bool CHEB>
+__global__ void __launch_bounds__((TX + 4) * CH)
 k_iter_fused2(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, IterCtl ic, int it,
               const R* __restrict__ pf, const R* __restrict__ rho, const R* __restrict__ j0p,
               const R* __restrict__ u_old, R* u_new)
 {
-    constexpr int QX = TX + 4, QY = TY + 4;   // q points
-    constexpr int UX = TX + 8, UY = TY + 8;   // u points
-    constexpr int NFRAME = UX * UY - QX * QY;
-    static_assert(NFRAME <= QX * QY, "frame larger than the block");
-    static_assert((TX * TY) % 64 == 0, "tile points must fill whole wavefronts");
-    __shared__ R su[2][UY][UX];
-    __shared__ R sq[3][QY][QX];   // q_xx, q_yy, q_xy
+    constexpr int QX = TX + 4, UX = TX + 8;
+    constexpr int RU = 2 * CH + 8;   // u ring: rows a chunk's q and output phases read, and the next chunk's
+    constexpr int RQ = CH + 4;       // q ring
+    static_assert((TX * CH) % 64 == 0, "strip points must fill whole wavefronts");
+    __shared__ R su[2][RU][UX];
+    __shared__ R sq[3][RQ][QX];   // q_xx, q_yy, q_xy
 
     const Tile tl = tiles[blockIdx.x];
     if (tl.dom < 0 || iter_skip(ic, tl.dom, it)) return;   // uniform per block
@@ -373,102 +373,156 @@ k_iter_fused2(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, It
     }
 
     const int tid = threadIdx.x + QX * threadIdx.y;
-    int qx, qy;
-    const bool interior = __builtin_amdgcn_readfirstlane(tid >> 6) < (TX * TY) / 64;
+    int qx, r;   // q column (LDS column qx + 2) and row within the chunk
+    const bool interior = __builtin_amdgcn_readfirstlane(tid >> 6) < (TX * CH) / 64;
     if (interior) {
-        qx = 2 + tid % TX; qy = 2 + tid / TX;
+        qx = 2 + tid % TX; r = tid / TX;
     } else {
-        const int e = tid - TX * TY;
-        if (e < 2 * QX) {
-            qy = e / QX; qx = e % QX;
-        } else if (e < 4 * QX) {
-            qy = QY - 4 + e / QX; qx = e % QX;
-        } else {
-            const int t = e - 4 * QX;
-            const int c = t % 4;
-            qy = 2 + t / 4;
-            qx = c < 2 ? c : QX - 4 + c;
-        }
+        const int e = tid - TX * CH;   // 0 .. 4 CH - 1
+        const int c = e % 4;
+        r = e / 4;
+        qx = c < 2 ? c : TX + c;
     }
-    const int x0 = tl.x0, y0 = tl.y0;
-    const unsigned col = (unsigned)wrapmod(x0 + qx - 2, nx) + (unsigned)nx * (unsigned)wrapmod(y0 + qy - 2, ny);
-    const bool owned = interior && (x0 + qx - 2 < nx) && (y0 + qy - 2 < ny);
-    // this thread's u-frame point (outer 2-wide ring of the UX x UY region)
-    int fx = 0, fy = 0;
-    const bool has_frame = tid < NFRAME;
-    if (has_frame) {
-        if (tid < 2 * UX) {
-            fy = tid / UX; fx = tid % UX;
-        } else if (tid < 4 * UX) {
-            const int t = tid - 2 * UX;
-            fy = UY - 2 + t / UX; fx = t % UX;
-        } else {
-            const int t = tid - 4 * UX;
-            const int c = t % 4;
-            fy = 2 + t / 4;
-            fx = c < 2 ? c : UX - 4 + c;
-        }
-    }
-    const unsigned fcol = has_frame
-        ? (unsigned)wrapmod(x0 + fx - 4, nx) + (unsigned)nx * (unsigned)wrapmod(y0 + fy - 4, ny) : 0u;
+    // the extra u columns (LDS 0, 1, TX+6, TX+7) of a chunk row, loaded by
+    // the frame threads
+    const bool has_extra = !interior;
+    const int ux_extra = has_extra ? ((tid - TX * CH) % 4 < 2 ? (tid - TX * CH) % 4 : TX + 4 + (tid - TX * CH) % 4) : 0;
+    const int x0 = tl.x0, y0 = tl.y0, H = tl.len;
+    const unsigned gx = (unsigned)wrapmod(x0 + qx - 2, nx);
+    const unsigned gxe = (unsigned)wrapmod(x0 + ux_extra - 4, nx);
+    const bool col_owned = interior && (x0 + qx - 2 < nx);
+    auto row_off = [&](int y) { return (unsigned)nx * (unsigned)wrapmod(y, ny); };
+    auto slotU = [&](int y) { return (y - y0 + 4 + RU) % RU; };   // y >= y0 - 4
+    auto slotQ = [&](int y) { return (y - y0 + 2 + RQ) % RQ; };   // y >= y0 - 2
 
-    // every lane issues every load; lanes with nothing to read use OUT
-    const unsigned ic_ = col * (unsigned)sizeof(R);
-    const unsigned io = owned ? ic_ : OUT;
-    const unsigned ifr = has_frame ? fcol * (unsigned)sizeof(R) : OUT;
-    R uq[2], fu[2], jj[2], vv[2] = {R(0), R(0)};
+    // u row y of the strip (+ frame) into the ring
+    auto load_u_row = [&](int y, bool live) {
+        const unsigned ro = row_off(y);
+        const unsigned iu = live ? (gx + ro) * (unsigned)sizeof(R) : OUT;
+        const unsigned ie = live && has_extra ? (gxe + ro) * (unsigned)sizeof(R) : OUT;
+        R v[2], w[2];
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
-        uq[a] = bload<R>(bU[a], ic_);
-        fu[a] = bload<R>(bU[a], ifr);
-        jj[a] = bload<R>(bJ[a], io);
-        if (CHEB) vv[a] = bload<R>(bV[a], it > 0 ? io : OUT);
-    }
-    const R pq = bload<R>(bP, ic_), P1q = bload<R>(bP1, ic_);
-    const R rr = bload<R>(bRho, io);
+        for (int a = 0; a < 2; ++a) {
+            v[a] = bload<R>(bU[a], iu);
+            w[a] = bload<R>(bU[a], ie);
+        }
+        if (live) {
+            const int sl = slotU(y);
 #pragma unroll
-    for (int a = 0; a < 2; ++a) su[a][qy + 2][qx + 2] = uq[a];
-    if (has_frame) {
+            for (int a = 0; a < 2; ++a) su[a][sl][qx + 2] = v[a];
+            if (has_extra) {
 #pragma unroll
-        for (int a = 0; a < 2; ++a) su[a][fy][fx] = fu[a];
-    }
-    __syncthreads();
-    {
+                for (int a = 0; a < 2; ++a) su[a][sl][ux_extra] = w[a];
+            }
+        }
+    };
+    // q row y (needs u rows y-2 .. y+2 in the ring)
+    auto q_row = [&](int y, R p, R P1) {
+        const int s0 = slotU(y), sm1 = slotU(y - 1), sm2 = slotU(y - 2), sp1 = slotU(y + 1), sp2 = slotU(y + 2);
         R G[2][2];   // G[a][b] = d_a u_b
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-            G[0][b] = d1<R>(su[b][qy + 2][qx], su[b][qy + 2][qx + 1], su[b][qy + 2][qx + 3], su[b][qy + 2][qx + 4]);
-            G[1][b] = d1<R>(su[b][qy][qx + 2], su[b][qy + 1][qx + 2], su[b][qy + 3][qx + 2], su[b][qy + 4][qx + 2]);
+            G[0][b] = d1<R>(su[b][s0][qx], su[b][s0][qx + 1], su[b][s0][qx + 3], su[b][s0][qx + 4]);
+            G[1][b] = d1<R>(su[b][sm2][qx + 2], su[b][sm1][qx + 2], su[b][sp1][qx + 2], su[b][sp2][qx + 2]);
         }
-        const R X = P1q * (G[0][0] + G[1][1]);
-        const R p2 = R(2) * pq;
-        sq[0][qy][qx] = X + p2 * G[0][0];
-        sq[1][qy][qx] = X + p2 * G[1][1];
-        sq[2][qy][qx] = pq * (G[0][1] + G[1][0]);
+        const R X = P1 * (G[0][0] + G[1][1]);
+        const R p2 = R(2) * p;
+        const int sl = slotQ(y);
+        sq[0][sl][qx] = X + p2 * G[0][0];
+        sq[1][sl][qx] = X + p2 * G[1][1];
+        sq[2][sl][qx] = p * (G[0][1] + G[1][0]);
+    };
+
+    // prologue: u rows y0-4 .. y0+3, then q rows y0-2 .. y0+1
+    if (r < 8) load_u_row(y0 - 4 + r, true);
+    R pp = R(0), pP1 = R(0);
+    {
+        const unsigned ip = r < 4 ? (gx + row_off(y0 - 2 + r)) * (unsigned)sizeof(R) : OUT;
+        pp = bload<R>(bP, ip);
+        pP1 = bload<R>(bP1, ip);
     }
     __syncthreads();
+    if (r < 4) q_row(y0 - 2 + r, pp, pP1);
+
     R dmax = R(0), dsum = R(0);   // dsum only carries a NaN (fmax drops it)
-    R un[2] = {R(0), R(0)};
-    if (interior && owned) {
-        const int px = qx, py = qy;
-        const R sd[2] = {
-            d1<R>(sq[0][py][px - 2], sq[0][py][px - 1], sq[0][py][px + 1], sq[0][py][px + 2]) +
-                d1<R>(sq[2][py - 2][px], sq[2][py - 1][px], sq[2][py + 1][px], sq[2][py + 2][px]),
-            d1<R>(sq[2][py][px - 2], sq[2][py][px - 1], sq[2][py][px + 1], sq[2][py][px + 2]) +
-                d1<R>(sq[1][py - 2][px], sq[1][py - 1][px], sq[1][py + 1][px], sq[1][py + 2][px])};
-        const R ri = R(1) / rr;
+    const R c12 = R(1.0 / 12.0);
+    // Inputs of one chunk, loaded a chunk ahead (they arrive while the
+    // previous chunk computes q and its outputs).
+    struct ChunkIn {
+        R u[2], ue[2];   // u row Y+4+r at the q column and the extra column
+        R p, P1;         // row Y+2+r
+        R j[2], v[2], rho;   // output row Y+r
+    };
+    auto load_chunk = [&](int Y, ChunkIn& c) {
+        const unsigned ro = row_off(Y + 4 + r);
+        const unsigned iu = (gx + ro) * (unsigned)sizeof(R);
+        const unsigned ie = has_extra ? (gxe + ro) * (unsigned)sizeof(R) : OUT;
+        const unsigned ip = (gx + row_off(Y + 2 + r)) * (unsigned)sizeof(R);
+        const bool out = col_owned && Y + r < y0 + H;
+        const unsigned io = out ? (gx + row_off(Y + r)) * (unsigned)sizeof(R) : OUT;
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
-            const R gv = -sd[a] * R(1.0 / 12.0);               // G(x_k)_a
-            const R d = fabs(gv + jj[a] - rr * uq[a]);          // |G(x_k) - x_k|, x_k = rho u_k - j0'
-            dmax = fmax(dmax, d);
-            dsum += d;
-            const R gu = (jj[a] + gv) * ri;
-            un[a] = CHEB ? next_iterate<R>(gu, uq[a], vv[a], omega, gam, it == 0) : gu;
+            c.u[a] = bload<R>(bU[a], iu);
+            c.ue[a] = bload<R>(bU[a], ie);
+            c.j[a] = bload<R>(bJ[a], io);
+            c.v[a] = CHEB ? bload<R>(bV[a], it > 0 ? io : OUT) : R(0);
         }
-    }
+        c.p = bload<R>(bP, ip);
+        c.P1 = bload<R>(bP1, ip);
+        c.rho = bload<R>(bRho, io);
+    };
+    ChunkIn nx_in;
+    load_chunk(y0, nx_in);
+    for (int Y = y0; Y < y0 + H; Y += CH) {
+        const ChunkIn cur = nx_in;
+        // L: the chunk's u rows into the ring
+        {
+            const int sl = slotU(Y + 4 + r);
 #pragma unroll
-    for (int a = 0; a < 2; ++a) bstore<R>(bV[a], io, un[a]);
+            for (int a = 0; a < 2; ++a) su[a][sl][qx + 2] = cur.u[a];
+            if (has_extra) {
+#pragma unroll
+                for (int a = 0; a < 2; ++a) su[a][sl][ux_extra] = cur.ue[a];
+            }
+        }
+        load_chunk(Y + CH, nx_in);   // rows wrap, so the loads past the strip stay in range
+        const int yo = Y + r;
+        const bool out = col_owned && yo < y0 + H;
+        const unsigned io = out ? (gx + row_off(yo)) * (unsigned)sizeof(R) : OUT;
+        __syncthreads();
+        // Q: q rows Y+2 .. Y+CH+1
+        q_row(Y + 2 + r, cur.p, cur.P1);
+        __syncthreads();
+        // O: output rows Y .. Y+CH-1 on the strip's wavefronts
+        R un[2] = {R(0), R(0)};
+        if (interior) {
+            const int s0 = slotQ(yo), sm1 = slotQ(yo - 1), sm2 = slotQ(yo - 2), sp1 = slotQ(yo + 1),
+                      sp2 = slotQ(yo + 2);
+            const int px = qx;
+            const R sd[2] = {
+                d1<R>(sq[0][s0][px - 2], sq[0][s0][px - 1], sq[0][s0][px + 1], sq[0][s0][px + 2]) +
+                    d1<R>(sq[2][sm2][px], sq[2][sm1][px], sq[2][sp1][px], sq[2][sp2][px]),
+                d1<R>(sq[2][s0][px - 2], sq[2][s0][px - 1], sq[2][s0][px + 1], sq[2][s0][px + 2]) +
+                    d1<R>(sq[1][sm2][px], sq[1][sm1][px], sq[1][sp1][px], sq[1][sp2][px])};
+            const int su0 = slotU(yo);
+            if (out) {
+                const R rr = cur.rho;
+                const R ri = R(1) / rr;
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    const R uk = su[a][su0][qx + 2];
+                    const R gv = -sd[a] * c12;                     // G(x_k)_a
+                    const R d = fabs(gv + cur.j[a] - rr * uk);     // |G(x_k) - x_k|, x_k = rho u_k - j0'
+                    dmax = fmax(dmax, d);
+                    dsum += d;
+                    const R gu = (cur.j[a] + gv) * ri;
+                    un[a] = CHEB ? next_iterate<R>(gu, uk, cur.v[a], omega, gam, it == 0) : gu;
+                }
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a) bstore<R>(bV[a], io, un[a]);
+    }
     block_max_part(ic.part, dsum == dsum ? (double)dmax : (double)dsum);
 }
 

@@ -38,7 +38,7 @@ template <class R>
 constexpr int fused_tx() { return sizeof(R) == 4 ? 64 : 32; }
 constexpr int kFusedTY = 8;
 constexpr int kClosTZ = 32;     // z chunk of the 3D closure kernels
-constexpr int kFused2TX = 32, kFused2TY = 24;   // 2D solve pass: 32 x 24 tiles (36 x 28 threads)
+constexpr int kFused2TX = 32, kFused2TY = 16;   // 2D solve pass: 32-wide strips, 16-row chunks (36 x 16 threads)
 int fused_tx_of(size_t rsize) { return rsize == 4 ? fused_tx<float>() : fused_tx<double>(); }
 
 template <int Q>
@@ -398,13 +398,13 @@ lb2p_status build_tiles(lb2p_ctx* c)
                     }
         }
         if (c->D == 2) {
-            // the 2D fused solve pass: kFused2TX x kFused2TY tiles, no z
-            for (int y = 0; y < g.ny; y += kFused2TY)
-                for (int x = 0; x < g.nx; x += kFused2TX) {
-                    Tile t{};
-                    t.dom = d; t.x0 = x; t.y0 = y; t.z0 = 0; t.len = 1;
-                    fused.push_back(t);
-                }
+            // the 2D fused solve pass: kFused2TX-wide strips over the whole
+            // height (each marches along y)
+            for (int x = 0; x < g.nx; x += kFused2TX) {
+                Tile t{};
+                t.dom = d; t.x0 = x; t.y0 = 0; t.z0 = 0; t.len = g.ny;
+                fused.push_back(t);
+            }
         } else {
             // the solve pass marches tz planes; the closure kernels, which
             // have registers for two blocks per CU, march kClosTZ (more
@@ -558,7 +558,9 @@ struct Impl {
         const bool fused = !(p.flags & LB2P_FLAG_UNFUSED_SOLVE);
         constexpr int kFusedTX = Lattice<Q>::D == 3 ? fused_tx<R>() : kFused2TX;
         constexpr int kTY = Lattice<Q>::D == 3 ? kFusedTY : kFused2TY;
-        const dim3 fblock(kFusedTX + 4, kTY + 4, 1);
+        // 3D: one thread per q point of a (TX+4) x (TY+4) plane tile; 2D: one
+        // per q point of a (TX+4)-wide strip row, kFused2TY rows per chunk
+        const dim3 fblock(kFusedTX + 4, Lattice<Q>::D == 3 ? kTY + 4 : kTY, 1);
         const dim3 fgrid((unsigned)c->fused_host.size());
         const int every = p.check_every > 0 ? p.check_every : 1;
         int next_check = std::max(1, c->last_iters + 1);
