@@ -1,5 +1,6 @@
 // kernels_fused.hpp -- one kernel per pass of the correction-current
-// iteration (Supplemental items 3-6) for D3Q59, carried in velocity form.
+// iteration (Supplemental items 3-6), carried in velocity form: the z-march
+// k_iter_fused3 for D3Q59 and the y-march k_iter_fused2 for D2Q21.
 //
 // The pass maps u_k = (j0' + x_k)/rho to u_{k+1} = (j0' + G(x_k))/rho, where
 // G(x) = -(1/12) d_b q_ab depends on x only through u (item 4 builds q from
@@ -13,9 +14,9 @@
 // the next u (the Chebyshev form also reads u_{k-1}, which it overwrites in
 // place).
 //
-// A block owns a TX x TY tile of an xy plane and marches through TZ planes of
-// z.  Its threads are the (TX+4) x (TY+4) points where q is needed (the tile
-// and a 2-wide frame for the outer first derivative).  Each thread keeps, in
+// In 3D a block owns a TX x TY tile of an xy plane and marches through TZ
+// planes of z.  Its threads are the (TX+4) x (TY+4) points where q is needed
+// (the tile and a 2-wide frame for the outer first derivative).  Each thread keeps, in
 // registers, the last five planes of u at its point (z-derivatives of u, and
 // u_k at the output plane) and of q_az (z-derivative in d_b q_ab); LDS holds
 // one u plane (tile + 4-wide frame) and one q plane (tile + 2-wide frame)
