@@ -110,7 +110,7 @@ def run_gpu(workload, storage, steps, warmup, shape=None, profile=True, tol=None
         prof = ctx.profile_read() if profile else None
         stats = ctx.stats()
         out.update(seconds=t1 - t0, prof=prof, stats=stats, N=P.N, Q=P.lattice, D=d, shape=shape,
-                   params=P, pull=P.gamma != 0.0)
+                   params=P, pull=P.gamma != 0.0, workload=workload, storage=storage)
     return out
 
 
@@ -152,7 +152,7 @@ def run_batch(workload, steps, warmup, fixed_iter, graph=True, limit=None, autot
         prof = ctx.profile_read()
         ctx.profile_enable(False)
         out.update(seconds=t1 - t0, prof=prof, stats=st, N=ctx.N, Q=21, D=2, ndom=len(doms),
-                   pull=any(p.gamma != 0.0 for p in plist),
+                   pull=any(p.gamma != 0.0 for p in plist), workload=workload, storage="f32",
                    mass_drift=float(np.max(np.abs(tot[:, 0] - tot0[:, 0]) / tot0[:, 0])))
     return out
 
@@ -184,7 +184,7 @@ def roofline(res, storage, warm=2, cheb=False):
 def measured_traffic(kernel, res):
     """HBM bytes per launch from committed rocprofv3 FETCH_SIZE/WRITE_SIZE
     counters (scaled by a plain copy kernel's reading), if they were taken on
-    the current kernel source; else None."""
+    the current kernel source and on this workload and storage; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -193,6 +193,8 @@ def measured_traffic(kernel, res):
             t = json.load(fh)
         from paper_1402_2920_amd import build as B
         if t.get("src_sha") != B.source_sha():
+            return None
+        if t.get("workload") != f"{res.get('workload')} {res.get('storage')}":
             return None
         ent = t["kernels"].get(kernel)
         return None if ent is None else ent["bytes_per_launch"]
