@@ -112,9 +112,10 @@ typedef struct {
                                fixed point and the stop rule do not depend
                                on it                                           */
     int check_every;        /* tolerance mode: the host reads the number of
-                               converged domains first one pass before the
-                               previous solve's pass count, then every
-                               check_every passes (0 = every pass)            */
+                               converged domains first one pass after the
+                               previous solve's pass count (passes launched
+                               after a domain converged exit at once), then
+                               every check_every passes (0 = every pass)      */
     double store_rho_ref;   /* reference density of BF16/F16 deviation storage
                                (<= 0: mean of the density given to lb2p_init) */
     int flags;              /* LB2P_FLAG_* (0 = defaults)                      */
@@ -141,8 +142,10 @@ typedef struct {
 typedef enum { LB2P_SOLVER_FIXED_POINT = 0, LB2P_SOLVER_CHEBYSHEV = 1 } lb2p_solver;
 
 /* lb2p_params.flags: LB2P_FLAG_UNFUSED_SOLVE runs each pass of the j~
- * iteration as two separate sweeps (items 4 and 5) instead of the fused
- * D3Q59 kernel; the result is the same map. */
+ * iteration as two separate sweeps (item 4, then item 5 and the update of
+ * j~) instead of the fused kernel, which carries the iterate as u =
+ * (j0' + j~)/rho and forms j~ after the last pass (D2Q21 and D3Q59); both
+ * compute the same map and stop on the same rule. */
 #define LB2P_FLAG_UNFUSED_SOLVE 1
 
 /* Diagnostics of the state (FP64 sums over all sites). */
@@ -202,8 +205,10 @@ lb2p_status lb2p_init(lb2p_ctx *ctx, const void *rho, const void *u, int dtype, 
 
 /* Advance nsteps >= 0 time steps (Supplemental items 1-12 each).
  * Asynchronous on the context's stream when fixed_iter > 0; otherwise the
- * host reads the convergence count back during each solve (check_every).
- * Returns ENOCONV if any step's solve hit max_iter.
+ * host reads the convergence count back during each solve (check_every),
+ * and the max_iter count and the non-finite flag once per call.
+ * Returns ENOCONV if any step's solve hit max_iter, ENONFINITE once a NaN or
+ * Inf density was seen (sticky until lb2p_init).
  * Errors: ESTATE (no init), ENOCONV, EHIP. */
 lb2p_status lb2p_step(lb2p_ctx *ctx, int nsteps);
 
