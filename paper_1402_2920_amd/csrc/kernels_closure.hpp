@@ -547,16 +547,40 @@ k_force_zm(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, IterC
                 ? (fcol + plane * (unsigned)wrap3(z0 - 3 + k, nz)) * (unsigned)sizeof(R) : OUT;
         };
         R rg[5] = {R(0), R(0), R(0), R(0), R(0)};   // the column's rho at c-2 .. c+2
+        // own-point inputs of step k (j0 and the previous j~ at plane c),
+        // loaded a step ahead like rho
+        const PlaneBuf bJ0[3] = {plane_buf(j0 + o, bytes), plane_buf(j0 + o + N, bytes),
+                                 plane_buf(j0 + o + 2 * N, bytes)};
+        const R* const pv = prev ? prev : j0;   // any valid plane when there is no previous j~
+        const PlaneBuf bPv[3] = {plane_buf(pv + o, bytes), plane_buf(pv + o + N, bytes),
+                                 plane_buf(pv + o + 2 * N, bytes)};
+        auto own_off = [&](int k) {
+            return owned && k >= 4 && k < nsteps && z0 + k - 4 < nz
+                ? (col + plane * (unsigned)(z0 + k - 4)) * (unsigned)sizeof(R) : OUT;
+        };
+        R nj[3], np_[3];
+        auto load_own = [&](int k) {
+            const unsigned i = own_off(k);
+            const unsigned ip = prev ? i : OUT;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                nj[a] = bload<R>(bJ0[a], i);
+                np_[a] = bload<R>(bPv[a], ip);
+            }
+        };
         R nlead = bload<R>(bR, lead_off(0));
         R nfr = bload<R>(bR, frame_off(0));
+        load_own(0);
         const R kap = R(dm.cf.kappa);
         for (int k = 0; k < nsteps; ++k) {
 #pragma unroll
             for (int s = 0; s < 4; ++s) rg[s] = rg[s + 1];
             rg[4] = nlead;
             const R fr = nfr;
+            const R cj[3] = {nj[0], nj[1], nj[2]}, cp[3] = {np_[0], np_[1], np_[2]};
             nlead = bload<R>(bR, lead_off(k + 1));
             nfr = bload<R>(bR, frame_off(k + 1));
+            load_own(k + 1);
             // plane c+1 = z0-3+k into its LDS slot
             const int slot = (k + 3) % 3;   // (z0 - 3 + k) mod 3 relative to z0: slots follow k
             sr[slot][ly + 2][lx + 2] = rg[3];
@@ -600,8 +624,8 @@ k_force_zm(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, IterC
                 for (int a = 0; a < 3; ++a) {
                     const long long ia = i0 + a * N;
                     const R fv = kr * fa[a];
-                    const R jp = j0[ia] + R(0.5) * fv;
-                    R jt = prev ? prev[ia] : R(0);
+                    const R jp = cj[a] + R(0.5) * fv;
+                    R jt = prev ? cp[a] : R(0);
                     if (hist) {
                         const R y1 = jt;
                         const R y2 = hist[ia];
