@@ -371,8 +371,8 @@ k_closure1_zm(const Domain* __restrict__ tab, const Tile* __restrict__ tiles,
 
     C1In<R> in;
     load_lead(0, in);
+    load_centre(0, in);
     for (int k = 0; k < nsteps; ++k) {
-        load_centre(k, in);
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -382,6 +382,9 @@ k_closure1_zm(const Domain* __restrict__ tab, const Tile* __restrict__ tiles,
         load_lead(k + 1, in);
         put(ly + 2, lx + 2, rg[2][0], rg[2][1], rg[2][2], rg[2][3], rg[2][4]);
         if (has_frame) put(fy, fx, in.fr[0], in.fr[1], in.fr[2], in.fr[3], in.fr[4]);
+        // the centre-plane inputs of the next step load while this one computes
+        const R own[5] = {in.own[0], in.own[1], in.own[2], in.own[3], in.own[4]};
+        load_centre(k + 1, in);
         __syncthreads();
         const bool out = owned && k >= 4 && z0 + k - 4 < nz;
         R oX = R(0), oT[6] = {}, oY[3] = {}, oXi[10] = {}, oJ[3] = {};
@@ -421,7 +424,7 @@ k_closure1_zm(const Domain* __restrict__ tab, const Tile* __restrict__ tiles,
                     M[1][b][c] = my; M[1][c][b] = my;
                     M[2][b][c] = mz; M[2][c][b] = mz;
                 }
-            const R ep = rg[2][3], inv = rg[2][4], eP1 = in.own[0];
+            const R ep = rg[2][3], inv = rg[2][4], eP1 = own[0];
             const R us[3] = {rg[2][0], rg[2][1], rg[2][2]};
             const R trG = G[0][0] + G[1][1] + G[2][2];
             oX = eP1 * trG;
@@ -440,7 +443,7 @@ k_closure1_zm(const Domain* __restrict__ tab, const Tile* __restrict__ tiles,
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 // item 7: j~ = j - j0' with j = rho u
-                jts[a] = form ? in.own[1] * us[a] - in.own[2 + a] : in.own[1 + a];
+                jts[a] = form ? own[1] * us[a] - own[2 + a] : own[1 + a];
                 oJ[a] = jts[a];
             }
             R V[3];
