@@ -13,6 +13,9 @@ need up to twice the solve passes of the rest of a 2000-step run.
 roofline: the kernel class with the largest share of the timed region,
 its algorithmic bytes per launch (per-site bytes below x sites) over its
 average HIP-event duration on the library's stream, against 8 TB/s.
+step_hbm: the whole step's bandwidth (population floor 2 Q s per site, the
+kernels' algorithmic bytes, the counters' measured bytes) against 8 TB/s and
+against a streaming copy measured in the same run.
 cpu_baseline: the FP64 oracle, unchanged, on a bounded sample of the same
 workload (a 16 x 16 x nz column for 3D grids), on this host's cores.
 """
@@ -181,10 +184,11 @@ def roofline(res, storage, warm=2, cheb=False):
                 avg_launch_us=round(avg_s * 1e6, 2)), per_kernel
 
 
-def measured_traffic(kernel, res):
-    """HBM bytes per launch from committed rocprofv3 FETCH_SIZE/WRITE_SIZE
-    counters (scaled by a plain copy kernel's reading), if they were taken on
-    the current kernel source and on this workload and storage; else None."""
+def traffic_table(res):
+    """Per-kernel-class HBM bytes per launch from committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE counters (scaled by a plain copy kernel's reading),
+    if they were taken on the current kernel source and on this workload and
+    storage; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -196,10 +200,63 @@ def measured_traffic(kernel, res):
             return None
         if t.get("workload") != f"{res.get('workload')} {res.get('storage')}":
             return None
-        ent = t["kernels"].get(kernel)
-        return None if ent is None else ent["bytes_per_launch"]
+        return {k: v["bytes_per_launch"] for k, v in t["kernels"].items()}
     except Exception:
         return None
+
+
+def measured_traffic(kernel, res):
+    t = traffic_table(res)
+    return None if t is None else t.get(kernel)
+
+
+def copy_rate_gbs(nbytes=2 << 30, reps=5):
+    """Streaming-copy rate of this GPU: torch's device copy of nbytes, read
+    plus write bytes over HIP-event time (the practical HBM ceiling that the
+    memory-bound kernels are compared with)."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    rate = 2 * nbytes * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return rate
+
+
+def step_hbm(res, storage, warm, cheb, steps, secs, copy_gbs):
+    """Whole-step bandwidth three ways, each as GB/s and as a fraction of the
+    8 TB/s peak and of the measured copy rate: the population floor 2 Q s per
+    site (every word read and written once), the kernels' algorithmic bytes
+    (the per-site table x launches) and the counters' measured bytes."""
+    prof = res["prof"]
+    Q, D, N = res["Q"], res["D"], res["N"]
+    s = STORE_BYTES[storage]
+    r = 8 if storage == "f64" else 4
+    pull = res.get("pull", False)
+
+    def rate(total_bytes):
+        gbs = total_bytes / secs / 1e9
+        return dict(gbs=round(gbs, 1), frac_peak=round(gbs / HBM_PEAK_GBS, 4),
+                    frac_copy=round(gbs / copy_gbs, 4) if copy_gbs else None,
+                    bytes_per_site_step=round(total_bytes / (N * steps), 1))
+
+    floor = rate(2 * Q * s * N * steps)
+    model = rate(sum(site_bytes(k, Q, D, s, r, warm, cheb, pull) * N * v[1] for k, v in prof.items() if v[1]))
+    tt = traffic_table(res)
+    meas = None
+    if tt is not None and all(k in tt for k, v in prof.items() if v[1]):
+        meas = rate(sum(tt[k] * v[1] for k, v in prof.items() if v[1]))
+    return dict(peak_gbs=HBM_PEAK_GBS, copy_gbs=round(copy_gbs, 1) if copy_gbs else None,
+                population_floor=floor, algorithmic=model, measured=meas,
+                note="time: the whole timed region; bytes: every kernel launch in it except the "
+                     "residual reductions (a few KB each)")
 
 
 def cpu_baseline(workload, nsteps_max=30, budget_s=15.0):
@@ -308,6 +365,8 @@ def main():
         roofline=roof,
         kernels=per_kernel,
     )
+    line["step_hbm"] = step_hbm(res, args.storage, args_warm, args.solver == "chebyshev", K, secs,
+                                copy_rate_gbs())
     ref = None
     if not args.no_cpu:
         cb, ref = cpu_baseline(args.workload)

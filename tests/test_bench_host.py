@@ -1,0 +1,71 @@
+"""Host-side logic of bench.py: the per-site byte model, the whole-step
+bandwidth report and the single-GPU guard (no GPU needed)."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_site_bytes_d3q59_f32():
+    # the per-kernel byte table of the 3D FP32 step (gamma = 0, previous-step
+    # warm start): populations 58 x 4 + FP64 rest plane, fields 4 B
+    sb = lambda k: bench.site_bytes(k, 59, 3, 4, 4, 1)
+    assert sb("moments") == 58 * 4 + 8 + 4 * 4 + 8
+    assert sb("force") == 76
+    assert sb("iter_fused") == 48
+    assert sb("closure1") == 132
+    assert sb("closure2") == 80
+    assert sb("collide") == 58 * 4 + 8 + 8 + (1 + 9 + 6 + 10) * 4
+    # gamma != 0: the collision pulls the populations again
+    assert bench.site_bytes("collide", 59, 3, 4, 4, 1, pull=True) == 2 * 240 + 26 * 4
+    # Chebyshev reads u_{k-1} too
+    assert bench.site_bytes("iter_fused", 59, 3, 4, 4, 1, cheb=True) == 60
+
+
+def test_step_hbm_sums_launches():
+    N, steps, secs = 1000, 2, 1e-3
+    prof = {k: (0.0, 0) for k in ("moments", "force", "iter_q", "iter_jt", "closure1", "closure2",
+                                  "collide", "iter_fused")}
+    prof.update(moments=(0.1, 2), force=(0.1, 2), closure1=(0.1, 2), closure2=(0.1, 2), collide=(0.1, 2),
+                iter_fused=(0.5, 26))
+    res = dict(prof=prof, Q=59, D=3, N=N, workload="none", storage="f32")
+    out = bench.step_hbm(res, "f32", 1, False, steps, secs, copy_gbs=5000.0)
+    assert out["population_floor"]["bytes_per_site_step"] == 2 * 59 * 4
+    per_step = 264 + 76 + 132 + 80 + 352 + 13 * 48
+    assert out["algorithmic"]["bytes_per_site_step"] == per_step
+    gbs = per_step * N * steps / secs / 1e9
+    assert out["algorithmic"]["gbs"] == pytest.approx(gbs, abs=0.1)
+    assert out["algorithmic"]["frac_peak"] == pytest.approx(gbs / 8000.0, abs=1e-4)
+    assert out["algorithmic"]["frac_copy"] == pytest.approx(gbs / 5000.0, abs=1e-4)
+    # no committed counters for this workload: measured stays null
+    assert out["measured"] is None
+
+
+def test_traffic_table_matches_workload_only():
+    res = dict(workload="no_such_workload", storage="f32")
+    assert bench.traffic_table(res) is None
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(path):
+        with open(path) as fh:
+            t = json.load(fh)
+        wl, stg = t["workload"].split()
+        tt = bench.traffic_table(dict(workload=wl, storage=stg))
+        from paper_1402_2920_amd import build as B
+        if t["src_sha"] == B.source_sha():
+            assert tt is not None and tt["iter_fused"] == t["kernels"]["iter_fused"]["bytes_per_launch"]
+        else:
+            assert tt is None
+
+
+def test_more_than_one_gpu_is_refused():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert p.returncode == 2
+    assert "one GPU" in p.stderr
