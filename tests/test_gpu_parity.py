@@ -30,8 +30,14 @@ CASES = [
     ("d2q21_cheb", 21, (40, 24), CHEB),
     ("d3q59_cheb", 59, (20, 12, 10), CHEB),
     ("d3q59_cheb_unfused", 59, (20, 12, 10), dict(CHEB, flags=1)),
+    # gamma != 0: the bulk operator keeps part of n_i - n_eq, so the
+    # collision pulls the populations again (gamma = 0 does not read them)
+    ("d2q21_gamma", 21, (40, 24), {}),
+    ("d2q21_gamma_neg", 21, (40, 24), {}),
+    ("d3q59_gamma", 59, (20, 12, 10), {}),
 ]
 NSTEPS = {"d3q59_tiles": 3, "d3q59_tiles_wide": 3}
+GAMMA = {"d2q21_gamma": 0.4, "d2q21_gamma_neg": -0.4, "d3q59_gamma": 0.4}
 
 
 @pytest.fixture(scope="module")
@@ -43,7 +49,7 @@ def L():
 
 @pytest.mark.parametrize("name,lattice,shape,extra", CASES)
 def test_f64_matches_oracle(orc, L, name, lattice, shape, extra):
-    rho, u, model = small_case(lattice, shape)
+    rho, u, model = small_case(lattice, shape, gamma=GAMMA.get(name, 0.0))
     ns = NSTEPS.get(name, 10)
     ref = oracle_reference(orc, model, rho, u, nsteps_long=ns)
     gpu = gpu_run(L, model, L.STORE_F64, rho, u, nsteps_long=ns, tol=1e-14, **extra)
@@ -65,7 +71,7 @@ F32_TOL = dict(rho_t0=1e-5, u_t0=2e-4, j0_t0=2e-4, force_t0=5e-4, jtilde_t0=1e-3
 
 @pytest.mark.parametrize("name,lattice,shape,extra", CASES)
 def test_f32_matches_oracle(orc, L, name, lattice, shape, extra):
-    rho, u, model = small_case(lattice, shape)
+    rho, u, model = small_case(lattice, shape, gamma=GAMMA.get(name, 0.0))
     ns = NSTEPS.get(name, 10)
     ref = oracle_reference(orc, model, rho, u, nsteps_long=ns)
     gpu = gpu_run(L, model, L.STORE_F32, rho, u, nsteps_long=ns, tol=1e-7, **extra)
@@ -79,7 +85,7 @@ def test_f32_matches_oracle(orc, L, name, lattice, shape, extra):
 def test_invariants_on_gpu(orc, L, name, lattice, shape, extra):
     """Mass and total momentum are conserved (Sec. VI: the lattice force sums
     to zero on a periodic lattice; j~ is a divergence)."""
-    rho, u, model = small_case(lattice, shape)
+    rho, u, model = small_case(lattice, shape, gamma=GAMMA.get(name, 0.0))
     gpu = gpu_run(L, model, L.STORE_F64, rho, u, nsteps_long=10, tol=1e-14, **extra)
     s0, sL = gpu["stats0"], gpu["statsL"]
     assert abs(sL["mass"] - s0["mass"]) <= 1e-13 * s0["mass"]

@@ -14,6 +14,14 @@ order and expects spurious currents to vanish in the continuum limit
   is sigma/R, with sigma = int sqrt(2 kappa W(rho)) drho for the
   square-gradient free energy whose force is kappa rho grad lap rho (Sec. II),
   W the excess grand-potential density.
+* viscosities (Sec. VII): a shear wave decays at nu k^2 with
+  nu = eta/rho = (1/2)(1+gamma)/(1-gamma) p/rho; a sound wave decays at
+  Gamma = nu_L k^2 / 2 with nu_L = (2(1-1/d) eta + eta_V)/rho and
+  eta_V/eta = 1 + 2/d - (rho/p) dp/drho, i.e. nu_L = (eta/rho)(3 - rho p'/p),
+  and oscillates at omega = sqrt(c^2 k^2 - Gamma^2) with c^2 = p' + kappa rho
+  k^2 (the linearised interface force).  Both hold in the ideal-gas part of
+  the EOS and at the liquid density, where rho p'/p is far from 1 (the
+  plain-BGK bulk viscosity would miss nu_L by 40% there).
 
 Measured values, D2Q21 (A = 0.8): bulk densities within 1.8e-4 of Maxwell at
 w = 3 and 8.1e-5 at w = 4.5 (about w^-2); steady max|u| 2.0e-4 at w = 3 and
@@ -21,11 +29,16 @@ w = 3 and 8.1e-5 at w = 4.5 (about w^-2); steady max|u| 2.0e-4 at w = 3 and
 D3Q59 (A = 0.74, near the critical point): 2.6e-5 and 1.4e-5 from Maxwell,
 max|u| 1.9e-5 and 8.9e-6 (about w^-1.9).  kappa beyond about 4x the w = 3
 value makes the 2D step unstable (w = 6 diverges).
+Viscosities at L = 64 (gamma = 0 and -0.4, both lattices): nu within 1.3e-3,
+nu_L within 3.6e-3, both falling about 4x per doubling of L.  gamma > 0 is
+left out: the scheme itself (oracle included) grows grid-scale noise there
+(a sound wave at gamma = 0.4 reaches NaN within 220 steps).
 """
 import math
 
 import numpy as np
 import pytest
+from scipy import optimize
 
 import lb2p_workloads as W
 
@@ -124,3 +137,94 @@ def test_laplace_law_2d(L):
         assert abs(v - 1.0) <= 0.07
     # the jump scales as 1/R
     assert abs(vals[0] - vals[1]) <= 0.02
+
+
+def _wave_grid(ent, L):
+    """A column of L sites along the last axis (the wave vector), narrow
+    across it."""
+    return (16, L) if ent["lattice"] == 21 else (12, 12, L)
+
+
+def _wave_run(Lb, ent, shape, rho, u, nsteps, every):
+    d = len(shape)
+    prm = Lb.Params(nx=shape[0], ny=shape[1], nz=shape[2] if d == 3 else 1, storage=Lb.STORE_F64, tol=1e-12,
+                    max_iter=1000, warm_start=1, **W.model_kwargs(ent))
+    ts, fields = [], []
+    with Lb.Context(prm) as ctx:
+        ctx.init(rho, np.ascontiguousarray(u))
+        t = 0
+        while t <= nsteps:
+            r, uu = ctx.moments()
+            ts.append(t)
+            fields.append((r.copy(), uu.copy()))
+            ctx.step(every)
+            t += every
+    return np.array(ts, float), fields
+
+
+def _eos_point(ent, rho0):
+    from oracle import oracle as O
+    _, p, dp = O.eos(_eos_model(ent), rho0)[0][:3]
+    return p, dp
+
+
+def _shear_nu(Lb, ent, L, rho0, U=1e-5):
+    """Measured and predicted kinematic shear viscosity from the decay of
+    u_x = U sin(k s), s the last axis."""
+    shape = _wave_grid(ent, L)
+    d, N = len(shape), int(np.prod(shape))
+    s = np.arange(N) // (N // L)
+    k = 2 * math.pi / L
+    u = np.zeros((d, N))
+    u[0] = U * np.sin(k * s)
+    p, _ = _eos_point(ent, rho0)
+    nu = 0.5 * (1 + ent["gamma"]) / (1 - ent["gamma"]) * p / rho0
+    T = int(1.0 / (nu * k * k))
+    ts, fl = _wave_run(Lb, ent, shape, np.full(N, rho0), u, T, max(1, T // 40))
+    a = np.array([2.0 / N * (uu[0] * np.sin(k * s)).sum() for _, uu in fl])
+    sel = ts >= 0.1 * T
+    return -np.polyfit(ts[sel], np.log(a[sel]), 1)[0] / k ** 2, nu
+
+
+def _sound(Lb, ent, L, rho0, eps=1e-5, periods=3):
+    """Measured and predicted (nu_L, omega/k) of a standing sound wave
+    rho = rho0 (1 + eps cos(k s)) released from rest."""
+    shape = _wave_grid(ent, L)
+    d, N = len(shape), int(np.prod(shape))
+    s = np.arange(N) // (N // L)
+    k = 2 * math.pi / L
+    p, dp = _eos_point(ent, rho0)
+    eta = 0.5 * (1 + ent["gamma"]) / (1 - ent["gamma"]) * p
+    nuL = eta / rho0 * (3 - rho0 * dp / p)
+    c2 = dp + ent["kappa"] * rho0 * k * k
+    G = 0.5 * nuL * k * k
+    w = math.sqrt(c2 * k * k - G * G)
+    T = int(periods * 2 * math.pi / w)
+    ts, fl = _wave_run(Lb, ent, shape, rho0 * (1 + eps * np.cos(k * s)), np.zeros((d, N)), T,
+                       max(1, int(T / periods / 60)))
+    a = np.array([2.0 / N * ((r - rho0) * np.cos(k * s)).sum() / (rho0 * eps) for r, _ in fl])
+    f = lambda t, A, g, om, ph: A * np.exp(-g * t) * np.cos(om * t + ph)
+    sel = ts >= 5
+    popt, _ = optimize.curve_fit(f, ts[sel], a[sel], p0=[1.0, G, w, 0.0])
+    return (2 * popt[1] / k ** 2, nuL), (popt[2] / k, w / k)
+
+
+@pytest.mark.parametrize("gamma", [0.0, -0.4])
+@pytest.mark.parametrize("name", ["d2q21_64_droplet", "d3q59_128_droplet"])
+def test_viscosities_match_sec7(L, name, gamma):
+    base = W.load_params()[name]["model"]
+    ent = dict(base, gamma=gamma)
+    for rho0, kappa in ((0.25, 0.0), (base["rho_l"], base["kappa"])):
+        err = {}
+        for n in (32, 64):
+            nu_m, nu_t = _shear_nu(L, ent, n, rho0)
+            (nl_m, nl_t), (c_m, c_t) = _sound(L, dict(ent, kappa=kappa), n, rho0)
+            err[n] = dict(nu=nu_m / nu_t - 1, nuL=nl_m / nl_t - 1, omega=c_m / c_t - 1)
+            print(f"{name} gamma {gamma} rho {rho0:.4f} kappa {kappa:.3g} L {n}: nu {nu_m:.5f}/{nu_t:.5f} "
+                  f"nu_L {nl_m:.5f}/{nl_t:.5f} omega/k {c_m:.5f}/{c_t:.5f}", flush=True)
+        assert abs(err[64]["nu"]) <= 2e-3
+        assert abs(err[64]["nuL"]) <= 5e-3
+        assert max(abs(err[32]["omega"]), abs(err[64]["omega"])) <= 1e-3
+        # second order in k: the error falls by about 4 when L doubles
+        assert abs(err[64]["nu"]) * 3 <= abs(err[32]["nu"])
+        assert abs(err[64]["nuL"]) * 3 <= abs(err[32]["nuL"])
