@@ -224,7 +224,7 @@ def test_viscosities_match_sec7(L, name, gamma):
                   f"nu_L {nl_m:.5f}/{nl_t:.5f} omega/k {c_m:.5f}/{c_t:.5f}", flush=True)
         assert abs(err[64]["nu"]) <= 2e-3
         assert abs(err[64]["nuL"]) <= 5e-3
-        assert max(abs(err[32]["omega"]), abs(err[64]["omega"])) <= 1e-3
+        assert abs(err[32]["omega"]) <= 2e-3 and abs(err[64]["omega"]) <= 5e-4
         # second order in k: the error falls by about 4 when L doubles
         assert abs(err[64]["nu"]) * 3 <= abs(err[32]["nu"])
         assert abs(err[64]["nuL"]) * 3 <= abs(err[32]["nuL"])
