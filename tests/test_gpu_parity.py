@@ -35,9 +35,21 @@ CASES = [
     ("d2q21_gamma", 21, (40, 24), {}),
     ("d2q21_gamma_neg", 21, (40, 24), {}),
     ("d3q59_gamma", 59, (20, 12, 10), {}),
+    # a reference density inside (rho1, rho3): c0^2 = c_s^2(rho0) and the
+    # weights W_i of Delta^int and Delta^corr differ from the rho0 = rho1 set
+    # (the paper leaves rho0 free)
+    ("d2q21_rho0", 21, (40, 24), {}),
+    ("d3q59_rho0", 59, (20, 12, 10), {}),
 ]
 NSTEPS = {"d3q59_tiles": 3, "d3q59_tiles_wide": 3}
 GAMMA = {"d2q21_gamma": 0.4, "d2q21_gamma_neg": -0.4, "d3q59_gamma": 0.4}
+RHO0 = {"d2q21_rho0": 1.0, "d3q59_rho0": 1.0}
+
+
+def case(name, lattice, shape):
+    rho, u, model = small_case(lattice, shape, gamma=GAMMA.get(name, 0.0))
+    model["rho0"] = RHO0.get(name, model["rho0"])
+    return rho, u, model
 
 
 @pytest.fixture(scope="module")
@@ -49,7 +61,7 @@ def L():
 
 @pytest.mark.parametrize("name,lattice,shape,extra", CASES)
 def test_f64_matches_oracle(orc, L, name, lattice, shape, extra):
-    rho, u, model = small_case(lattice, shape, gamma=GAMMA.get(name, 0.0))
+    rho, u, model = case(name, lattice, shape)
     ns = NSTEPS.get(name, 10)
     ref = oracle_reference(orc, model, rho, u, nsteps_long=ns)
     gpu = gpu_run(L, model, L.STORE_F64, rho, u, nsteps_long=ns, tol=1e-14, **extra)
@@ -71,7 +83,7 @@ F32_TOL = dict(rho_t0=1e-5, u_t0=2e-4, j0_t0=2e-4, force_t0=5e-4, jtilde_t0=1e-3
 
 @pytest.mark.parametrize("name,lattice,shape,extra", CASES)
 def test_f32_matches_oracle(orc, L, name, lattice, shape, extra):
-    rho, u, model = small_case(lattice, shape, gamma=GAMMA.get(name, 0.0))
+    rho, u, model = case(name, lattice, shape)
     ns = NSTEPS.get(name, 10)
     ref = oracle_reference(orc, model, rho, u, nsteps_long=ns)
     gpu = gpu_run(L, model, L.STORE_F32, rho, u, nsteps_long=ns, tol=1e-7, **extra)
@@ -85,7 +97,7 @@ def test_f32_matches_oracle(orc, L, name, lattice, shape, extra):
 def test_invariants_on_gpu(orc, L, name, lattice, shape, extra):
     """Mass and total momentum are conserved (Sec. VI: the lattice force sums
     to zero on a periodic lattice; j~ is a divergence)."""
-    rho, u, model = small_case(lattice, shape, gamma=GAMMA.get(name, 0.0))
+    rho, u, model = case(name, lattice, shape)
     gpu = gpu_run(L, model, L.STORE_F64, rho, u, nsteps_long=10, tol=1e-14, **extra)
     s0, sL = gpu["stats0"], gpu["statsL"]
     assert abs(sL["mass"] - s0["mass"]) <= 1e-13 * s0["mass"]
