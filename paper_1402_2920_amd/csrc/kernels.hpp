@@ -793,168 +793,6 @@ __global__ void k_check_done(IterCtl ic, int launched, int ndom, int* out)
 }
 
 // ---------------------------------------------------------------------------
-// Items 9-11, first part: per site X = (p - rho dp/drho) d_g u_g,
-// T_ag = p (d_a u_g + d_g u_a), Y_b = rho^-1 d_b p + u_g d_g u_b, and the
-// rank-3 tensor Xi' (all first-order derivatives of per-site products).
-// ---------------------------------------------------------------------------
-template <int Q, class R>
-__global__ void __launch_bounds__(256) k_closure1(const Domain* __restrict__ tab,
-                                                  const Tile* __restrict__ tiles,
-                                                  const SolveInfo* __restrict__ info,
-                                                  const R* __restrict__ pf, const R* __restrict__ u,
-                                                  const R* __restrict__ jtA, const R* __restrict__ jtB,
-                                                  R* __restrict__ X, R* __restrict__ T,
-                                                  R* __restrict__ Y, R* __restrict__ Xi)
-{
-    using L = Lattice<Q>;
-    constexpr int D = L::D;
-    const Where w = locate(tab, tiles);
-    if (!w.ok) return;
-    const Domain& dm = tab[w.dom];
-    const long long o = dm.off, St = dm.g.S;
-    const Nb2 nb = make_nb2(dm.g, w.x, w.y, w.z);
-    const unsigned i0 = nb.i0;
-    const R* jt = (info[w.dom].final_buf ? jtB : jtA) + o;
-    const R* const pp = pf + o;            // p
-    const R* const pri = pf + o + 2 * St;  // 1/rho
-    const R* const uo = u + o;
-
-    R G[3][3] = {};    // d_a u_b
-    R M[3][3][3] = {}; // d_a (p u_b u_g)
-    R Pg[3] = {}, C[3] = {};  // d_a p, d_a (p/rho) with p/rho = c_s^2
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-        R pv[4], cv[4], uv[4][3];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const unsigned t = nb.i0 + nb.o[a][k];
-            pv[k] = ldo(pp, t);
-            cv[k] = pv[k] * ldo(pri, t);
-#pragma unroll
-            for (int b = 0; b < D; ++b) uv[k][b] = ldo(uo + b * St, t);
-        }
-        Pg[a] = d1<R>(pv[0], pv[1], pv[2], pv[3]);
-        C[a] = d1<R>(cv[0], cv[1], cv[2], cv[3]);
-#pragma unroll
-        for (int b = 0; b < D; ++b) {
-            G[a][b] = d1<R>(uv[0][b], uv[1][b], uv[2][b], uv[3][b]);
-#pragma unroll
-            for (int c = b; c < D; ++c) {
-                R m = d1<R>(pv[0] * uv[0][b] * uv[0][c], pv[1] * uv[1][b] * uv[1][c],
-                            pv[2] * uv[2][b] * uv[2][c], pv[3] * uv[3][b] * uv[3][c]);
-                M[a][b][c] = m;
-                M[a][c][b] = m;
-            }
-        }
-    }
-    const R ep = ldo(pp, i0), eP1 = ldo(pf + o + St, i0), inv = ldo(pri, i0);
-    R us[3] = {R(0), R(0), R(0)};
-#pragma unroll
-    for (int a = 0; a < D; ++a) us[a] = ldo(uo + a * St, i0);
-    R trG = R(0);
-#pragma unroll
-    for (int a = 0; a < D; ++a) trG += G[a][a];
-
-    sto(X + o, i0, eP1 * trG);
-#pragma unroll
-    for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int c = a; c < D; ++c) sto(T + o + sym2<D>(a, c) * St, i0, ep * (G[a][c] + G[c][a]));
-#pragma unroll
-    for (int b = 0; b < D; ++b) {
-        R acc = Pg[b] * inv;
-#pragma unroll
-        for (int c = 0; c < D; ++c) acc += us[c] * G[c][b];
-        sto(Y + o + b * St, i0, acc);
-    }
-
-    const R gm = R(dm.cf.gamma);
-    const R KX = (gm * gm + R(4) * gm + R(1)) / (R(3) * (gm + R(1)));
-    const R KJ = (R(1) - gm) * R(dm.cf.c0sq);
-    R jts[3] = {R(0), R(0), R(0)};
-#pragma unroll
-    for (int a = 0; a < D; ++a) jts[a] = ldo(jt + a * St, i0);
-    R V[3];
-#pragma unroll
-    for (int a = 0; a < D; ++a) V[a] = ep * C[a] + eP1 * us[a] * trG;
-#pragma unroll
-    for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int b = a; b < D; ++b)
-#pragma unroll
-            for (int c = b; c < D; ++c) {
-                R br = M[c][a][b] + M[b][a][c] + M[a][b][c];
-                R dj = R(0);
-                if (a == b) { br += V[c]; dj += jts[c]; }
-                if (a == c) { br += V[b]; dj += jts[b]; }
-                if (b == c) { br += V[a]; dj += jts[a]; }
-                sto(Xi + o + sym3<D>(a, b, c) * St, i0, KX * br + KJ * dj);
-            }
-}
-
-// ---------------------------------------------------------------------------
-// Item 11, second part: Sigma_ab from the derivatives of X, T, Y and the
-// site values (with d_a j_b recomputed from j = rho u).
-// ---------------------------------------------------------------------------
-template <int Q, class R>
-__global__ void __launch_bounds__(256) k_closure2(const Domain* __restrict__ tab,
-                                                  const Tile* __restrict__ tiles,
-                                                  const R* __restrict__ rho, const R* __restrict__ u,
-                                                  const R* __restrict__ X, const R* __restrict__ T,
-                                                  const R* __restrict__ Y, R* __restrict__ Sig)
-{
-    using L = Lattice<Q>;
-    constexpr int D = L::D;
-    const Where w = locate(tab, tiles);
-    if (!w.ok) return;
-    const Domain& dm = tab[w.dom];
-    const long long o = dm.off, St = dm.g.S;
-    const Nb2 nb = make_nb2(dm.g, w.x, w.y, w.z);
-    const unsigned i0 = nb.i0;
-    const R* const rh = rho + o;
-    const R* const uo = u + o;
-    R DX[3] = {}, DT[3] = {}, DY[3][3] = {}, G[3][3] = {};
-    R trJ = R(0);
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-        DX[a] = d1_nb<R>(X + o, nb, a);
-#pragma unroll
-        for (int c = 0; c < D; ++c) DT[a] += d1_nb<R>(T + o + sym2<D>(a, c) * St, nb, c);
-#pragma unroll
-        for (int b = 0; b < D; ++b) DY[a][b] = d1_nb<R>(Y + o + b * St, nb, a);
-        R jv[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const unsigned t = i0 + nb.o[a][k];
-            jv[k] = ldo(rh, t) * ldo(uo + a * St, t);
-        }
-        trJ += d1<R>(jv[0], jv[1], jv[2], jv[3]);
-#pragma unroll
-        for (int b = 0; b < D; ++b) G[a][b] = d1_nb<R>(uo + b * St, nb, a);
-    }
-    const R r = ldo(rh, i0);
-    const EosVal<R> e = eos_all<R>(dm.cf.eos, r);
-    R us[3] = {R(0), R(0), R(0)};
-#pragma unroll
-    for (int a = 0; a < D; ++a) us[a] = ldo(uo + a * St, i0);
-    R trG = R(0), trDY = R(0);
-#pragma unroll
-    for (int a = 0; a < D; ++a) { trG += G[a][a]; trDY += DY[a][a]; }
-    const R gm = R(dm.cf.gamma);
-    const R KS1 = R(-0.25) * (gm + R(1)) * (gm + R(1)) / (gm - R(1));
-    const R KS2 = (gm * gm + R(4) * gm + R(1)) / (R(6) * (gm - R(1)));
-#pragma unroll
-    for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int b = a; b < D; ++b) {
-            const R br1 = us[a] * DX[b] + us[b] * DX[a] + us[b] * DT[a] + us[a] * DT[b];
-            R br2 = -e.dp * trJ * (G[a][b] + G[b][a]) - e.p * (DY[a][b] + DY[b][a]);
-            if (a == b) br2 += -e.P1 * trDY + e.P2 * trG * trJ;
-            sto(Sig + o + sym2<D>(a, b) * St, i0, KS1 * br1 + KS2 * br2);
-        }
-}
-
-// ---------------------------------------------------------------------------
 // Item 11 per velocity and item 12: pull n_i(r), collide with
 // Delta^bulk + Delta^int + Delta^corr and store n*_i(r) in the other buffer.
 // Velocities come in antipodal pairs; each pair shares its even part.

@@ -1,7 +1,8 @@
-// kernels_closure.hpp -- the closure kernels (items 9-11) for D3Q59 as
-// z-marches: k_closure1_zm (the level-1 fields X, T, Y and Xi' from first
+// kernels_closure.hpp -- the closure kernels (items 9-11): for D3Q59 as
+// z-marches, k_closure1_zm (the level-1 fields X, T, Y and Xi' from first
 // derivatives of u, p and per-site products) and k_closure2_zm (Sigma from the
-// derivatives of X, T, Y).
+// derivatives of X, T, Y); for D2Q21 on LDS tiles, k_closure1_t2 and
+// k_closure2_t2 (at the end of this file).
 //
 // A block owns a TX x TY tile of an xy plane (one thread per tile point) and
 // marches through TZ planes of z, like the fused solve pass.  Each thread
@@ -235,8 +236,8 @@ k_closure2_zm(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, co
 
 // Items 9-10 and the Xi' part of item 11: per site X = P1 d_g u_g,
 // T_ag = p (d_a u_g + d_g u_a), Y_b = rho^-1 d_b p + u_g d_g u_b and Xi'
-// from d_a (p u_b u_g), d_a (p/rho) and j~ (the same arithmetic as the
-// per-site k_closure1).
+// from d_a (p u_b u_g), d_a (p/rho) and j~ (per site, the same terms in the
+// same order as the 2D k_closure1_t2).
 template <class R>
 struct C1In {
     R lead[5];    // own point, lead plane c+2: ux, uy, uz, p, 1/rho
@@ -654,6 +655,216 @@ k_force_zm(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, IterC
         }
     }
     block_max_part(ic.part, amax);
+}
+
+
+// ---------------------------------------------------------------------------
+// The closure kernels for D2Q21 on TX x TY tiles of a domain.  A block first
+// copies the fields whose first derivatives it takes into LDS, for its tile
+// and a 2-wide frame (one global load per field and point, where a per-site
+// kernel loads every stencil neighbour: 4 per field and axis), then each
+// thread evaluates its site from LDS.  Per site, the terms and their order
+// are those of the per-site forms, so the results round the same way.
+// ---------------------------------------------------------------------------
+
+// Domain index of point k of the (TX+4) x (TY+4) tile-plus-frame region
+// (periodic; a tile may reach past the domain's edge).
+template <int UX>
+__device__ __forceinline__ unsigned frame_site(int k, int x0, int y0, int nx, int ny)
+{
+    const int lx = k % UX, ly = k / UX;
+    return (unsigned)wrapmod(x0 + lx - 2, nx) + (unsigned)nx * (unsigned)wrapmod(y0 + ly - 2, ny);
+}
+
+// Items 9-11, first part (see k_closure1_zm for the fields): X, T, Y and Xi'.
+template <class R, int TX, int TY>
+__global__ void __launch_bounds__(TX * TY)
+k_closure1_t2(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, const SolveInfo* __restrict__ info,
+              const R* __restrict__ pf, const R* __restrict__ u, const R* __restrict__ jtA,
+              const R* __restrict__ jtB, R* __restrict__ X, R* __restrict__ T, R* __restrict__ Y,
+              R* __restrict__ Xi)
+{
+    constexpr int D = 2;
+    constexpr int UX = TX + 4, UY = TY + 4;
+    __shared__ R sl[4][UY][UX];   // p, p/rho, ux, uy
+
+    const Tile tl = tiles[blockIdx.x];
+    if (tl.dom < 0) return;   // uniform per block
+    const Domain& dm = tab[tl.dom];
+    const int nx = dm.g.nx, ny = dm.g.ny;
+    const long long o = dm.off, St = dm.g.S;
+    const R* const pp = pf + o;            // p
+    const R* const pri = pf + o + 2 * St;  // 1/rho
+    const R* const uo = u + o;
+    const int tid = threadIdx.x + TX * threadIdx.y;
+    for (int k = tid; k < UX * UY; k += TX * TY) {
+        const unsigned t = frame_site<UX>(k, tl.x0, tl.y0, nx, ny);
+        const R pv = ldo(pp, t);
+        R* const sp = &sl[0][0][0] + k;
+        sp[0] = pv;
+        sp[UX * UY] = pv * ldo(pri, t);
+        sp[2 * UX * UY] = ldo(uo, t);
+        sp[3 * UX * UY] = ldo(uo + St, t);
+    }
+    __syncthreads();
+    const int x = tl.x0 + (int)threadIdx.x, y = tl.y0 + (int)threadIdx.y;
+    if (x >= nx || y >= ny) return;
+    const unsigned i0 = (unsigned)x + (unsigned)nx * (unsigned)y;
+    const int cx = (int)threadIdx.x + 2, cy = (int)threadIdx.y + 2;
+    // field f at the k-th neighbour (-2, -1, +1, +2) along axis a
+    auto at = [&](int f, int a, int k) -> R {
+        const int d = k < 2 ? k - 2 : k - 1;
+        return a == 0 ? sl[f][cy][cx + d] : sl[f][cy + d][cx];
+    };
+    const R* jt = (info[tl.dom].final_buf ? jtB : jtA) + o;
+
+    R G[3][3] = {};    // d_a u_b
+    R M[3][3][3] = {}; // d_a (p u_b u_g)
+    R Pg[3] = {}, C[3] = {};  // d_a p, d_a (p/rho)
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        R pv[4], cv[4], uv[4][3];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            pv[k] = at(0, a, k);
+            cv[k] = at(1, a, k);
+#pragma unroll
+            for (int b = 0; b < D; ++b) uv[k][b] = at(2 + b, a, k);
+        }
+        Pg[a] = d1<R>(pv[0], pv[1], pv[2], pv[3]);
+        C[a] = d1<R>(cv[0], cv[1], cv[2], cv[3]);
+#pragma unroll
+        for (int b = 0; b < D; ++b) {
+            G[a][b] = d1<R>(uv[0][b], uv[1][b], uv[2][b], uv[3][b]);
+#pragma unroll
+            for (int c = b; c < D; ++c) {
+                R m = d1<R>(pv[0] * uv[0][b] * uv[0][c], pv[1] * uv[1][b] * uv[1][c],
+                            pv[2] * uv[2][b] * uv[2][c], pv[3] * uv[3][b] * uv[3][c]);
+                M[a][b][c] = m;
+                M[a][c][b] = m;
+            }
+        }
+    }
+    const R ep = sl[0][cy][cx], eP1 = ldo(pf + o + St, i0), inv = ldo(pri, i0);
+    R us[3] = {sl[2][cy][cx], sl[3][cy][cx], R(0)};
+    R trG = R(0);
+#pragma unroll
+    for (int a = 0; a < D; ++a) trG += G[a][a];
+
+    sto(X + o, i0, eP1 * trG);
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int c = a; c < D; ++c) sto(T + o + sym2<D>(a, c) * St, i0, ep * (G[a][c] + G[c][a]));
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+        R acc = Pg[b] * inv;
+#pragma unroll
+        for (int c = 0; c < D; ++c) acc += us[c] * G[c][b];
+        sto(Y + o + b * St, i0, acc);
+    }
+
+    const R gm = R(dm.cf.gamma);
+    const R KX = (gm * gm + R(4) * gm + R(1)) / (R(3) * (gm + R(1)));
+    const R KJ = (R(1) - gm) * R(dm.cf.c0sq);
+    R jts[3] = {R(0), R(0), R(0)};
+#pragma unroll
+    for (int a = 0; a < D; ++a) jts[a] = ldo(jt + a * St, i0);
+    R V[3];
+#pragma unroll
+    for (int a = 0; a < D; ++a) V[a] = ep * C[a] + eP1 * us[a] * trG;
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = a; b < D; ++b)
+#pragma unroll
+            for (int c = b; c < D; ++c) {
+                R br = M[c][a][b] + M[b][a][c] + M[a][b][c];
+                R dj = R(0);
+                if (a == b) { br += V[c]; dj += jts[c]; }
+                if (a == c) { br += V[b]; dj += jts[b]; }
+                if (b == c) { br += V[a]; dj += jts[a]; }
+                sto(Xi + o + sym3<D>(a, b, c) * St, i0, KX * br + KJ * dj);
+            }
+}
+
+// Item 11, second part: Sigma from the derivatives of X, T, Y, j = rho u and
+// u (see k_closure2_zm).
+template <class R, int TX, int TY>
+__global__ void __launch_bounds__(TX * TY)
+k_closure2_t2(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, const R* __restrict__ rho,
+              const R* __restrict__ u, const R* __restrict__ X, const R* __restrict__ T,
+              const R* __restrict__ Y, R* __restrict__ Sig)
+{
+    constexpr int D = 2;
+    constexpr int UX = TX + 4, UY = TY + 4;
+    // X, Txx, Tyy, Txy, Yx, Yy, rho ux, rho uy, ux, uy
+    __shared__ R sl[10][UY][UX];
+
+    const Tile tl = tiles[blockIdx.x];
+    if (tl.dom < 0) return;   // uniform per block
+    const Domain& dm = tab[tl.dom];
+    const int nx = dm.g.nx, ny = dm.g.ny;
+    const long long o = dm.off, St = dm.g.S;
+    const R* const rh = rho + o;
+    const R* const uo = u + o;
+    const int tid = threadIdx.x + TX * threadIdx.y;
+    for (int k = tid; k < UX * UY; k += TX * TY) {
+        const unsigned t = frame_site<UX>(k, tl.x0, tl.y0, nx, ny);
+        R* const sp = &sl[0][0][0] + k;
+        constexpr int P = UX * UY;
+        sp[0] = ldo(X + o, t);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) sp[(1 + c) * P] = ldo(T + o + c * St, t);
+        sp[4 * P] = ldo(Y + o, t);
+        sp[5 * P] = ldo(Y + o + St, t);
+        const R r = ldo(rh, t), ux = ldo(uo, t), uy = ldo(uo + St, t);
+        sp[6 * P] = r * ux;
+        sp[7 * P] = r * uy;
+        sp[8 * P] = ux;
+        sp[9 * P] = uy;
+    }
+    __syncthreads();
+    const int x = tl.x0 + (int)threadIdx.x, y = tl.y0 + (int)threadIdx.y;
+    if (x >= nx || y >= ny) return;
+    const unsigned i0 = (unsigned)x + (unsigned)nx * (unsigned)y;
+    const int cx = (int)threadIdx.x + 2, cy = (int)threadIdx.y + 2;
+    // D1 of LDS field f along axis a
+    auto dd = [&](int f, int a) -> R {
+        return a == 0 ? d1<R>(sl[f][cy][cx - 2], sl[f][cy][cx - 1], sl[f][cy][cx + 1], sl[f][cy][cx + 2])
+                      : d1<R>(sl[f][cy - 2][cx], sl[f][cy - 1][cx], sl[f][cy + 1][cx], sl[f][cy + 2][cx]);
+    };
+    R DX[3] = {}, DT[3] = {}, DY[3][3] = {}, G[3][3] = {};
+    R trJ = R(0);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        DX[a] = dd(0, a);
+#pragma unroll
+        for (int c = 0; c < D; ++c) DT[a] += dd(1 + sym2<D>(a, c), c);
+#pragma unroll
+        for (int b = 0; b < D; ++b) DY[a][b] = dd(4 + b, a);
+        trJ += dd(6 + a, a);
+#pragma unroll
+        for (int b = 0; b < D; ++b) G[a][b] = dd(8 + b, a);
+    }
+    const R r = ldo(rh, i0);
+    const EosVal<R> e = eos_all<R>(dm.cf.eos, r);
+    R us[3] = {sl[8][cy][cx], sl[9][cy][cx], R(0)};
+    R trG = R(0), trDY = R(0);
+#pragma unroll
+    for (int a = 0; a < D; ++a) { trG += G[a][a]; trDY += DY[a][a]; }
+    const R gm = R(dm.cf.gamma);
+    const R KS1 = R(-0.25) * (gm + R(1)) * (gm + R(1)) / (gm - R(1));
+    const R KS2 = (gm * gm + R(4) * gm + R(1)) / (R(6) * (gm - R(1)));
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = a; b < D; ++b) {
+            const R br1 = us[a] * DX[b] + us[b] * DX[a] + us[b] * DT[a] + us[a] * DT[b];
+            R br2 = -e.dp * trJ * (G[a][b] + G[b][a]) - e.p * (DY[a][b] + DY[b][a]);
+            if (a == b) br2 += -e.P1 * trDY + e.P2 * trG * trJ;
+            sto(Sig + o + sym2<D>(a, b) * St, i0, KS1 * br1 + KS2 * br2);
+        }
 }
 
 }  // namespace lb2p

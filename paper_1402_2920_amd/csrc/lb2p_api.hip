@@ -39,6 +39,7 @@ constexpr int fused_tx() { return sizeof(R) == 4 ? 64 : 32; }
 constexpr int kFusedTY = 8;
 constexpr int kClosTZ = 32;     // z chunk of the 3D closure kernels
 constexpr int kFused2TX = 32, kFused2TY = 16;   // 2D solve pass: 32-wide strips, 16-row chunks (36 x 16 threads)
+constexpr int kClos2TX = 32, kClos2TY = 8;      // 2D closure kernels: LDS tiles (256 threads)
 int fused_tx_of(size_t rsize) { return rsize == 4 ? fused_tx<float>() : fused_tx<double>(); }
 
 template <int Q>
@@ -224,7 +225,7 @@ struct lb2p_ctx {
     // tiles
     int bx = 64, by = 4, tz = 32;
     std::vector<Tile> site_host, fused_host;   // launch order
-    std::vector<Tile> clos_host;               // 3D closure z-march (shorter z chunks)
+    std::vector<Tile> clos_host;               // closure kernels: 3D z-march chunks, 2D LDS tiles
     Tile* site_tiles = nullptr;
     Tile* fused_tiles = nullptr;
     Tile* clos_tiles = nullptr;
@@ -405,6 +406,13 @@ lb2p_status build_tiles(lb2p_ctx* c)
                 t.dom = d; t.x0 = x; t.y0 = 0; t.z0 = 0; t.len = g.ny;
                 fused.push_back(t);
             }
+            // the 2D closure kernels: fixed kClos2TX x kClos2TY LDS tiles
+            for (int y = 0; y < g.ny; y += kClos2TY)
+                for (int x = 0; x < g.nx; x += kClos2TX) {
+                    Tile t{};
+                    t.dom = d; t.x0 = x; t.y0 = y; t.z0 = 0; t.len = 1;
+                    clos.push_back(t);
+                }
         } else {
             // the solve pass marches tz planes; the closure kernels, which
             // have registers for two blocks per CU, march kClosTZ (more
@@ -663,10 +671,11 @@ struct Impl {
                                    (const R*)c->j0p, (R*)c->u, (const R*)c->u1, (R*)c->jt0, (R*)c->jt1,
                                    (R*)c->X, (R*)c->T, (R*)c->Y, (R*)c->Xi, closure_forms ? 1 : 0);
             } else {
-                hipLaunchKernelGGL((k_closure1<Q, R>), sgrid(c), sblock(c), 0, c->stream, c->dtab,
-                                   c->site_tiles, (const SolveInfo*)c->info, (const R*)c->pf,
-                                   (const R*)c->u, (const R*)c->jt0, (const R*)c->jt1, (R*)c->X,
-                                   (R*)c->T, (R*)c->Y, (R*)c->Xi);
+                hipLaunchKernelGGL((k_closure1_t2<R, kClos2TX, kClos2TY>), dim3((unsigned)c->clos_host.size()),
+                                   dim3(kClos2TX, kClos2TY, 1), 0, c->stream, c->dtab, c->clos_tiles,
+                                   (const SolveInfo*)c->info, (const R*)c->pf, (const R*)c->u,
+                                   (const R*)c->jt0, (const R*)c->jt1, (R*)c->X, (R*)c->T, (R*)c->Y,
+                                   (R*)c->Xi);
             }
         }
         {
@@ -678,9 +687,10 @@ struct Impl {
                                    (const R*)c->rho, (const R*)c->u, (const R*)c->X, (const R*)c->T,
                                    (const R*)c->Y, (R*)c->Sig);
             } else {
-                hipLaunchKernelGGL((k_closure2<Q, R>), sgrid(c), sblock(c), 0, c->stream, c->dtab,
-                                   c->site_tiles, (const R*)c->rho, (const R*)c->u, (const R*)c->X,
-                                   (const R*)c->T, (const R*)c->Y, (R*)c->Sig);
+                hipLaunchKernelGGL((k_closure2_t2<R, kClos2TX, kClos2TY>), dim3((unsigned)c->clos_host.size()),
+                                   dim3(kClos2TX, kClos2TY, 1), 0, c->stream, c->dtab, c->clos_tiles,
+                                   (const R*)c->rho, (const R*)c->u, (const R*)c->X, (const R*)c->T,
+                                   (const R*)c->Y, (R*)c->Sig);
             }
         }
         {
