@@ -58,11 +58,10 @@ def site_bytes(kernel, Q, D, s, r, warm, cheb=False, pull=False):
                  + 3 * D * r + 3 * r,
         "iter_q": (2 + D) * r + nsig * r,
         "iter_jt": (nsig + 1 + 2 * D) * r + 2 * D * r + (D * r if cheb else 0),
-        # 3D: also forms j~ = rho u - j0' after the velocity-form solve (reads
+        # also forms j~ = rho u - j0' after the velocity-form solve (reads
         # rho and j0' instead of j~, writes j~; the copy of u when the solve
         # ended in the second buffer is not counted)
-        "closure1": ((4 + 2 * D) * r + (1 + nsig + D + nxi + D) * r if D == 3
-                     else (3 + 2 * D) * r + (1 + nsig + D + nxi) * r),
+        "closure1": (4 + 2 * D) * r + (1 + nsig + D + nxi + D) * r,
         "closure2": (2 + nsig + 2 * D) * r + nsig * r,
         "collide": (2 * pops if pull else pops + 8) + (1 + 3 * D + nsig + nxi) * r,
         # fused pass (velocity form): read u, p, P1 and (own site) j0', rho;

@@ -677,12 +677,17 @@ __device__ __forceinline__ unsigned frame_site(int k, int x0, int y0, int nx, in
 }
 
 // Items 9-11, first part (see k_closure1_zm for the fields): X, T, Y and Xi'.
+// With `form` set (after the velocity-form solve) the kernel also forms
+// j~ = rho u - j0' from the final iterate (u1 when the pass count left it
+// there, else u0), stores it in the j~ buffer the pass count selects and
+// copies a final u1 to u0, as k_jt_final does; otherwise it reads u0 and
+// that j~ buffer.
 template <class R, int TX, int TY>
 __global__ void __launch_bounds__(TX * TY)
 k_closure1_t2(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, const SolveInfo* __restrict__ info,
-              const R* __restrict__ pf, const R* __restrict__ u, const R* __restrict__ jtA,
-              const R* __restrict__ jtB, R* __restrict__ X, R* __restrict__ T, R* __restrict__ Y,
-              R* __restrict__ Xi)
+              const R* __restrict__ pf, const R* __restrict__ rho, const R* __restrict__ j0p, R* u0,
+              const R* __restrict__ u1, R* __restrict__ jtA, R* __restrict__ jtB, R* __restrict__ X,
+              R* __restrict__ T, R* __restrict__ Y, R* __restrict__ Xi, int form)
 {
     constexpr int D = 2;
     constexpr int UX = TX + 4, UY = TY + 4;
@@ -695,7 +700,9 @@ k_closure1_t2(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, co
     const long long o = dm.off, St = dm.g.S;
     const R* const pp = pf + o;            // p
     const R* const pri = pf + o + 2 * St;  // 1/rho
-    const R* const uo = u + o;
+    const bool odd = info[tl.dom].final_buf != 0;   // uniform per block
+    // the final iterate; with odd && form, u0 is only written (own points)
+    const R* const uo = (form && odd ? u1 : u0) + o;
     const int tid = threadIdx.x + TX * threadIdx.y;
     for (int k = tid; k < UX * UY; k += TX * TY) {
         const unsigned t = frame_site<UX>(k, tl.x0, tl.y0, nx, ny);
@@ -716,7 +723,7 @@ k_closure1_t2(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, co
         const int d = k < 2 ? k - 2 : k - 1;
         return a == 0 ? sl[f][cy][cx + d] : sl[f][cy + d][cx];
     };
-    const R* jt = (info[tl.dom].final_buf ? jtB : jtA) + o;
+    R* const jt = (odd ? jtB : jtA) + o;
 
     R G[3][3] = {};    // d_a u_b
     R M[3][3][3] = {}; // d_a (p u_b u_g)
@@ -768,8 +775,18 @@ k_closure1_t2(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, co
     const R KX = (gm * gm + R(4) * gm + R(1)) / (R(3) * (gm + R(1)));
     const R KJ = (R(1) - gm) * R(dm.cf.c0sq);
     R jts[3] = {R(0), R(0), R(0)};
+    if (form) {
+        const R r = ldo(rho + o, i0);
 #pragma unroll
-    for (int a = 0; a < D; ++a) jts[a] = ldo(jt + a * St, i0);
+        for (int a = 0; a < D; ++a) {
+            jts[a] = r * us[a] - ldo(j0p + o + a * St, i0);
+            sto(jt + a * St, i0, jts[a]);
+            if (odd) sto(u0 + o + a * St, i0, us[a]);
+        }
+    } else {
+#pragma unroll
+        for (int a = 0; a < D; ++a) jts[a] = ldo(jt + a * St, i0);
+    }
     R V[3];
 #pragma unroll
     for (int a = 0; a < D; ++a) V[a] = ep * C[a] + eP1 * us[a] * trG;

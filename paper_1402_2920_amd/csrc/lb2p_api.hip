@@ -521,8 +521,8 @@ struct Impl {
     // advance: the solve belongs to a time step (lb2p_step), not to a
     // re-evaluation of the same state (lb2p_moments)
     // form_final: store j~ = rho u - j0' (and u) after a velocity-form
-    // solve; a 3D time step leaves that to k_closure1_zm, which reads the
-    // same words anyway.
+    // solve; a time step leaves that to the first closure kernel
+    // (k_closure1_zm, k_closure1_t2), which reads the same words anyway.
     static lb2p_status solve(lb2p_ctx* c, bool advance = true, bool form_final = true)
     {
         const lb2p_params& p = c->prm;
@@ -656,9 +656,9 @@ struct Impl {
 
     static lb2p_status step(lb2p_ctx* c)
     {
-        // 3D fused solve: k_closure1_zm forms the final j~ and u
-        const bool closure_forms =
-            Lattice<Q>::D == 3 && !(c->prm.flags & LB2P_FLAG_UNFUSED_SOLVE);
+        // after the fused solve the first closure kernel forms the final j~
+        // and u (k_closure1_zm in 3D, k_closure1_t2 in 2D)
+        const bool closure_forms = !(c->prm.flags & LB2P_FLAG_UNFUSED_SOLVE);
         lb2p_status st = solve(c, true, !closure_forms);
         if (st != LB2P_OK) return st;
         {
@@ -673,9 +673,9 @@ struct Impl {
             } else {
                 hipLaunchKernelGGL((k_closure1_t2<R, kClos2TX, kClos2TY>), dim3((unsigned)c->clos_host.size()),
                                    dim3(kClos2TX, kClos2TY, 1), 0, c->stream, c->dtab, c->clos_tiles,
-                                   (const SolveInfo*)c->info, (const R*)c->pf, (const R*)c->u,
-                                   (const R*)c->jt0, (const R*)c->jt1, (R*)c->X, (R*)c->T, (R*)c->Y,
-                                   (R*)c->Xi);
+                                   (const SolveInfo*)c->info, (const R*)c->pf, (const R*)c->rho,
+                                   (const R*)c->j0p, (R*)c->u, (const R*)c->u1, (R*)c->jt0, (R*)c->jt1,
+                                   (R*)c->X, (R*)c->T, (R*)c->Y, (R*)c->Xi, closure_forms ? 1 : 0);
             }
         }
         {
