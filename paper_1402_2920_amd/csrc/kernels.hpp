@@ -531,110 +531,6 @@ struct IterCtl {
     double* part;                // per-block maxima (block_max_part)
 };
 
-// ---------------------------------------------------------------------------
-// Item 2: f = kappa rho d_a d_b d_b rho (Sec. IV E), j0' = j0 + f/2.
-// Also the iteration's start: j~ (zero or the previous step's), u = (j0'+j~)/rho,
-// and max|j0'| for the stop rule.
-// ---------------------------------------------------------------------------
-template <int Q, class R>
-__global__ void __launch_bounds__(256) k_force(const Domain* __restrict__ tab,
-                                               const Tile* __restrict__ tiles, IterCtl ic,
-                                               const R* __restrict__ rho, const R* __restrict__ j0,
-                                               R* __restrict__ f, R* __restrict__ j0p,
-                                               R* __restrict__ u, const R* jt_prevA,
-                                               const R* jt_prevB, const SolveInfo* prev_info,
-                                               R* jt0, R* __restrict__ pf, R* hist, R* hist2, int order)
-{
-    using L = Lattice<Q>;
-    const Where w = locate(tab, tiles);
-    if (w.dom < 0) return;
-    double amax = 0.0;
-    if (w.ok) {
-        const Domain& dm = tab[w.dom];
-        const long long o = dm.off, St = dm.g.S;
-        const Nb2 nb = make_nb2(dm.g, w.x, w.y, w.z);
-        const unsigned i0 = nb.i0;
-        const R* const rh = rho + o;
-        const R r = ldo(rh, i0);
-        // rho at i0 + (dx, dy, dz) with |d| <= 2 along at most two axes
-        auto RH = [&](int dx, int dy, int dz) {
-            int t = 0;
-            if (dx) t += nb.o[0][dx < 0 ? dx + 2 : dx + 1];
-            if (dy) t += nb.o[1][dy < 0 ? dy + 2 : dy + 1];
-            if (dz) t += nb.o[2][dz < 0 ? dz + 2 : dz + 1];
-            return ldo(rh, i0 + (unsigned)t);
-        };
-        R fa[3] = {R(0), R(0), R(0)};
-        if constexpr (L::D == 3) {
-            // (100): tau -3 ; (110): tau 1/2 ; (200): tau 1/4 (Table III)
-            fa[0] = R(-3) * (RH(1, 0, 0) - RH(-1, 0, 0)) +
-                    R(0.5) * (RH(1, 1, 0) + RH(1, -1, 0) + RH(1, 0, 1) + RH(1, 0, -1) -
-                              RH(-1, 1, 0) - RH(-1, -1, 0) - RH(-1, 0, 1) - RH(-1, 0, -1)) +
-                    R(0.5) * (RH(2, 0, 0) - RH(-2, 0, 0));
-            fa[1] = R(-3) * (RH(0, 1, 0) - RH(0, -1, 0)) +
-                    R(0.5) * (RH(1, 1, 0) + RH(-1, 1, 0) + RH(0, 1, 1) + RH(0, 1, -1) -
-                              RH(1, -1, 0) - RH(-1, -1, 0) - RH(0, -1, 1) - RH(0, -1, -1)) +
-                    R(0.5) * (RH(0, 2, 0) - RH(0, -2, 0));
-            fa[2] = R(-3) * (RH(0, 0, 1) - RH(0, 0, -1)) +
-                    R(0.5) * (RH(1, 0, 1) + RH(-1, 0, 1) + RH(0, 1, 1) + RH(0, -1, 1) -
-                              RH(1, 0, -1) - RH(-1, 0, -1) - RH(0, 1, -1) - RH(0, -1, -1)) +
-                    R(0.5) * (RH(0, 0, 2) - RH(0, 0, -2));
-        } else {
-            // (10): tau -2 ; (11): tau 1/2 ; (20): tau 1/4
-            fa[0] = R(-2) * (RH(1, 0, 0) - RH(-1, 0, 0)) +
-                    R(0.5) * (RH(1, 1, 0) + RH(1, -1, 0) - RH(-1, 1, 0) - RH(-1, -1, 0)) +
-                    R(0.5) * (RH(2, 0, 0) - RH(-2, 0, 0));
-            fa[1] = R(-2) * (RH(0, 1, 0) - RH(0, -1, 0)) +
-                    R(0.5) * (RH(1, 1, 0) + RH(-1, 1, 0) - RH(1, -1, 0) - RH(-1, -1, 0)) +
-                    R(0.5) * (RH(0, 2, 0) - RH(0, -2, 0));
-        }
-        const R kr = R(dm.cf.kappa) * r;
-        const R inv = R(1) / r;
-        // rho is fixed during the iteration: its EOS terms and 1/rho are
-        // evaluated once here (planes p, P1 = p - rho p', 1/rho)
-        {
-            const EosVal<R> e = eos_all<R>(dm.cf.eos, r);
-            R* const pfo = pf + o;
-            sto(pfo, i0, e.p);
-            sto(pfo + St, i0, e.P1);
-            sto(pfo + 2 * St, i0, inv);
-        }
-        // start of the iteration (Sec. IX allows zero or the previous step's
-        // value): zero, the previous step's final iterate y1, or the
-        // extrapolation from the previous steps: linear 2 y1 - y2 (order 1)
-        // or quadratic y3 + 3 (y1 - y2) (order 2); hist keeps y1 and hist2
-        // y2 for the next step (when non-null)
-        const R* prev = nullptr;
-        if (prev_info) prev = prev_info[w.dom].final_buf ? jt_prevB : jt_prevA;
-#pragma unroll
-        for (int a = 0; a < L::D; ++a) {
-            const R fv = kr * fa[a];
-            const R jp = ldo(j0 + o + a * St, i0) + R(0.5) * fv;
-            R jt = prev ? ldo(prev + o + a * St, i0) : R(0);
-            if (hist) {
-                const R y1 = jt;
-                const R y2 = ldo(hist + o + a * St, i0);
-                sto(hist + o + a * St, i0, y1);
-                R y3 = R(0);
-                if (hist2) {
-                    y3 = ldo(hist2 + o + a * St, i0);
-                    sto(hist2 + o + a * St, i0, y2);
-                }
-                if (order == 2)
-                    jt = y3 + R(3) * (y1 - y2);
-                else if (order == 1)
-                    jt = R(2) * y1 - y2;
-            }
-            sto(f + o + a * St, i0, fv);
-            sto(j0p + o + a * St, i0, jp);
-            if (jt0) sto(jt0 + o + a * St, i0, jt);   // the velocity-form solve needs only u
-            sto(u + o + a * St, i0, (jp + jt) * inv);
-            amax = fmax(amax, fabs((double)jp));
-        }
-    }
-    block_max_part(ic.part, amax);
-}
-
 __device__ __forceinline__ bool iter_skip(const IterCtl& c, int dom, int it)
 {
     if (*((volatile int*)(c.done_at + dom)) >= 0) return true;

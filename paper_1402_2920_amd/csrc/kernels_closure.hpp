@@ -2,7 +2,8 @@
 // z-marches, k_closure1_zm (the level-1 fields X, T, Y and Xi' from first
 // derivatives of u, p and per-site products) and k_closure2_zm (Sigma from the
 // derivatives of X, T, Y); for D2Q21 on LDS tiles, k_closure1_t2 and
-// k_closure2_t2 (at the end of this file).
+// k_closure2_t2 (at the end of this file).  The force kernels of item 2,
+// k_force_zm (3D) and k_force_t2 (2D), are here too.
 //
 // A block owns a TX x TY tile of an xy plane (one thread per tile point) and
 // marches through TZ planes of z, like the fused solve pass.  Each thread
@@ -486,8 +487,8 @@ k_closure1_zm(const Domain* __restrict__ tab, const Tile* __restrict__ tiles,
 
 // Item 2 for D3Q59 as a z-march: f = kappa rho (sum over the force stencil of
 // Table III of tau_i d_i rho(r + d_i)), j0' = j0 + f/2, the per-step planes p,
-// P1 = p - rho p', 1/rho, and the start of the iteration (the same arithmetic
-// as the per-site k_force).  The stencil reaches (+-1, 0, 0), (+-1, +-1, 0)
+// P1 = p - rho p', 1/rho, and the start of the iteration (per site, the same
+// terms as k_force_t2 in 2D).  The stencil reaches (+-1, 0, 0), (+-1, +-1, 0)
 // and (+-2, 0, 0) and their permutations, so three planes of rho (c-1, c,
 // c+1, tile + 2-wide frame) sit in LDS and the column's rho at c-2 .. c+2 in
 // registers.
@@ -882,6 +883,87 @@ k_closure2_t2(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, co
             if (a == b) br2 += -e.P1 * trDY + e.P2 * trG * trJ;
             sto(Sig + o + sym2<D>(a, b) * St, i0, KS1 * br1 + KS2 * br2);
         }
+}
+
+
+// Item 2 for D2Q21 on LDS tiles: f = kappa rho d_a d_b d_b rho (Sec. IV E,
+// Table III), j0' = j0 + f/2; the planes p, P1 and 1/rho of the iteration;
+// its start j~ (zero, the previous step's, or extrapolated from the previous
+// steps: linear 2 y1 - y2 or quadratic y3 + 3 (y1 - y2), with hist and hist2
+// keeping y1 and y2 for the next step when non-null); u = (j0' + j~)/rho;
+// and per-block maxima of |j0'| for the stop rule.  rho is staged in LDS for
+// the tile and a 2-wide frame; the rest is per site.
+template <class R, int TX, int TY>
+__global__ void __launch_bounds__(TX * TY)
+k_force_t2(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, IterCtl ic, const R* __restrict__ rho,
+           const R* __restrict__ j0, R* __restrict__ f, R* __restrict__ j0p, R* __restrict__ u,
+           const R* jt_prevA, const R* jt_prevB, const SolveInfo* prev_info, R* jt0, R* __restrict__ pf,
+           R* hist, R* hist2, int order)
+{
+    constexpr int UX = TX + 4, UY = TY + 4;
+    __shared__ R sr[UY][UX];
+
+    const Tile tl = tiles[blockIdx.x];
+    if (tl.dom < 0) return;   // uniform per block (padding: no slot)
+    const Domain& dm = tab[tl.dom];
+    const int nx = dm.g.nx, ny = dm.g.ny;
+    const long long o = dm.off, St = dm.g.S;
+    const R* const rh = rho + o;
+    const int tid = threadIdx.x + TX * threadIdx.y;
+    for (int k = tid; k < UX * UY; k += TX * TY)
+        (&sr[0][0])[k] = ldo(rh, frame_site<UX>(k, tl.x0, tl.y0, nx, ny));
+    __syncthreads();
+    double amax = 0.0;
+    const int x = tl.x0 + (int)threadIdx.x, y = tl.y0 + (int)threadIdx.y;
+    if (x < nx && y < ny) {
+        const unsigned i0 = (unsigned)x + (unsigned)nx * (unsigned)y;
+        const int cx = (int)threadIdx.x + 2, cy = (int)threadIdx.y + 2;
+        auto RH = [&](int dx, int dy) -> R { return sr[cy + dy][cx + dx]; };
+        const R r = RH(0, 0);
+        // (10): tau -2 ; (11): tau 1/2 ; (20): tau 1/4
+        R fa[2];
+        fa[0] = R(-2) * (RH(1, 0) - RH(-1, 0)) + R(0.5) * (RH(1, 1) + RH(1, -1) - RH(-1, 1) - RH(-1, -1)) +
+                R(0.5) * (RH(2, 0) - RH(-2, 0));
+        fa[1] = R(-2) * (RH(0, 1) - RH(0, -1)) + R(0.5) * (RH(1, 1) + RH(-1, 1) - RH(1, -1) - RH(-1, -1)) +
+                R(0.5) * (RH(0, 2) - RH(0, -2));
+        const R kr = R(dm.cf.kappa) * r;
+        const R inv = R(1) / r;
+        {
+            const EosVal<R> e = eos_all<R>(dm.cf.eos, r);
+            R* const pfo = pf + o;
+            sto(pfo, i0, e.p);
+            sto(pfo + St, i0, e.P1);
+            sto(pfo + 2 * St, i0, inv);
+        }
+        const R* prev = nullptr;
+        if (prev_info) prev = prev_info[tl.dom].final_buf ? jt_prevB : jt_prevA;
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const R fv = kr * fa[a];
+            const R jp = ldo(j0 + o + a * St, i0) + R(0.5) * fv;
+            R jt = prev ? ldo(prev + o + a * St, i0) : R(0);
+            if (hist) {
+                const R y1 = jt;
+                const R y2 = ldo(hist + o + a * St, i0);
+                sto(hist + o + a * St, i0, y1);
+                R y3 = R(0);
+                if (hist2) {
+                    y3 = ldo(hist2 + o + a * St, i0);
+                    sto(hist2 + o + a * St, i0, y2);
+                }
+                if (order == 2)
+                    jt = y3 + R(3) * (y1 - y2);
+                else if (order == 1)
+                    jt = R(2) * y1 - y2;
+            }
+            sto(f + o + a * St, i0, fv);
+            sto(j0p + o + a * St, i0, jp);
+            if (jt0) sto(jt0 + o + a * St, i0, jt);   // the velocity-form solve needs only u
+            sto(u + o + a * St, i0, (jp + jt) * inv);
+            amax = fmax(amax, fabs((double)jp));
+        }
+    }
+    block_max_part(ic.part, amax);
 }
 
 }  // namespace lb2p

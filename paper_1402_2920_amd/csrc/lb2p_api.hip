@@ -554,14 +554,14 @@ struct Impl {
                                    (const R*)c->jt0, (const R*)c->jt1, prev, jstart, (R*)c->pf, hist, hist2,
                                    order);
             } else {
-                hipLaunchKernelGGL((k_force<Q, R>), sgrid(c), sblock(c), 0, c->stream, c->dtab,
-                                   c->site_tiles, ic, (const R*)c->rho, (const R*)c->j0, (R*)c->f,
-                                   (R*)c->j0p, (R*)c->u, (const R*)c->jt0, (const R*)c->jt1, prev, jstart,
-                                   (R*)c->pf, hist, hist2, order);
+                hipLaunchKernelGGL((k_force_t2<R, kClos2TX, kClos2TY>), dim3((unsigned)c->clos_host.size()),
+                                   dim3(kClos2TX, kClos2TY, 1), 0, c->stream, c->dtab, c->clos_tiles, ic,
+                                   (const R*)c->rho, (const R*)c->j0, (R*)c->f, (R*)c->j0p, (R*)c->u,
+                                   (const R*)c->jt0, (const R*)c->jt1, prev, jstart, (R*)c->pf, hist, hist2,
+                                   order);
             }
             hipLaunchKernelGGL(k_reduce_max, dim3(c->ndom), dim3(256), 0, c->stream, (const double*)c->pmax,
-                               (const int*)(Lattice<Q>::D == 3 ? c->clos_range : c->site_range), c->jscale,
-                               1LL, (const int*)nullptr);
+                               (const int*)c->clos_range, c->jscale, 1LL, (const int*)nullptr);
         }
         const bool fused = !(p.flags & LB2P_FLAG_UNFUSED_SOLVE);
         constexpr int kFusedTX = Lattice<Q>::D == 3 ? fused_tx<R>() : kFused2TX;

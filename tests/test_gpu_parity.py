@@ -152,14 +152,15 @@ def test_chebyshev_needs_fewer_passes(L, lattice, shape):
     assert np.abs(out[0][1] - out[1][1]).max() <= 1e-10 * scale
 
 
+@pytest.mark.parametrize("lattice,shape", [(59, (20, 12, 10)), (21, (40, 24))])
 @pytest.mark.parametrize("warm", [0, 2, 3])
-def test_warm_start_forms_reach_the_same_fixed_point(orc, L, warm):
+def test_warm_start_forms_reach_the_same_fixed_point(orc, L, warm, lattice, shape):
     """Zero start and the extrapolated warm start change only the first
     iterate: over 10 steps both stay on the oracle (FP64, 1e-10)."""
-    rho, u, model = small_case(59, (20, 12, 10))
+    rho, u, model = small_case(lattice, shape)
     ref = oracle_reference(orc, model, rho, u, nsteps_long=10)
     gpu = gpu_run(L, model, L.STORE_F64, rho, u, nsteps_long=10, tol=1e-14, warm_start=warm)
     e = compare(orc, ref, gpu)
-    print("warm", warm, {k: f"{v:.2e}" for k, v in e.items()}, flush=True)
+    print("warm", warm, lattice, {k: f"{v:.2e}" for k, v in e.items()}, flush=True)
     for k, v in e.items():
         assert v <= F64_TOL, (k, v)
