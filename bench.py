@@ -385,7 +385,7 @@ def main():
     if args.batch_steps > 0:
         bw = "d2q21_batch512"
         bres = run_batch(bw, args.batch_steps, args.warmup, args.batch_iters)
-        broof, _ = roofline(bres, "f32", warm=1)
+        broof, bkern = roofline(bres, "f32", warm=1)
         bN = bres["N"]
         line["batched"] = dict(
             workload=f"{bw}: {bres['ndom']} periodic D2Q21 domains, sides 32..256, one droplet each, "
@@ -395,7 +395,8 @@ def main():
             solve=f"{args.batch_iters} j~ passes per step (fixed), all timed steps in one HIP graph launch",
             resid_over_jscale=float(f"{bres['stats']['resid'] / max(bres['stats']['jscale'], 1e-300):.3e}"),
             max_rel_mass_drift=float(f"{bres['mass_drift']:.3e}"),
-            roofline=dict(broof, note="per-kernel HIP events from 4 eager steps after the graph run"))
+            roofline=dict(broof, note="per-kernel HIP events from 4 eager steps after the graph run"),
+            kernels={k: v for k, v in bkern.items() if v["launches"]})
     if ref is not None:
         errs = {}
         stgs = [args.storage] + ([] if args.no_variants or args.storage != "f32" else ["bf16", "f16"])

@@ -94,7 +94,12 @@ typedef struct {
                                than 2^29 sites per domain (its FP64 mass
                                plane stays below 4 GiB)                        */
     int storage;            /* lb2p_storage                                    */
-    double gamma;           /* BGK parameter, -1 < gamma < 1 (Sec. II)         */
+    double gamma;           /* BGK parameter, -1 < gamma < 1 (Sec. II); the
+                               shear viscosity is (1/2)(1+gamma)/(1-gamma) p
+                               (Sec. VII).  Measured: gamma > 0 lets the
+                               update grow grid-scale noise (a gamma = 0.4
+                               sound wave reaches NaN within a few hundred
+                               steps); gamma <= 0 stays bounded            */
     double kappa;           /* interfacial stiffness >= 0 (Sec. II)            */
     lb2p_eos eos;           /* equation of state (App. B)                      */
     double rho0;            /* fixed reference density of Delta^int and
