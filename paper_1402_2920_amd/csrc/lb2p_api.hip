@@ -38,7 +38,7 @@ template <class R>
 constexpr int fused_tx() { return sizeof(R) == 4 ? 64 : 32; }
 constexpr int kFusedTY = 8;
 constexpr int kClosTZ = 32;     // z chunk of the 3D closure kernels
-constexpr int kFused2TX = 32, kFused2TY = 16;   // 2D solve pass: 32-wide strips, 16-row chunks (36 x 16 threads)
+constexpr int kFused2TX = 32, kFused2TY = 8;    // 2D solve pass: 32-wide strips, 8-row chunks (36 x 8 threads)
 constexpr int kClos2TX = 32, kClos2TY = 8;      // 2D closure kernels: LDS tiles (256 threads)
 int fused_tx_of(size_t rsize) { return rsize == 4 ? fused_tx<float>() : fused_tx<double>(); }
 
