@@ -228,3 +228,28 @@ def test_viscosities_match_sec7(L, name, gamma):
         # second order in k: the error falls by about 4 when L doubles
         assert abs(err[64]["nu"]) * 3 <= abs(err[32]["nu"])
         assert abs(err[64]["nuL"]) * 3 <= abs(err[32]["nuL"])
+
+
+def test_droplet_spurious_currents_fall_with_resolution_2d(L):
+    """Spurious currents around a circular droplet (the paper's central claim,
+    abstract and Sec. X): R/w fixed at 16/3, the interface width w and kappa
+    (as w^2) raised together.  The steady max|u| falls with w (measured
+    2.0e-4 at w = 3, 1.41e-4 at w = 3.5: exponent 2.3).  Wider interfaces
+    (w = 4, kappa x 1.78) make the droplet step diverge in the oracle as well;
+    the near-critical 3D set's droplets dissolve at these sizes."""
+    from oracle import eos_tools as E
+    ent = W.load_params()["d2q21_64_droplet"]["model"]
+    rg, rl, _ = E.maxwell(_eos_model(ent))
+    umax = {}
+    for w, n in ((3.0, 96), (3.5, 112)):
+        e = dict(ent, kappa=ent["kappa"] * (w / 3.0) ** 2)
+        rho, u = W.droplet((n, n), 16.0 / 3.0 * w, rg, rl, width=w, noise=0.0)
+        snaps = _run(L, e, (n, n), rho, u, [2000, 4000])
+        um = [float(np.sqrt((uu ** 2).sum(0)).max()) for _, uu in snaps]
+        print(f"droplet w {w}: max|u| {um[0]:.3e} (2000) {um[1]:.3e} (4000)", flush=True)
+        assert abs(um[1] - um[0]) <= 0.05 * um[1]   # steady
+        umax[w] = um[1]
+    assert umax[3.0] <= 3e-4
+    expo = math.log(umax[3.0] / umax[3.5]) / math.log(3.5 / 3.0)
+    print(f"droplet spurious-current exponent {expo:.2f}", flush=True)
+    assert expo >= 1.5
