@@ -8,8 +8,9 @@ order and expects spurious currents to vanish in the continuum limit
   construction of App. B, and the mismatch shrinks as the interface is
   resolved by more lattice spacings (width w, with kappa scaled as w^2 so the
   profile keeps its shape);
-* spurious currents: the steady velocity next to a planar interface (zero in
-  the continuum) is small and falls off quickly with w;
+* spurious currents: the steady velocity next to a planar interface and
+  around a 2D droplet (zero in the continuum) is small and falls off quickly
+  with w;
 * the Laplace law: the bulk pressure jump across a circular interface in 2D
   is sigma/R, with sigma = int sqrt(2 kappa W(rho)) drho for the
   square-gradient free energy whose force is kappa rho grad lap rho (Sec. II),
