@@ -8,7 +8,9 @@ exports the populations 4).  The oracle advances a periodic window of side
 W > 2R cut from the same initial fields; its central sites, whose
 dependence cone never meets the window's wrap, must equal the full-size GPU
 result.  Centres are seeded, one sits on a slab wall and on the periodic
-seam of the big lattice.
+seam of the big lattice.  FP64 and FP32 storage meet their fixed bars; BF16
+storage a bound derived per window from the codec's arithmetic (see
+_bf16_bound).
 
 Long run: the D2Q21 64 x 64 droplet over 1000 steps in FP64 against the
 oracle (both to their own stop rule; the GPU warm-starts j~).
@@ -49,7 +51,63 @@ def _centres(shape, seed=1402, n=2):
     return cs
 
 
-@pytest.mark.parametrize("storage,tol", [("STORE_F64", 1e-10), ("STORE_F32", 1e-5)])
+def _offset_fit_error(orc, m, Q, rho_all):
+    """Largest error, over the densities present, of the rest-equilibrium
+    offset that BF16/FP16 storage subtracts: per shell k a cubic in rho,
+    least-squares fitted on 201 points to w_k(c_s^2(rho)) rho over the
+    lattice's density range padded by 0.05 + 0.25 (max - min) (the codec's
+    stated construction), here fitted again from the oracle's EOS and
+    weights."""
+    mn, mx, rref = float(rho_all.min()), float(rho_all.max()), float(rho_all.mean())
+    pad = 0.05 + 0.25 * (mx - mn)
+    h = max(rref - (mn - pad), (mx + pad) - rref)
+    _, shell = orc.velocities(Q)
+    first = {int(k): i for i, k in reversed(list(enumerate(shell)))}
+    t = -1.0 + np.arange(201) / 100.0
+    rr = np.linspace(mn, mx, 201)
+    wt = np.array([orc.weights(Q, v) for v in orc.eos(m, rref + h * t)[:, 0]])
+    wr = np.array([orc.weights(Q, v) for v in orc.eos(m, rr)[:, 0]])
+    err = 0.0
+    for k, i in first.items():
+        if k == 0:
+            continue
+        coef = np.linalg.lstsq(np.vander(t, 4, increasing=True), wt[:, i] * (rref + h * t), rcond=None)[0]
+        fit = np.vander((rr - rref) / h, 4, increasing=True) @ coef
+        err = max(err, float(np.abs(fit - wr[:, i] * rr).max()))
+    return err
+
+
+def _bf16_bound(orc, m, Q, c, perm, rho0, n_init, no, off_err):
+    """Bound for BF16 storage on the inner window, from the FP32 bar and
+    the arithmetic of the codec.  A stored word is the deviation d of n_i
+    from the rest equilibrium w_i(c_s^2(rho)) rho in the writer's density
+    (r - c_i), less the offset's error; BF16 keeps it to 2^-8.
+    * output: 2^-8 (max |d| of the exported populations + offset error);
+    * input: the initial populations are stored the same way, and their
+      rounding passes through the step's stencils (force, solve, closure)
+      with the gain the FP32 bar allows for FP32 rounding,
+      G = 1e-5 / 2^-24 ~ 168;
+    * the FP32 compute: the FP32 bar (1e-5).
+    All relative to max |n|, as rel_err."""
+    lo, hi = RADIUS - 4, WIN - RADIUS + 4   # inner region plus the pull reach (|c| <= 3)
+    sub = rho0[lo:hi, lo:hi, lo:hi]
+    cs2 = orc.eos(m, sub.ravel())[:, 0]
+    w = np.array([orc.weights(Q, v) for v in cs2])[:, perm]        # [site][i], library order
+    rest = (w * sub.ravel()[:, None]).T.reshape(Q, *sub.shape)      # w_i rho at each writer
+    k = RADIUS - lo
+    d_out = 0.0
+    for i in range(Q):
+        cx, cy, cz = (int(v) for v in c[i])
+        wr = np.roll(rest[i], shift=(cz, cy, cx), axis=(0, 1, 2))   # value of the site r - c_i, at r
+        d_out = max(d_out, float(np.abs(no[i] - wr[k:-k, k:-k, k:-k]).max()))
+    # initial populations (written by each site in its own density)
+    d_in = float(np.abs(n_init[:, lo:hi, lo:hi, lo:hi] - rest).max())
+    gain = 1e-5 / 2.0 ** -24
+    scale = float(np.abs(no).max())
+    return 1e-5 + (2.0 ** -8 * (d_out + off_err) + gain * 2.0 ** -8 * (d_in + off_err)) / scale
+
+
+@pytest.mark.parametrize("storage,tol", [("STORE_F64", 1e-10), ("STORE_F32", 1e-5), ("STORE_BF16", None)])
 def test_fullsize_windows_match_oracle(orc, L, storage, tol):
     import torch
     name = "d3q59_256_slab"
@@ -70,20 +128,26 @@ def test_fullsize_windows_match_oracle(orc, L, storage, tol):
     rho3 = rho.reshape(nz, ny, nx)
     u3 = u.reshape(3, nz, ny, nx)
     inner = slice(RADIUS, WIN - RADIUS)
+    off_err = None
     for centre in _centres(shape):
         rw, idx = _cut(rho3, centre, WIN)
         uw = np.stack([_cut(u3[a], centre, WIN)[0] for a in range(3)])
         m = orc.Model(Q=Q, nx=WIN, ny=WIN, nz=WIN, tol=-1.0, max_iter=K_FIXED,
                       **{k: v for k, v in W.oracle_kwargs(entry["model"]).items() if k != "Q"})
         n = orc.init(m, rw.ravel(), uw.reshape(3, -1).T.copy())
+        rho0 = orc.fields(m, n)["rho"].reshape(WIN, WIN, WIN)   # the density each site writes with
+        n_init = n[perm].reshape(Q, WIN, WIN, WIN).copy()
         orc.step(m, n, 1)
         no = n[perm].reshape(Q, WIN, WIN, WIN)[:, inner, inner, inner]
+        if tol is None and off_err is None:
+            off_err = _offset_fit_error(orc, m, Q, rho)
+        bound = tol if tol is not None else _bf16_bound(orc, m, Q, c_lib, perm, rho0, n_init, no, off_err)
         it = [torch.as_tensor(i, device="cuda:0") for i in idx]
         ng = nd.index_select(1, it[2]).index_select(2, it[1]).index_select(3, it[0])
         ng = ng.cpu().numpy()[:, inner, inner, inner]
         e = rel_err(ng, no)
-        print(storage, "window at", centre, f"pop rel err {e:.2e}", flush=True)
-        assert e <= tol, (centre, e)
+        print(storage, "window at", centre, f"pop rel err {e:.2e} (bound {bound:.2e})", flush=True)
+        assert e <= bound, (centre, e)
     del nd
     torch.cuda.empty_cache()
 
