@@ -9,8 +9,8 @@ W > 2R cut from the same initial fields; its central sites, whose
 dependence cone never meets the window's wrap, must equal the full-size GPU
 result.  Centres are seeded, one sits on a slab wall and on the periodic
 seam of the big lattice.  FP64 and FP32 storage meet their fixed bars; BF16
-storage a bound derived per window from the codec's arithmetic (see
-_bf16_bound).
+and FP16 storage a bound derived per window from the codec's arithmetic (see
+_reduced_bound).
 
 Long run: the D2Q21 64 x 64 droplet over 1000 steps in FP64 against the
 oracle (both to their own stop rule; the GPU warm-starts j~).
@@ -77,12 +77,13 @@ def _offset_fit_error(orc, m, Q, rho_all):
     return err
 
 
-def _bf16_bound(orc, m, Q, c, perm, rho0, n_init, no, off_err):
-    """Bound for BF16 storage on the inner window, from the FP32 bar and
-    the arithmetic of the codec.  A stored word is the deviation d of n_i
-    from the rest equilibrium w_i(c_s^2(rho)) rho in the writer's density
-    (r - c_i), less the offset's error; BF16 keeps it to 2^-8.
-    * output: 2^-8 (max |d| of the exported populations + offset error);
+def _reduced_bound(orc, m, Q, c, perm, rho0, n_init, no, off_err, eps):
+    """Bound for BF16 or FP16 storage on the inner window, from the FP32
+    bar and the arithmetic of the codec.  A stored word is the deviation d of
+    n_i from the rest equilibrium w_i(c_s^2(rho)) rho in the writer's density
+    (r - c_i), less the offset's error; the format keeps it to its unit
+    roundoff eps (BF16 2^-8, FP16 2^-11).
+    * output: eps (max |d| of the exported populations + offset error);
     * input: the initial populations are stored the same way, and their
       rounding passes through the step's stencils (force, solve, closure)
       with the gain the FP32 bar allows for FP32 rounding,
@@ -104,10 +105,11 @@ def _bf16_bound(orc, m, Q, c, perm, rho0, n_init, no, off_err):
     d_in = float(np.abs(n_init[:, lo:hi, lo:hi, lo:hi] - rest).max())
     gain = 1e-5 / 2.0 ** -24
     scale = float(np.abs(no).max())
-    return 1e-5 + (2.0 ** -8 * (d_out + off_err) + gain * 2.0 ** -8 * (d_in + off_err)) / scale
+    return 1e-5 + (eps * (d_out + off_err) + gain * eps * (d_in + off_err)) / scale
 
 
-@pytest.mark.parametrize("storage,tol", [("STORE_F64", 1e-10), ("STORE_F32", 1e-5), ("STORE_BF16", None)])
+@pytest.mark.parametrize("storage,tol", [("STORE_F64", 1e-10), ("STORE_F32", 1e-5), ("STORE_BF16", 2.0 ** -8),
+                                         ("STORE_F16", 2.0 ** -11)])
 def test_fullsize_windows_match_oracle(orc, L, storage, tol):
     import torch
     name = "d3q59_256_slab"
@@ -129,6 +131,7 @@ def test_fullsize_windows_match_oracle(orc, L, storage, tol):
     u3 = u.reshape(3, nz, ny, nx)
     inner = slice(RADIUS, WIN - RADIUS)
     off_err = None
+    reduced = storage in ("STORE_BF16", "STORE_F16")
     for centre in _centres(shape):
         rw, idx = _cut(rho3, centre, WIN)
         uw = np.stack([_cut(u3[a], centre, WIN)[0] for a in range(3)])
@@ -139,9 +142,11 @@ def test_fullsize_windows_match_oracle(orc, L, storage, tol):
         n_init = n[perm].reshape(Q, WIN, WIN, WIN).copy()
         orc.step(m, n, 1)
         no = n[perm].reshape(Q, WIN, WIN, WIN)[:, inner, inner, inner]
-        if tol is None and off_err is None:
-            off_err = _offset_fit_error(orc, m, Q, rho)
-        bound = tol if tol is not None else _bf16_bound(orc, m, Q, c_lib, perm, rho0, n_init, no, off_err)
+        bound = tol
+        if reduced:   # tol is the format's unit roundoff
+            if off_err is None:
+                off_err = _offset_fit_error(orc, m, Q, rho)
+            bound = _reduced_bound(orc, m, Q, c_lib, perm, rho0, n_init, no, off_err, tol)
         it = [torch.as_tensor(i, device="cuda:0") for i in idx]
         ng = nd.index_select(1, it[2]).index_select(2, it[1]).index_select(3, it[0])
         ng = ng.cpu().numpy()[:, inner, inner, inner]
