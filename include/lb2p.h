@@ -25,6 +25,9 @@
  *     per-site fields) until lb2p_destroy.
  *   - Errors LB2P_ENOCONV and LB2P_ENONFINITE are sticky: every later call
  *     reports them until the next lb2p_init / lb2p_set_populations.
+ *   - Threads: distinct contexts may be used from different threads at once
+ *     (the only state they share, the process-wide cache of tuned tile
+ *     shapes, is locked).  Calls on one context must not overlap.
  */
 #ifndef LB2P_H
 #define LB2P_H

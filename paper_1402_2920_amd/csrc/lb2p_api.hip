@@ -17,6 +17,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -187,7 +188,9 @@ double spectral_bound_from_eos(int D, const EosParams& e, const lb2p_eos& in)
     return 1.05 * D * smax * m / 12.0;
 }
 
-// Tile-shape choices remembered per (lattice, storage, domain sizes).
+// Tile-shape choices remembered per (lattice, storage, domain sizes), shared
+// by every context of the process; tune_mutex() guards it (contexts may be
+// created and tuned from different threads).
 struct TuneChoice {
     int bx, by, tz;
 };
@@ -195,6 +198,11 @@ std::map<std::string, TuneChoice>& tune_cache()
 {
     static std::map<std::string, TuneChoice> m;
     return m;
+}
+std::mutex& tune_mutex()
+{
+    static std::mutex mu;
+    return mu;
 }
 
 }  // namespace
@@ -854,6 +862,7 @@ void default_shape(lb2p_ctx* c)
     c->bx = maxnx >= 256 ? 256 : (maxnx >= 128 ? 128 : 64);
     c->by = 256 / c->bx;
     c->tz = 128;
+    std::lock_guard<std::mutex> lock(tune_mutex());
     auto it = tune_cache().find(tune_key(c));
     if (it != tune_cache().end()) {
         c->bx = it->second.bx;
@@ -864,6 +873,7 @@ void default_shape(lb2p_ctx* c)
 
 void load_tune_file()
 {
+    std::lock_guard<std::mutex> lock(tune_mutex());
     static bool loaded = false;
     if (loaded) return;
     loaded = true;
@@ -1512,7 +1522,10 @@ lb2p_status lb2p_autotune(lb2p_ctx* c, int steps)
     c->sticky = LB2P_OK;
     if (st != LB2P_OK) return st;
     const std::string key = tune_key(c);
-    tune_cache()[key] = best;
+    {
+        std::lock_guard<std::mutex> lock(tune_mutex());
+        tune_cache()[key] = best;
+    }
     if (const char* path = std::getenv("LB2P_TUNE_CACHE")) {
         if (FILE* fh = std::fopen(path, "a")) {
             std::fprintf(fh, "%s %d %d %d\n", key.c_str(), best.bx, best.by, best.tz);
