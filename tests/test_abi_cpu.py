@@ -66,6 +66,9 @@ def _p(L, **kw):
     (dict(gamma=1.0), "EINVAL"), (dict(gamma=-1.0), "EINVAL"), (dict(nx=7), "EINVAL"),
     (dict(lattice=21, nz=4), "EINVAL"), (dict(lattice=20), "EINVAL"), (dict(kappa=-1.0), "EINVAL"),
     (dict(tol=-1.0), "EINVAL"), (dict(max_iter=0), "EINVAL"), (dict(storage=7), "EINVAL"),
+    # a domain of 2^29 sites or more: its FP64 plane would pass 4 GiB, beyond
+    # the kernels' 32-bit byte offsets (refused before any allocation)
+    (dict(nx=813, ny=813, nz=813), "EINVAL"),
     # App. B: the paper's example EOS violates positive bulk viscosity in 3D
     (dict(A=1.2, rho1=0.5, cs2_rho1=0.6), "EEOS"),
     # weights negative for c_s^2 below the Sec. III window
