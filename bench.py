@@ -187,7 +187,8 @@ def traffic_table(res):
     """Per-kernel-class HBM bytes per launch from committed rocprofv3
     FETCH_SIZE/WRITE_SIZE counters (scaled by a plain copy kernel's reading),
     if they were taken on the current kernel source and on this workload and
-    storage; else None."""
+    storage (profiles/traffic.json: one entry per "workload storage"); else
+    None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -197,9 +198,13 @@ def traffic_table(res):
         from paper_1402_2920_amd import build as B
         if t.get("src_sha") != B.source_sha():
             return None
-        if t.get("workload") != f"{res.get('workload')} {res.get('storage')}":
+        key = f"{res.get('workload')} {res.get('storage')}"
+        ent = t.get("workloads", {}).get(key)
+        if ent is None and t.get("workload") == key:
+            ent = t
+        if ent is None:
             return None
-        return {k: v["bytes_per_launch"] for k, v in t["kernels"].items()}
+        return {k: v["bytes_per_launch"] for k, v in ent["kernels"].items()}
     except Exception:
         return None
 

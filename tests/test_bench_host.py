@@ -55,13 +55,17 @@ def test_traffic_table_matches_workload_only():
     if os.path.exists(path):
         with open(path) as fh:
             t = json.load(fh)
-        wl, stg = t["workload"].split()
-        tt = bench.traffic_table(dict(workload=wl, storage=stg))
         from paper_1402_2920_amd import build as B
-        if t["src_sha"] == B.source_sha():
-            assert tt is not None and tt["iter_fused"] == t["kernels"]["iter_fused"]["bytes_per_launch"]
-        else:
-            assert tt is None
+        for key, ent in t["workloads"].items():
+            wl, stg = key.split()
+            tt = bench.traffic_table(dict(workload=wl, storage=stg))
+            if t["src_sha"] == B.source_sha():
+                assert tt is not None and tt["iter_fused"] == ent["kernels"]["iter_fused"]["bytes_per_launch"]
+            else:
+                assert tt is None
+        # another storage of a profiled workload has no entry
+        wl = next(iter(t["workloads"])).split()[0]
+        assert bench.traffic_table(dict(workload=wl, storage="f64")) is None
 
 
 def test_more_than_one_gpu_is_refused():
