@@ -257,7 +257,8 @@ typedef enum {
     LB2P_K_CLOSURE1 = 4,   /* items 9-10 and Xi'                             */
     LB2P_K_CLOSURE2 = 5,   /* Sigma                                          */
     LB2P_K_COLLIDE = 6,    /* item 11 per velocity and item 12               */
-    LB2P_K_ITER_FUSED = 7, /* items 3-6 of one pass in one kernel (D3Q59)    */
+    LB2P_K_ITER_FUSED = 7, /* items 3-6 of one pass in one kernel (velocity
+                              form, both lattices)                        */
     LB2P_NKERNEL = 8
 } lb2p_kernel;
 
