@@ -177,3 +177,141 @@ def test_closure_matches_chapman_enskog(orc, d, L, bound):
     for k in e1:
         assert e2[k] < bound, (k, e2[k])
         assert 12.0 < e1[k] / e2[k] < 20.0, (k, e1[k], e2[k])
+
+
+# ---------------------------------------------------------------------------
+# The j~ term of Xi' (Sec. VIII; Supplemental item 11).  Xi' carries
+# (1 - g) c0^2 (d_ab j~_g + perm.) so that the third moment of Delta^corr,
+# whose first term (g - 1) W_i/c0^2 j~.c_i contributes (g - 1) c0^2
+# (d_ab j~_g + perm.), comes out as the closure Xi of the Chapman-Enskog
+# expansion, which does not depend on j~ (Sec. VIII lists the four moments
+# Delta^corr must have).  The pins below run the oracle's closure into the
+# oracle's per-site collision and take the moment with numpy.
+# ---------------------------------------------------------------------------
+
+def _jt_field(d, L, X):
+    """A long-wavelength correction current, O(1e-2) like the closure terms."""
+    k = 2 * math.pi / L
+    if d == 2:
+        x, y = X
+        return [0.03 * sp.cos(k * x - 0.3) * sp.sin(k * y + 0.4) + 0.01,
+                -0.025 * sp.sin(k * x + 1.2) - 0.015 * sp.cos(k * y)]
+    x, y, z = X
+    return [0.03 * sp.cos(k * x - 0.3) * sp.sin(k * z + 0.4) + 0.01,
+            -0.025 * sp.sin(k * y + 1.2) - 0.015 * sp.cos(k * x),
+            0.02 * sp.cos(k * z + 0.7) * sp.cos(k * y - 0.2) - 0.005]
+
+
+def _corr_third_moment(orc, m, rho, u, jt, Sig, Xip):
+    """sum_i Delta^corr_i c_a c_b c_g per site, from the oracle's collision."""
+    c, _ = orc.velocities(m.Q)
+    c = c.astype(float)
+    N = rho.size
+    dc = np.zeros((N, m.Q))
+    zero_n = np.zeros(m.Q)
+    for s in range(N):
+        dc[s] = orc.site_collision(m, zero_n, rho[s], u[s], np.zeros(3), jt[s], Sig[s], Xip[s])[2]
+    return np.einsum("si,ia,ib,ig->sabg", dc, c, c, c, optimize=True)
+
+
+def _jt_case(orc, d, L):
+    """rho, u, j~ on an L^d box; the oracle's closure with that j~; the
+    analytic CE Xi on the same grid."""
+    X, rho_e, u_e = _fields(d, L)
+    jt_e = _jt_field(d, L, X)
+    grids = np.meshgrid(*[np.arange(L, dtype=float)] * d, indexing="ij")[::-1]
+    coords = [gg.ravel() for gg in grids]
+    ev = lambda e: np.broadcast_to(np.asarray(sp.lambdify(X, e, "numpy")(*coords), dtype=float),
+                                   coords[0].shape).copy()
+    N = L**d
+    rho = ev(rho_e)
+    u = np.zeros((N, 3))
+    jt = np.zeros((N, 3))
+    for a in range(d):
+        u[:, a] = ev(u_e[a])
+        jt[:, a] = ev(jt_e[a])
+    m = orc.Model(Q=59 if d == 3 else 21, nx=L, ny=L, nz=L if d == 3 else 1, gamma=GAMMA,
+                  rho0=0.3, **EOS)
+    Sig, Xip = orc.closure(m, rho, rho[:, None] * u, jt)
+    return m, rho, u, jt, Sig, Xip
+
+
+def _jt_term(orc, m, rho, jt, cs2):
+    """(1 - g) cs2 (d_ab j~_g + d_ag j~_b + d_bg j~_a) for a per-site cs2."""
+    N = rho.size
+    I = np.eye(3)
+    t = (np.einsum("ab,sg->sabg", I, jt) + np.einsum("ag,sb->sabg", I, jt)
+         + np.einsum("bg,sa->sabg", I, jt))
+    d = m.dim
+    mask = np.zeros((3, 3, 3))
+    mask[:d, :d, :d] = 1.0
+    return (1.0 - m.gamma) * np.asarray(cs2).reshape(-1, 1, 1, 1) * t * mask
+
+
+@pytest.mark.parametrize("d,L", [(2, 24), (3, 10)])
+def test_corr_third_moment_independent_of_jtilde(orc, d, L):
+    """Exact pin: the third moment of Delta^corr built from the oracle's Xi'
+    does not change when j~ does (random j~ per site, not only smooth ones).
+    Planted mistakes in the j~ term -- the local p/rho of the Supplemental
+    wording in place of c0^2 = c_s^2(rho0), or the wrong sign -- change it
+    by O(|j~|), far above the rounding level."""
+    m, rho, u, jt, Sig, Xip = _jt_case(orc, d, L)
+    rng = np.random.default_rng(1402)
+    jt_r = np.zeros_like(jt)
+    jt_r[:, :d] = rng.uniform(-0.05, 0.05, size=(rho.size, d))
+    Sig_r, Xip_r = orc.closure(m, rho, rho[:, None] * u, jt_r)
+    Sig_0, Xip_0 = orc.closure(m, rho, rho[:, None] * u, np.zeros_like(jt))
+    assert np.array_equal(Sig_r, Sig_0)        # Sigma does not involve j~
+    M_0 = _corr_third_moment(orc, m, rho, u, np.zeros_like(jt), Sig_0, Xip_0)
+    M_r = _corr_third_moment(orc, m, rho, u, jt_r, Sig_r, Xip_r)
+    scale = np.abs(M_0).max()
+    assert scale > 1e-4
+    tol = 1e-12 * max(scale, 0.05)
+    assert np.abs(M_r - M_0).max() < tol
+    # the same check on the two plausible misreadings of the term
+    c0sq = orc.eos(m, m.rho0)[0, 0]
+    cs2_loc = orc.eos(m, rho)[:, 0]
+    assert np.abs(cs2_loc - c0sq).min() > 0.02   # the densities sit away from rho0
+    for wrong in (Xip_r - _jt_term(orc, m, rho, jt_r, c0sq) + _jt_term(orc, m, rho, jt_r, cs2_loc),
+                  Xip_r - 2.0 * _jt_term(orc, m, rho, jt_r, c0sq)):
+        M_w = _corr_third_moment(orc, m, rho, u, jt_r, Sig_r, wrong)
+        assert np.abs(M_w - M_0).max() > 1e3 * tol
+
+
+@pytest.mark.parametrize("d,L,bound", [(2, 48, 5e-5), (3, 16, 5e-3)])
+def test_corr_third_moment_matches_chapman_enskog_with_jtilde(orc, d, L, bound):
+    """With a non-zero long-wavelength j~, the third moment of Delta^corr
+    (oracle closure -> oracle collision) converges to the continuum Xi of
+    the Chapman-Enskog expansion at the fourth order of the stencils, as in
+    the j~ = 0 pin of Xi' above; the planted misreadings of the j~ term do
+    not (their error is O(|j~|) and does not shrink)."""
+    xs, t, rho_f, u_f, Sigma, Xi = derived_closure(d)
+    errs, wrong_errs = [], []
+    for LL in (L, 2 * L):
+        m, rho, u, jt, Sig, Xip = _jt_case(orc, d, LL)
+        M = _corr_third_moment(orc, m, rho, u, jt, Sig, Xip)
+        X, rho_e, u_e = _fields(d, LL)
+        sub = {rho_f: rho_e}
+        for a in range(d):
+            sub[u_f[a]] = u_e[a]
+        grids = np.meshgrid(*[np.arange(LL, dtype=float)] * d, indexing="ij")[::-1]
+        coords = [gg.ravel() for gg in grids]
+        cs2_loc = orc.eos(m, rho)[:, 0]
+        c0sq = orc.eos(m, m.rho0)[0, 0]
+        M_w = _corr_third_moment(orc, m, rho, u, jt, Sig,
+                                 Xip - _jt_term(orc, m, rho, jt, c0sq) + _jt_term(orc, m, rho, jt, cs2_loc))
+        e, ew = {}, {}
+        for (a, b, c), expr in Xi.items():
+            ref = np.broadcast_to(np.asarray(
+                sp.lambdify(X, expr.subs(sub).doit(), "numpy")(*coords), dtype=float), coords[0].shape)
+            scale = np.abs(ref).max()
+            e[a, b, c] = np.abs(M[:, a, b, c] - ref).max() / scale
+            ew[a, b, c] = np.abs(M_w[:, a, b, c] - ref).max() / scale
+        errs.append(e)
+        wrong_errs.append(ew)
+    for k in errs[0]:
+        assert errs[1][k] < bound, (k, errs[1][k])
+        assert 12.0 < errs[0][k] / errs[1][k] < 20.0, (k, errs[0][k], errs[1][k])
+    # with the local p/rho the error stays O(1e-2) and does not converge
+    worst = max(wrong_errs[1].values())
+    assert worst > 100 * bound
