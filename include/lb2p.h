@@ -223,6 +223,11 @@ lb2p_status lb2p_step(lb2p_ctx *ctx, int nsteps);
 /* Density and converged flow velocity u = j/rho of the CURRENT state
  * (items 1-8 evaluated without colliding).  rho_out [N], u_out [d][N]
  * (either may be NULL); dtype lb2p_dtype; host or device.  st may be NULL.
+ * A query: the state and what the next lb2p_step starts its solve from (the
+ * last step's j~) are unchanged, so later steps give the same results
+ * whether or not it was called.  It reads the non-finite flag of the steps
+ * since the last synchronising call (lb2p_step does so itself only in the
+ * tolerance mode, fixed_iter == 0).
  * Errors: ESTATE, ENOCONV, ENONFINITE, EHIP. */
 lb2p_status lb2p_moments(lb2p_ctx *ctx, void *rho_out, void *u_out, int dtype,
                          int on_device, lb2p_stats *st);

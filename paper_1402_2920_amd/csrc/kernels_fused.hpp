@@ -577,4 +577,34 @@ __global__ void __launch_bounds__(256) k_jt_final(const Domain* __restrict__ tab
     }
 }
 
+// Copy each domain's final j~ (the buffer its SolveInfo selects) into a
+// plain [d][S] field.
+template <int Q, class R>
+__global__ void __launch_bounds__(256) k_keep_jt(const Domain* __restrict__ tab,
+                                                 const Tile* __restrict__ tiles,
+                                                 const SolveInfo* __restrict__ info,
+                                                 const R* __restrict__ jtA, const R* __restrict__ jtB,
+                                                 R* __restrict__ out)
+{
+    using L = Lattice<Q>;
+    const Where w = locate(tab, tiles);
+    if (!w.ok) return;
+    const Domain& dm = tab[w.dom];
+    const long long St = dm.g.S;
+    const long long i0 = dm.off + sidx(dm.g, w.x, w.y, w.z);
+    const R* jt = info[w.dom].final_buf ? jtB : jtA;
+#pragma unroll
+    for (int a = 0; a < L::D; ++a) out[a * St + i0] = jt[a * St + i0];
+}
+
+// The SolveInfo of a kept j~: its pass count, in buffer 0 of the kept field.
+__global__ void k_info_keep(const SolveInfo* __restrict__ info, SolveInfo* __restrict__ keep, int ndom)
+{
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= ndom) return;
+    SolveInfo k = info[d];
+    k.final_buf = 0;
+    keep[d] = k;
+}
+
 }  // namespace lb2p

@@ -247,7 +247,7 @@ struct lb2p_ctx {
     int* clos_range = nullptr;
     // stop-rule state
     int stride = 0;                            // passes per domain in res
-    void* scratch = nullptr;
+    void* ctl = nullptr;                       // control block (stop rule, flags, sums)
     unsigned long long* res = nullptr;
     unsigned long long* jscale = nullptr;
     int* done_at = nullptr;
@@ -256,18 +256,24 @@ struct lb2p_ctx {
     int* nconv = nullptr;
     int* ndone = nullptr;
     double* sums = nullptr;
-    struct HostScratch {
+    struct HostReadback {
         int ndone;       // domains whose stop rule has held
         int ndone_last;  // the largest pass count at which it held
         int nconv;
         int flags;
         double sums[4];
     };
-    HostScratch* host = nullptr;               // pinned readback area
+    HostReadback* host = nullptr;               // pinned readback area
     bool status_pending = false;               // tolerance-mode status not yet read
     bool initialized = false;
-    bool have_prev = false;
+    bool have_prev = false;      // a time step's j~ exists to start the next solve
     int nprev = 0;               // solves since init whose j~ can start the next one
+    // lb2p_moments re-solves the current state into the j~ buffers; the last
+    // time step's final j~, which starts the next step's solve, is moved
+    // first to the Y field (idle between steps) with its SolveInfo in
+    // info_keep, and prev_keep says the next solve reads it from there
+    bool prev_keep = false;
+    SolveInfo* info_keep = nullptr;
     void* jhist = nullptr;       // final j~ of the steps before the previous one (extrapolated
                                  // warm start: j~(t-2), then j~(t-3) for the quadratic form)
     bool sigma_valid = false;
@@ -535,6 +541,7 @@ struct Impl {
     {
         const lb2p_params& p = c->prm;
         const int max_it = p.fixed_iter > 0 ? p.fixed_iter : p.max_iter;
+        if (max_it >= c->stride) return LB2P_ESTATE;   // passes index res[] and omega[] below stride
         const long long nres = (long long)c->ndom * c->stride;
         hipLaunchKernelGGL(k_reset_ctl, dim3((unsigned)((std::max<long long>(nres, c->ndom) + 255) / 256)),
                            dim3(256), 0, c->stream, c->res, nres, c->jscale, c->done_at, c->ndom,
@@ -543,7 +550,10 @@ struct Impl {
         IterCtl ic{c->res, c->jscale, c->done_at, c->stride, p.fixed_iter > 0 ? -1.0 : p.tol, c->omega, c->pmax};
         {
             ProfScope _ps(c, LB2P_K_FORCE);
-            const SolveInfo* prev = (p.warm_start && c->have_prev) ? c->info : nullptr;
+            const SolveInfo* prev =
+                (p.warm_start && c->have_prev) ? (c->prev_keep ? c->info_keep : c->info) : nullptr;
+            const R* prevA = c->prev_keep ? (const R*)c->Y : (const R*)c->jt0;
+            const R* prevB = c->prev_keep ? (const R*)c->Y : (const R*)c->jt1;
             // warm_start 2/3: keep the history only for solves that advance
             // time; extrapolate linearly once two previous steps exist and
             // quadratically (warm_start 3) once three do
@@ -559,14 +569,12 @@ struct Impl {
                 hipLaunchKernelGGL((k_force_zm<R, TX, kFusedTY>), dim3((unsigned)c->clos_host.size()),
                                    dim3(TX, kFusedTY, 1), 0, c->stream, c->dtab, c->clos_tiles, ic,
                                    (const R*)c->rho, (const R*)c->j0, (R*)c->f, (R*)c->j0p, (R*)c->u,
-                                   (const R*)c->jt0, (const R*)c->jt1, prev, jstart, (R*)c->pf, hist, hist2,
-                                   order);
+                                   prevA, prevB, prev, jstart, (R*)c->pf, hist, hist2, order);
             } else {
                 hipLaunchKernelGGL((k_force_t2<R, kClos2TX, kClos2TY>), dim3((unsigned)c->clos_host.size()),
                                    dim3(kClos2TX, kClos2TY, 1), 0, c->stream, c->dtab, c->clos_tiles, ic,
                                    (const R*)c->rho, (const R*)c->j0, (R*)c->f, (R*)c->j0p, (R*)c->u,
-                                   (const R*)c->jt0, (const R*)c->jt1, prev, jstart, (R*)c->pf, hist, hist2,
-                                   order);
+                                   prevA, prevB, prev, jstart, (R*)c->pf, hist, hist2, order);
             }
             hipLaunchKernelGGL(k_reduce_max, dim3(c->ndom), dim3(256), 0, c->stream, (const double*)c->pmax,
                                (const int*)c->clos_range, c->jscale, 1LL, (const int*)nullptr);
@@ -657,9 +665,24 @@ struct Impl {
         } else {
             c->last_iters = max_it;
         }
-        c->have_prev = true;
-        if (advance) c->nprev = std::min(c->nprev + 1, 3);
+        if (advance) {
+            c->have_prev = true;
+            c->prev_keep = false;
+            c->nprev = std::min(c->nprev + 1, 3);
+        }
         return LB2P_OK;
+    }
+
+    // Before lb2p_moments re-solves the current state: move the last step's
+    // final j~ (the next step's warm start) out of the j~ buffers.
+    static void keep_prev(lb2p_ctx* c)
+    {
+        if (!c->have_prev || c->prev_keep || !c->prm.warm_start) return;
+        hipLaunchKernelGGL((k_keep_jt<Q, R>), sgrid(c), sblock(c), 0, c->stream, c->dtab, c->site_tiles,
+                           (const SolveInfo*)c->info, (const R*)c->jt0, (const R*)c->jt1, (R*)c->Y);
+        hipLaunchKernelGGL(k_info_keep, dim3((c->ndom + 255) / 256), dim3(256), 0, c->stream,
+                           (const SolveInfo*)c->info, c->info_keep, c->ndom);
+        c->prev_keep = true;
     }
 
     static lb2p_status step(lb2p_ctx* c)
@@ -754,8 +777,12 @@ size_t storage_bytes(int storage)
     }
 }
 
-// Copy a field [ncomp][S] of type R to a caller buffer of dtype.
-lb2p_status copy_out(lb2p_ctx* c, const void* src, int ncomp, void* dst, int dtype, int on_device)
+// Copy a field [ncomp][S] of type R to a caller buffer of dtype.  A device
+// buffer of the other precision is converted into directly; a host one goes
+// through a device staging area: `stage` (at least ncomp * S elements of
+// dtype) when given, else a stream-ordered allocation.
+lb2p_status copy_out(lb2p_ctx* c, const void* src, int ncomp, void* dst, int dtype, int on_device,
+                     void* stage = nullptr)
 {
     const long long n = (long long)ncomp * c->S;
     const bool same = (dtype == LB2P_DTYPE_F64) == (c->rsize == 8);
@@ -763,7 +790,12 @@ lb2p_status copy_out(lb2p_ctx* c, const void* src, int ncomp, void* dst, int dty
     const void* from = src;
     void* tmp = nullptr;
     if (!same) {
-        HIPCHK(hipMallocAsync(&tmp, n * out_elem, c->stream));
+        if (on_device)
+            tmp = dst;
+        else if (stage)
+            tmp = stage;
+        else
+            HIPCHK(hipMallocAsync(&tmp, n * out_elem, c->stream));
         const int tb = 256;
         const long long nb = (n + tb - 1) / tb;
         if (c->rsize == 8)
@@ -774,9 +806,10 @@ lb2p_status copy_out(lb2p_ctx* c, const void* src, int ncomp, void* dst, int dty
                                (const float*)src, (double*)tmp, n);
         from = tmp;
     }
-    HIPCHK(hipMemcpyAsync(dst, from, n * out_elem,
-                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
-    if (tmp) HIPCHK(hipFreeAsync(tmp, c->stream));
+    if (from != dst)
+        HIPCHK(hipMemcpyAsync(dst, from, n * out_elem,
+                              on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+    if (tmp && tmp != dst && tmp != stage) HIPCHK(hipFreeAsync(tmp, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     return LB2P_OK;
 }
@@ -822,7 +855,7 @@ void free_ctx(lb2p_ctx* c)
     if (c->site_range) (void)hipFree(c->site_range);
     if (c->fused_range) (void)hipFree(c->fused_range);
     if (c->clos_range) (void)hipFree(c->clos_range);
-    if (c->scratch) (void)hipFree(c->scratch);
+    if (c->ctl) (void)hipFree(c->ctl);
     if (c->dtab) (void)hipFree(c->dtab);
     if (c->omega) (void)hipFree(c->omega);
     if (c->jhist) (void)hipFree(c->jhist);
@@ -981,9 +1014,9 @@ lb2p_status create_impl(int ndom, const lb2p_params* pp, void* hip_stream, lb2p_
     if (e == hipSuccess) e = hipMalloc((void**)&c->dtab, ndom * sizeof(Domain));
     const size_t nres = (size_t)ndom * c->stride;
     const size_t sbytes = 256 + sizeof(unsigned long long) * nres + (sizeof(unsigned long long) +
-                          sizeof(int) + sizeof(SolveInfo)) * (size_t)ndom + 64;
-    if (e == hipSuccess) e = hipMalloc(&c->scratch, sbytes);
-    if (e == hipSuccess) e = hipHostMalloc((void**)&c->host, sizeof(lb2p_ctx::HostScratch), hipHostMallocDefault);
+                          sizeof(int) + 2 * sizeof(SolveInfo)) * (size_t)ndom + 64;
+    if (e == hipSuccess) e = hipMalloc(&c->ctl, sbytes);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&c->host, sizeof(lb2p_ctx::HostReadback), hipHostMallocDefault);
     if (e == hipSuccess && p0.solver == LB2P_SOLVER_CHEBYSHEV)
         e = hipMalloc((void**)&c->omega, sizeof(double) * nres);
     if (e == hipSuccess) e = hipMalloc((void**)&c->mass, sizeof(double) * (size_t)S);
@@ -1004,7 +1037,7 @@ lb2p_status create_impl(int ndom, const lb2p_params* pp, void* hip_stream, lb2p_
     c->rho = take(1); c->j0 = take(D); c->f = take(D); c->j0p = take(D); c->u = take(D);
     c->jt0 = take(D); c->jt1 = take(D); c->q = take(nsig); c->T = c->q;
     c->X = take(1); c->Y = take(D); c->Xi = take(nxi); c->Sig = take(nsig); c->pf = take(3); c->u1 = take(D);
-    char* sb = (char*)c->scratch;
+    char* sb = (char*)c->ctl;
     c->flags = (int*)(sb + 0);
     c->nconv = (int*)(sb + 4);
     c->ndone = (int*)(sb + 8);   // two ints
@@ -1012,8 +1045,9 @@ lb2p_status create_impl(int ndom, const lb2p_params* pp, void* hip_stream, lb2p_
     c->res = (unsigned long long*)(sb + 256);
     c->jscale = c->res + nres;
     c->info = (SolveInfo*)(c->jscale + ndom);
-    c->done_at = (int*)(c->info + ndom);
-    std::memset(c->host, 0, sizeof(lb2p_ctx::HostScratch));
+    c->info_keep = c->info + ndom;
+    c->done_at = (int*)(c->info_keep + ndom);
+    std::memset(c->host, 0, sizeof(lb2p_ctx::HostReadback));
     c->info_host.assign(ndom, SolveInfo{0, 0, 1, 0});
     std::vector<double> om;
     if (c->omega) {
@@ -1030,7 +1064,7 @@ lb2p_status create_impl(int ndom, const lb2p_params* pp, void* hip_stream, lb2p_
     if ((c->omega && hipMemcpyAsync(c->omega, om.data(), sizeof(double) * nres, hipMemcpyHostToDevice,
                                     c->stream) != hipSuccess) ||
         hipMemcpyAsync(c->dtab, c->dom.data(), ndom * sizeof(Domain), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
-        hipMemsetAsync(c->scratch, 0, sbytes, c->stream) != hipSuccess ||
+        hipMemsetAsync(c->ctl, 0, sbytes, c->stream) != hipSuccess ||
         hipMemsetAsync(c->fields, 0, (size_t)ncomp * S * c->rsize, c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess) {
         free_ctx(c);
@@ -1071,7 +1105,10 @@ lb2p_status run_steps(lb2p_ctx* c, int nsteps)
     if (gs > 0 && !c->prof) {
         // a captured step warm-starts j~ from the previous step(s); the first
         // steps after lb2p_init have none, so they run eagerly
-        while (s < nsteps && (!c->have_prev || (c->prm.warm_start >= 2 && c->nprev < c->prm.warm_start))) {
+        // (and so does the first step after lb2p_moments, which reads its start
+        // from where that call kept it)
+        while (s < nsteps && (!c->have_prev || c->prev_keep ||
+                              (c->prm.warm_start >= 2 && c->nprev < c->prm.warm_start))) {
             lb2p_status st = dispatch(c, [&](auto impl) { return decltype(impl)::step(c); });
             if (st != LB2P_OK) return st;
             ++s;
@@ -1247,6 +1284,7 @@ lb2p_status lb2p_init(lb2p_ctx* c, const void* rho, const void* u, int dtype, in
     HIPCHK(hipStreamSynchronize(c->stream));
     c->initialized = true;
     c->have_prev = false;
+    c->prev_keep = false;
     c->nprev = 0;
     c->sigma_valid = false;
     c->sticky = LB2P_OK;
@@ -1265,23 +1303,34 @@ lb2p_status lb2p_step(lb2p_ctx* c, int nsteps)
     return c->sticky;
 }
 
-lb2p_status lb2p_moments(lb2p_ctx* c, void* rho_out, void* u_out, int dtype, int on_device,
-                         lb2p_stats* st)
+}  // extern "C"
+
+namespace {
+
+// lb2p_moments; `stage` (device, or null) stages the precision conversion of
+// host outputs, one field at a time.
+lb2p_status moments_impl(lb2p_ctx* c, void* rho_out, void* u_out, int dtype, int on_device, lb2p_stats* st,
+                         void* stage)
 {
     if (!c) return LB2P_EINVAL;
     if (!c->initialized) return LB2P_ESTATE;
     if (dtype != LB2P_DTYPE_F64 && dtype != LB2P_DTYPE_F32) return LB2P_EINVAL;
-    lb2p_status s = dispatch(c, [&](auto impl) { return decltype(impl)::solve(c, false); });
+    // the solve below must not change what the next lb2p_step starts from
+    lb2p_status s = dispatch(c, [&](auto impl) {
+        decltype(impl)::keep_prev(c);
+        return decltype(impl)::solve(c, false);
+    });
     if (s != LB2P_OK) return s;
+    c->status_pending = true;   // the call synchronises anyway: read the flags too
     s = read_status(c);
     if (s != LB2P_OK) return s;
     c->sigma_valid = false;
     if (rho_out) {
-        s = copy_out(c, c->rho, 1, rho_out, dtype, on_device);
+        s = copy_out(c, c->rho, 1, rho_out, dtype, on_device, stage);
         if (s != LB2P_OK) return s;
     }
     if (u_out) {
-        s = copy_out(c, c->u, c->D, u_out, dtype, on_device);
+        s = copy_out(c, c->u, c->D, u_out, dtype, on_device, stage);
         if (s != LB2P_OK) return s;
     }
     if (st) {
@@ -1290,6 +1339,17 @@ lb2p_status lb2p_moments(lb2p_ctx* c, void* rho_out, void* u_out, int dtype, int
     }
     return c->sticky;
 }
+
+}  // namespace
+
+extern "C" {
+
+lb2p_status lb2p_moments(lb2p_ctx* c, void* rho_out, void* u_out, int dtype, int on_device,
+                         lb2p_stats* st)
+{
+    return moments_impl(c, rho_out, u_out, dtype, on_device, st, nullptr);
+}
+
 
 lb2p_status lb2p_stats_get(lb2p_ctx* c, lb2p_stats* st)
 {
@@ -1437,6 +1497,7 @@ lb2p_status lb2p_set_populations(lb2p_ctx* c, const double* n_in, int on_device)
     HIPCHK(hipStreamSynchronize(c->stream));
     c->initialized = true;
     c->have_prev = false;
+    c->prev_keep = false;
     c->nprev = 0;
     c->sigma_valid = false;
     c->sticky = LB2P_OK;
@@ -1458,7 +1519,9 @@ lb2p_status lb2p_autotune(lb2p_ctx* c, int steps)
     void* const A_orig = c->A;
     void* const B_orig = c->B;
     const lb2p_params keep = c->prm;
-    if (c->prm.fixed_iter <= 0) c->prm.fixed_iter = 4;   // the same work for every candidate
+    // the same work for every candidate; the residual record of each domain
+    // has max_iter + 1 slots (fixed_iter + 1 when fixed), so at most that
+    if (c->prm.fixed_iter <= 0) c->prm.fixed_iter = std::min(4, c->prm.max_iter);
     c->prm.graph_steps = 0;
     const bool prof_keep = c->prof;
     c->prof = false;
@@ -1484,6 +1547,7 @@ lb2p_status lb2p_autotune(lb2p_ctx* c, int steps)
                 break;
             }
             c->have_prev = false;
+            c->prev_keep = false;
             c->nprev = 0;
             st = run_steps(c, 1);   // warm-up
             if (st != LB2P_OK) break;
@@ -1518,6 +1582,7 @@ lb2p_status lb2p_autotune(lb2p_ctx* c, int steps)
     (void)hipStreamSynchronize(c->stream);
     (void)hipFree(save);
     c->have_prev = false;
+    c->prev_keep = false;
     c->nprev = 0;
     c->sticky = LB2P_OK;
     if (st != LB2P_OK) return st;

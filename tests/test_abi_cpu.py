@@ -75,6 +75,13 @@ def _p(L, **kw):
     (dict(cs2_rho1=0.38), "EEOS"),
     # A > 0 without a two-phase region
     (dict(A=0.5), "EEOS"),
+    # non-finite or out-of-range settings are refused before any device call
+    (dict(kappa=float("nan")), "EINVAL"), (dict(gamma=float("nan")), "EINVAL"),
+    (dict(rho0=float("nan")), "EINVAL"), (dict(rho0=0.0), "EINVAL"),
+    (dict(tol=float("nan")), "EINVAL"), (dict(A=float("nan")), "EINVAL"),
+    (dict(cs2_rho1=float("nan")), "EINVAL"), (dict(rho1=1.2), "EINVAL"),
+    (dict(warm_start=4), "EINVAL"), (dict(warm_start=-1), "EINVAL"),
+    (dict(fixed_iter=-1), "EINVAL"), (dict(graph_steps=-1), "EINVAL"),
 ])
 def test_create_rejects_bad_parameters(L, kw, status):
     assert L.create_status(_p(L, **kw)) == getattr(L, status)
