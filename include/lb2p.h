@@ -47,7 +47,9 @@ typedef enum {
     LB2P_ENONFINITE = 4,  /* NaN or Inf found in the density                   */
     LB2P_ENOMEM = 5,      /* device allocation failed                          */
     LB2P_EHIP = 6,        /* HIP runtime error                                 */
-    LB2P_ESTATE = 7       /* call out of order (e.g. step before init)        */
+    LB2P_ESTATE = 7,      /* call out of order (e.g. step before init)        */
+    LB2P_ESIZE = 8        /* output larger than the static staging area of
+                             lb2p_moments_noalloc                              */
 } lb2p_status;
 
 /* Velocity sets of Tables I (D3Q59) and II (D2Q21). */
@@ -231,6 +233,22 @@ lb2p_status lb2p_step(lb2p_ctx *ctx, int nsteps);
  * Errors: ESTATE, ENOCONV, ENONFINITE, EHIP. */
 lb2p_status lb2p_moments(lb2p_ctx *ctx, void *rho_out, void *u_out, int dtype,
                          int on_device, lb2p_stats *st);
+
+/* lb2p_moments for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc).  The
+ * same results as lb2p_moments, bit for bit.  Where lb2p_moments allocates
+ * a stream-ordered device buffer per call (to convert a host output to the
+ * other precision), this call stages the conversion in a static device
+ * array of LB2P_NOALLOC_STAGE_BYTES that every GPU running the library
+ * holds until the process ends; device outputs are converted in place.  It
+ * calls no hipMalloc/hipFree.  Errors: as lb2p_moments, and LB2P_ESIZE
+ * (nothing done) when a host output needs conversion and d * N elements of
+ * dtype exceed the array.  The array is shared by every context on one GPU
+ * and keeps the last call's contents: calls that overlap on one GPU (from
+ * different threads or processes sharing the library) race on it. */
+#define LB2P_NOALLOC_STAGE_BYTES (64ull << 20)
+lb2p_status lb2p_moments_noalloc(lb2p_ctx *ctx, void *rho_out, void *u_out, int dtype,
+                                 int on_device, lb2p_stats *st);
 
 /* One per-site field of the last evaluated items 1-11 (see lb2p_field), as
  * dtype into out (host or device), component-major.  Sigma and Xi' are only

@@ -205,6 +205,40 @@ std::mutex& tune_mutex()
     return mu;
 }
 
+// Staging of lb2p_moments_noalloc: a static device array instead of a
+// per-call allocation.  Every GPU that runs the library holds its own copy
+// (allocated when the code object loads, kept until the process ends).  Its
+// name is a host-side stand-in: host code uses only the device address that
+// hipGetSymbolAddress returns for the current device, resolved once per
+// device by the first lb2p_create there (scratch_address).
+constexpr size_t kNoAllocStageBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocStageBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex& scratch_mutex()
+{
+    static std::mutex mu;
+    return mu;
+}
+
+// Device address of `scratch` on device dev (the current device).
+lb2p_status scratch_address(int dev, void** out)
+{
+    static void* addr[kMaxDevices] = {};
+    if (dev < 0 || dev >= kMaxDevices) return LB2P_EHIP;
+    std::lock_guard<std::mutex> lock(scratch_mutex());
+    if (!addr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return LB2P_EHIP;
+        }
+        addr[dev] = ptr;
+    }
+    *out = addr[dev];
+    return LB2P_OK;
+}
+
 }  // namespace
 
 struct lb2p_ctx {
@@ -280,6 +314,9 @@ struct lb2p_ctx {
     lb2p_status sticky = LB2P_OK;
     int last_iters = 0;
     std::vector<SolveInfo> info_host;
+    std::vector<unsigned long long> js_host;   // max|j0'| bits per domain (stats readback)
+    int device = 0;                            // the HIP device current at create
+    void* stage = nullptr;                     // this device's static staging array (device address)
     // graphs of graph_steps fixed-iteration steps, one per buffer parity
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     hipStream_t cap_stream = nullptr;          // capture only (the NULL stream cannot be captured)
@@ -1049,6 +1086,11 @@ lb2p_status create_impl(int ndom, const lb2p_params* pp, void* hip_stream, lb2p_
     c->done_at = (int*)(c->info_keep + ndom);
     std::memset(c->host, 0, sizeof(lb2p_ctx::HostReadback));
     c->info_host.assign(ndom, SolveInfo{0, 0, 1, 0});
+    c->js_host.assign(ndom, 0ull);
+    if (hipGetDevice(&c->device) != hipSuccess || scratch_address(c->device, &c->stage) != LB2P_OK) {
+        free_ctx(c);
+        return LB2P_EHIP;
+    }
     std::vector<double> om;
     if (c->omega) {
         // Chebyshev weights per domain: omega_0 = 1, omega_1 = 1/(1 - r^2/2),
@@ -1170,6 +1212,7 @@ const char* lb2p_strerror(lb2p_status st)
         case LB2P_ENOMEM: return "out of device memory";
         case LB2P_EHIP: return "HIP runtime error";
         case LB2P_ESTATE: return "call out of order";
+        case LB2P_ESIZE: return "output larger than the static staging area of lb2p_moments_noalloc";
     }
     return "unknown status";
 }
@@ -1350,6 +1393,18 @@ lb2p_status lb2p_moments(lb2p_ctx* c, void* rho_out, void* u_out, int dtype, int
     return moments_impl(c, rho_out, u_out, dtype, on_device, st, nullptr);
 }
 
+lb2p_status lb2p_moments_noalloc(lb2p_ctx* c, void* rho_out, void* u_out, int dtype, int on_device,
+                                 lb2p_stats* st)
+{
+    if (!c) return LB2P_EINVAL;
+    if (dtype != LB2P_DTYPE_F64 && dtype != LB2P_DTYPE_F32) return LB2P_EINVAL;
+    // host outputs of the other precision are staged one field at a time,
+    // the widest being u: d * N elements of dtype
+    const bool convert = (dtype == LB2P_DTYPE_F64) != (c->rsize == 8);
+    const size_t need = (size_t)c->D * (size_t)c->S * (dtype == LB2P_DTYPE_F64 ? 8 : 4);
+    if (convert && !on_device && need > kNoAllocStageBytes) return LB2P_ESIZE;
+    return moments_impl(c, rho_out, u_out, dtype, on_device, st, c->stage);
+}
 
 lb2p_status lb2p_stats_get(lb2p_ctx* c, lb2p_stats* st)
 {
@@ -1363,7 +1418,7 @@ lb2p_status lb2p_stats_get(lb2p_ctx* c, lb2p_stats* st)
     HIPCHK(hipMemcpyAsync(&c->host->flags, c->flags, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipMemcpyAsync(c->info_host.data(), c->info, c->ndom * sizeof(SolveInfo),
                           hipMemcpyDeviceToHost, c->stream));
-    std::vector<unsigned long long> js(c->ndom);
+    std::vector<unsigned long long>& js = c->js_host;
     HIPCHK(hipMemcpyAsync(js.data(), c->jscale, c->ndom * sizeof(unsigned long long), hipMemcpyDeviceToHost,
                           c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));

@@ -17,7 +17,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblb2p.so")
 
-OK, EINVAL, EEOS, ENOCONV, ENONFINITE, ENOMEM, EHIP, ESTATE = range(8)
+OK, EINVAL, EEOS, ENOCONV, ENONFINITE, ENOMEM, EHIP, ESTATE, ESIZE = range(9)
+NOALLOC_STAGE_BYTES = 64 << 20
 D2Q21, D3Q59 = 21, 59
 STORE_F64, STORE_F32, STORE_BF16, STORE_F16 = 0, 1, 2, 3
 DTYPE_F64, DTYPE_F32 = 0, 1
@@ -56,7 +57,7 @@ class _Stats(ctypes.Structure):
 
 EXPORTED = [
     "lb2p_default_params", "lb2p_create", "lb2p_create_batch", "lb2p_domain_totals",
-    "lb2p_autotune", "lb2p_init", "lb2p_step", "lb2p_moments",
+    "lb2p_autotune", "lb2p_init", "lb2p_step", "lb2p_moments", "lb2p_moments_noalloc",
     "lb2p_get_field", "lb2p_get_populations", "lb2p_set_populations", "lb2p_velocities",
     "lb2p_stats_get", "lb2p_profile_enable", "lb2p_profile_read", "lb2p_destroy", "lb2p_strerror",
 ]
@@ -91,6 +92,7 @@ def lib():
         L.lb2p_init.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int]
         L.lb2p_step.argtypes = [vp, ctypes.c_int]
         L.lb2p_moments.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_Stats)]
+        L.lb2p_moments_noalloc.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_Stats)]
         L.lb2p_get_field.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, ctypes.c_int]
         L.lb2p_get_populations.argtypes = [vp, vp, ctypes.c_int]
         L.lb2p_set_populations.argtypes = [vp, vp, ctypes.c_int]
@@ -265,12 +267,15 @@ class Context:
                                        ctypes.byref(st)), "lb2p_moments", allow)
         return rho, u
 
-    def moments_into(self, rho, u, allow=(ENOCONV,)):
-        """Write into caller buffers (torch device tensors or numpy)."""
+    def moments_into(self, rho, u, allow=(ENOCONV,), noalloc=False):
+        """Write into caller buffers (torch device tensors or numpy);
+        ``noalloc`` calls lb2p_moments_noalloc."""
         code = DTYPE_F64 if str(rho.dtype).endswith("float64") else DTYPE_F32
         pr, dev = _ptr(rho, code)
         pu, _ = _ptr(u, code)
-        return self._check(lib().lb2p_moments(self._ctx, pr, pu, code, dev, None), "lb2p_moments", allow)
+        fn = lib().lb2p_moments_noalloc if noalloc else lib().lb2p_moments
+        name = "lb2p_moments_noalloc" if noalloc else "lb2p_moments"
+        return self._check(fn(self._ctx, pr, pu, code, dev, None), name, allow)
 
     def field(self, which: int, dtype=np.float64) -> np.ndarray:
         ncomp = {FIELD_RHO: 1, FIELD_SIGMA: 6 if self.dim == 3 else 3,

@@ -88,7 +88,7 @@ def test_create_rejects_bad_parameters(L, kw, status):
 
 
 def test_strerror(L):
-    for s in range(8):
+    for s in range(9):
         assert isinstance(L.strerror(s), str) and L.strerror(s)
     assert L.strerror(99) == "unknown status"
 
