@@ -135,7 +135,25 @@ typedef struct {
     double spectral_bound;  /* Chebyshev only: upper bound b < 1 of the
                                spectrum of the map's linear part (0 = bound
                                from the EOS, see lb2p_solver)                  */
+    int iter_prec;          /* lb2p_iter_prec: precision of the per-site
+                               fields and of the j~ iteration (Sec. IX) on
+                               FP32/BF16/F16 storage                           */
 } lb2p_params;
+
+/* lb2p_params.iter_prec.  The populations keep their storage format in
+ * every case; this selects the precision of everything else (the per-site
+ * fields of items 1-11, so also of the j~ iteration).
+ *   LB2P_ITER_AUTO: FP64 with F64 storage; otherwise FP32, unless the stop
+ *     rule's tolerance (tolerance mode) is below LB2P_F32_TOL_FLOOR, where
+ *     the FP32 iteration can no longer meet it: then FP64.
+ *   LB2P_ITER_F32:  FP32 (EINVAL with F64 storage).
+ *   LB2P_ITER_F64:  FP64.
+ * In the FP32 iteration the iterate u is an FP32 number, so the stop rule's
+ * |G(j~) - j~| = |G + j0' - rho u| cannot fall much below the rounding of
+ * rho u next to max|j0'|; the floor is measured on the slab workload (the
+ * rule stalls at tol 1e-7; 2e-7 and above converge). */
+typedef enum { LB2P_ITER_AUTO = 0, LB2P_ITER_F32 = 1, LB2P_ITER_F64 = 2 } lb2p_iter_prec;
+#define LB2P_F32_TOL_FLOOR 2e-7
 
 /* lb2p_params.solver.  Both reach the fixed point of items 3-8 and stop on
  * the same rule (max_r |G(j~) - j~| <= tol * max_r |j0'|, Sec. IX).
@@ -171,8 +189,10 @@ typedef struct {
 typedef struct lb2p_ctx lb2p_ctx;
 
 /* Fill *out with defaults for a lattice and grid: gamma 0, kappa 0, the EOS
- * rho1 0.3, rho2 1.0, A 0, cs2_rho1 0.45, rho0 = rho1, FP32 storage,
- * tol 1e-6 (F32) / 1e-13 (F64), max_iter 200, warm_start 1, no graph. */
+ * rho1 0.3, rho2 1.0, A 0, cs2_rho1 0.45, rho0 = rho1, the given storage,
+ * tol 4e-7 (FP32 fields: twice the floor of the FP32 iteration, and on the
+ * slab workload the FP32 velocity within 1e-5 of FP64 over 100 steps) or
+ * 1e-13 (F64), max_iter 200, warm_start 1, iter_prec AUTO, no graph. */
 lb2p_status lb2p_default_params(int lattice, int nx, int ny, int nz, int storage,
                                 lb2p_params *out);
 

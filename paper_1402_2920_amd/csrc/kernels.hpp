@@ -36,18 +36,25 @@ struct Coef {
     double Wk[8];         // W_k = w_k(c0^2), reference shell weights
     EosParams eos;
     double cheb_gamma;    // extrapolation 2/(2 - b) of the Chebyshev solver
+    // c_s^2 and p at the domain's reference density rho_ref (DevScale): the
+    // per-step planes hold p and c_s^2 = p/rho as deviations from these
+    double cref, pref;
 };
 
-// Population storage codecs.  Plain forms hold n_i.  The BF16/FP16 forms
-// hold (n_i - o_i) / W_k, the deviation from the rest equilibrium of the site
-// that wrote the value, scaled per shell by the reference weight W_k.  That
-// site keeps a record of its density, rec = fp16(rho - rho_ref), beside the
-// populations, and o_i = P_k(rec) with P_k a cubic fitted on the host to
-// w_k(c_s^2(rho)) rho (Sec. III weights) over the domain's density range.
-// Writer and reader evaluate the same P_k on the same record, so the
-// offsets agree exactly; the fit only decides how small the stored
-// deviation is.  What remains is the velocity and non-equilibrium part,
-// small next to W_k, which BF16/FP16 resolve far better than n_i itself.
+// Population storage codecs.  FP64 storage holds n_i itself.  The FP32,
+// BF16 and FP16 forms hold d_i = n_i - o_i, the deviation from the rest
+// equilibrium of the site that wrote the value (BF16/FP16 scaled per shell
+// by the reference weight, d_i / W_k).  That site keeps a record of its
+// density, rec = fp16(rho - rho_ref), beside the populations, and
+// o_i = P_k(rec) with P_k a cubic fitted on the host to w_k(c_s^2(rho)) rho
+// (Sec. III weights) over the domain's density range, evaluated in FP32.
+// Writer and reader evaluate the same P_k on the same record, so the offsets
+// agree exactly and n_i = o_i + d_i holds as a sum of two exact numbers; the
+// fit only decides how small the stored deviation is.  What remains is the
+// velocity and non-equilibrium part, small next to o_i.  Readers never form
+// n_i in the storage precision: sums over velocities (item 1, the mass
+// balance of the collision) add o_i and d_i in FP64, and the collision
+// computes the deviation it stores in FP64.
 struct DevScale {
     float off[8];       // w_k(c_s^2(rho_ref)) rho_ref
     float scl[8];       // W_k
@@ -73,42 +80,35 @@ struct Tile {
 template <class S>
 struct Codec;
 
+// dev(v, ...): the value's deviation from its offset (the value itself for
+// FP64); put(d, ...): the stored form of deviation d.
 template <>
 struct Codec<double> {
     static constexpr bool kLocal = false;
-    __device__ static inline double dec(double v, const DevScale&, int, float) { return v; }
-    __device__ static inline double enc(double v, const DevScale&, int, float) { return v; }
+    __device__ static inline double dev(double v, const DevScale&, int) { return v; }
+    __device__ static inline double put(double d, const DevScale&, int) { return d; }
+};
+// BF16/FP16 store the deviation scaled by 1/W_k (one rounding, from FP64);
+// FP32 stores it unscaled (its exponent range needs no scale).
+template <class S>
+struct DevCodec {
+    static constexpr bool kLocal = true;
+    __device__ static inline float dev(S v, const DevScale& s, int k) { return static_cast<float>(v) * s.scl[k]; }
+    __device__ static inline S put(double d, const DevScale& s, int k)
+    {
+        return static_cast<S>(d * (double)s.inv[k]);
+    }
 };
 template <>
 struct Codec<float> {
-    static constexpr bool kLocal = false;
-    __device__ static inline float dec(float v, const DevScale&, int, float) { return v; }
-    __device__ static inline float enc(float v, const DevScale&, int, float) { return v; }
+    static constexpr bool kLocal = true;
+    __device__ static inline float dev(float v, const DevScale&, int) { return v; }
+    __device__ static inline float put(double d, const DevScale&, int) { return static_cast<float>(d); }
 };
 template <>
-struct Codec<_Float16> {
-    static constexpr bool kLocal = true;
-    __device__ static inline float dec(_Float16 v, const DevScale& s, int k, float off)
-    {
-        return fmaf(static_cast<float>(v), s.scl[k], off);
-    }
-    __device__ static inline _Float16 enc(float v, const DevScale& s, int k, float off)
-    {
-        return static_cast<_Float16>((v - off) * s.inv[k]);
-    }
-};
+struct Codec<_Float16> : DevCodec<_Float16> {};
 template <>
-struct Codec<__bf16> {
-    static constexpr bool kLocal = true;
-    __device__ static inline float dec(__bf16 v, const DevScale& s, int k, float off)
-    {
-        return fmaf(static_cast<float>(v), s.scl[k], off);
-    }
-    __device__ static inline __bf16 enc(float v, const DevScale& s, int k, float off)
-    {
-        return static_cast<__bf16>((v - off) * s.inv[k]);
-    }
-};
+struct Codec<__bf16> : DevCodec<__bf16> {};
 
 // The rest population (c = 0) is kept apart from the moving ones, at higher
 // precision: FP64 beside FP64/FP32 moving populations, FP32 beside BF16/FP16.
@@ -135,8 +135,9 @@ __host__ __device__ inline long long eq_offset_bytes(long long St)
 {
     return (St * (long long)sizeof(typename RestOf<S>::T) + 255) / 256 * 256;
 }
-// After the rest plane: for BF16/FP16 the density record of the site that
-// wrote each value (fp16 [S]), then the moving planes.
+// After the rest plane: for the deviation forms (FP32, BF16, FP16) the
+// density record of the site that wrote each value (fp16 [S]), then the
+// moving planes.
 template <class S>
 __host__ __device__ inline long long moving_offset_bytes(long long St)
 {
@@ -173,6 +174,13 @@ template <class S>
 __device__ inline const S* moving_planes(const S* A, long long St)
 {
     return reinterpret_cast<const S*>(reinterpret_cast<const char*>(A) + moving_offset_bytes<S>(St));
+}
+
+// Number of velocities in shell k.
+template <int Q>
+__host__ __device__ constexpr int kShellSize(int k)
+{
+    return Q == 59 ? kD3Q59.shell_size[k] : kD2Q21.shell_size[k];
 }
 
 // Density record of a site and the offset of a value of shell k it wrote.
@@ -398,11 +406,13 @@ __global__ void __launch_bounds__(256) k_reduce_max(const double* __restrict__ p
 
 // ---------------------------------------------------------------------------
 // Initial populations: n_i(r) = n_eq(rho(r), u(r)) with local weights,
-// written pre-shifted so that the first pull returns them.
+// written pre-shifted so that the first pull returns them.  Evaluated in FP64
+// from the caller's FP64 density (u in the field precision): only the
+// storage rounds.
 // ---------------------------------------------------------------------------
 template <int Q, class R, class S>
 __global__ void __launch_bounds__(256) k_init(const Domain* __restrict__ tab, const Tile* __restrict__ tiles,
-                                              const R* __restrict__ rho, const R* __restrict__ u,
+                                              const double* __restrict__ rho, const R* __restrict__ u,
                                               S* __restrict__ A)
 {
     using L = Lattice<Q>;
@@ -413,38 +423,60 @@ __global__ void __launch_bounds__(256) k_init(const Domain* __restrict__ tab, co
     const long long o = dm.off, St = g.S;
     const NbP nb = make_nbp(g, w.x, w.y, w.z);
     const unsigned i0 = nb.i0;
-    const R r = ldo(rho + o, i0);
-    R uu[3] = {R(0), R(0), R(0)};
+    const double r = ldo(rho + o, i0);
+    double uu[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-    for (int a = 0; a < L::D; ++a) uu[a] = ldo(u + o + a * St, i0);
-    const R cs2 = eos_cs2<R>(dm.cf.eos, r);
-    R wl[8];
-    shell_weights<Q, R>(cs2, wl);
-    const R inv = R(1) / cs2;
-    const R a0 = R(1) - (uu[0] * uu[0] + uu[1] * uu[1] + uu[2] * uu[2]) * R(0.5) * inv;
+    for (int a = 0; a < L::D; ++a) uu[a] = (double)ldo(u + o + a * St, i0);
+    const double cs2 = eos_cs2<double>(dm.cf.eos, r);
+    double wl[8];
+    shell_weights<Q, double>(cs2, wl);
+    const double inv = 1.0 / cs2;
+    const double a0 = 1.0 - (uu[0] * uu[0] + uu[1] * uu[1] + uu[2] * uu[2]) * 0.5 * inv;
     using T0 = typename RestOf<S>::T;
     S* const mv = moving_planes(A, St) + o;
     if constexpr (Codec<S>::kLocal) sto(eq_plane(A, St) + o, i0, density_record(dm.ds, float(r)));
-    T0 moved = T0(0);
+    double moved = 0.0;
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-        const R uc = uu[0] * R(L::cx(i)) + uu[1] * R(L::cy(i)) + uu[2] * R(L::cz(i));
-        const R neq = wl[L::shell(i)] * r * (a0 + uc * inv + R(0.5) * uc * uc * inv * inv);
+        const double uc = uu[0] * L::cx(i) + uu[1] * L::cy(i) + uu[2] * L::cz(i);
+        const double neq = wl[L::shell(i)] * r * (a0 + uc * inv + 0.5 * uc * uc * inv * inv);
         const unsigned slot = nb.at(-L::cx(i), -L::cy(i), -L::cz(i));
-        float off = 0.f;
-        if constexpr (Codec<S>::kLocal)   // the record the slot's own thread writes
-            off = rest_offset(dm.ds, L::shell(i), density_record(dm.ds, float(ldo(rho + o, slot))));
-        const S e = Codec<S>::enc(neq, dm.ds, L::shell(i), off);
-        sto(mv + (size_t)(i - 1) * St, slot, e);
-        moved += T0(Codec<S>::dec(e, dm.ds, L::shell(i), off));
+        if constexpr (Codec<S>::kLocal) {
+            // the record the slot's own thread writes
+            const float off =
+                rest_offset(dm.ds, L::shell(i), density_record(dm.ds, float(ldo(rho + o, slot))));
+            const S e = Codec<S>::put(neq - (double)off, dm.ds, L::shell(i));
+            sto(mv + (size_t)(i - 1) * St, slot, e);
+            moved += (double)off + (double)Codec<S>::dev(e, dm.ds, L::shell(i));
+        } else {
+            const S e = Codec<S>::put(S(neq), dm.ds, L::shell(i));
+            sto(mv + (size_t)(i - 1) * St, slot, e);
+            moved += (double)e;
+        }
     }
     // rest population: the site's density minus the stored moving ones
-    sto(rest_plane(A) + o, i0, T0(r) - moved);
+    sto(rest_plane(A) + o, i0, T0(r - moved));
+}
+
+// Pulled population i of a site as an FP64 number: o_i + d_i for the
+// deviation forms (both terms exact in FP64), n_i for FP64 storage.
+template <class S>
+__device__ __forceinline__ double pulled(const S* mv, const _Float16* eqa, const DevScale& ds, int k,
+                                         unsigned src)
+{
+    const S b = ldo(mv, src);
+    if constexpr (Codec<S>::kLocal)
+        return (double)rest_offset(ds, k, ldo(eqa, src)) + (double)Codec<S>::dev(b, ds, k);
+    else
+        return (double)b;
 }
 
 // ---------------------------------------------------------------------------
 // Item 1: rho = sum_i n_i, j0 = sum_i n_i c_i of the pulled populations, and
-// FP64 block partial sums of mass and momentum plus a non-finite flag.
+// FP64 block partial sums of mass and momentum plus a non-finite flag.  Both
+// sums run in FP64, so rho and j0 carry only the rounding of their own
+// precision (the FP32 rounding of j0 next to its own size, not next to the
+// populations').
 // ---------------------------------------------------------------------------
 template <int Q, class R, class S>
 __global__ void __launch_bounds__(256) k_moments(const Domain* __restrict__ tab,
@@ -467,29 +499,32 @@ __global__ void __launch_bounds__(256) k_moments(const Domain* __restrict__ tab,
         const long long o = dm.off, St = g.S;
         const NbP nb = make_nbp(g, w.x, w.y, w.z);
         const unsigned i0 = nb.i0;
-        // density accumulated in FP64: the exact sum of the stored values (the
-        // conserved mass), kept for the collision's mass balance
+        // the density is the exact sum of the stored values (the conserved
+        // mass), kept for the collision's mass balance
         double racc = (double)ldo(rest_plane(A) + o, i0);
-        R jx = R(0), jy = R(0), jz = R(0);
+        double jx = 0.0, jy = 0.0, jz = 0.0;
         const S* const mv = moving_planes(A, St) + o;
         const _Float16* const eqa = eq_plane(A, St) + o;
 #pragma unroll
-        for (int i = 1; i < Q; ++i) {
-            const unsigned src = nb.at(-L::cx(i), -L::cy(i), -L::cz(i));
-            float off = 0.f;
-            if constexpr (Codec<S>::kLocal) off = rest_offset(dm.ds, L::shell(i), ldo(eqa, src));
-            const R v = Codec<S>::dec(ldo(mv + (size_t)(i - 1) * St, src), dm.ds, L::shell(i), off);
-            racc += (double)v;
-            if (L::cx(i)) jx += R(L::cx(i)) * v;
-            if (L::cy(i)) jy += R(L::cy(i)) * v;
-            if (L::cz(i)) jz += R(L::cz(i)) * v;
+        for (int p = 0; p < L::NPAIR; ++p) {
+            const int ip = 2 * p + 1, im = 2 * p + 2, k = L::shell(ip);
+            // the antipodal pair (c, -c): its sum enters rho, its difference j0
+            const double vp = pulled(mv + (size_t)(ip - 1) * St, eqa, dm.ds, k,
+                                     nb.at(-L::cx(ip), -L::cy(ip), -L::cz(ip)));
+            const double vm = pulled(mv + (size_t)(im - 1) * St, eqa, dm.ds, k,
+                                     nb.at(-L::cx(im), -L::cy(im), -L::cz(im)));
+            racc += vp + vm;
+            const double dv = vp - vm;
+            if (L::cx(ip)) jx += L::cx(ip) * dv;
+            if (L::cy(ip)) jy += L::cy(ip) * dv;
+            if (L::cz(ip)) jz += L::cz(ip) * dv;
         }
         const R r = R(racc);
         sto(mass + o, i0, racc);
         sto(rho + o, i0, r);
-        sto(j0 + o, i0, jx);
-        sto(j0 + o + St, i0, jy);
-        if (L::D == 3) sto(j0 + o + 2 * St, i0, jz);
+        sto(j0 + o, i0, R(jx));
+        sto(j0 + o + St, i0, R(jy));
+        if (L::D == 3) sto(j0 + o + 2 * St, i0, R(jz));
         if (!(r > R(0) && r < R(1e30))) atomicOr(flags, 1);
         m[0] = racc; m[1] = jx; m[2] = jy; m[3] = jz;
     }
@@ -570,7 +605,7 @@ __global__ void __launch_bounds__(256) k_iter_q(const Domain* __restrict__ tab,
     R trG = R(0);
 #pragma unroll
     for (int a = 0; a < D; ++a) trG += G[a][a];
-    const R p = ldo(pf + o, nb.i0), P1 = ldo(pf + o + St, nb.i0);
+    const R p = R(dm.cf.pref) + ldo(pf + o, nb.i0), P1 = ldo(pf + o + St, nb.i0);
 #pragma unroll
     for (int a = 0; a < D; ++a)
 #pragma unroll
@@ -692,13 +727,18 @@ __global__ void k_check_done(IterCtl ic, int launched, int ndom, int* out)
 // Item 11 per velocity and item 12: pull n_i(r), collide with
 // Delta^bulk + Delta^int + Delta^corr and store n*_i(r) in the other buffer.
 // Velocities come in antipodal pairs; each pair shares its even part.
+// The deviation forms store n*_i - o_i: with n*_i = g n_i + (1-g) n_eq_i +
+// Delta_i, that is g (n_i - o_i) + (1-g) (w_k rho - o_i) + (1-g) w_k rho
+// (u.c/c_s^2 + ...) + Delta_i, whose O(1) part (1-g)(w_k rho - o_i) is formed
+// in FP64 once per shell, so the stored deviation carries no rounding of
+// the O(1) equilibrium.
 // ---------------------------------------------------------------------------
 template <int Q, class R, class S, bool ANY_PULL>
 __global__ void __launch_bounds__(256) k_collide(const Domain* __restrict__ tab,
                                                  const Tile* __restrict__ tiles,
                                                  const SolveInfo* __restrict__ info,
                                                  const S* __restrict__ A, S* __restrict__ B,
-                                                 const R* __restrict__ rho, const R* __restrict__ u,
+                                                 const R* __restrict__ u,
                                                  const R* __restrict__ f, const R* __restrict__ jtA,
                                                  const R* __restrict__ jtB, const R* __restrict__ Sig,
                                                  const R* __restrict__ Xi, const double* __restrict__ mass)
@@ -706,6 +746,13 @@ __global__ void __launch_bounds__(256) k_collide(const Domain* __restrict__ tab,
     // multiply-adds fused only as written in each expression, so that both
     // instantiations round a gamma = 0 site identically
 #pragma clang fp contract(on)
+    // The collision computes in FP64 whatever the field precision: at an
+    // interface Xi' and Sigma are large next to the flow (Xi' holds
+    // p d(c_s^2), of order 1e-2 where u is 1e-4), and their Hermite terms
+    // leave no first moment only in exact arithmetic; FP32 rounding of those
+    // terms feeds the momentum of every step.  The arithmetic is a few
+    // percent of this memory-bound kernel's time.
+    using E = double;
     using L = Lattice<Q>;
     constexpr int D = L::D;
     const Where w = locate(tab, tiles);
@@ -717,51 +764,52 @@ __global__ void __launch_bounds__(256) k_collide(const Domain* __restrict__ tab,
     const unsigned i0 = nb.i0;
     const R* jt = (info[w.dom].final_buf ? jtB : jtA) + o;
 
-    const R r = ldo(rho + o, i0);
-    R us[3] = {R(0), R(0), R(0)}, fs[3] = {R(0), R(0), R(0)}, js[3] = {R(0), R(0), R(0)};
+    const double r64 = ldo(mass + o, i0);   // the exact pulled mass of item 1
+    const E r = E(r64);
+    E us[3] = {E(0), E(0), E(0)}, fs[3] = {E(0), E(0), E(0)}, js[3] = {E(0), E(0), E(0)};
 #pragma unroll
     for (int a = 0; a < D; ++a) {
         us[a] = ldo(u + o + a * St, i0);
         fs[a] = ldo(f + o + a * St, i0);
         js[a] = ldo(jt + a * St, i0);
     }
-    R Sg[6], Xp[10];
+    E Sg[6], Xp[10];
 #pragma unroll
     for (int k = 0; k < L::NSIG; ++k) Sg[k] = ldo(Sig + o + k * St, i0);
 #pragma unroll
     for (int k = 0; k < L::NXI; ++k) Xp[k] = ldo(Xi + o + k * St, i0);
 
-    const R gm = R(dm.cf.gamma);
-    const R c0 = R(dm.cf.c0sq);
-    const R ic0 = R(1) / c0;
+    const E gm = E(dm.cf.gamma);
+    const E c0 = E(dm.cf.c0sq);
+    const E ic0 = E(1) / c0;
     // n_eq pieces (local weights)
-    const R cs2 = eos_cs2<R>(dm.cf.eos, r);
-    R wl[8];
-    shell_weights<Q, R>(cs2, wl);
-    const R ics = R(1) / cs2;
-    const R uu = us[0] * us[0] + us[1] * us[1] + us[2] * us[2];
-    const R a0 = R(1) - R(0.5) * uu * ics;
-    const R a1 = ics;
-    const R a2 = R(0.5) * ics * ics;
-    const R omg = R(1) - gm;  // weight of n_eq
+    const E cs2 = eos_cs2<E>(dm.cf.eos, r);
+    E wl[8];
+    shell_weights<Q, E>(cs2, wl);
+    const E ics = E(1) / cs2;
+    const E uu = us[0] * us[0] + us[1] * us[1] + us[2] * us[2];
+    const E a0m = -E(0.5) * uu * ics;   // a0 - 1
+    const E a1 = ics;
+    const E a2 = E(0.5) * ics * ics;
+    const E omg = E(1) - gm;  // weight of n_eq
 #pragma unroll
     for (int k = 0; k < L::NSHELL; ++k) wl[k] *= omg * r;
     // Delta^corr pieces: W_k [ b.c + c.S'.c + s0 + X'(c,c,c) ]
-    R trS = R(0);
+    E trS = E(0);
 #pragma unroll
     for (int a = 0; a < D; ++a) trS += Sg[a];
-    R v[3] = {R(0), R(0), R(0)};   // v_g = sum_a Xi'_aag
+    E v[3] = {E(0), E(0), E(0)};   // v_g = sum_a Xi'_aag
 #pragma unroll
     for (int gg = 0; gg < D; ++gg)
 #pragma unroll
         for (int a = 0; a < D; ++a) v[gg] += Xp[sym3<D>(a, a, gg)];
-    const R kS = R(0.5) * ic0 * ic0;
-    const R kX = ic0 * ic0 * ic0 / R(6);
-    R bvec[3];
+    const E kS = E(0.5) * ic0 * ic0;
+    const E kX = ic0 * ic0 * ic0 / E(6);
+    E bvec[3];
 #pragma unroll
     for (int a = 0; a < D; ++a)
-        bvec[a] = R(0.5) * (R(1) + gm) * ic0 * fs[a] + (gm - R(1)) * ic0 * js[a] - R(0.5) * ic0 * ic0 * v[a];
-    const R s0 = -R(0.5) * ic0 * trS;
+        bvec[a] = E(0.5) * (E(1) + gm) * ic0 * fs[a] + (gm - E(1)) * ic0 * js[a] - E(0.5) * ic0 * ic0 * v[a];
+    const E s0 = -E(0.5) * ic0 * trS;
 
     // Moving velocities first; the rest population then takes what the
     // collision invariant sum_i Delta_i = 0 (Sec. VI) leaves for it,
@@ -770,79 +818,96 @@ __global__ void __launch_bounds__(256) k_collide(const Domain* __restrict__ tab,
     // gamma = 0 the bulk operator relaxes fully: n*_i = n_eq_i + Delta^int_i
     // + Delta^corr_i does not depend on n_i, the pulled populations are not
     // read at all, and the mass balance uses the exact pulled mass of item 1.
-    // Otherwise n_i is pulled and n*_0 = n_0 - sum_{i>0} (n*_i - n_i) (small
-    // differences, rounded far below the populations themselves).
-    // uniform per block; instantiated without the pulling path when no
-    // domain of the launch has gamma != 0
+    // Otherwise n_i is pulled and n*_0 = n_0 - sum_{i>0} (n*_i - n_i).
+    // Uniform per block; instantiated without the pulling path when no
+    // domain of the launch has gamma != 0.
     const bool pull = ANY_PULL && dm.cf.gamma != 0.0;
     const S* const amv = moving_planes(A, St) + o;
     S* const bmv = moving_planes(B, St) + o;
     const _Float16* const eqa = eq_plane(A, St) + o;
-    // this site's record for the values it writes, and their rest offsets
+    // Per shell: the offset of the values this site writes (its own record)
+    // and the O(1) part of what it stores, (1-g)(w_k rho - o_k), which is
+    // small only as a difference of two O(1) FP64 numbers
     float ownoff[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    E rest[8];
+    double moved = 0.0;   // no pull: sum of n*_i (exact in FP64)
     if constexpr (Codec<S>::kLocal) {
-        const _Float16 rec = density_record(dm.ds, float(r));
+        const _Float16 rec = density_record(dm.ds, float(r64));
         sto(eq_plane(B, St) + o, i0, rec);
 #pragma unroll
-        for (int k = 1; k < L::NSHELL; ++k) ownoff[k] = rest_offset(dm.ds, k, rec);
+        for (int k = 1; k < L::NSHELL; ++k) {
+            ownoff[k] = rest_offset(dm.ds, k, rec);
+            rest[k] = wl[k] - omg * E(ownoff[k]);
+            moved += (double)kShellSize<Q>(k) * (double)ownoff[k];
+        }
+    } else {
+#pragma unroll
+        for (int k = 1; k < L::NSHELL; ++k) rest[k] = wl[k];
     }
-    R dsum = R(0);        // pull: sum of (n*_i - n_i)
-    double moved = 0.0;   // no pull: sum of n*_i (exact in FP64)
+    double dsum = 0.0;   // pull: sum of (n*_i - n_i)
 #pragma unroll
     for (int p = 0; p < L::NPAIR; ++p) {
         const int ip = 2 * p + 1, im = 2 * p + 2;
         const int cxv = L::cx(ip), cyv = L::cy(ip), czv = L::cz(ip);
         const int k = L::shell(ip);
-        const R cx = R(cxv), cy = R(cyv), cz = R(czv);
-        const R uc = us[0] * cx + us[1] * cy + us[2] * cz;
+        const E cx = E(cxv), cy = E(cyv), cz = E(czv);
+        const E uc = us[0] * cx + us[1] * cy + us[2] * cz;
         // c.Sigma.c
-        R cSc = Sg[0] * cx * cx + Sg[1] * cy * cy;
+        E cSc = Sg[0] * cx * cx + Sg[1] * cy * cy;
         if (D == 3) {
-            cSc += Sg[2] * cz * cz + R(2) * (Sg[3] * cx * cy + Sg[4] * cx * cz + Sg[5] * cy * cz);
+            cSc += Sg[2] * cz * cz + E(2) * (Sg[3] * cx * cy + Sg[4] * cx * cz + Sg[5] * cy * cz);
         } else {
-            cSc += R(2) * Sg[2] * cx * cy;
+            cSc += E(2) * Sg[2] * cx * cy;
         }
         // Xi'(c,c,c)
-        R cXc;
+        E cXc;
         if (D == 3) {
             cXc = Xp[0] * cx * cx * cx + Xp[1] * cy * cy * cy + Xp[2] * cz * cz * cz +
-                  R(3) * (Xp[3] * cx * cx * cy + Xp[4] * cx * cx * cz + Xp[5] * cx * cy * cy +
+                  E(3) * (Xp[3] * cx * cx * cy + Xp[4] * cx * cx * cz + Xp[5] * cx * cy * cy +
                           Xp[6] * cx * cz * cz + Xp[7] * cy * cy * cz + Xp[8] * cy * cz * cz) +
-                  R(6) * Xp[9] * cx * cy * cz;
+                  E(6) * Xp[9] * cx * cy * cz;
         } else {
             cXc = Xp[0] * cx * cx * cx + Xp[1] * cy * cy * cy +
-                  R(3) * (Xp[2] * cx * cx * cy + Xp[3] * cx * cy * cy);
+                  E(3) * (Xp[2] * cx * cx * cy + Xp[3] * cx * cy * cy);
         }
-        const R bc = bvec[0] * cx + bvec[1] * cy + (D == 3 ? bvec[2] * cz : R(0));
-        const R Wk = R(dm.cf.Wk[k]);
-        const R even = wl[k] * (a0 + a2 * uc * uc) + Wk * (kS * cSc + s0);
-        const R odd = wl[k] * a1 * uc + Wk * (bc + kX * cXc);
-        R np = R(0), nm = R(0);
+        const E bc = bvec[0] * cx + bvec[1] * cy + (D == 3 ? bvec[2] * cz : E(0));
+        const E Wk = E(dm.cf.Wk[k]);
+        const E even = rest[k] + wl[k] * (a0m + a2 * uc * uc) + Wk * (kS * cSc + s0);
+        const E odd = wl[k] * a1 * uc + Wk * (bc + kX * cXc);
+        // pulled n_i relative to this site's offset (the value itself for
+        // FP64 storage), and its exact FP64 form for the mass balance
+        E np = E(0), nm = E(0);
+        double npx = 0.0, nmx = 0.0;
         if (pull) {
             const unsigned sp = nb.at(-cxv, -cyv, -czv), sm = nb.at(cxv, cyv, czv);
-            float offp = 0.f, offm = 0.f;
+            const S bp = ldo(amv + (size_t)(ip - 1) * St, sp), bm = ldo(amv + (size_t)(im - 1) * St, sm);
             if constexpr (Codec<S>::kLocal) {
-                offp = rest_offset(dm.ds, k, ldo(eqa, sp));
-                offm = rest_offset(dm.ds, k, ldo(eqa, sm));
+                const double dp0 = (double)rest_offset(dm.ds, k, ldo(eqa, sp)) - (double)ownoff[k];
+                const double dm0 = (double)rest_offset(dm.ds, k, ldo(eqa, sm)) - (double)ownoff[k];
+                npx = dp0 + (double)Codec<S>::dev(bp, dm.ds, k);
+                nmx = dm0 + (double)Codec<S>::dev(bm, dm.ds, k);
+            } else {
+                npx = (double)bp;
+                nmx = (double)bm;
             }
-            np = Codec<S>::dec(ldo(amv + (size_t)(ip - 1) * St, sp), dm.ds, k, offp);
-            nm = Codec<S>::dec(ldo(amv + (size_t)(im - 1) * St, sm), dm.ds, k, offm);
+            np = E(npx);
+            nm = E(nmx);
         }
-        const S ep = Codec<S>::enc(gm * np + even + odd, dm.ds, k, ownoff[k]);
-        const S em = Codec<S>::enc(gm * nm + even - odd, dm.ds, k, ownoff[k]);
+        const S ep = Codec<S>::put(gm * np + even + odd, dm.ds, k);
+        const S em = Codec<S>::put(gm * nm + even - odd, dm.ds, k);
         sto(bmv + (size_t)(ip - 1) * St, i0, ep);
         sto(bmv + (size_t)(im - 1) * St, i0, em);
-        const R dp = Codec<S>::dec(ep, dm.ds, k, ownoff[k]), dmm = Codec<S>::dec(em, dm.ds, k, ownoff[k]);
+        const double dp = (double)Codec<S>::dev(ep, dm.ds, k), dmm = (double)Codec<S>::dev(em, dm.ds, k);
         if (pull)
-            dsum += (dp - np) + (dmm - nm);
+            dsum += (dp - npx) + (dmm - nmx);
         else
-            moved += (double)dp + (double)dmm;
+            moved += dp + dmm;
     }
     using T0 = typename RestOf<S>::T;
     if (pull)
-        sto(rest_plane(B) + o, i0, ldo(rest_plane(A) + o, i0) - T0(dsum));
+        sto(rest_plane(B) + o, i0, T0((double)ldo(rest_plane(A) + o, i0) - dsum));
     else
-        sto(rest_plane(B) + o, i0, T0(ldo(mass + o, i0) - moved));
+        sto(rest_plane(B) + o, i0, T0(r64 - moved));
 }
 
 // Pre-collision populations of the current state as FP64 [Q][S].
@@ -863,13 +928,9 @@ __global__ void __launch_bounds__(256) k_export(const Domain* __restrict__ tab,
     const _Float16* const eqa = eq_plane(A, St) + o;
     sto(out + o, i0, (double)ldo(rest_plane(A) + o, i0));
 #pragma unroll
-    for (int i = 1; i < Q; ++i) {
-        const unsigned src = nb.at(-L::cx(i), -L::cy(i), -L::cz(i));
-        float off = 0.f;
-        if constexpr (Codec<S>::kLocal) off = rest_offset(dm.ds, L::shell(i), ldo(eqa, src));
-        sto(out + o + (size_t)i * St, i0, (double)Codec<S>::dec(ldo(mv + (size_t)(i - 1) * St, src), dm.ds,
-                                                                L::shell(i), off));
-    }
+    for (int i = 1; i < Q; ++i)
+        sto(out + o + (size_t)i * St, i0,
+            pulled(mv + (size_t)(i - 1) * St, eqa, dm.ds, L::shell(i), nb.at(-L::cx(i), -L::cy(i), -L::cz(i))));
 }
 
 template <int Q, class S>
@@ -885,7 +946,6 @@ __global__ void __launch_bounds__(256) k_import(const Domain* __restrict__ tab,
     const long long o = dm.off, St = g.S;
     const NbP nb = make_nbp(g, w.x, w.y, w.z);
     const unsigned i0 = nb.i0;
-    using RT = decltype(Codec<S>::dec(S(), dm.ds, 0, 0.f));
     S* const mv = moving_planes(A, St) + o;
     sto(rest_plane(A) + o, i0, (typename RestOf<S>::T)ldo(in + o, i0));
     // no density is at hand for the slots: every record is the reference
@@ -894,10 +954,13 @@ __global__ void __launch_bounds__(256) k_import(const Domain* __restrict__ tab,
     if constexpr (Codec<S>::kLocal) sto(eq_plane(A, St) + o, i0, eref);
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-        float off = 0.f;
-        if constexpr (Codec<S>::kLocal) off = rest_offset(dm.ds, L::shell(i), eref);
-        sto(mv + (size_t)(i - 1) * St, nb.at(-L::cx(i), -L::cy(i), -L::cz(i)),
-            Codec<S>::enc((RT)ldo(in + o + (size_t)i * St, i0), dm.ds, L::shell(i), off));
+        const double v = ldo(in + o + (size_t)i * St, i0);
+        S e;
+        if constexpr (Codec<S>::kLocal)
+            e = Codec<S>::put(v - (double)rest_offset(dm.ds, L::shell(i), eref), dm.ds, L::shell(i));
+        else
+            e = Codec<S>::put(S(v), dm.ds, L::shell(i));
+        sto(mv + (size_t)(i - 1) * St, nb.at(-L::cx(i), -L::cy(i), -L::cz(i)), e);
     }
 }
 

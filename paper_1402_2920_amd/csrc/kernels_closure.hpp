@@ -18,6 +18,23 @@
 
 namespace lb2p {
 
+// The per-step planes of one site (item 1's EOS, fixed during the solve):
+// [0] p - p_ref, [1] P1 = p - rho p', [2] 1/rho, [3] c_s^2 - c_s^2(rho_ref).
+// p and c_s^2 are evaluated in FP64 from the FP64 density and kept as
+// deviations from their reference values: the closure differentiates them,
+// and their deviations carry the field precision of their own size.  P1 and
+// 1/rho only scale other terms.
+template <class R>
+__device__ __forceinline__ void store_step_planes(const Coef& cf, R* at, long long St, double r64, R r, R inv)
+{
+    const double cs2 = eos_cs2<double>(cf.eos, r64);
+    const R psi = eos_psi<R>(cf.eos, r);
+    at[0] = R(r64 * cs2 - cf.pref);
+    at[St] = -r * r * R(cs2) * psi;
+    at[2 * St] = inv;
+    at[3 * St] = R(cs2 - cf.cref);
+}
+
 // Inputs of one z step.
 template <class R>
 struct C2In {
@@ -241,9 +258,9 @@ k_closure2_zm(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, co
 // same order as the 2D k_closure1_t2).
 template <class R>
 struct C1In {
-    R lead[5];    // own point, lead plane c+2: ux, uy, uz, p, 1/rho
-    R own[5];     // own point, centre plane: P1, then rho and j0' (form) or j~
-    R fr[5];      // frame point, centre plane: ux, uy, uz, p, 1/rho
+    R lead[5];    // own point, lead plane c+2: ux, uy, uz, p - p_ref, c_s^2 - c_s^2_ref
+    R own[6];     // own point, centre plane: P1, then rho and j0' (form) or j~, then 1/rho
+    R fr[5];      // frame point, centre plane: ux, uy, uz, p - p_ref, c_s^2 - c_s^2_ref
 };
 
 template <class R, int TX, int TY>
@@ -277,9 +294,11 @@ k_closure1_zm(const Domain* __restrict__ tab, const Tile* __restrict__ tiles,
     R* const jt = odd ? jtB : jtA;
     const R* const u = (form && odd) ? u1 : u0;
     const PlaneBuf bU[3] = {plane_buf(u + o, bytes), plane_buf(u + o + N, bytes), plane_buf(u + o + 2 * N, bytes)};
-    const PlaneBuf bP = plane_buf(pf + o, bytes);
+    const PlaneBuf bP = plane_buf(pf + o, bytes);             // p - p_ref
     const PlaneBuf bP1 = plane_buf(pf + o + N, bytes);
     const PlaneBuf bRi = plane_buf(pf + o + 2 * N, bytes);
+    const PlaneBuf bC = plane_buf(pf + o + 3 * N, bytes);     // c_s^2 - c_s^2_ref
+    const R pref = R(dm.cf.pref);
     const PlaneBuf bJ[3] = {plane_buf(jt + o, bytes), plane_buf(jt + o + N, bytes), plane_buf(jt + o + 2 * N, bytes)};
     const PlaneBuf bRho = plane_buf(rho + o, bytes);
     const PlaneBuf bJ0[3] = {plane_buf(j0p + o, bytes), plane_buf(j0p + o + N, bytes),
@@ -324,7 +343,7 @@ k_closure1_zm(const Domain* __restrict__ tab, const Tile* __restrict__ tiles,
 #pragma unroll
         for (int b = 0; b < 3; ++b) in.lead[b] = bload<R>(bU[b], i);
         in.lead[3] = bload<R>(bP, i);
-        in.lead[4] = bload<R>(bRi, i);
+        in.lead[4] = bload<R>(bC, i);
     };
     auto load_centre = [&](int k, C1In<R>& in) {
         const bool live = k >= 4 && k < nsteps;
@@ -340,19 +359,22 @@ k_closure1_zm(const Domain* __restrict__ tab, const Tile* __restrict__ tiles,
             for (int b = 0; b < 3; ++b) in.own[1 + b] = bload<R>(bJ[b], i);
             in.own[4] = R(0);
         }
+        in.own[5] = bload<R>(bRi, i);
         const unsigned f = live && has_frame ? (fcol + zc) * (unsigned)sizeof(R) : OUT;
 #pragma unroll
         for (int b = 0; b < 3; ++b) in.fr[b] = bload<R>(bU[b], f);
         in.fr[3] = bload<R>(bP, f);
-        in.fr[4] = bload<R>(bRi, f);
+        in.fr[4] = bload<R>(bC, f);
     };
-    // planar LDS fields of one point
-    auto put = [&](int py, int px, R ux, R uy, R uz, R p, R ri) {
+    // planar LDS fields of one point (pd = p - p_ref, cd = c_s^2 - c_s^2_ref:
+    // first derivatives of p and p/rho are those of the deviations)
+    auto put = [&](int py, int px, R ux, R uy, R uz, R pd, R cd) {
+        const R p = pref + pd;
         sl[0][py][px] = ux;
         sl[1][py][px] = uy;
         sl[2][py][px] = uz;
-        sl[3][py][px] = p;
-        sl[4][py][px] = p * ri;
+        sl[3][py][px] = pd;
+        sl[4][py][px] = cd;
         sl[5][py][px] = p * ux * ux;
         sl[6][py][px] = p * ux * uy;
         sl[7][py][px] = p * ux * uz;
@@ -361,7 +383,7 @@ k_closure1_zm(const Domain* __restrict__ tab, const Tile* __restrict__ tiles,
         sl[10][py][px] = p * uz * uz;
     };
 
-    R rg[5][5];   // ux, uy, uz, p, 1/rho at planes c-2 .. c+2
+    R rg[5][5];   // ux, uy, uz, p - p_ref, c_s^2 - c_s^2_ref at planes c-2 .. c+2
 #pragma unroll
     for (int s = 0; s < 5; ++s)
 #pragma unroll
@@ -385,7 +407,7 @@ k_closure1_zm(const Domain* __restrict__ tab, const Tile* __restrict__ tiles,
         put(ly + 2, lx + 2, rg[2][0], rg[2][1], rg[2][2], rg[2][3], rg[2][4]);
         if (has_frame) put(fy, fx, in.fr[0], in.fr[1], in.fr[2], in.fr[3], in.fr[4]);
         // the centre-plane inputs of the next step load while this one computes
-        const R own[5] = {in.own[0], in.own[1], in.own[2], in.own[3], in.own[4]};
+        const R own[6] = {in.own[0], in.own[1], in.own[2], in.own[3], in.own[4], in.own[5]};
         load_centre(k + 1, in);
         __syncthreads();
         const bool out = owned && k >= 4 && z0 + k - 4 < nz;
@@ -401,8 +423,8 @@ k_closure1_zm(const Domain* __restrict__ tab, const Tile* __restrict__ tiles,
             // z derivatives from the ring; products formed per plane (items 9-10)
             auto dzr = [&](int f) { return d1<R>(rg[0][f], rg[1][f], rg[3][f], rg[4][f]); };
             auto dzm = [&](int b, int c) {
-                return d1<R>(rg[0][3] * rg[0][b] * rg[0][c], rg[1][3] * rg[1][b] * rg[1][c],
-                             rg[3][3] * rg[3][b] * rg[3][c], rg[4][3] * rg[4][b] * rg[4][c]);
+                return d1<R>((pref + rg[0][3]) * rg[0][b] * rg[0][c], (pref + rg[1][3]) * rg[1][b] * rg[1][c],
+                             (pref + rg[3][3]) * rg[3][b] * rg[3][c], (pref + rg[4][3]) * rg[4][b] * rg[4][c]);
             };
             R G[3][3];      // d_a u_b
             R M[3][3][3];   // d_a (p u_b u_c)
@@ -414,8 +436,7 @@ k_closure1_zm(const Domain* __restrict__ tab, const Tile* __restrict__ tiles,
                 G[2][b] = dzr(b);
             }
             Pg[0] = dxl(3); Pg[1] = dyl(3); Pg[2] = dzr(3);
-            C[0] = dxl(4); C[1] = dyl(4);
-            C[2] = d1<R>(rg[0][3] * rg[0][4], rg[1][3] * rg[1][4], rg[3][3] * rg[3][4], rg[4][3] * rg[4][4]);
+            C[0] = dxl(4); C[1] = dyl(4); C[2] = dzr(4);
             constexpr int PI[3][3] = {{5, 6, 7}, {6, 8, 9}, {7, 9, 10}};
 #pragma unroll
             for (int b = 0; b < 3; ++b)
@@ -426,7 +447,7 @@ k_closure1_zm(const Domain* __restrict__ tab, const Tile* __restrict__ tiles,
                     M[1][b][c] = my; M[1][c][b] = my;
                     M[2][b][c] = mz; M[2][c][b] = mz;
                 }
-            const R ep = rg[2][3], inv = rg[2][4], eP1 = own[0];
+            const R ep = pref + rg[2][3], inv = own[5], eP1 = own[0];
             const R us[3] = {rg[2][0], rg[2][1], rg[2][2]};
             const R trG = G[0][0] + G[1][1] + G[2][2];
             oX = eP1 * trG;
@@ -495,14 +516,18 @@ k_closure1_zm(const Domain* __restrict__ tab, const Tile* __restrict__ tiles,
 template <class R, int TX, int TY>
 __global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 1)))
 k_force_zm(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, IterCtl ic,
-           const R* __restrict__ rho, const R* __restrict__ j0, R* __restrict__ f, R* __restrict__ j0p,
+           const double* __restrict__ mass, const R* __restrict__ j0, R* __restrict__ f, R* __restrict__ j0p,
            R* __restrict__ u, const R* jt_prevA, const R* jt_prevB, const SolveInfo* prev_info, R* jt0,
            R* __restrict__ pf, R* hist, R* hist2, int order)
 {
     constexpr int UX = TX + 4, UY = TY + 4;
     constexpr int NFRAME = UX * UY - TX * TY;
     static_assert(NFRAME <= TX * TY, "frame larger than the block");
-    __shared__ R sr[3][UY][UX];   // rho at planes (slot = plane mod 3)
+    // The stencil runs in FP64 on the FP64 mass of item 1: the force is a
+    // third derivative of a field of size 1 whose differences are small, so
+    // an FP32 rho (or its FP32 deviation) would leave rounding noise of the
+    // size of the force's own FP32 resolution in every step's momentum.
+    __shared__ double sr[3][UY][UX];   // rho at planes (slot = plane mod 3)
 
     const Tile tl = tiles[blockIdx.x];
     double amax = 0.0;
@@ -514,7 +539,8 @@ k_force_zm(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, IterC
         const unsigned bytes = (unsigned)dm.g.N * (unsigned)sizeof(R);
         const unsigned OUT = bytes;
         const long long o = dm.off;
-        const PlaneBuf bR = plane_buf(rho + o, bytes);
+        const unsigned mbytes = (unsigned)dm.g.N * 8u;
+        const PlaneBuf bM = plane_buf(mass + o, mbytes);
         const R* prev = nullptr;
         if (prev_info) prev = prev_info[tl.dom].final_buf ? jt_prevB : jt_prevA;
 
@@ -545,13 +571,13 @@ k_force_zm(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, IterC
         // c+1 = z0-3+k enters LDS, output at c = z0-4+k for 4 <= k < TZ+4.
         const int nsteps = TZ + 4;
         auto lead_off = [&](int k) {
-            return k < nsteps ? (col + plane * (unsigned)wrap3(z0 - 2 + k, nz)) * (unsigned)sizeof(R) : OUT;
+            return k < nsteps ? (col + plane * (unsigned)wrap3(z0 - 2 + k, nz)) * 8u : mbytes;
         };
         auto frame_off = [&](int k) {
             return has_frame && k >= 2 && k < nsteps
-                ? (fcol + plane * (unsigned)wrap3(z0 - 3 + k, nz)) * (unsigned)sizeof(R) : OUT;
+                ? (fcol + plane * (unsigned)wrap3(z0 - 3 + k, nz)) * 8u : mbytes;
         };
-        R rg[5] = {R(0), R(0), R(0), R(0), R(0)};   // the column's rho at c-2 .. c+2
+        double rg[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // the column's rho at c-2 .. c+2
         // own-point inputs of step k (j0 and the previous j~ at plane c),
         // loaded a step ahead like rho
         const PlaneBuf bJ0[3] = {plane_buf(j0 + o, bytes), plane_buf(j0 + o + N, bytes),
@@ -573,18 +599,17 @@ k_force_zm(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, IterC
                 np_[a] = bload<R>(bPv[a], ip);
             }
         };
-        R nlead = bload<R>(bR, lead_off(0));
-        R nfr = bload<R>(bR, frame_off(0));
+        double nlead = bload<double>(bM, lead_off(0));
+        double nfr = bload<double>(bM, frame_off(0));
         load_own(0);
-        const R kap = R(dm.cf.kappa);
         for (int k = 0; k < nsteps; ++k) {
 #pragma unroll
             for (int s = 0; s < 4; ++s) rg[s] = rg[s + 1];
             rg[4] = nlead;
-            const R fr = nfr;
+            const double fr = nfr;
             const R cj[3] = {nj[0], nj[1], nj[2]}, cp[3] = {np_[0], np_[1], np_[2]};
-            nlead = bload<R>(bR, lead_off(k + 1));
-            nfr = bload<R>(bR, frame_off(k + 1));
+            nlead = bload<double>(bM, lead_off(k + 1));
+            nfr = bload<double>(bM, frame_off(k + 1));
             load_own(k + 1);
             // plane c+1 = z0-3+k into its LDS slot
             const int slot = (k + 3) % 3;   // (z0 - 3 + k) mod 3 relative to z0: slots follow k
@@ -595,40 +620,36 @@ k_force_zm(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, IterC
             if (k >= 4 && owned && zc < nz) {
                 const int sc = (k + 2) % 3, sm = (k + 1) % 3, sp = slot;   // planes c, c-1, c+1
                 const int py = ly + 2, px = lx + 2;
-                auto RH = [&](int dx, int dy, int dz) -> R {
+                auto RH = [&](int dx, int dy, int dz) -> double {
                     if (dz == 0) return sr[sc][py + dy][px + dx];
                     if (dz == 1) return (dx == 0 && dy == 0) ? rg[3] : sr[sp][py + dy][px + dx];
                     if (dz == -1) return (dx == 0 && dy == 0) ? rg[1] : sr[sm][py + dy][px + dx];
                     return dz == 2 ? rg[4] : rg[0];
                 };
-                R fa[3];
+                double fa[3];
                 // (100): tau -3 ; (110): tau 1/2 ; (200): tau 1/4 (Table III)
-                fa[0] = R(-3) * (RH(1, 0, 0) - RH(-1, 0, 0)) +
-                        R(0.5) * (RH(1, 1, 0) + RH(1, -1, 0) + RH(1, 0, 1) + RH(1, 0, -1) -
-                                  RH(-1, 1, 0) - RH(-1, -1, 0) - RH(-1, 0, 1) - RH(-1, 0, -1)) +
-                        R(0.5) * (RH(2, 0, 0) - RH(-2, 0, 0));
-                fa[1] = R(-3) * (RH(0, 1, 0) - RH(0, -1, 0)) +
-                        R(0.5) * (RH(1, 1, 0) + RH(-1, 1, 0) + RH(0, 1, 1) + RH(0, 1, -1) -
-                                  RH(1, -1, 0) - RH(-1, -1, 0) - RH(0, -1, 1) - RH(0, -1, -1)) +
-                        R(0.5) * (RH(0, 2, 0) - RH(0, -2, 0));
-                fa[2] = R(-3) * (RH(0, 0, 1) - RH(0, 0, -1)) +
-                        R(0.5) * (RH(1, 0, 1) + RH(-1, 0, 1) + RH(0, 1, 1) + RH(0, -1, 1) -
-                                  RH(1, 0, -1) - RH(-1, 0, -1) - RH(0, 1, -1) - RH(0, -1, -1)) +
-                        R(0.5) * (RH(0, 0, 2) - RH(0, 0, -2));
-                const R r = rg[2];
-                const R kr = kap * r;
+                fa[0] = -3.0 * (RH(1, 0, 0) - RH(-1, 0, 0)) +
+                        0.5 * (RH(1, 1, 0) + RH(1, -1, 0) + RH(1, 0, 1) + RH(1, 0, -1) -
+                               RH(-1, 1, 0) - RH(-1, -1, 0) - RH(-1, 0, 1) - RH(-1, 0, -1)) +
+                        0.5 * (RH(2, 0, 0) - RH(-2, 0, 0));
+                fa[1] = -3.0 * (RH(0, 1, 0) - RH(0, -1, 0)) +
+                        0.5 * (RH(1, 1, 0) + RH(-1, 1, 0) + RH(0, 1, 1) + RH(0, 1, -1) -
+                               RH(1, -1, 0) - RH(-1, -1, 0) - RH(0, -1, 1) - RH(0, -1, -1)) +
+                        0.5 * (RH(0, 2, 0) - RH(0, -2, 0));
+                fa[2] = -3.0 * (RH(0, 0, 1) - RH(0, 0, -1)) +
+                        0.5 * (RH(1, 0, 1) + RH(-1, 0, 1) + RH(0, 1, 1) + RH(0, -1, 1) -
+                               RH(1, 0, -1) - RH(-1, 0, -1) - RH(0, 1, -1) - RH(0, -1, -1)) +
+                        0.5 * (RH(0, 0, 2) - RH(0, 0, -2));
+                const double r64 = rg[2];
+                const R r = R(r64);
+                const double kr = dm.cf.kappa * r64;
                 const R inv = R(1) / r;
                 const long long i0 = o + col + (long long)plane * zc;
-                {
-                    const EosVal<R> e = eos_all<R>(dm.cf.eos, r);
-                    pf[i0] = e.p;
-                    pf[i0 + N] = e.P1;
-                    pf[i0 + 2 * N] = inv;
-                }
+                store_step_planes<R>(dm.cf, pf + i0, N, r64, r, inv);
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
                     const long long ia = i0 + a * N;
-                    const R fv = kr * fa[a];
+                    const R fv = R(kr * fa[a]);
                     const R jp = cj[a] + R(0.5) * fv;
                     R jt = prev ? cp[a] : R(0);
                     if (hist) {
@@ -692,25 +713,26 @@ k_closure1_t2(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, co
 {
     constexpr int D = 2;
     constexpr int UX = TX + 4, UY = TY + 4;
-    __shared__ R sl[4][UY][UX];   // p, p/rho, ux, uy
+    __shared__ R sl[4][UY][UX];   // p - p_ref, c_s^2 - c_s^2_ref, ux, uy
 
     const Tile tl = tiles[blockIdx.x];
     if (tl.dom < 0) return;   // uniform per block
     const Domain& dm = tab[tl.dom];
     const int nx = dm.g.nx, ny = dm.g.ny;
     const long long o = dm.off, St = dm.g.S;
-    const R* const pp = pf + o;            // p
+    const R* const pp = pf + o;            // p - p_ref
     const R* const pri = pf + o + 2 * St;  // 1/rho
+    const R* const pc = pf + o + 3 * St;   // c_s^2 - c_s^2_ref
+    const R pref = R(dm.cf.pref);
     const bool odd = info[tl.dom].final_buf != 0;   // uniform per block
     // the final iterate; with odd && form, u0 is only written (own points)
     const R* const uo = (form && odd ? u1 : u0) + o;
     const int tid = threadIdx.x + TX * threadIdx.y;
     for (int k = tid; k < UX * UY; k += TX * TY) {
         const unsigned t = frame_site<UX>(k, tl.x0, tl.y0, nx, ny);
-        const R pv = ldo(pp, t);
         R* const sp = &sl[0][0][0] + k;
-        sp[0] = pv;
-        sp[UX * UY] = pv * ldo(pri, t);
+        sp[0] = ldo(pp, t);
+        sp[UX * UY] = ldo(pc, t);
         sp[2 * UX * UY] = ldo(uo, t);
         sp[3 * UX * UY] = ldo(uo + St, t);
     }
@@ -746,14 +768,14 @@ k_closure1_t2(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, co
             G[a][b] = d1<R>(uv[0][b], uv[1][b], uv[2][b], uv[3][b]);
 #pragma unroll
             for (int c = b; c < D; ++c) {
-                R m = d1<R>(pv[0] * uv[0][b] * uv[0][c], pv[1] * uv[1][b] * uv[1][c],
-                            pv[2] * uv[2][b] * uv[2][c], pv[3] * uv[3][b] * uv[3][c]);
+                R m = d1<R>((pref + pv[0]) * uv[0][b] * uv[0][c], (pref + pv[1]) * uv[1][b] * uv[1][c],
+                            (pref + pv[2]) * uv[2][b] * uv[2][c], (pref + pv[3]) * uv[3][b] * uv[3][c]);
                 M[a][b][c] = m;
                 M[a][c][b] = m;
             }
         }
     }
-    const R ep = sl[0][cy][cx], eP1 = ldo(pf + o + St, i0), inv = ldo(pri, i0);
+    const R ep = pref + sl[0][cy][cx], eP1 = ldo(pf + o + St, i0), inv = ldo(pri, i0);
     R us[3] = {sl[2][cy][cx], sl[3][cy][cx], R(0)};
     R trG = R(0);
 #pragma unroll
@@ -895,51 +917,46 @@ k_closure2_t2(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, co
 // the tile and a 2-wide frame; the rest is per site.
 template <class R, int TX, int TY>
 __global__ void __launch_bounds__(TX * TY)
-k_force_t2(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, IterCtl ic, const R* __restrict__ rho,
+k_force_t2(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, IterCtl ic, const double* __restrict__ mass,
            const R* __restrict__ j0, R* __restrict__ f, R* __restrict__ j0p, R* __restrict__ u,
            const R* jt_prevA, const R* jt_prevB, const SolveInfo* prev_info, R* jt0, R* __restrict__ pf,
            R* hist, R* hist2, int order)
 {
     constexpr int UX = TX + 4, UY = TY + 4;
-    __shared__ R sr[UY][UX];
+    __shared__ double sr[UY][UX];   // FP64 rho (the stencil runs in FP64, as in k_force_zm)
 
     const Tile tl = tiles[blockIdx.x];
     if (tl.dom < 0) return;   // uniform per block (padding: no slot)
     const Domain& dm = tab[tl.dom];
     const int nx = dm.g.nx, ny = dm.g.ny;
     const long long o = dm.off, St = dm.g.S;
-    const R* const rh = rho + o;
+    const double* const mh = mass + o;
     const int tid = threadIdx.x + TX * threadIdx.y;
     for (int k = tid; k < UX * UY; k += TX * TY)
-        (&sr[0][0])[k] = ldo(rh, frame_site<UX>(k, tl.x0, tl.y0, nx, ny));
+        (&sr[0][0])[k] = ldo(mh, frame_site<UX>(k, tl.x0, tl.y0, nx, ny));
     __syncthreads();
     double amax = 0.0;
     const int x = tl.x0 + (int)threadIdx.x, y = tl.y0 + (int)threadIdx.y;
     if (x < nx && y < ny) {
         const unsigned i0 = (unsigned)x + (unsigned)nx * (unsigned)y;
         const int cx = (int)threadIdx.x + 2, cy = (int)threadIdx.y + 2;
-        auto RH = [&](int dx, int dy) -> R { return sr[cy + dy][cx + dx]; };
-        const R r = RH(0, 0);
+        auto RH = [&](int dx, int dy) -> double { return sr[cy + dy][cx + dx]; };
+        const double r64 = RH(0, 0);
+        const R r = R(r64);
         // (10): tau -2 ; (11): tau 1/2 ; (20): tau 1/4
-        R fa[2];
-        fa[0] = R(-2) * (RH(1, 0) - RH(-1, 0)) + R(0.5) * (RH(1, 1) + RH(1, -1) - RH(-1, 1) - RH(-1, -1)) +
-                R(0.5) * (RH(2, 0) - RH(-2, 0));
-        fa[1] = R(-2) * (RH(0, 1) - RH(0, -1)) + R(0.5) * (RH(1, 1) + RH(-1, 1) - RH(1, -1) - RH(-1, -1)) +
-                R(0.5) * (RH(0, 2) - RH(0, -2));
-        const R kr = R(dm.cf.kappa) * r;
+        double fa[2];
+        fa[0] = -2.0 * (RH(1, 0) - RH(-1, 0)) + 0.5 * (RH(1, 1) + RH(1, -1) - RH(-1, 1) - RH(-1, -1)) +
+                0.5 * (RH(2, 0) - RH(-2, 0));
+        fa[1] = -2.0 * (RH(0, 1) - RH(0, -1)) + 0.5 * (RH(1, 1) + RH(-1, 1) - RH(1, -1) - RH(-1, -1)) +
+                0.5 * (RH(0, 2) - RH(0, -2));
+        const double kr = dm.cf.kappa * r64;
         const R inv = R(1) / r;
-        {
-            const EosVal<R> e = eos_all<R>(dm.cf.eos, r);
-            R* const pfo = pf + o;
-            sto(pfo, i0, e.p);
-            sto(pfo + St, i0, e.P1);
-            sto(pfo + 2 * St, i0, inv);
-        }
+        store_step_planes<R>(dm.cf, pf + o + i0, St, r64, r, inv);
         const R* prev = nullptr;
         if (prev_info) prev = prev_info[tl.dom].final_buf ? jt_prevB : jt_prevA;
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
-            const R fv = kr * fa[a];
+            const R fv = R(kr * fa[a]);
             const R jp = ldo(j0 + o + a * St, i0) + R(0.5) * fv;
             R jt = prev ? ldo(prev + o + a * St, i0) : R(0);
             if (hist) {

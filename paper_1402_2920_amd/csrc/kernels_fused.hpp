@@ -115,8 +115,9 @@ k_iter_fused3(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, It
     const long long N = dm.g.S;   // component stride
     const unsigned plane = (unsigned)nx * (unsigned)ny;
     const unsigned bytes = (unsigned)dm.g.N * (unsigned)sizeof(R);
-    const PlaneBuf bP = plane_buf(pf + dm.off, bytes);
+    const PlaneBuf bP = plane_buf(pf + dm.off, bytes);   // p - p_ref
     const PlaneBuf bP1 = plane_buf(pf + dm.off + N, bytes);
+    const R pref = R(dm.cf.pref);
     const PlaneBuf bRho = plane_buf(rho + dm.off, bytes);
     const PlaneBuf bJ[3] = {plane_buf(j0p + dm.off, bytes), plane_buf(j0p + dm.off + N, bytes),
                             plane_buf(j0p + dm.off + 2 * N, bytes)};
@@ -228,7 +229,7 @@ k_iter_fused3(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, It
     };
     auto load_pp = [&](int k, StepIn<R>& in) {
         const unsigned ic_ = (col + plane * (unsigned)wrap3(z0 - 6 + k, nz)) * (unsigned)sizeof(R);
-        in.p = bload<R>(bP, ic_);
+        in.p = pref + bload<R>(bP, ic_);
         in.P1 = bload<R>(bP1, ic_);
     };
 
@@ -361,8 +362,9 @@ k_iter_fused2(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, It
     const unsigned bytes = (unsigned)dm.g.N * (unsigned)sizeof(R);
     const unsigned OUT = bytes;
     const long long o = dm.off;
-    const PlaneBuf bP = plane_buf(pf + o, bytes);
+    const PlaneBuf bP = plane_buf(pf + o, bytes);   // p - p_ref
     const PlaneBuf bP1 = plane_buf(pf + o + N, bytes);
+    const R pref = R(dm.cf.pref);
     const PlaneBuf bRho = plane_buf(rho + o, bytes);
     const PlaneBuf bJ[2] = {plane_buf(j0p + o, bytes), plane_buf(j0p + o + N, bytes)};
     const PlaneBuf bU[2] = {plane_buf(u_old + o, bytes), plane_buf(u_old + o + N, bytes)};
@@ -439,7 +441,7 @@ k_iter_fused2(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, It
     R pp = R(0), pP1 = R(0);
     {
         const unsigned ip = r < 4 ? (gx + row_off(y0 - 2 + r)) * (unsigned)sizeof(R) : OUT;
-        pp = bload<R>(bP, ip);
+        pp = pref + bload<R>(bP, ip);
         pP1 = bload<R>(bP1, ip);
     }
     __syncthreads();
@@ -468,7 +470,7 @@ k_iter_fused2(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, It
             c.j[a] = bload<R>(bJ[a], io);
             c.v[a] = CHEB ? bload<R>(bV[a], it > 0 ? io : OUT) : R(0);
         }
-        c.p = bload<R>(bP, ip);
+        c.p = pref + bload<R>(bP, ip);
         c.P1 = bload<R>(bP1, ip);
         c.rho = bload<R>(bRho, io);
     };

@@ -189,6 +189,14 @@ __device__ __host__ inline R eos_cs2(const EosParams& e, R rho)
     return R(e.cs2_1);
 }
 
+// psi = A sin(pi (rho - rho1)/(rho2 - rho1)) on (rho1, rho3), zero outside.
+template <class R>
+__device__ __host__ inline R eos_psi(const EosParams& e, R rho)
+{
+    if (rho > R(e.rho1) && rho < R(e.rho3)) return R(e.A) * eos_sin<R>((rho - R(e.rho1)) * R(e.inv_delta_pi));
+    return R(0);
+}
+
 // c_s^2, p, dp/drho, p - rho dp/drho, rho d2p/drho2 (psi' jumps at the ends
 // of (rho1, rho3); outside the interval psi = psi' = 0).
 template <class R>

@@ -106,6 +106,9 @@ lb2p_status check_params(const lb2p_params& p)
     if (p.graph_steps < 0) return LB2P_EINVAL;
     if (p.solver != LB2P_SOLVER_FIXED_POINT && p.solver != LB2P_SOLVER_CHEBYSHEV) return LB2P_EINVAL;
     if (p.warm_start < 0 || p.warm_start > 3) return LB2P_EINVAL;
+    if (p.iter_prec != LB2P_ITER_AUTO && p.iter_prec != LB2P_ITER_F32 && p.iter_prec != LB2P_ITER_F64)
+        return LB2P_EINVAL;
+    if (p.storage == LB2P_STORE_F64 && p.iter_prec == LB2P_ITER_F32) return LB2P_EINVAL;
     if (!(p.spectral_bound >= 0.0 && p.spectral_bound < 1.0)) return LB2P_EINVAL;
     if (!(p.rho0 > 0.0)) return LB2P_EINVAL;
     if ((long long)p.nx * p.ny * p.nz > (1LL << 31)) return LB2P_EINVAL;
@@ -162,6 +165,15 @@ void set_devscale(DevScale& ds, int Q, const EosParams& eos, double rref, double
             hj *= h;
         }
     }
+}
+
+// c_s^2 and p at the domain's reference density (the per-step planes hold
+// deviations from them).
+void set_refs(Domain& dm)
+{
+    const double r = (double)dm.ds.rref;
+    dm.cf.cref = eos_cs2<double>(dm.cf.eos, r);
+    dm.cf.pref = r * dm.cf.cref;
 }
 
 // Upper bound of the spectrum of the j~ map's linear part,
@@ -550,7 +562,7 @@ struct Impl {
     static void launch_init(lb2p_ctx* c)
     {
         hipLaunchKernelGGL((k_init<Q, R, S>), sgrid(c), sblock(c), 0, c->stream, c->dtab,
-                           c->site_tiles, (const R*)c->rho, (const R*)c->u, (S*)c->A);
+                           c->site_tiles, (const double*)c->mass, (const R*)c->u, (S*)c->A);
     }
 
     static void launch_moments(lb2p_ctx* c, bool write_fields)
@@ -605,12 +617,12 @@ struct Impl {
                 constexpr int TX = fused_tx<R>();
                 hipLaunchKernelGGL((k_force_zm<R, TX, kFusedTY>), dim3((unsigned)c->clos_host.size()),
                                    dim3(TX, kFusedTY, 1), 0, c->stream, c->dtab, c->clos_tiles, ic,
-                                   (const R*)c->rho, (const R*)c->j0, (R*)c->f, (R*)c->j0p, (R*)c->u,
+                                   (const double*)c->mass, (const R*)c->j0, (R*)c->f, (R*)c->j0p, (R*)c->u,
                                    prevA, prevB, prev, jstart, (R*)c->pf, hist, hist2, order);
             } else {
                 hipLaunchKernelGGL((k_force_t2<R, kClos2TX, kClos2TY>), dim3((unsigned)c->clos_host.size()),
                                    dim3(kClos2TX, kClos2TY, 1), 0, c->stream, c->dtab, c->clos_tiles, ic,
-                                   (const R*)c->rho, (const R*)c->j0, (R*)c->f, (R*)c->j0p, (R*)c->u,
+                                   (const double*)c->mass, (const R*)c->j0, (R*)c->f, (R*)c->j0p, (R*)c->u,
                                    prevA, prevB, prev, jstart, (R*)c->pf, hist, hist2, order);
             }
             hipLaunchKernelGGL(k_reduce_max, dim3(c->ndom), dim3(256), 0, c->stream, (const double*)c->pmax,
@@ -766,7 +778,7 @@ struct Impl {
             auto kc = c->any_pull ? k_collide<Q, R, S, true> : k_collide<Q, R, S, false>;
             hipLaunchKernelGGL(kc, sgrid(c), sblock(c), 0, c->stream, c->dtab,
                                c->site_tiles, (const SolveInfo*)c->info, (const S*)c->A, (S*)c->B,
-                               (const R*)c->rho, (const R*)c->u, (const R*)c->f, (const R*)c->jt0,
+                               (const R*)c->u, (const R*)c->f, (const R*)c->jt0,
                                (const R*)c->jt1, (const R*)c->Sig, (const R*)c->Xi, (const double*)c->mass);
         }
         HIPCHK(hipGetLastError());
@@ -792,9 +804,15 @@ auto by_storage(lb2p_ctx* c, F&& fn)
 {
     switch (c->prm.storage) {
         case LB2P_STORE_F64: return fn(Impl<Q, double, double>{});
-        case LB2P_STORE_F32: return fn(Impl<Q, float, float>{});
-        case LB2P_STORE_BF16: return fn(Impl<Q, float, __bf16>{});
-        default: return fn(Impl<Q, float, _Float16>{});
+        case LB2P_STORE_F32:
+            if (c->rsize == 8) return fn(Impl<Q, double, float>{});
+            return fn(Impl<Q, float, float>{});
+        case LB2P_STORE_BF16:
+            if (c->rsize == 8) return fn(Impl<Q, double, __bf16>{});
+            return fn(Impl<Q, float, __bf16>{});
+        default:
+            if (c->rsize == 8) return fn(Impl<Q, double, _Float16>{});
+            return fn(Impl<Q, float, _Float16>{});
     }
 }
 
@@ -803,6 +821,21 @@ auto dispatch(lb2p_ctx* c, F&& fn)
 {
     if (c->Q == 59) return by_storage<59>(c, fn);
     return by_storage<21>(c, fn);
+}
+
+// Precision of the per-site fields, and with them of the j~ iteration:
+// FP64 with FP64 storage; otherwise FP32 unless iter_prec asks for FP64, or
+// leaves it to the library (AUTO) and the stop rule's tolerance is below
+// what the FP32 iteration can meet.  In the FP32 velocity-form iteration the
+// iterate u is an FP32 number, so |G(x_k) - x_k| = |G + j0' - rho u_k|
+// cannot fall much below the rounding of rho u next to max|j0'|
+// (measured: it stalls at tol 1e-7 on the slab workload, and tolerances
+// down to 2e-7 converge).
+size_t field_bytes(const lb2p_params& p)
+{
+    if (p.storage == LB2P_STORE_F64 || p.iter_prec == LB2P_ITER_F64) return 8;
+    if (p.iter_prec == LB2P_ITER_AUTO && p.fixed_iter <= 0 && p.tol < LB2P_F32_TOL_FLOOR) return 8;
+    return 4;
 }
 
 size_t storage_bytes(int storage)
@@ -875,6 +908,26 @@ lb2p_status copy_in(lb2p_ctx* c, const void* src, int ncomp, void* dst, int dtyp
     else
         hipLaunchKernelGGL((k_convert<double, float>), dim3((unsigned)nb), dim3(tb), 0, c->stream,
                            (const double*)tmp, (float*)dst, n);
+    HIPCHK(hipFreeAsync(tmp, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return LB2P_OK;
+}
+
+// Copy a caller buffer of n elements of dtype into an FP64 device array.
+lb2p_status copy_in_f64(lb2p_ctx* c, const void* src, long long n, double* dst, int dtype, int on_device)
+{
+    if (dtype == LB2P_DTYPE_F64) {
+        HIPCHK(hipMemcpyAsync(dst, src, n * 8, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                              c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        return LB2P_OK;
+    }
+    void* tmp = nullptr;
+    HIPCHK(hipMallocAsync(&tmp, n * 4, c->stream));
+    HIPCHK(hipMemcpyAsync(tmp, src, n * 4, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                          c->stream));
+    hipLaunchKernelGGL((k_convert<float, double>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream,
+                       (const float*)tmp, dst, n);
     HIPCHK(hipFreeAsync(tmp, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     return LB2P_OK;
@@ -970,7 +1023,7 @@ lb2p_status create_impl(int ndom, const lb2p_params* pp, void* hip_stream, lb2p_
         if (p.lattice != p0.lattice || p.storage != p0.storage || p.tol != p0.tol ||
             p.max_iter != p0.max_iter || p.fixed_iter != p0.fixed_iter ||
             p.warm_start != p0.warm_start || p.flags != p0.flags || p.graph_steps != p0.graph_steps ||
-            p.solver != p0.solver)
+            p.solver != p0.solver || p.iter_prec != p0.iter_prec)
             return LB2P_EINVAL;
     }
     load_tune_file();
@@ -983,7 +1036,7 @@ lb2p_status create_impl(int ndom, const lb2p_params* pp, void* hip_stream, lb2p_
     c->ndom = ndom;
     c->stream = (hipStream_t)hip_stream;
     c->elem = storage_bytes(p0.storage);
-    c->rsize = p0.storage == LB2P_STORE_F64 ? 8 : 4;
+    c->rsize = field_bytes(p0);
     long long off = 0;
     std::vector<double> cheb_rho;
     for (int d = 0; d < ndom; ++d) {
@@ -1015,6 +1068,7 @@ lb2p_status create_impl(int ndom, const lb2p_params* pp, void* hip_stream, lb2p_
         {
             const double r0 = p.store_rho_ref > 0.0 ? p.store_rho_ref : p.rho0;
             set_devscale(dm.ds, c->Q, dm.cf.eos, r0, 0.75 * r0, 1.25 * r0);
+            set_refs(dm);
         }
         {
             const double b = p.spectral_bound > 0.0 ? p.spectral_bound
@@ -1033,8 +1087,8 @@ lb2p_status create_impl(int ndom, const lb2p_params* pp, void* hip_stream, lb2p_
     const long long S = c->S;
     const int D = c->D;
     const int nsig = D == 3 ? 6 : 3, nxi = D == 3 ? 10 : 4;
-    // rho | j0 | f | j0p | u | jt0 | jt1 | q (alias T) | X | Y | Xi | Sig | pf (3) | u1
-    const int ncomp = 1 + 6 * D + nsig + 1 + D + nxi + nsig + 3 + D;
+    // rho | j0 | f | j0p | u | jt0 | jt1 | q (alias T) | X | Y | Xi | Sig | pf (4) | u1
+    const int ncomp = 1 + 6 * D + nsig + 1 + D + nxi + nsig + 4 + D;
     {
         long long mo = 0;
         switch (p0.storage) {
@@ -1073,7 +1127,7 @@ lb2p_status create_impl(int ndom, const lb2p_params* pp, void* hip_stream, lb2p_
     auto take = [&](int nc) { void* ptr = fb + foff * c->rsize; foff += (size_t)nc * S; return ptr; };
     c->rho = take(1); c->j0 = take(D); c->f = take(D); c->j0p = take(D); c->u = take(D);
     c->jt0 = take(D); c->jt1 = take(D); c->q = take(nsig); c->T = c->q;
-    c->X = take(1); c->Y = take(D); c->Xi = take(nxi); c->Sig = take(nsig); c->pf = take(3); c->u1 = take(D);
+    c->X = take(1); c->Y = take(D); c->Xi = take(nxi); c->Sig = take(nsig); c->pf = take(4); c->u1 = take(D);
     char* sb = (char*)c->ctl;
     c->flags = (int*)(sb + 0);
     c->nconv = (int*)(sb + 4);
@@ -1240,7 +1294,7 @@ lb2p_status lb2p_default_params(int lattice, int nx, int ny, int nz, int storage
     p.kappa = 0.0;
     p.eos.rho1 = 0.3; p.eos.rho2 = 1.0; p.eos.A = 0.0; p.eos.cs2_rho1 = 0.45;
     p.rho0 = 0.3;
-    p.tol = storage == LB2P_STORE_F64 ? 1e-13 : 1e-6;
+    p.tol = storage == LB2P_STORE_F64 ? 1e-13 : 4e-7;
     p.max_iter = 200;
     p.fixed_iter = 0;
     p.warm_start = 1;
@@ -1250,6 +1304,7 @@ lb2p_status lb2p_default_params(int lattice, int nx, int ny, int nz, int storage
     p.graph_steps = 0;
     p.solver = LB2P_SOLVER_FIXED_POINT;
     p.spectral_bound = 0.0;
+    p.iter_prec = LB2P_ITER_AUTO;
     *out = p;
     return LB2P_OK;
 }
@@ -1275,7 +1330,9 @@ lb2p_status lb2p_init(lb2p_ctx* c, const void* rho, const void* u, int dtype, in
 {
     if (!c || !rho || !u) return LB2P_EINVAL;
     if (dtype != LB2P_DTYPE_F64 && dtype != LB2P_DTYPE_F32) return LB2P_EINVAL;
-    lb2p_status st = copy_in(c, rho, 1, c->rho, dtype, on_device);
+    // the density goes to the FP64 mass plane (the initial populations are
+    // evaluated from it in FP64) and, rounded, to the rho field
+    lb2p_status st = copy_in_f64(c, rho, c->S, c->mass, dtype, on_device);
     if (st != LB2P_OK) return st;
     st = copy_in(c, u, c->D, c->u, dtype, on_device);
     if (st != LB2P_OK) return st;
@@ -1283,21 +1340,23 @@ lb2p_status lb2p_init(lb2p_ctx* c, const void* rho, const void* u, int dtype, in
     // domain's mean initial density (host FP64 sum)
     // the density range of every domain (for the reduced-storage offsets)
     // and, where no reference density is given, its mean
-    const bool need_rho = c->prm.storage == LB2P_STORE_BF16 || c->prm.storage == LB2P_STORE_F16 ||
+    const bool need_rho = c->prm.storage != LB2P_STORE_F64 ||
                           std::any_of(c->dprm.begin(), c->dprm.end(),
                                       [](const lb2p_params& p) { return !(p.store_rho_ref > 0.0); });
+    {
+        const long long n = c->S;
+        const long long nb = (n + 255) / 256;
+        if (c->rsize == 8)
+            HIPCHK(hipMemcpyAsync(c->rho, c->mass, n * 8, hipMemcpyDeviceToDevice, c->stream));
+        else
+            hipLaunchKernelGGL((k_convert<double, float>), dim3((unsigned)nb), dim3(256), 0, c->stream,
+                               (const double*)c->mass, (float*)c->rho, n);
+    }
     std::vector<double> hrho;
     if (need_rho) {
         hrho.resize(c->S);
-        if (c->rsize == 8) {
-            HIPCHK(hipMemcpyAsync(hrho.data(), c->rho, c->S * 8, hipMemcpyDeviceToHost, c->stream));
-            HIPCHK(hipStreamSynchronize(c->stream));
-        } else {
-            std::vector<float> tmp(c->S);
-            HIPCHK(hipMemcpyAsync(tmp.data(), c->rho, c->S * 4, hipMemcpyDeviceToHost, c->stream));
-            HIPCHK(hipStreamSynchronize(c->stream));
-            for (long long k = 0; k < c->S; ++k) hrho[k] = tmp[k];
-        }
+        HIPCHK(hipMemcpyAsync(hrho.data(), c->mass, c->S * 8, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
     }
     for (int d = 0; d < c->ndom; ++d) {
         double rref = c->dprm[d].store_rho_ref;
@@ -1317,6 +1376,7 @@ lb2p_status lb2p_init(lb2p_ctx* c, const void* rho, const void* u, int dtype, in
             hi = mx + pad;
         }
         set_devscale(c->dom[d].ds, c->Q, c->dom[d].cf.eos, rref, lo, hi);
+        set_refs(c->dom[d]);
     }
     HIPCHK(hipMemcpyAsync(c->dtab, c->dom.data(), c->ndom * sizeof(Domain), hipMemcpyHostToDevice, c->stream));
     dispatch(c, [&](auto impl) { decltype(impl)::launch_init(c); });

@@ -25,6 +25,9 @@ DTYPE_F64, DTYPE_F32 = 0, 1
 FIELD_RHO, FIELD_J0, FIELD_FORCE, FIELD_JTILDE, FIELD_U, FIELD_SIGMA, FIELD_XI = range(7)
 FLAG_UNFUSED_SOLVE = 1
 SOLVER_FIXED_POINT, SOLVER_CHEBYSHEV = 0, 1
+ITER_AUTO, ITER_F32, ITER_F64 = 0, 1, 2
+F32_TOL_FLOOR = 2e-7
+F32_TOL_DEFAULT = 4e-7
 STORAGE_NAMES = {"f64": STORE_F64, "f32": STORE_F32, "bf16": STORE_BF16, "f16": STORE_F16}
 
 
@@ -47,7 +50,7 @@ class _Params(ctypes.Structure):
                 ("warm_start", ctypes.c_int), ("check_every", ctypes.c_int),
                 ("store_rho_ref", ctypes.c_double), ("flags", ctypes.c_int),
                 ("graph_steps", ctypes.c_int), ("solver", ctypes.c_int),
-                ("spectral_bound", ctypes.c_double)]
+                ("spectral_bound", ctypes.c_double), ("iter_prec", ctypes.c_int)]
 
 
 class _Stats(ctypes.Structure):
@@ -150,14 +153,15 @@ class Params:
     graph_steps: int = 0
     solver: int = SOLVER_FIXED_POINT
     spectral_bound: float = 0.0
+    iter_prec: int = ITER_AUTO
 
     def to_c(self) -> _Params:
-        tol = self.tol if self.tol is not None else (1e-13 if self.storage == STORE_F64 else 1e-6)
+        tol = self.tol if self.tol is not None else (1e-13 if self.storage == STORE_F64 else F32_TOL_DEFAULT)
         return _Params(self.lattice, self.nx, self.ny, self.nz, self.storage, self.gamma, self.kappa,
                        _Eos(self.rho1, self.rho2, self.A, self.cs2_rho1), self.rho0, tol,
                        self.max_iter, self.fixed_iter, self.warm_start, self.check_every,
                        self.store_rho_ref, self.flags, self.graph_steps, self.solver,
-                       self.spectral_bound)
+                       self.spectral_bound, self.iter_prec)
 
     @property
     def dim(self) -> int:

@@ -51,7 +51,8 @@ def test_default_params(L):
     st = L.lib().lb2p_default_params(59, 32, 32, 32, L.STORE_F32, ctypes.byref(prm))
     assert st == L.OK
     assert (prm.nx, prm.ny, prm.nz, prm.storage) == (32, 32, 32, L.STORE_F32)
-    assert prm.gamma == 0.0 and prm.tol == 1e-6 and prm.max_iter == 200 and prm.warm_start == 1
+    assert prm.gamma == 0.0 and prm.tol == 4e-7 and prm.max_iter == 200 and prm.warm_start == 1
+    assert prm.iter_prec == L.ITER_AUTO
     assert prm.eos.rho1 == 0.3 and prm.eos.rho2 == 1.0 and prm.rho0 == 0.3
     assert L.lib().lb2p_default_params(59, 8, 8, 8, L.STORE_F64, None) == L.EINVAL
 
@@ -82,6 +83,9 @@ def _p(L, **kw):
     (dict(cs2_rho1=float("nan")), "EINVAL"), (dict(rho1=1.2), "EINVAL"),
     (dict(warm_start=4), "EINVAL"), (dict(warm_start=-1), "EINVAL"),
     (dict(fixed_iter=-1), "EINVAL"), (dict(graph_steps=-1), "EINVAL"),
+    (dict(iter_prec=3), "EINVAL"), (dict(iter_prec=-1), "EINVAL"),
+    # FP64 storage computes in FP64: an FP32 iteration is not offered
+    (dict(storage=0, iter_prec=1), "EINVAL"),
 ])
 def test_create_rejects_bad_parameters(L, kw, status):
     assert L.create_status(_p(L, **kw)) == getattr(L, status)

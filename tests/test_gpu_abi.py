@@ -45,9 +45,12 @@ def test_set_populations_then_step_matches_oracle(orc, L, lattice, shape):
     assert e <= 1e-10
 
 
-def test_set_populations_f32_rounds_once(L):
-    """FP32 storage keeps each moving population to one FP32 rounding and
-    the rest population (FP64 plane) exactly."""
+def test_set_populations_f32_round_trip(L):
+    """FP32 storage keeps the rest population (FP64 plane) exactly and each
+    moving one as its deviation from the rest-equilibrium offset o_k of the
+    reference density's record (set_populations has no local density):
+    one FP32 rounding of (n - o_k)/W_k and one of the product W_k b, i.e.
+    |error| <= 2^-23 |n - o_k| with |o_k| <= w_1 rho_ref < 0.1 here."""
     rho, u, model = small_case(59, (20, 12, 10))
     rng = np.random.default_rng(5)
     with L.Context(_params(L, model, L.STORE_F32)) as ctx:
@@ -55,7 +58,7 @@ def test_set_populations_f32_rounds_once(L):
         ctx.set_populations(n)
         back = ctx.populations()
     assert np.array_equal(back[0], n[0])
-    assert np.array_equal(back[1:], n[1:].astype(np.float32).astype(np.float64))
+    assert np.abs(back[1:] - n[1:]).max() <= 2.0**-23 * 0.13
 
 
 def test_profiler_counts_launches(L):

@@ -1,11 +1,10 @@
 """GPU parity: the HIP library against the FP64 oracle on the same seeded
 inputs (small grids spanning several blocks with ragged edges).
 
-Per-field bar: FP64 path 1e-10 relative (max |G-O| / max |O|); FP32 path
-1e-5 relative for rho and the populations.  Derived FP32 fields (u, j~,
-Sigma, Xi') are differences of O(1) numbers and carry the FP32 rounding of
-their inputs amplified by the stencils; their bounds are stated per field
-below.
+Per-field bar (max |G-O| / max |O| over every component): FP64 path 1e-10;
+FP32 path (FP32 fields and iteration at the default tolerance 4e-7) 1e-5 for
+every compared field, the flow velocity u included; FP32 storage with FP64
+fields (iter_prec F64) 1e-6.
 """
 import numpy as np
 import pytest
@@ -71,14 +70,13 @@ def test_f64_matches_oracle(orc, L, name, lattice, shape, extra):
         assert v <= F64_TOL, (k, v)
 
 
-# FP32 bounds.  rho and the populations: 1e-5 (the FP32 target).  Fields
-# built by finite differences of FP32 inputs: the input rounding eps32*|g|
-# (eps32 = 6e-8) times the stencil gain (sum |tau| = 11 for the force stencil,
-# about 2 per first-derivative level) over the field's own scale, which is
-# 1e-2..1e-3 of |g| for these smooth inputs -> 1e-4..1e-3; u after 10 steps
-# also carries the implicit solve's high-k gain 1/(1-lambda) <= 5.
-F32_TOL = dict(rho_t0=1e-5, u_t0=2e-4, j0_t0=2e-4, force_t0=5e-4, jtilde_t0=1e-3, sigma_t0=3e-3,
-               xi_t0=1e-3, pop_t1=1e-5, rho_tL=1e-5, u_tL=1e-3)
+# FP32 bar: 1e-5 for every field.  What keeps u there: the populations are
+# stored as FP32 deviations from the writer's rest equilibrium and summed in
+# FP64 (item 1); the force stencil and the collision run in FP64; p and c_s^2
+# enter the closure as FP32 deviations of FP64 values; the FP32 iteration
+# stops at 4e-7 (the stop rule's own error then stays below 1e-5 of u).
+F32_TOL = 1e-5
+F32_STORAGE_F64_FIELDS_TOL = 1e-6
 
 
 @pytest.mark.parametrize("name,lattice,shape,extra", CASES)
@@ -86,11 +84,27 @@ def test_f32_matches_oracle(orc, L, name, lattice, shape, extra):
     rho, u, model = case(name, lattice, shape)
     ns = NSTEPS.get(name, 10)
     ref = oracle_reference(orc, model, rho, u, nsteps_long=ns)
-    gpu = gpu_run(L, model, L.STORE_F32, rho, u, nsteps_long=ns, tol=1e-7, **extra)
+    gpu = gpu_run(L, model, L.STORE_F32, rho, u, nsteps_long=ns, tol=4e-7, iter_prec=L.ITER_F32, **extra)
     e = compare(orc, ref, gpu)
     print(name, "f32", {k: f"{v:.2e}" for k, v in e.items()}, flush=True)
     for k, v in e.items():
-        assert v <= F32_TOL[k], (k, v)
+        assert v <= F32_TOL, (k, v)
+
+
+@pytest.mark.parametrize("name,lattice,shape,extra", [c for c in CASES if c[0] in (
+    "d2q21", "d3q59", "d3q59_tiles", "d2q21_gamma", "d3q59_cheb", "d3q59_unfused")])
+def test_f32_storage_f64_fields_match_oracle(orc, L, name, lattice, shape, extra):
+    """iter_prec F64: FP32 storage, FP64 fields and iteration (tolerance
+    1e-14, as the FP64 path); what remains is the FP32 rounding of each
+    stored deviation."""
+    rho, u, model = case(name, lattice, shape)
+    ns = NSTEPS.get(name, 10)
+    ref = oracle_reference(orc, model, rho, u, nsteps_long=ns)
+    gpu = gpu_run(L, model, L.STORE_F32, rho, u, nsteps_long=ns, tol=1e-14, iter_prec=L.ITER_F64, **extra)
+    e = compare(orc, ref, gpu)
+    print(name, "f32 storage, f64 fields", {k: f"{v:.2e}" for k, v in e.items()}, flush=True)
+    for k, v in e.items():
+        assert v <= F32_STORAGE_F64_FIELDS_TOL, (k, v)
 
 
 @pytest.mark.parametrize("name,lattice,shape,extra", CASES)
