@@ -48,22 +48,26 @@ def site_bytes(kernel, Q, D, s, r, warm, cheb=False, pull=False):
     nsig = 6 if D == 3 else 3
     nxi = 10 if D == 3 else 4
     t0 = 8 if s >= 4 else 4
-    rec = 2 if s == 2 else 0
+    rec = 0 if s == 8 else 2     # the writer's density record of the deviation forms
     pops = (Q - 1) * s + t0 + rec
     return {
-        "moments": pops + (1 + D) * r + 8,
-        # warm: 0 zero start, 1 previous j~, 2/3 extrapolated (history read
-        # and written); writes f, j0', u and p, P1, 1/rho
-        "force": (1 + D) * r + (D * r if warm else 0) + (2 * D * r * (warm - 1) if warm >= 2 else 0)
-                 + 3 * D * r + 3 * r,
+        # pulled populations; writes rho, j0, the FP64 mass and the four
+        # per-step EOS planes (p - p_ref, P1, 1/rho, c_s^2 - c_s^2_ref)
+        "moments": pops + (1 + D) * r + 8 + 4 * r,
+        # reads the FP64 mass (stencil) and j0; warm: 0 zero start, 1 previous
+        # j~, 2/3 extrapolated (history read and written); writes f, j0', u
+        "force": 8 + D * r + (D * r if warm else 0) + (2 * D * r * (warm - 1) if warm >= 2 else 0)
+                 + 3 * D * r,
         "iter_q": (2 + D) * r + nsig * r,
         "iter_jt": (nsig + 1 + 2 * D) * r + 2 * D * r + (D * r if cheb else 0),
-        # also forms j~ = rho u - j0' after the velocity-form solve (reads
-        # rho and j0' instead of j~, writes j~; the copy of u when the solve
-        # ended in the second buffer is not counted)
-        "closure1": (4 + 2 * D) * r + (1 + nsig + D + nxi + D) * r,
+        # reads u, p - p_ref, c_s^2 - c_s^2_ref, P1, 1/rho and (to form j~ =
+        # rho u - j0' after the velocity-form solve) rho and j0'; writes X, T,
+        # Y, Xi' and j~ (the copy of u when the solve ended in the second
+        # buffer is not counted)
+        "closure1": (5 + 2 * D) * r + (1 + nsig + D + nxi + D) * r,
         "closure2": (2 + nsig + 2 * D) * r + nsig * r,
-        "collide": (2 * pops if pull else pops + 8) + (1 + 3 * D + nsig + nxi) * r,
+        # fields u, f, j~, Sigma, Xi' and the FP64 mass
+        "collide": (2 * pops if pull else pops + 8) + (3 * D + nsig + nxi) * r,
         # fused pass (velocity form): read u, p, P1 and (own site) j0', rho;
         # write the next u (Chebyshev: also read u_{k-1})
         "iter_fused": (3 + 2 * D) * r + D * r + (D * r if cheb else 0),

@@ -404,6 +404,23 @@ __global__ void __launch_bounds__(256) k_reduce_max(const double* __restrict__ p
     }
 }
 
+// The per-step planes of one site (item 1's EOS, fixed during the solve):
+// [0] p - p_ref, [1] P1 = p - rho p', [2] 1/rho, [3] c_s^2 - c_s^2(rho_ref).
+// p and c_s^2 are evaluated in FP64 from the FP64 density and kept as
+// deviations from their reference values: the closure differentiates them,
+// and their deviations carry the field precision of their own size.  P1 and
+// 1/rho only scale other terms.
+template <class R>
+__device__ __forceinline__ void store_step_planes(const Coef& cf, R* at, long long St, double r64, R r, R inv)
+{
+    const double cs2 = eos_cs2<double>(cf.eos, r64);
+    const R psi = eos_psi<R>(cf.eos, r);
+    at[0] = R(r64 * cs2 - cf.pref);
+    at[St] = -r * r * R(cs2) * psi;
+    at[2 * St] = inv;
+    at[3 * St] = R(cs2 - cf.cref);
+}
+
 // ---------------------------------------------------------------------------
 // Initial populations: n_i(r) = n_eq(rho(r), u(r)) with local weights,
 // written pre-shifted so that the first pull returns them.  Evaluated in FP64
@@ -483,7 +500,8 @@ __global__ void __launch_bounds__(256) k_moments(const Domain* __restrict__ tab,
                                                  const Tile* __restrict__ tiles,
                                                  const S* __restrict__ A, R* __restrict__ rho,
                                                  R* __restrict__ j0, double* __restrict__ partial,
-                                                 int* __restrict__ flags, double* __restrict__ mass)
+                                                 int* __restrict__ flags, double* __restrict__ mass,
+                                                 R* __restrict__ pf)
 {
     using L = Lattice<Q>;
     const Where w = locate(tab, tiles);
@@ -522,6 +540,8 @@ __global__ void __launch_bounds__(256) k_moments(const Domain* __restrict__ tab,
         const R r = R(racc);
         sto(mass + o, i0, racc);
         sto(rho + o, i0, r);
+        // item 1's EOS, fixed for the rest of the step (the per-step planes)
+        if (pf) store_step_planes<R>(dm.cf, pf + o + i0, St, racc, r, R(1) / r);
         sto(j0 + o, i0, R(jx));
         sto(j0 + o + St, i0, R(jy));
         if (L::D == 3) sto(j0 + o + 2 * St, i0, R(jz));

@@ -18,23 +18,6 @@
 
 namespace lb2p {
 
-// The per-step planes of one site (item 1's EOS, fixed during the solve):
-// [0] p - p_ref, [1] P1 = p - rho p', [2] 1/rho, [3] c_s^2 - c_s^2(rho_ref).
-// p and c_s^2 are evaluated in FP64 from the FP64 density and kept as
-// deviations from their reference values: the closure differentiates them,
-// and their deviations carry the field precision of their own size.  P1 and
-// 1/rho only scale other terms.
-template <class R>
-__device__ __forceinline__ void store_step_planes(const Coef& cf, R* at, long long St, double r64, R r, R inv)
-{
-    const double cs2 = eos_cs2<double>(cf.eos, r64);
-    const R psi = eos_psi<R>(cf.eos, r);
-    at[0] = R(r64 * cs2 - cf.pref);
-    at[St] = -r * r * R(cs2) * psi;
-    at[2 * St] = inv;
-    at[3 * St] = R(cs2 - cf.cref);
-}
-
 // Inputs of one z step.
 template <class R>
 struct C2In {
@@ -507,9 +490,8 @@ k_closure1_zm(const Domain* __restrict__ tab, const Tile* __restrict__ tiles,
 }
 
 // Item 2 for D3Q59 as a z-march: f = kappa rho (sum over the force stencil of
-// Table III of tau_i d_i rho(r + d_i)), j0' = j0 + f/2, the per-step planes p,
-// P1 = p - rho p', 1/rho, and the start of the iteration (per site, the same
-// terms as k_force_t2 in 2D).  The stencil reaches (+-1, 0, 0), (+-1, +-1, 0)
+// Table III of tau_i d_i rho(r + d_i)), j0' = j0 + f/2 and the start of the
+// iteration (per site, the same terms as k_force_t2 in 2D).  The stencil reaches (+-1, 0, 0), (+-1, +-1, 0)
 // and (+-2, 0, 0) and their permutations, so three planes of rho (c-1, c,
 // c+1, tile + 2-wide frame) sit in LDS and the column's rho at c-2 .. c+2 in
 // registers.
@@ -518,7 +500,7 @@ __global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(si
 k_force_zm(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, IterCtl ic,
            const double* __restrict__ mass, const R* __restrict__ j0, R* __restrict__ f, R* __restrict__ j0p,
            R* __restrict__ u, const R* jt_prevA, const R* jt_prevB, const SolveInfo* prev_info, R* jt0,
-           R* __restrict__ pf, R* hist, R* hist2, int order)
+           R* hist, R* hist2, int order)
 {
     constexpr int UX = TX + 4, UY = TY + 4;
     constexpr int NFRAME = UX * UY - TX * TY;
@@ -641,11 +623,9 @@ k_force_zm(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, IterC
                                RH(1, 0, -1) - RH(-1, 0, -1) - RH(0, 1, -1) - RH(0, -1, -1)) +
                         0.5 * (RH(0, 0, 2) - RH(0, 0, -2));
                 const double r64 = rg[2];
-                const R r = R(r64);
                 const double kr = dm.cf.kappa * r64;
-                const R inv = R(1) / r;
+                const R inv = R(1) / R(r64);   // as the 1/rho plane of item 1
                 const long long i0 = o + col + (long long)plane * zc;
-                store_step_planes<R>(dm.cf, pf + i0, N, r64, r, inv);
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
                     const long long ia = i0 + a * N;
@@ -919,7 +899,7 @@ template <class R, int TX, int TY>
 __global__ void __launch_bounds__(TX * TY)
 k_force_t2(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, IterCtl ic, const double* __restrict__ mass,
            const R* __restrict__ j0, R* __restrict__ f, R* __restrict__ j0p, R* __restrict__ u,
-           const R* jt_prevA, const R* jt_prevB, const SolveInfo* prev_info, R* jt0, R* __restrict__ pf,
+           const R* jt_prevA, const R* jt_prevB, const SolveInfo* prev_info, R* jt0,
            R* hist, R* hist2, int order)
 {
     constexpr int UX = TX + 4, UY = TY + 4;
@@ -942,7 +922,6 @@ k_force_t2(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, IterC
         const int cx = (int)threadIdx.x + 2, cy = (int)threadIdx.y + 2;
         auto RH = [&](int dx, int dy) -> double { return sr[cy + dy][cx + dx]; };
         const double r64 = RH(0, 0);
-        const R r = R(r64);
         // (10): tau -2 ; (11): tau 1/2 ; (20): tau 1/4
         double fa[2];
         fa[0] = -2.0 * (RH(1, 0) - RH(-1, 0)) + 0.5 * (RH(1, 1) + RH(1, -1) - RH(-1, 1) - RH(-1, -1)) +
@@ -950,8 +929,7 @@ k_force_t2(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, IterC
         fa[1] = -2.0 * (RH(0, 1) - RH(0, -1)) + 0.5 * (RH(1, 1) + RH(-1, 1) - RH(1, -1) - RH(-1, -1)) +
                 0.5 * (RH(0, 2) - RH(0, -2));
         const double kr = dm.cf.kappa * r64;
-        const R inv = R(1) / r;
-        store_step_planes<R>(dm.cf, pf + o + i0, St, r64, r, inv);
+        const R inv = R(1) / R(r64);   // as the 1/rho plane of item 1
         const R* prev = nullptr;
         if (prev_info) prev = prev_info[tl.dom].final_buf ? jt_prevB : jt_prevA;
 #pragma unroll

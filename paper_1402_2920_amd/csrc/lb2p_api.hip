@@ -570,7 +570,8 @@ struct Impl {
         ProfScope _ps(c, LB2P_K_MOMENTS);
         hipLaunchKernelGGL((k_moments<Q, R, S>), sgrid(c), sblock(c), 0, c->stream, c->dtab,
                            c->site_tiles, (const S*)c->A, write_fields ? (R*)c->rho : (R*)c->X,
-                           write_fields ? (R*)c->j0 : (R*)c->T, c->partial, c->flags, c->mass);
+                           write_fields ? (R*)c->j0 : (R*)c->T, c->partial, c->flags, c->mass,
+                           write_fields ? (R*)c->pf : (R*)nullptr);
     }
 
     // Items 1-8.  In the default (tolerance) mode the host reads how many
@@ -618,12 +619,12 @@ struct Impl {
                 hipLaunchKernelGGL((k_force_zm<R, TX, kFusedTY>), dim3((unsigned)c->clos_host.size()),
                                    dim3(TX, kFusedTY, 1), 0, c->stream, c->dtab, c->clos_tiles, ic,
                                    (const double*)c->mass, (const R*)c->j0, (R*)c->f, (R*)c->j0p, (R*)c->u,
-                                   prevA, prevB, prev, jstart, (R*)c->pf, hist, hist2, order);
+                                   prevA, prevB, prev, jstart, hist, hist2, order);
             } else {
                 hipLaunchKernelGGL((k_force_t2<R, kClos2TX, kClos2TY>), dim3((unsigned)c->clos_host.size()),
                                    dim3(kClos2TX, kClos2TY, 1), 0, c->stream, c->dtab, c->clos_tiles, ic,
                                    (const double*)c->mass, (const R*)c->j0, (R*)c->f, (R*)c->j0p, (R*)c->u,
-                                   prevA, prevB, prev, jstart, (R*)c->pf, hist, hist2, order);
+                                   prevA, prevB, prev, jstart, hist, hist2, order);
             }
             hipLaunchKernelGGL(k_reduce_max, dim3(c->ndom), dim3(256), 0, c->stream, (const double*)c->pmax,
                                (const int*)c->clos_range, c->jscale, 1LL, (const int*)nullptr);

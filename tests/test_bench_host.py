@@ -15,16 +15,20 @@ import bench  # noqa: E402
 
 def test_site_bytes_d3q59_f32():
     # the per-kernel byte table of the 3D FP32 step (gamma = 0, previous-step
-    # warm start): populations 58 x 4 + FP64 rest plane, fields 4 B
+    # warm start): populations 58 x 4 + FP64 rest plane + 2-byte density
+    # record, fields 4 B, the FP64 mass 8 B
     sb = lambda k: bench.site_bytes(k, 59, 3, 4, 4, 1)
-    assert sb("moments") == 58 * 4 + 8 + 4 * 4 + 8
-    assert sb("force") == 76
+    pops = 58 * 4 + 8 + 2
+    assert sb("moments") == pops + 4 * 4 + 8 + 4 * 4
+    assert sb("force") == 8 + 3 * 4 + 3 * 4 + 9 * 4
     assert sb("iter_fused") == 48
-    assert sb("closure1") == 132
+    assert sb("closure1") == 11 * 4 + 23 * 4
     assert sb("closure2") == 80
-    assert sb("collide") == 58 * 4 + 8 + 8 + (1 + 9 + 6 + 10) * 4
+    assert sb("collide") == pops + 8 + (9 + 6 + 10) * 4
     # gamma != 0: the collision pulls the populations again
-    assert bench.site_bytes("collide", 59, 3, 4, 4, 1, pull=True) == 2 * 240 + 26 * 4
+    assert bench.site_bytes("collide", 59, 3, 4, 4, 1, pull=True) == 2 * pops + 25 * 4
+    # FP64 storage has no density record
+    assert bench.site_bytes("moments", 59, 3, 8, 8, 1) == 58 * 8 + 8 + 4 * 8 + 8 + 4 * 8
     # Chebyshev reads u_{k-1} too
     assert bench.site_bytes("iter_fused", 59, 3, 4, 4, 1, cheb=True) == 60
 
@@ -38,7 +42,7 @@ def test_step_hbm_sums_launches():
     res = dict(prof=prof, Q=59, D=3, N=N, workload="none", storage="f32")
     out = bench.step_hbm(res, "f32", 1, False, steps, secs, copy_gbs=5000.0)
     assert out["population_floor"]["bytes_per_site_step"] == 2 * 59 * 4
-    per_step = 264 + 76 + 132 + 80 + 352 + 13 * 48
+    per_step = 282 + 68 + 136 + 80 + 350 + 13 * 48
     assert out["algorithmic"]["bytes_per_site_step"] == per_step
     gbs = per_step * N * steps / secs / 1e9
     assert out["algorithmic"]["gbs"] == pytest.approx(gbs, abs=0.1)
