@@ -294,6 +294,51 @@ def cpu_baseline(workload, nsteps_max=30, budget_s=15.0):
     return res, dict(shape=shape, steps=steps, rho=F["rho"], u=F["u"][:, :d].T.copy())
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+_ONE_CORE = '''
+import sys, time
+sys.path.insert(0, sys.argv[1])
+from oracle import oracle as orc
+import lb2p_workloads as W
+workload, budget = sys.argv[2], float(sys.argv[3])
+full = tuple(W.load_params()[workload]["shape"])
+shape = (16, 16, full[2]) if len(full) == 3 else (64, 64)
+entry, shape, rho, u = W.build(workload, shape)
+d = len(shape)
+m = orc.Model(nx=shape[0], ny=shape[1], nz=shape[2] if d == 3 else 1, tol=1e-13, max_iter=2000,
+              **W.oracle_kwargs(entry["model"]))
+n = orc.init(m, rho, u.T.copy())
+t0 = time.perf_counter(); steps = 0
+while steps < 30 and time.perf_counter() - t0 < budget:
+    orc.step(m, n, 1); steps += 1
+dt = time.perf_counter() - t0
+print(m.N * steps / dt / 1e6, steps, orc.num_threads())
+'''
+
+
+def cpu_one_core(workload, budget_s=10.0):
+    """The same oracle sample on one host core (OMP_NUM_THREADS=1, its own
+    process): (MLUPS, steps)."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    p = subprocess.run([sys.executable, "-c", _ONE_CORE, ROOT, workload, str(budget_s)], env=env,
+                       capture_output=True, text=True, timeout=300)
+    if p.returncode != 0:
+        return None, 0
+    mlups, steps, threads = p.stdout.split()[-3:]
+    return (round(float(mlups), 4), int(steps)) if int(threads) == 1 else (None, 0)
+
+
 def sample_errors(workload, storage, ref, iter_prec=0):
     """max and RMS error of rho and u on the cpu-baseline sample after the
     same number of steps (GPU in `storage`, at the tolerance of the timed
@@ -338,6 +383,8 @@ def main():
                     help="steps run before warm-up and timing: the relaxation of the synthetic start, whose "
                          "solves need more passes than the rest of the run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-whole-run", action="store_true",
+                    help="skip the configuration's whole run (all its steps from the synthetic start)")
     ap.add_argument("--no-variants", action="store_true", help="skip the BF16/F16 storage lines")
     ap.add_argument("--batch-steps", type=int, default=1000,
                     help="steps of the 512-domain batched workload in one graph (0: skip)")
@@ -376,9 +423,22 @@ def main():
     )
     line["step_hbm"] = step_hbm(res, args.storage, args_warm, args.solver == "chebyshev", K, secs,
                                 copy_rate_gbs())
+    # the configuration's whole run from the synthetic start (the first steps
+    # relax the initial walls and noise and need more solve passes)
+    wsteps = entry.get("steps", 0)
+    if wsteps and not args.no_whole_run:
+        wr = run_gpu(args.workload, args.storage, wsteps, 0, profile=False, solver=args.solver,
+                     autotune=not args.no_autotune, warm_start=args_warm, settle=0)
+        line["whole_run"] = dict(steps=wsteps, value=round(N * wsteps / wr["seconds"] / 1e6, 2), unit="MLUPS",
+                                 ms_per_step=round(1e3 * wr["seconds"] / wsteps, 4),
+                                 note="all steps of the configuration from its synthetic start, transient "
+                                      "included, one timed region")
     ref = None
     if not args.no_cpu:
         cb, ref = cpu_baseline(args.workload)
+        one, one_steps = cpu_one_core(args.workload)
+        cb["one_core"] = dict(value=one, unit="MLUPS", steps=one_steps)
+        cb["host_cpu"] = cpu_model()
         line["cpu_baseline"] = cb
     if not args.no_variants and args.storage == "f32":
         var = {}

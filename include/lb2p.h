@@ -175,6 +175,16 @@ typedef enum { LB2P_SOLVER_FIXED_POINT = 0, LB2P_SOLVER_CHEBYSHEV = 1 } lb2p_sol
  * (j0' + j~)/rho and forms j~ after the last pass (D2Q21 and D3Q59); both
  * compute the same map and stop on the same rule. */
 #define LB2P_FLAG_UNFUSED_SOLVE 1
+/* LB2P_FLAG_STENCIL_CLOSURE: a second formulation of items 10-11 (the
+ * Supplemental preamble notes that the differential operators may be moved
+ * left or right, giving algorithms that agree to the Chapman-Enskog order
+ * but differ numerically).  The derivatives of X = P1 div u,
+ * T_ag = p (d_a u_g + d_g u_a) and Y_b = rho^-1 d_b p + u_g d_g u_b are taken
+ * with the product rule, so that every second derivative acts on p or on u
+ * alone and uses the Table III stencils for the Laplacian (Sec. IV C) and
+ * the traceless d_a d_b (Sec. IV D) in place of two nested first
+ * derivatives; Xi' and the rest of the step are unchanged. */
+#define LB2P_FLAG_STENCIL_CLOSURE 2
 
 /* Diagnostics of the state (FP64 sums over all sites). */
 typedef struct {
@@ -190,9 +200,12 @@ typedef struct lb2p_ctx lb2p_ctx;
 
 /* Fill *out with defaults for a lattice and grid: gamma 0, kappa 0, the EOS
  * rho1 0.3, rho2 1.0, A 0, cs2_rho1 0.45, rho0 = rho1, the given storage,
- * tol 4e-7 (FP32 fields: twice the floor of the FP32 iteration, and on the
- * slab workload the FP32 velocity within 1e-5 of FP64 over 100 steps) or
- * 1e-13 (F64), max_iter 200, warm_start 1, iter_prec AUTO, no graph. */
+ * tol 1e-13 (F64), 4e-7 (F32: twice the floor of the FP32 iteration; on the
+ * slab workload the FP32 velocity stays within 1e-5 of FP64 over 100 steps)
+ * or the format's unit roundoff (BF16 2^-9, F16 2^-12: j0' comes from
+ * populations rounded to that relative size, so a tighter rule only spends
+ * passes on storage noise), max_iter 200, warm_start 1, iter_prec AUTO, no
+ * graph. */
 lb2p_status lb2p_default_params(int lattice, int nx, int ny, int nz, int storage,
                                 lb2p_params *out);
 

@@ -154,6 +154,27 @@ static void make_stencil(int dim, int nshell, const int reps[][3],
     }
 }
 
+/* Columns "d_alpha d_alpha" (Sec. IV C) and traceless "d_alpha d_beta"
+ * (Sec. IV D) of Table III. */
+static void second_stencils(int dim, stencil *LAP, stencil *TRL)
+{
+    if (dim == 3) {
+        static const int rl[2][3] = {{0,0,0},{1,0,0}};
+        static const double tl[2] = {-6.0, 1.0};
+        static const int rt[2][3] = {{1,0,0},{1,1,0}};
+        static const double tt[2] = {0.5, 0.25};
+        make_stencil(3, 2, rl, tl, LAP);
+        make_stencil(3, 2, rt, tt, TRL);
+    } else {
+        static const int rl[2][3] = {{0,0,0},{1,0,0}};
+        static const double tl[2] = {-4.0, 1.0};
+        static const int rt[2][3] = {{1,0,0},{1,1,0}};
+        static const double tt[2] = {1.0, 0.25};
+        make_stencil(2, 2, rl, tl, LAP);
+        make_stencil(2, 2, rt, tt, TRL);
+    }
+}
+
 /* Column "d_alpha" (Sec. IV B) and column "d_alpha d_beta d_beta" (Sec. IV E). */
 static void stencils(int dim, stencil *D1, stencil *D3)
 {
@@ -182,6 +203,7 @@ typedef struct {
     double W[64];      /* W_i = w_i(c0^2), reference weights (R2) */
     double c0sq;       /* c0^2 = c_s^2(rho0)                       */
     stencil D1, D3;
+    stencil LAP, TRL;  /* Laplacian and traceless second derivative */
 } lattice;
 
 /* ------------------------------------------------------------------------ */
@@ -217,6 +239,30 @@ static double apply_stencil(const orc_params *P, const stencil *S,
 }
 
 static double delta(int a, int b) { return a == b ? 1.0 : 0.0; }
+
+/* d_a d_b g at site s from the Table III second-derivative stencils: the
+ * traceless part sum_i tau_i (d_ia d_ib - d_ab |d_i|^2 / dim) g(r + d_i)
+ * (Sec. IV D) plus d_ab / dim times the Laplacian sum_i tau_i g(r + d_i)
+ * (Sec. IV C).  H[3a + b] for a, b < dim. */
+static void hessian(const orc_params *P, const stencil *LAP, const stencil *TRL, int dim,
+                    const double *g, int stride, int comp, long s, double *H)
+{
+    double lap = 0.0;
+    for (int i = 0; i < LAP->n; ++i) {
+        long t = neighbour(P, s, LAP->d[i][0], LAP->d[i][1], LAP->d[i][2]);
+        lap += LAP->tau[i] * g[t * stride + comp];
+    }
+    for (int k = 0; k < 9; ++k) H[k] = 0.0;
+    for (int i = 0; i < TRL->n; ++i) {
+        long t = neighbour(P, s, TRL->d[i][0], TRL->d[i][1], TRL->d[i][2]);
+        double v = g[t * stride + comp], dd = 0.0;
+        for (int a = 0; a < dim; ++a) dd += TRL->d[i][a] * TRL->d[i][a];
+        for (int a = 0; a < dim; ++a)
+            for (int b = 0; b < dim; ++b)
+                H[3*a + b] += TRL->tau[i] * (TRL->d[i][a] * TRL->d[i][b] - delta(a, b) * dd / dim) * v;
+    }
+    for (int a = 0; a < dim; ++a) H[4*a] += lap / dim;
+}
 
 /* ------------------------------------------------------------------------ */
 /* Equation of state (App. B)                                                */
@@ -259,6 +305,7 @@ static void lattice_setup(const orc_params *P, lattice *L)
     L->c0sq = cs2_of(P, P->rho0);
     orc_weights(P->Q, L->c0sq, L->W);
     stencils(L->dim, &L->D1, &L->D3);
+    second_stencils(L->dim, &L->LAP, &L->TRL);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -461,6 +508,7 @@ void orc_closure(const orc_params *P, const double *rho, const double *j,
 
     double *u = (double *)calloc((size_t)N * 3, sizeof(double));
     double *pf = (double *)calloc((size_t)N, sizeof(double));      /* p            */
+    double *P1f = (double *)calloc((size_t)N, sizeof(double));     /* p - rho p'   */
     double *por = (double *)calloc((size_t)N, sizeof(double));     /* p/rho        */
     double *puu = (double *)calloc((size_t)N * 9, sizeof(double)); /* p u_b u_g    */
     double *G = (double *)calloc((size_t)N * 9, sizeof(double));   /* d_a u_b      */
@@ -479,6 +527,7 @@ void orc_closure(const orc_params *P, const double *rho, const double *j,
         orc_eos(P, rho[s], e);
         for (int a = 0; a < 3; ++a) u[3*s + a] = j[3*s + a] / rho[s];
         pf[s] = e[1];
+        P1f[s] = e[3];
         por[s] = e[1] / rho[s];
         for (int b = 0; b < 3; ++b)
             for (int c = 0; c < 3; ++c)
@@ -533,12 +582,49 @@ void orc_closure(const orc_params *P, const double *rho, const double *j,
         const double *us = &u[3*s], *Gs = &G[9*s], *Ms = &M[27*s], *Cs = &C[3*s];
         double trG = 0.0, trJ = 0.0, trDY = 0.0;
         for (int a = 0; a < dim; ++a) { trG += Gs[4*a]; trJ += J[9*s + 4*a]; }
-        for (int a = 0; a < dim; ++a) {
-            DX[a] = apply_stencil(P, D1, X, 1, 0, s, a);
-            for (int c = 0; c < dim; ++c)
-                DT[a] += apply_stencil(P, D1, T, 9, 3*a + c, s, c);
-            for (int b = 0; b < dim; ++b)
-                DY[a][b] = apply_stencil(P, D1, Y, 3, b, s, a);
+        if (P->flags & ORC_STENCIL_CLOSURE) {
+            /* The same three derivatives with the outer operator carried
+             * through the products (product rule), so that every second
+             * derivative acts on p or on u alone and takes the Table III
+             * stencils of Secs. IV C-D (hessian); first derivatives stay
+             * Sec. IV B:
+             *   d_a X      = (d_a P1) tr G + P1 d_a d_g u_g
+             *   d_g T_ag   = (d_g p)(G_ag + G_ga) + p (d_a d_g u_g + d_g d_g u_a)
+             *   d_a Y_b    = -rho^-2 (d_a rho)(d_b p) + rho^-1 d_a d_b p
+             *                + G_ag G_gb + u_g d_a d_g u_b                     */
+            double Hu[3][9] = {{0}}, Hp[9], DP1[3] = {0}, Drho[3] = {0};
+            for (int c = 0; c < dim; ++c) hessian(P, &L.LAP, &L.TRL, dim, u, 3, c, s, Hu[c]);
+            hessian(P, &L.LAP, &L.TRL, dim, pf, 1, 0, s, Hp);
+            for (int a = 0; a < dim; ++a) {
+                DP1[a] = apply_stencil(P, D1, P1f, 1, 0, s, a);
+                Drho[a] = apply_stencil(P, D1, rho, 1, 0, s, a);
+            }
+            double ddiv[3] = {0}, lapu[3] = {0};   /* d_a d_g u_g, d_g d_g u_a */
+            for (int a = 0; a < dim; ++a)
+                for (int c = 0; c < dim; ++c) {
+                    ddiv[a] += Hu[c][3*a + c];
+                    lapu[a] += Hu[a][3*c + c];
+                }
+            for (int a = 0; a < dim; ++a) {
+                DX[a] = DP1[a] * trG + P1 * ddiv[a];
+                DT[a] = p * (ddiv[a] + lapu[a]);
+                for (int c = 0; c < dim; ++c)
+                    DT[a] += Pg[3*s + c] * (Gs[3*a + c] + Gs[3*c + a]);
+                for (int b = 0; b < dim; ++b) {
+                    double v = -Drho[a] * Pg[3*s + b] / (rho[s] * rho[s]) + Hp[3*a + b] / rho[s];
+                    for (int c = 0; c < dim; ++c)
+                        v += Gs[3*a + c] * Gs[3*c + b] + us[c] * Hu[b][3*a + c];
+                    DY[a][b] = v;
+                }
+            }
+        } else {
+            for (int a = 0; a < dim; ++a) {
+                DX[a] = apply_stencil(P, D1, X, 1, 0, s, a);
+                for (int c = 0; c < dim; ++c)
+                    DT[a] += apply_stencil(P, D1, T, 9, 3*a + c, s, c);
+                for (int b = 0; b < dim; ++b)
+                    DY[a][b] = apply_stencil(P, D1, Y, 3, b, s, a);
+            }
         }
         for (int a = 0; a < dim; ++a) trDY += DY[a][a];
 
@@ -575,7 +661,7 @@ void orc_closure(const orc_params *P, const double *rho, const double *j,
                 }
     }
 
-    free(u); free(pf); free(por); free(puu); free(G); free(J); free(Pg);
+    free(u); free(pf); free(P1f); free(por); free(puu); free(G); free(J); free(Pg);
     free(M); free(C); free(X); free(T); free(Y);
 }
 
@@ -617,6 +703,15 @@ static void site_collision(const orc_params *P, const lattice *L,
                     + W[i] / (2.0 * c0sq * c0sq) * h2
                     + W[i] / (6.0 * c0sq * c0sq * c0sq) * h3;
     }
+}
+
+void orc_hessian(const orc_params *P, const double *g, double *H)
+{
+    long N = nsites(P);
+    lattice L;
+    lattice_setup(P, &L);
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < N; ++s) hessian(P, &L.LAP, &L.TRL, L.dim, g, 1, 0, s, &H[9*s]);
 }
 
 void orc_site_collision(const orc_params *P, const double *n_site, double rho,

@@ -36,6 +36,11 @@ typedef struct {
 } orc_params;
 
 #define ORC_NO_CORR 1
+#define ORC_STENCIL_CLOSURE 2   /* items 10-11: the derivatives of X, T, Y taken
+                                   with the product rule, second derivatives of p
+                                   and u by the Table III Laplacian and traceless
+                                   stencils (Secs. IV C-D); the Supplemental
+                                   preamble allows moving the operators so */
 
 /* Per-step diagnostics of the implicit velocity solve. */
 typedef struct {
@@ -44,6 +49,10 @@ typedef struct {
     double jscale;      /* max|j0'| used to scale the stop rule               */
     int converged;      /* 1 if the stop rule was met before max_iter         */
 } orc_info;
+
+/* d_a d_b g of a scalar field g[N] at every site from the Table III
+ * second-derivative stencils (Secs. IV C-D): H[9*s + 3*a + b]. */
+void orc_hessian(const orc_params *P, const double *g, double *H);
 
 /* Velocity set: fills c[Q*3] and shell[Q]; returns Q or -1. */
 int orc_velocities(int Q, int *c, int *shell);

@@ -36,6 +36,7 @@ class OrcInfo(ctypes.Structure):
 
 
 NO_CORR = 1
+STENCIL_CLOSURE = 2
 
 
 def build(force: bool = False) -> str:
@@ -64,6 +65,7 @@ def lib():
         L.orc_step.argtypes = [pp, dp, ctypes.c_int, ctypes.POINTER(OrcInfo)]
         L.orc_totals.argtypes = [pp, dp, dp, dp]
         L.orc_jtilde_map.argtypes = [pp, dp, dp, dp, dp]
+        L.orc_hessian.argtypes = [pp, dp, dp]
         L.orc_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -222,6 +224,14 @@ def jtilde_map(m: Model, rho, j0p, jt):
     prm = m.c_params()
     lib().orc_jtilde_map(ctypes.byref(prm), _p(np.ascontiguousarray(rho, dtype=np.float64)),
                          _p(_vec3(j0p, N)), _p(_vec3(jt, N)), _p(out))
+    return out
+
+
+def hessian(m: Model, g) -> np.ndarray:
+    """d_a d_b g [N, 3, 3] from the Table III Laplacian and traceless stencils."""
+    out = np.zeros((m.N, 3, 3))
+    prm = m.c_params()
+    lib().orc_hessian(ctypes.byref(prm), _p(np.ascontiguousarray(g, dtype=np.float64).reshape(m.N)), _p(out))
     return out
 
 

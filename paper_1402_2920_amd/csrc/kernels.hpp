@@ -88,15 +88,17 @@ struct Codec<double> {
     __device__ static inline double dev(double v, const DevScale&, int) { return v; }
     __device__ static inline double put(double d, const DevScale&, int) { return d; }
 };
-// BF16/FP16 store the deviation scaled by 1/W_k (one rounding, from FP64);
-// FP32 stores it unscaled (its exponent range needs no scale).
+// BF16/FP16 store the deviation scaled by 1/W_k (formed in FP32: the FP32
+// rounding is far below the format's, and FP32 -> BF16/FP16 is one
+// conversion instruction where FP64 -> FP16 is a long sequence); FP32
+// stores it unscaled (its exponent range needs no scale).
 template <class S>
 struct DevCodec {
     static constexpr bool kLocal = true;
     __device__ static inline float dev(S v, const DevScale& s, int k) { return static_cast<float>(v) * s.scl[k]; }
     __device__ static inline S put(double d, const DevScale& s, int k)
     {
-        return static_cast<S>(d * (double)s.inv[k]);
+        return static_cast<S>(static_cast<float>(d) * s.inv[k]);
     }
 };
 template <>

@@ -961,4 +961,156 @@ k_force_t2(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, IterC
     block_max_part(ic.part, amax);
 }
 
+// ---------------------------------------------------------------------------
+// Sigma in the stencil formulation (LB2P_FLAG_STENCIL_CLOSURE), per site.
+// The derivatives of item 11 are taken with the outer operator carried
+// through the products (the Supplemental preamble allows moving the
+// operators), so that every second derivative acts on p or on u alone and
+// takes the Table III stencils for d_a d_a (Sec. IV C) and the traceless
+// d_a d_b (Sec. IV D):
+//   d_a X     = (d_a P1) tr G + P1 d_a d_g u_g
+//   d_g T_ag  = (d_g p)(G_ag + G_ga) + p (d_a d_g u_g + d_g d_g u_a)
+//   d_a Y_b   = -rho^-2 (d_a rho)(d_b p) + rho^-1 d_a d_b p + G_ag G_gb + u_g d_a d_g u_b
+// with first derivatives by the stencil of Sec. IV B; Sigma then as in
+// k_closure2_zm / k_closure2_t2.  p enters as p - p_ref (the per-step plane)
+// and rho as the FP64 mass of item 1.
+// ---------------------------------------------------------------------------
+
+// d_a d_b F at one site from the compact stencils: Laplacian (rest -2D,
+// shell (100) 1) and traceless part (shell (100) tau1, shell (110) 1/4).
+template <int D, class R, class F>
+__device__ __forceinline__ void hess_compact(F at, R H[3][3])
+{
+    constexpr double tau1 = D == 3 ? 0.5 : 1.0, tau2 = 0.25;
+    const R c0 = at(0, 0, 0);
+    R lap = R(-2 * D) * c0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) H[a][b] = R(0);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const int e[3] = {a == 0, a == 1, a == 2};
+        const R sp = at(e[0], e[1], e[2]), sm = at(-e[0], -e[1], -e[2]);
+        lap += sp + sm;
+        // traceless (d_c d_c - |d|^2 / D) on the diagonal: 1 - 1/D for c = a, -1/D otherwise
+#pragma unroll
+        for (int c = 0; c < D; ++c) H[c][c] += R(tau1 * ((c == a ? 1.0 : 0.0) - 1.0 / D)) * (sp + sm);
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = a + 1; b < D; ++b) {
+            int e1[3] = {0, 0, 0}, e2[3] = {0, 0, 0};
+            e1[a] = 1; e2[b] = 1;
+            // the four vectors +-e_a +-e_b: d_a d_b = +1 for (+,+), (-,-), -1 otherwise
+            const R pp = at(e1[0] + e2[0], e1[1] + e2[1], e1[2] + e2[2]);
+            const R mm = at(-e1[0] - e2[0], -e1[1] - e2[1], -e1[2] - e2[2]);
+            const R pm = at(e1[0] - e2[0], e1[1] - e2[1], e1[2] - e2[2]);
+            const R mp = at(-e1[0] + e2[0], -e1[1] + e2[1], -e1[2] + e2[2]);
+            const R sum = pp + mm + pm + mp;
+            H[a][b] += R(tau2) * ((pp + mm) - (pm + mp));
+#pragma unroll
+            for (int c = 0; c < D; ++c)
+                H[c][c] += R(tau2 * ((c == a || c == b ? 1.0 : 0.0) - 2.0 / D)) * sum;
+        }
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        H[a][a] += lap * R(1.0 / D);
+#pragma unroll
+        for (int b = 0; b < a; ++b) H[a][b] = H[b][a];
+    }
+}
+
+template <int Q, class R>
+__global__ void __launch_bounds__(256) k_sigma_stencil(const Domain* __restrict__ tab,
+                                                       const Tile* __restrict__ tiles,
+                                                       const R* __restrict__ pf, const double* __restrict__ mass,
+                                                       const R* __restrict__ u, R* __restrict__ Sig)
+{
+    using L = Lattice<Q>;
+    constexpr int D = L::D;
+    const Where w = locate(tab, tiles);
+    if (!w.ok) return;
+    const Domain& dm = tab[w.dom];
+    const long long o = dm.off, St = dm.g.S;
+    const NbP nb = make_nbp(dm.g, w.x, w.y, w.z);
+    const unsigned i0 = nb.i0;
+    const R* const pdev = pf + o;
+    const R* const pP1 = pf + o + St;
+    const double* const ms = mass + o;
+    const R* const uo = u + o;
+    auto at3 = [&](int dx, int dy, int dz) { return nb.at(dx, dy, D == 3 ? dz : 0); };
+    // first derivatives (Sec. IV B) along axis a of a field given by value(index)
+    auto d1f = [&](auto value, int a) {
+        const int e[3] = {a == 0, a == 1, a == 2};
+        return d1<R>(value(at3(-2 * e[0], -2 * e[1], -2 * e[2])), value(at3(-e[0], -e[1], -e[2])),
+                     value(at3(e[0], e[1], e[2])), value(at3(2 * e[0], 2 * e[1], 2 * e[2])));
+    };
+    R G[3][3] = {}, Pg[3] = {}, DP1[3] = {}, Drho[3] = {}, trJ = R(0);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+#pragma unroll
+        for (int b = 0; b < D; ++b) G[a][b] = d1f([&](unsigned t) { return ldo(uo + b * St, t); }, a);
+        Pg[a] = d1f([&](unsigned t) { return ldo(pdev, t); }, a);
+        DP1[a] = d1f([&](unsigned t) { return ldo(pP1, t); }, a);
+        Drho[a] = R(d1<double>(ldo(ms, at3(a == 0 ? -2 : 0, a == 1 ? -2 : 0, a == 2 ? -2 : 0)),
+                               ldo(ms, at3(a == 0 ? -1 : 0, a == 1 ? -1 : 0, a == 2 ? -1 : 0)),
+                               ldo(ms, at3(a == 0 ? 1 : 0, a == 1 ? 1 : 0, a == 2 ? 1 : 0)),
+                               ldo(ms, at3(a == 0 ? 2 : 0, a == 1 ? 2 : 0, a == 2 ? 2 : 0))));
+        // d_a j_a with j = rho u
+        trJ += d1f([&](unsigned t) { return R(ldo(ms, t)) * ldo(uo + a * St, t); }, a);
+    }
+    R Hu[3][3][3], Hp[3][3];
+#pragma unroll
+    for (int c = 0; c < D; ++c)
+        hess_compact<D, R>([&](int dx, int dy, int dz) { return ldo(uo + c * St, at3(dx, dy, dz)); }, Hu[c]);
+    hess_compact<D, R>([&](int dx, int dy, int dz) { return ldo(pdev, at3(dx, dy, dz)); }, Hp);
+
+    const R r = R(ldo(ms, i0));
+    const R ri = R(1) / r;
+    const EosVal<R> e = eos_all<R>(dm.cf.eos, r);
+    const R us[3] = {ldo(uo, i0), ldo(uo + St, i0), D == 3 ? ldo(uo + 2 * St, i0) : R(0)};
+    R trG = R(0);
+#pragma unroll
+    for (int a = 0; a < D; ++a) trG += G[a][a];
+    R DX[3] = {}, DT[3] = {}, DY[3][3] = {};
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        R ddiv = R(0), lapu = R(0);
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            ddiv += Hu[c][a][c];
+            lapu += Hu[a][c][c];
+        }
+        DX[a] = DP1[a] * trG + e.P1 * ddiv;
+        R dt = e.p * (ddiv + lapu);
+#pragma unroll
+        for (int c = 0; c < D; ++c) dt += Pg[c] * (G[a][c] + G[c][a]);
+        DT[a] = dt;
+#pragma unroll
+        for (int b = 0; b < D; ++b) {
+            R v = -Drho[a] * Pg[b] * ri * ri + Hp[a][b] * ri;
+#pragma unroll
+            for (int c = 0; c < D; ++c) v += G[a][c] * G[c][b] + us[c] * Hu[b][a][c];
+            DY[a][b] = v;
+        }
+    }
+    R trDY = R(0);
+#pragma unroll
+    for (int a = 0; a < D; ++a) trDY += DY[a][a];
+    const R gm = R(dm.cf.gamma);
+    const R KS1 = R(-0.25) * (gm + R(1)) * (gm + R(1)) / (gm - R(1));
+    const R KS2 = (gm * gm + R(4) * gm + R(1)) / (R(6) * (gm - R(1)));
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = a; b < D; ++b) {
+            const R br1 = us[a] * DX[b] + us[b] * DX[a] + us[b] * DT[a] + us[a] * DT[b];
+            R br2 = -e.dp * trJ * (G[a][b] + G[b][a]) - e.p * DY[a][b] - e.p * DY[b][a];
+            if (a == b) br2 += -e.P1 * trDY + e.P2 * trG * trJ;
+            sto(Sig + o + sym2<D>(a, b) * St, i0, KS1 * br1 + KS2 * br2);
+        }
+}
+
 }  // namespace lb2p

@@ -24,10 +24,13 @@ STORE_F64, STORE_F32, STORE_BF16, STORE_F16 = 0, 1, 2, 3
 DTYPE_F64, DTYPE_F32 = 0, 1
 FIELD_RHO, FIELD_J0, FIELD_FORCE, FIELD_JTILDE, FIELD_U, FIELD_SIGMA, FIELD_XI = range(7)
 FLAG_UNFUSED_SOLVE = 1
+FLAG_STENCIL_CLOSURE = 2
 SOLVER_FIXED_POINT, SOLVER_CHEBYSHEV = 0, 1
 ITER_AUTO, ITER_F32, ITER_F64 = 0, 1, 2
 F32_TOL_FLOOR = 2e-7
 F32_TOL_DEFAULT = 4e-7
+# lb2p_default_params: FP64 1e-13, FP32 4e-7, BF16/F16 the format's unit roundoff
+DEFAULT_TOL = {0: 1e-13, 1: F32_TOL_DEFAULT, 2: 2.0**-9, 3: 2.0**-12}
 STORAGE_NAMES = {"f64": STORE_F64, "f32": STORE_F32, "bf16": STORE_BF16, "f16": STORE_F16}
 
 
@@ -156,7 +159,7 @@ class Params:
     iter_prec: int = ITER_AUTO
 
     def to_c(self) -> _Params:
-        tol = self.tol if self.tol is not None else (1e-13 if self.storage == STORE_F64 else F32_TOL_DEFAULT)
+        tol = self.tol if self.tol is not None else DEFAULT_TOL.get(self.storage, F32_TOL_DEFAULT)
         return _Params(self.lattice, self.nx, self.ny, self.nz, self.storage, self.gamma, self.kappa,
                        _Eos(self.rho1, self.rho2, self.A, self.cs2_rho1), self.rho0, tol,
                        self.max_iter, self.fixed_iter, self.warm_start, self.check_every,

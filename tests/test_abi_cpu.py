@@ -55,6 +55,11 @@ def test_default_params(L):
     assert prm.iter_prec == L.ITER_AUTO
     assert prm.eos.rho1 == 0.3 and prm.eos.rho2 == 1.0 and prm.rho0 == 0.3
     assert L.lib().lb2p_default_params(59, 8, 8, 8, L.STORE_F64, None) == L.EINVAL
+    # the binding's default tolerance per storage is the library's
+    for stg in (L.STORE_F64, L.STORE_F32, L.STORE_BF16, L.STORE_F16):
+        assert L.lib().lb2p_default_params(59, 32, 32, 32, stg, ctypes.byref(prm)) == L.OK
+        assert prm.tol == L.DEFAULT_TOL[stg] == L.Params(lattice=59, nx=8, ny=8, nz=8, storage=stg).to_c().tol
+    assert L.DEFAULT_TOL[L.STORE_BF16] == 2.0**-9 and L.DEFAULT_TOL[L.STORE_F16] == 2.0**-12
 
 
 def _p(L, **kw):

@@ -39,6 +39,12 @@ CASES = [
     # (the paper leaves rho0 free)
     ("d2q21_rho0", 21, (40, 24), {}),
     ("d3q59_rho0", 59, (20, 12, 10), {}),
+    # the stencil formulation of items 10-11 (Laplacian and traceless
+    # second-derivative stencils of Table III through the product rule);
+    # the oracle runs the same formulation
+    ("d2q21_stencil", 21, (40, 24), dict(flags=2)),
+    ("d3q59_stencil", 59, (20, 12, 10), dict(flags=2)),
+    ("d3q59_stencil_tiles", 59, (40, 24, 36), dict(flags=2)),
 ]
 NSTEPS = {"d3q59_tiles": 3, "d3q59_tiles_wide": 3}
 GAMMA = {"d2q21_gamma": 0.4, "d2q21_gamma_neg": -0.4, "d3q59_gamma": 0.4}
@@ -48,6 +54,8 @@ RHO0 = {"d2q21_rho0": 1.0, "d3q59_rho0": 1.0}
 def case(name, lattice, shape):
     rho, u, model = small_case(lattice, shape, gamma=GAMMA.get(name, 0.0))
     model["rho0"] = RHO0.get(name, model["rho0"])
+    if "stencil" in name:
+        model["flags"] = 2   # the oracle's ORC_STENCIL_CLOSURE
     return rho, u, model
 
 

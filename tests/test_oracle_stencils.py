@@ -5,6 +5,9 @@ IX; Supplemental items 2-8).
   are exact on polynomials of degree <= 4 (their Taylor conditions in Sec. IV),
   so on a periodic lattice they reproduce the continuum derivatives (sympy) at
   every site farther than the stencil radius from the periodic seam.
+* The Laplacian and traceless second-derivative stencils (Secs. IV C, IV D)
+  are exact on polynomials of degree <= 3 and not on quartics (their Taylor
+  conditions leave the fourth-order term): second-order accurate.
 * Sec. VI: the total lattice force vanishes on a periodic lattice.
 * Sec. IX: the iteration solves a linear system; the iterate matches a dense
   direct solve built column by column from the one-pass map.
@@ -151,3 +154,39 @@ def test_iteration_matches_direct_solve(orc, Q, shape):
     assert np.abs(F["jt"][:, :d] - jt_direct).max() <= 1e-11 * scale
     # the spectral radius of T is below one here (the iteration converges)
     assert np.max(np.abs(np.linalg.eigvals(Tm))) < 1.0
+
+
+def _poly(d, deg, rng, scale):
+    syms = sp.symbols("x y z")[:d]
+    e = sp.Float(0.7)
+    for exps in __import__("itertools").product(range(deg + 1), repeat=d):
+        if 0 < sum(exps) <= deg:
+            e += sp.Float(rng.uniform(-1, 1) * scale ** sum(exps)) * sp.Mul(*[s**k for s, k in zip(syms, exps)])
+    return syms, e
+
+
+@pytest.mark.parametrize("Q,shape", [(21, (14, 12)), (59, (9, 10, 8))])
+def test_second_derivative_stencils_exact_on_cubics(orc, Q, shape):
+    """d_a d_b g from the Table III Laplacian + traceless stencils equals the
+    exact Hessian of any cubic at every site one step off the seam, and
+    misses that of a quartic by the fourth-order term."""
+    d = len(shape)
+    rng = np.random.default_rng(21)
+    m = orc.Model(Q=Q, nx=shape[0], ny=shape[1], nz=shape[2] if d == 3 else 1)
+    shift = shape[0] / 2
+    ok = _interior(shape, 1)
+    for deg, exact_expected in ((3, True), (4, False)):
+        syms, e = _poly(d, deg, rng, 0.1)
+        g = _poly_field(shape, e, syms, shift)
+        H = orc.hessian(m, g)
+        err = 0.0
+        scale = 0.0
+        for a in range(d):
+            for b in range(d):
+                ref = _poly_field(shape, sp.diff(e, syms[a], syms[b]), syms, shift)
+                err = max(err, np.abs(H[ok, a, b] - ref[ok]).max())
+                scale = max(scale, np.abs(ref[ok]).max())
+        if exact_expected:
+            assert err <= 1e-12 * max(scale, 1.0), (deg, err)
+        else:
+            assert err > 1e-6 * scale, (deg, err)
