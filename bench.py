@@ -11,8 +11,11 @@ synthetic start: the first steps relax the initial tanh walls and noise and
 need up to twice the solve passes of the rest of a 2000-step run.
 
 roofline: the kernel class with the largest share of the timed region,
-its algorithmic bytes per launch (per-site bytes below x sites) over its
-average HIP-event duration on the library's stream, against 8 TB/s.
+its algorithmic bytes per launch (per-site bytes x sites) over its average
+HIP-event duration on the library's stream, against 8 TB/s.  For the solve
+pass the per-site bytes are the pass's minimum, (1 + 3D) r (rho, j0', the
+iterate in and out); the bytes the fused pass moves by design (it also
+reads p and P1) are reported beside them.
 step_hbm: the whole step's bandwidth (population floor 2 Q s per site, the
 kernels' algorithmic bytes, the counters' measured bytes) against 8 TB/s and
 against a streaming copy measured in the same run.
@@ -41,7 +44,8 @@ def site_bytes(kernel, Q, D, s, r, warm, cheb=False, pull=False):
     population or field word the kernel must read or write once (stencil
     neighbours are reuse, not extra traffic).  The rest population is one
     plane of t0 bytes (FP64 beside FP64/FP32 storage, FP32 beside BF16/FP16);
-    BF16/FP16 storage adds a 2-byte density record per site.  The moments
+    the deviation forms (FP32, BF16, FP16 storage) add the writer's 2-byte
+    density record per site.  The moments
     kernel writes the exact pulled mass (FP64), which the collision reads in
     place of the pulled populations when gamma = 0 (pull=False); with
     gamma != 0 the collision pulls the populations again."""
@@ -163,28 +167,41 @@ def run_batch(workload, steps, warmup, fixed_iter, graph=True, limit=None, autot
     return out
 
 
+def minimal_pass_bytes(D, r, cheb=False):
+    """Bytes per site that one pass of the j~ fixed point (items 3-8) cannot
+    do without: rho and j0' at the site, the current iterate in, the next one
+    out ((1 + 3D) r; Chebyshev also reads the iterate before).  The fused
+    pass moves 2 r more: it reads the per-step planes p - p_ref and P1
+    (formed in FP64 by the moments kernel) instead of evaluating the EOS's
+    exp, sin and cos at every stencil point of every pass."""
+    return (1 + 3 * D) * r + (D * r if cheb else 0)
+
+
 def roofline(res, storage, warm=2, cheb=False):
     prof = res["prof"]
     Q, D, N = res["Q"], res["D"], res["N"]
     s = STORE_BYTES[storage]
-    r = 8 if storage == "f64" else 4
+    r = res.get("rsize", 8 if storage == "f64" else 4)
     pull = res.get("pull", False)
     total = {k: v[0] for k, v in prof.items()}
     dom = max(total, key=total.get)
     ms, n = prof[dom]
     avg_s = ms / 1e3 / max(n, 1)
-    bytes_launch = site_bytes(dom, Q, D, s, r, warm, cheb, pull) * N
-    achieved = bytes_launch / avg_s / 1e9
+    design = site_bytes(dom, Q, D, s, r, warm, cheb, pull)
+    alg = minimal_pass_bytes(D, r, cheb) if dom == "iter_fused" else design
+    achieved = alg * N / avg_s / 1e9
     per_kernel = {k: dict(ms_total=round(v[0], 3), launches=v[1],
                           avg_us=round(1e3 * v[0] / max(v[1], 1), 2),
                           gbs=round(site_bytes(k, Q, D, s, r, warm, cheb, pull) * N / (v[0] / 1e3 / max(v[1], 1)) / 1e9, 1)
                           if v[1] else None)
                   for k, v in prof.items()}
     traffic = measured_traffic(dom, res)
-    return dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                bytes_per_site=site_bytes(dom, Q, D, s, r, warm, cheb, pull), launches=n,
-                avg_launch_us=round(avg_s * 1e6, 2)), per_kernel
+    out = dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+               frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic, bytes_per_site=alg, launches=n,
+               avg_launch_us=round(avg_s * 1e6, 2))
+    if alg != design:
+        out.update(design_bytes_per_site=design, design_frac=round(design * N / avg_s / 1e9 / HBM_PEAK_GBS, 4))
+    return out, per_kernel
 
 
 def traffic_table(res):

@@ -18,6 +18,7 @@
 
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include <type_traits>
 
 #include "lattice.hpp"
 
@@ -768,13 +769,19 @@ __global__ void __launch_bounds__(256) k_collide(const Domain* __restrict__ tab,
     // multiply-adds fused only as written in each expression, so that both
     // instantiations round a gamma = 0 site identically
 #pragma clang fp contract(on)
-    // The collision computes in FP64 whatever the field precision: at an
-    // interface Xi' and Sigma are large next to the flow (Xi' holds
-    // p d(c_s^2), of order 1e-2 where u is 1e-4), and their Hermite terms
-    // leave no first moment only in exact arithmetic; FP32 rounding of those
-    // terms feeds the momentum of every step.  The arithmetic is a few
-    // percent of this memory-bound kernel's time.
-    using E = double;
+    // Precision.  The O(1) parts -- c_s^2, the local weights and the
+    // per-shell rest part (1-g)(w_k rho - o_k) -- are FP64 in every form.
+    // The per-velocity Hermite terms (E) are FP64 beside FP64 and FP32
+    // storage: at an interface Xi' and Sigma are large next to the flow (Xi'
+    // holds p d(c_s^2), of order 1e-2 where u is 1e-4), their terms leave no
+    // first moment only in exact arithmetic, and FP32 rounding of them would
+    // feed the momentum of every step (the arithmetic is then a few percent
+    // of this memory-bound kernel's time).  Beside BF16/FP16 storage with
+    // FP32 fields they are FP32: the stored deviation rounds each of those
+    // terms at 2^-9 (BF16) or 2^-12 (FP16) of its size, 2^15 and 2^12 times
+    // the FP32 rounding, and in FP64 this kernel would be bound by FP64
+    // issue rather than by its 230 bytes per site.
+    using E = typename std::conditional<sizeof(S) == 2 && sizeof(R) == 4, float, double>::type;
     using L = Lattice<Q>;
     constexpr int D = L::D;
     const Where w = locate(tab, tiles);
@@ -787,7 +794,6 @@ __global__ void __launch_bounds__(256) k_collide(const Domain* __restrict__ tab,
     const R* jt = (info[w.dom].final_buf ? jtB : jtA) + o;
 
     const double r64 = ldo(mass + o, i0);   // the exact pulled mass of item 1
-    const E r = E(r64);
     E us[3] = {E(0), E(0), E(0)}, fs[3] = {E(0), E(0), E(0)}, js[3] = {E(0), E(0), E(0)};
 #pragma unroll
     for (int a = 0; a < D; ++a) {
@@ -804,18 +810,21 @@ __global__ void __launch_bounds__(256) k_collide(const Domain* __restrict__ tab,
     const E gm = E(dm.cf.gamma);
     const E c0 = E(dm.cf.c0sq);
     const E ic0 = E(1) / c0;
-    // n_eq pieces (local weights)
-    const E cs2 = eos_cs2<E>(dm.cf.eos, r);
+    // n_eq pieces (local weights), (1-g) w_k rho in FP64
+    const double cs2 = eos_cs2<double>(dm.cf.eos, r64);
+    double wl64[8];
+    shell_weights<Q, double>(cs2, wl64);
+    const double omg64 = 1.0 - dm.cf.gamma;   // weight of n_eq
+#pragma unroll
+    for (int k = 0; k < L::NSHELL; ++k) wl64[k] *= omg64 * r64;
     E wl[8];
-    shell_weights<Q, E>(cs2, wl);
-    const E ics = E(1) / cs2;
+#pragma unroll
+    for (int k = 0; k < L::NSHELL; ++k) wl[k] = E(wl64[k]);
+    const E ics = E(1.0 / cs2);
     const E uu = us[0] * us[0] + us[1] * us[1] + us[2] * us[2];
     const E a0m = -E(0.5) * uu * ics;   // a0 - 1
     const E a1 = ics;
     const E a2 = E(0.5) * ics * ics;
-    const E omg = E(1) - gm;  // weight of n_eq
-#pragma unroll
-    for (int k = 0; k < L::NSHELL; ++k) wl[k] *= omg * r;
     // Delta^corr pieces: W_k [ b.c + c.S'.c + s0 + X'(c,c,c) ]
     E trS = E(0);
 #pragma unroll
@@ -859,12 +868,12 @@ __global__ void __launch_bounds__(256) k_collide(const Domain* __restrict__ tab,
 #pragma unroll
         for (int k = 1; k < L::NSHELL; ++k) {
             ownoff[k] = rest_offset(dm.ds, k, rec);
-            rest[k] = wl[k] - omg * E(ownoff[k]);
+            rest[k] = E(wl64[k] - omg64 * (double)ownoff[k]);
             moved += (double)kShellSize<Q>(k) * (double)ownoff[k];
         }
     } else {
 #pragma unroll
-        for (int k = 1; k < L::NSHELL; ++k) rest[k] = wl[k];
+        for (int k = 1; k < L::NSHELL; ++k) rest[k] = E(wl64[k]);
     }
     double dsum = 0.0;   // pull: sum of (n*_i - n_i)
 #pragma unroll

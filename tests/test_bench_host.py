@@ -52,6 +52,27 @@ def test_step_hbm_sums_launches():
     assert out["measured"] is None
 
 
+def test_roofline_solve_pass_on_its_minimal_bytes():
+    # the solve pass is priced on the bytes a pass cannot do without, rho,
+    # j0' and the iterate in and out: (1 + 3D) r, 40 B in 3D FP32, 28 B in 2D
+    assert bench.minimal_pass_bytes(3, 4) == 40
+    assert bench.minimal_pass_bytes(2, 4) == 28
+    assert bench.minimal_pass_bytes(3, 4, cheb=True) == 52
+    N = 1 << 20
+    prof = {k: (0.0, 0) for k in ("moments", "force", "closure1", "closure2", "collide")}
+    prof.update(collide=(1.0, 1), iter_fused=(2.0, 10))
+    res = dict(prof=prof, Q=59, D=3, N=N, workload="none", storage="f32")
+    roof, _ = bench.roofline(res, "f32", warm=1)
+    assert roof["kernel"] == "iter_fused" and roof["bytes_per_site"] == 40
+    assert roof["design_bytes_per_site"] == 48
+    assert roof["achieved"] == pytest.approx(40 * N / 200e-6 / 1e9, abs=0.1)
+    assert roof["frac"] == pytest.approx(roof["achieved"] / 8000.0, abs=1e-4)
+    # another dominant kernel keeps its own algorithmic bytes
+    prof.update(collide=(5.0, 1))
+    roof, _ = bench.roofline(dict(res, prof=prof), "f32", warm=1)
+    assert roof["kernel"] == "collide" and roof["bytes_per_site"] == 350 and "design_bytes_per_site" not in roof
+
+
 def test_traffic_table_matches_workload_only():
     res = dict(workload="no_such_workload", storage="f32")
     assert bench.traffic_table(res) is None
