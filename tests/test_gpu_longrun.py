@@ -81,7 +81,7 @@ def _check(name, form, cp, e_rho, e_u, abs_u):
     b_rho, b_u = BOUNDS[form]
     if form == "f32" and name == "slab_column":
         b_u = SLAB_F32_EU
-    print(f"{name} {form} step {cp}: e_rho {e_rho:.2e} (<= {b_rho:.0e}) e_u {e_u:.2e} (<= {b_u:.0e}) "
+    print(f"{name} {form} step {cp}: e_rho {e_rho:.2e} (<= {b_rho:g}) e_u {e_u:.2e} (<= {b_u:g}) "
           f"|du| {abs_u:.2e}", flush=True)
     assert e_rho <= b_rho and e_u <= b_u, (name, form, cp, e_rho, e_u)
     if form == "bf16":
