@@ -8,10 +8,11 @@ Cases (inputs from lb2p_workloads, the same builders the GPU side uses):
   droplet48    D3Q59 48^3 reduction of the 128^3 droplet workload (radius
                scaled to 12), 1000 steps, references at 100 and 1000;
   batch16      the first 16 domains of the 512-domain D2Q21 batch (their own
-               EOS and kappa), 1000 steps, references at 100 and 1000.
+               EOS and kappa), 1000 steps, references at 100 and 1000;
+  batch512_100 all 512 domains of the batch, 100 steps, reference at 100.
 Each reference keeps rho and u at a seeded sample of sites (every site of
 8 sampled (x, y) columns for the slab, 4096 sites for the droplet, 512 per
-domain for the batch) plus max|u| and max rho over all sites, the scales of
+domain for batch16, 32 per domain for batch512_100) plus max|u| and max rho over all sites, the scales of
 the relative errors.  The oracle runs its own stop rule from a zero start
 (tol 1e-13).
 
@@ -107,6 +108,7 @@ CASES = {
     "slab_column": lambda: run_single("slab_column", "d3q59_256_slab", (16, 16, 256), [500, 1000, 2000], 0),
     "droplet48": lambda: run_single("droplet48", "d3q59_128_droplet", (48, 48, 48), [100, 1000], 4096),
     "batch16": lambda: run_batch("batch16", 16, [100, 1000], 512),
+    "batch512_100": lambda: run_batch("batch512_100", 512, [100], 32),
 }
 
 
