@@ -79,7 +79,7 @@ def _errors(got, ref_rho, ref_u, rhomax, umax):
 
 def _check(name, form, cp, e_rho, e_u, abs_u):
     b_rho, b_u = BOUNDS[form]
-    if form == "f32" and name == "slab_column":
+    if form == "f32" and name in ("slab_column", "c3"):
         b_u = SLAB_F32_EU
     print(f"{name} {form} step {cp}: e_rho {e_rho:.2e} (<= {b_rho:g}) e_u {e_u:.2e} (<= {b_u:g}) "
           f"|du| {abs_u:.2e}", flush=True)
@@ -120,38 +120,70 @@ def test_c1_1000_steps(L, c1_ref, form):
         _check("c1", form, c, *_errors(g, rr, ur, float(rr.max()), umax))
 
 
-@pytest.mark.timeout(900)
-def test_c5_512_two_droplets_500_steps_against_gpu_f64(L):
-    """512^3 two droplets colliding, 500 steps: FP32 and BF16 storage against
-    the library's FP64 path (flagged: the host cannot hold the FP64 oracle's
-    2 x 63 GB of populations).  The references run one after the other;
-    rho and u come back to the host at a seeded sample of 2^20 sites."""
+def _against_gpu_f64(L, workload, checkpoints, forms, nsample, seed):
+    """Run the workload at full size in FP64 and in each storage form, one
+    after the other, and return per form the (rho, u) sample at each
+    checkpoint plus the FP64 run's whole-lattice max rho and max|u| there."""
     import torch
-    entry, shape, rho, u = W.build("d3q59_512_two_droplets")
+    entry, shape, rho, u = W.build(workload)
     N = rho.size
-    idx = np.sort(np.random.default_rng(1406).choice(N, size=1 << 20, replace=False))
-    steps = entry["steps"]
+    idx = np.sort(np.random.default_rng(seed).choice(N, size=min(nsample, N), replace=False))
     torch.cuda.set_device(0)
     res = {}
-    for form in ("f64", "f32", "bf16"):
+    for form in ("f64",) + tuple(forms):
         st, ip, tol = _form(L, form)
         P = L.Params(nx=shape[0], ny=shape[1], nz=shape[2], storage=st, iter_prec=ip, tol=tol, max_iter=300,
                      **W.model_kwargs(entry["model"]))
         t0 = time.time()
+        out = []
         with L.Context(P, stream=torch.cuda.current_stream()) as ctx:
             ctx.init(torch.tensor(rho, device="cuda:0"), torch.tensor(u, device="cuda:0").contiguous())
-            for s in range(0, steps, 100):
-                ctx.step(100)
-                print(f"c5 {form}: step {s + 100}, {time.time() - t0:.0f} s", flush=True)
+            done = 0
             rd = torch.empty(N, dtype=torch.float64, device="cuda:0")
             ud = torch.empty((3, N), dtype=torch.float64, device="cuda:0")
-            ctx.moments_into(rd, ud)
             ti = torch.as_tensor(idx, device="cuda:0")
-            res[form] = (rd[ti].cpu().numpy(), ud[:, ti].cpu().numpy(),
-                         float(rd.max()), float(ud.square().sum(0).sqrt().max()))
+            for c in checkpoints:
+                while done < c:
+                    k = min(100, c - done)
+                    ctx.step(k)
+                    done += k
+                    print(f"{workload} {form}: step {done}, {time.time() - t0:.0f} s", flush=True)
+                ctx.moments_into(rd, ud)
+                out.append((rd[ti].cpu().numpy(), ud[:, ti].cpu().numpy(), float(rd.max()),
+                            float(ud.square().sum(0).sqrt().max())))
             del rd, ud, ti
+        res[form] = out
         torch.cuda.empty_cache()
-    rr, ur, rhomax, umax = res["f64"]
+    return res
+
+
+@pytest.mark.timeout(900)
+def test_c5_512_two_droplets_500_steps_against_gpu_f64(L):
+    """512^3 two droplets colliding, 500 steps: FP32 and BF16 storage against
+    the library's FP64 path (flagged: the host cannot hold the FP64 oracle's
+    2 x 63 GB of populations).  rho and u come back to the host at a seeded
+    sample of 2^20 sites."""
+    entry = W.load_params()["d3q59_512_two_droplets"]
+    steps = entry["steps"]
+    res = _against_gpu_f64(L, "d3q59_512_two_droplets", [steps], ("f32", "bf16"), 1 << 20, 1406)
+    rr, ur, rhomax, umax = res["f64"][0]
     assert umax > 1e-3   # the droplets still move
     for form in ("f32", "bf16"):
-        _check("c5", form, steps, *_errors(res[form][:2], rr, ur, rhomax, umax))
+        _check("c5", form, steps, *_errors(res[form][0][:2], rr, ur, rhomax, umax))
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("name,workload,checkpoints", [("c2", "d3q59_128_droplet", [100, 1000]),
+                                                       ("c3", "d3q59_256_slab", [500, 1000, 2000])])
+def test_full_size_run_against_gpu_f64(L, name, workload, checkpoints):
+    """The 128^3 droplet for its 1000 steps and the 256^3 slab for its 2000,
+    at full size, in FP32, FP16 and BF16 storage against the library's FP64
+    path (itself within 1e-10 of the oracle on every window the oracle can
+    run), at the stated bounds; the oracle references of the same workloads
+    on reduced grids are in test_gpu_longrun_oracle.py."""
+    forms = ("f32", "f16", "bf16")
+    res = _against_gpu_f64(L, workload, checkpoints, forms, 1 << 20, 1407)
+    for k, c in enumerate(checkpoints):
+        rr, ur, rhomax, umax = res["f64"][k]
+        for form in forms:
+            _check(name, form, c, *_errors(res[form][k][:2], rr, ur, rhomax, umax))
