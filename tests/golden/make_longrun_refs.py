@@ -71,44 +71,75 @@ def run_single(case, workload, shape, checkpoints, nsample):
                 tol=TOL, oracle_seconds=round(time.time() - t0, 1), threads=O.num_threads())
 
 
-def run_batch(case, ndom, checkpoints, per_dom):
+def _batch_domain(args):
+    """One domain of a batch case (runs in a worker process)."""
+    k, ndom, checkpoints, idx = args
+    entry = W.load_params()["d2q21_batch512"]
+    dd = entry["domains"][k]
+    shape = (dd["nx"], dd["ny"])
+    rho, u = W.droplet(shape, dd["radius"], dd["rho_g"], dd["rho_l"], width=dd["width"], noise=entry["noise"],
+                       seed=dd["seed"])
+    m = O.Model(nx=shape[0], ny=shape[1], nz=1, tol=TOL, max_iter=4000, **W.oracle_kwargs(dd))
+    n = O.init(m, rho, u.T.copy())
+    done, vv, um, rm = 0, [], [], []
+    for c in checkpoints:
+        O.step(m, n, c - done)
+        done = c
+        F = O.fields(m, n)
+        assert F["converged"]
+        uu = F["u"][:, :2]
+        vv.append(np.concatenate([F["rho"][idx][None], uu[idx].T], axis=0))
+        um.append(float(np.sqrt((uu**2).sum(axis=1)).max()))
+        rm.append(float(F["rho"].max()))
+    return k, shape, np.stack(vv), um, rm
+
+
+def run_batch(case, ndom, checkpoints, per_dom, workers=1):
+    """Domains one by one (the oracle's threads within each) or, with
+    workers > 1, one domain per single-threaded worker process."""
     doms = W.build_batch("d2q21_batch512", limit=ndom)
     rng = np.random.default_rng(1402016)
-    idx_all, vals_dom, umax, rmax = [], [], [], []
+    idxs = []
+    for dd, shape, rho, u in doms:
+        N = shape[0] * shape[1]
+        idxs.append(np.sort(rng.choice(N, size=min(per_dom, N), replace=False)))
     t0 = time.time()
+    jobs = [(k, ndom, checkpoints, idxs[k]) for k in range(len(doms))]
+    results = [None] * len(doms)
+    if workers > 1:
+        import multiprocessing as mp
+        os.environ["OMP_NUM_THREADS"] = "1"
+        with mp.get_context("spawn").Pool(workers) as pool:
+            for r in pool.imap_unordered(_batch_domain, jobs):
+                results[r[0]] = r
+                print(f"{case}: domain {r[0]} {r[1]} done, {time.time() - t0:.0f} s", flush=True)
+    else:
+        for j in jobs:
+            r = _batch_domain(j)
+            results[r[0]] = r
+            print(f"{case}: domain {r[0]} {r[1]} done, {time.time() - t0:.0f} s", flush=True)
+    idx_all, vals_dom, umax, rmax = [], [], [], []
     off = 0
     for k, (dd, shape, rho, u) in enumerate(doms):
-        m = O.Model(nx=shape[0], ny=shape[1], nz=1, tol=TOL, max_iter=4000, **W.oracle_kwargs(dd))
-        idx = np.sort(rng.choice(m.N, size=min(per_dom, m.N), replace=False))
-        n = O.init(m, rho, u.T.copy())
-        done, vv, um, rm = 0, [], [], []
-        for c in checkpoints:
-            O.step(m, n, c - done)
-            done = c
-            F = O.fields(m, n)
-            assert F["converged"]
-            uu = F["u"][:, :2]
-            vv.append(np.concatenate([F["rho"][idx][None], uu[idx].T], axis=0))
-            um.append(float(np.sqrt((uu**2).sum(axis=1)).max()))
-            rm.append(float(F["rho"].max()))
-        idx_all.append(idx + off)
-        vals_dom.append(np.stack(vv))          # [ncp, 3, nsample_dom]
+        _, _, vv, um, rm = results[k]
+        idx_all.append(idxs[k] + off)
+        vals_dom.append(vv)                    # [ncp, 3, nsample_dom]
         umax.append(um)
         rmax.append(rm)
-        off += m.N
-        print(f"{case}: domain {k} {shape} done, {time.time() - t0:.0f} s", flush=True)
+        off += shape[0] * shape[1]
     np.save(os.path.join(OUT, f"{case}_idx.npy"), np.concatenate(idx_all).astype(np.int64))
     np.save(os.path.join(OUT, f"{case}_vals.npy"), np.concatenate(vals_dom, axis=2))
     return dict(workload="d2q21_batch512", ndom=ndom, checkpoints=checkpoints,
                 umax_per_domain=umax, rhomax_per_domain=rmax, per_domain_sample=per_dom, tol=TOL,
-                oracle_seconds=round(time.time() - t0, 1), threads=O.num_threads())
+                oracle_seconds=round(time.time() - t0, 1),
+                threads=1 if workers > 1 else O.num_threads(), workers=workers)
 
 
 CASES = {
     "slab_column": lambda: run_single("slab_column", "d3q59_256_slab", (16, 16, 256), [500, 1000, 2000], 0),
     "droplet48": lambda: run_single("droplet48", "d3q59_128_droplet", (48, 48, 48), [100, 1000], 4096),
     "batch16": lambda: run_batch("batch16", 16, [100, 1000], 512),
-    "batch512_100": lambda: run_batch("batch512_100", 512, [100], 32),
+    "batch512_100": lambda: run_batch("batch512_100", 512, [100], 32, workers=8),
 }
 
 

@@ -209,8 +209,8 @@ LONG_RUNS = [
 
 @pytest.mark.parametrize("name,storage,steps", LONG_RUNS)
 def test_workload_runs_stay_bounded(L, name, storage, steps):
-    """The workloads' own step counts at full size, in the benchmark's
-    configuration (tolerance stop rule, extrapolated warm start): no
+    """The workloads' own step counts at full size (tolerance stop rule at
+    the storage's default tolerance, linearly extrapolated warm start): no
     non-finite value, the flow velocity stays small (|u| < 0.05) and the
     mass is conserved (rest-plane balance)."""
     import torch
