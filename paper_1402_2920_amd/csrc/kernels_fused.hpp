@@ -17,10 +17,11 @@
 // In 3D a block owns a TX x TY tile of an xy plane and marches through TZ
 // planes of z.  Its threads are the (TX+4) x (TY+4) points where q is needed
 // (the tile and a 2-wide frame for the outer first derivative).  Each thread keeps, in
-// registers, the last five planes of u at its point (z-derivatives of u, and
-// u_k at the output plane) and of q_az (z-derivative in d_b q_ab); LDS holds
-// one u plane (tile + 4-wide frame) and one q plane (tile + 2-wide frame)
-// for the x and y derivatives.
+// registers, five planes of u at its point (z-derivatives of u, and u_k at
+// the output plane) and of q_az (z-derivative in d_b q_ab); LDS holds a u
+// plane (tile + 4-wide frame) and a q plane (tile + 2-wide frame) for the x
+// and y derivatives, in two buffers each, so that a plane step writes one
+// buffer while it reads the other and needs a single barrier.
 #pragma once
 
 #include "kernels.hpp"
@@ -105,8 +106,9 @@ k_iter_fused3(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, It
     constexpr int UX = TX + 8, UY = TY + 8;   // u points
     constexpr int NFRAME = UX * UY - QX * QY;
     static_assert(NFRAME <= QX * QY, "frame larger than the block");
-    __shared__ R su[3][UY][UX];
-    __shared__ R sq[5][QY][QX];   // q_xx, q_yy, q_xy, q_xz, q_yz (q_zz is only needed along z)
+    // two buffers of each plane: a step writes one while it reads the other
+    __shared__ R su[2][3][UY][UX];
+    __shared__ R sq[2][5][QY][QX];   // q_xx, q_yy, q_xy, q_xz, q_yz (q_zz is only needed along z)
 
     const Tile tl = tiles[blockIdx.x];
     if (tl.dom < 0 || iter_skip(ic, tl.dom, it)) return;   // uniform per block
@@ -183,30 +185,42 @@ k_iter_fused3(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, It
     // addressed by a compile-time phase avoid the moves but need the loop
     // unrolled five times, which costs registers and, measured, occupancy
     // and time.)
-    R ur[5][3];        // u at planes lead-4 .. lead (lead-4 is the output plane)
-    R qz[5][3];        // q_xz, q_yz, q_zz at planes c-4 .. c
-    R sd[3][3];        // x,y part of d_b q_ab at planes c-2 .. c
+    R ur[5][3];        // u at five consecutive planes (see the step below)
+    R qz[5][3];        // q_xz, q_yz, q_zz at planes c-4 .. c of the last q plane c
+    R sd[2][3];        // x,y part of d_b q_ab at the last two planes it was taken
 #pragma unroll
     for (int k = 0; k < 5; ++k)
 #pragma unroll
         for (int a = 0; a < 3; ++a) { ur[k][a] = R(0); qz[k][a] = R(0); }
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
+    for (int k = 0; k < 2; ++k)
 #pragma unroll
         for (int a = 0; a < 3; ++a) sd[k][a] = R(0);
     R dmax = R(0), dsum = R(0);   // dsum only carries a NaN (fmax drops it)
     const R c12 = R(1.0 / 12.0);
 
-    // Step k: lead plane z0-4+k, centre plane c = z0-6+k, output plane
-    // z0-8+k (written for 8 <= k < TZ+8).  Steps run in pairs, so one past
-    // the end may run with its output dropped; every plane index stays in
-    // [z0-6, z0+TZ+6) and is wrapped.
-    const int nsteps = TZ + 8;
-    auto out_plane = [&](int k) -> bool { return k >= 8 && k < nsteps && z0 + k - 8 < nz; };
+    // Step k, with c_k = z0-6+k and one barrier, at its end:
+    //   1. u plane c_k into LDS buffer k&1 (own point from the ring, frame
+    //      point loaded);
+    //   2. q at plane c_{k-1} from LDS buffer (k-1)&1 (written last step)
+    //      and the ring, into q buffer (k-1)&1;
+    //   3. the x,y part of d_b q_ab at plane c_{k-2} from q buffer k&1
+    //      (written last step), and the next iterate at the output plane
+    //      o = c_{k-3} = z0-9+k (written for 9 <= k < TZ+9);
+    //   4. the ring shifts in the lead plane z0-4+k.
+    // Before its shift the ring holds planes z0-9+k .. z0-5+k: ur[0] is the
+    // output plane, ur[2] = c_{k-1}, ur[3] = c_k.  The three phases touch
+    // different buffers, so one barrier per step orders every LDS write
+    // before its reads in the next step and every read before the write two
+    // steps later.  Steps run in pairs, so one past the end may run with its
+    // output dropped; every plane index stays in [z0-7, z0+TZ+7) and is
+    // wrapped.
+    const int nsteps = TZ + 9;
+    auto out_plane = [&](int k) -> bool { return k >= 9 && k < nsteps && z0 + k - 9 < nz; };
     // Loaders of the inputs of step k, one per group of fields.
     auto load_own = [&](int k, StepIn<R>& in) {
         const bool own = owned && out_plane(k);
-        const unsigned io = own ? (col + plane * (unsigned)(z0 + k - 8)) * (unsigned)sizeof(R) : OUT;
+        const unsigned io = own ? (col + plane * (unsigned)(z0 + k - 9)) * (unsigned)sizeof(R) : OUT;
 #pragma unroll
         for (int a = 0; a < 3; ++a) in.j[a] = bload<R>(bJ[a], io);
         in.rho = bload<R>(bRho, io);
@@ -228,7 +242,7 @@ k_iter_fused3(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, It
         for (int a = 0; a < 3; ++a) in.fu[a] = bload<R>(bU[a], ifr);
     };
     auto load_pp = [&](int k, StepIn<R>& in) {
-        const unsigned ic_ = (col + plane * (unsigned)wrap3(z0 - 6 + k, nz)) * (unsigned)sizeof(R);
+        const unsigned ic_ = (col + plane * (unsigned)wrap3(z0 - 7 + k, nz)) * (unsigned)sizeof(R);
         in.p = pref + bload<R>(bP, ic_);
         in.P1 = bload<R>(bP1, ic_);
     };
@@ -237,67 +251,60 @@ k_iter_fused3(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, It
     // its last use, with the inputs of step k+2 (the same phase two steps
     // later): every load has two steps to complete, in two register sets.
     auto run_step = [&](int k, StepIn<R>& in) {
-        // 1. lead plane of the u ring at this thread's point
+        const int b = k & 1;
+        // 1. u plane c_k into LDS buffer b: own point and frame point
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
-#pragma unroll
-            for (int a = 0; a < 3; ++a) ur[s][a] = ur[s + 1][a];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) ur[4][a] = in.u[a];
-        load_lead(k + 2, in);
-        // 2. u plane c = lead-2 into LDS: own point and frame point
-#pragma unroll
-        for (int a = 0; a < 3; ++a) su[a][qy + 2][qx + 2] = ur[2][a];
+        for (int a = 0; a < 3; ++a) su[b][a][qy + 2][qx + 2] = ur[3][a];
         if (has_frame) {
 #pragma unroll
-            for (int a = 0; a < 3; ++a) su[a][fy][fx] = in.fu[a];
+            for (int a = 0; a < 3; ++a) su[b][a][fy][fx] = in.fu[a];
         }
         load_frame(k + 2, in);
-        __syncthreads();
-        // 3. q at plane c
-        if (k >= 4) {
+        // 2. q at plane c_{k-1}
+        if (k >= 5) {
+            const int bu = b ^ 1;
             R G[3][3];   // G[a][b] = d_a u_b
 #pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                G[0][b] = d1<R>(su[b][qy + 2][qx], su[b][qy + 2][qx + 1], su[b][qy + 2][qx + 3],
-                                su[b][qy + 2][qx + 4]);
-                G[1][b] = d1<R>(su[b][qy][qx + 2], su[b][qy + 1][qx + 2], su[b][qy + 3][qx + 2],
-                                su[b][qy + 4][qx + 2]);
-                G[2][b] = d1<R>(ur[0][b], ur[1][b], ur[3][b], ur[4][b]);
+            for (int c = 0; c < 3; ++c) {
+                G[0][c] = d1<R>(su[bu][c][qy + 2][qx], su[bu][c][qy + 2][qx + 1], su[bu][c][qy + 2][qx + 3],
+                                su[bu][c][qy + 2][qx + 4]);
+                G[1][c] = d1<R>(su[bu][c][qy][qx + 2], su[bu][c][qy + 1][qx + 2], su[bu][c][qy + 3][qx + 2],
+                                su[bu][c][qy + 4][qx + 2]);
+                G[2][c] = d1<R>(ur[0][c], ur[1][c], ur[3][c], ur[4][c]);
             }
             const R X = in.P1 * (G[0][0] + G[1][1] + G[2][2]);
             const R p2 = R(2) * in.p;
             const R qxz = in.p * (G[0][2] + G[2][0]);
             const R qyz = in.p * (G[1][2] + G[2][1]);
-            sq[0][qy][qx] = X + p2 * G[0][0];
-            sq[1][qy][qx] = X + p2 * G[1][1];
-            sq[2][qy][qx] = in.p * (G[0][1] + G[1][0]);
-            sq[3][qy][qx] = qxz;
-            sq[4][qy][qx] = qyz;
+            sq[bu][0][qy][qx] = X + p2 * G[0][0];
+            sq[bu][1][qy][qx] = X + p2 * G[1][1];
+            sq[bu][2][qy][qx] = in.p * (G[0][1] + G[1][0]);
+            sq[bu][3][qy][qx] = qxz;
+            sq[bu][4][qy][qx] = qyz;
             if (interior) {   // d_z q_az is only taken at tile points
 #pragma unroll
-                for (int s = 0; s < 4; ++s)
+                for (int s_ = 0; s_ < 4; ++s_)
 #pragma unroll
-                    for (int a = 0; a < 3; ++a) qz[s][a] = qz[s + 1][a];
+                    for (int a = 0; a < 3; ++a) qz[s_][a] = qz[s_ + 1][a];
                 qz[4][0] = qxz; qz[4][1] = qyz; qz[4][2] = X + p2 * G[2][2];
             }
         }
         load_pp(k + 2, in);
-        __syncthreads();
-        // 4. the next iterate at the output plane z0 + k - 8
+        // 3. the x,y part of the divergence at c_{k-2}; the next iterate at
+        //    the output plane c_{k-3}
         R un[3] = {R(0), R(0), R(0)};
         const bool out = owned && out_plane(k);
-        if (k >= 4 && interior) {
+        if (k >= 6 && interior) {
             const int px = qx, py = qy;
 #pragma unroll
-            for (int a = 0; a < 3; ++a) { sd[0][a] = sd[1][a]; sd[1][a] = sd[2][a]; }
+            for (int a = 0; a < 3; ++a) sd[0][a] = sd[1][a];
             // a = x: d_x q_xx + d_y q_xy ; a = y: d_x q_xy + d_y q_yy ; a = z: d_x q_xz + d_y q_yz
-            sd[2][0] = d1<R>(sq[0][py][px - 2], sq[0][py][px - 1], sq[0][py][px + 1], sq[0][py][px + 2]) +
-                       d1<R>(sq[2][py - 2][px], sq[2][py - 1][px], sq[2][py + 1][px], sq[2][py + 2][px]);
-            sd[2][1] = d1<R>(sq[2][py][px - 2], sq[2][py][px - 1], sq[2][py][px + 1], sq[2][py][px + 2]) +
-                       d1<R>(sq[1][py - 2][px], sq[1][py - 1][px], sq[1][py + 1][px], sq[1][py + 2][px]);
-            sd[2][2] = d1<R>(sq[3][py][px - 2], sq[3][py][px - 1], sq[3][py][px + 1], sq[3][py][px + 2]) +
-                       d1<R>(sq[4][py - 2][px], sq[4][py - 1][px], sq[4][py + 1][px], sq[4][py + 2][px]);
+            sd[1][0] = d1<R>(sq[b][0][py][px - 2], sq[b][0][py][px - 1], sq[b][0][py][px + 1], sq[b][0][py][px + 2]) +
+                       d1<R>(sq[b][2][py - 2][px], sq[b][2][py - 1][px], sq[b][2][py + 1][px], sq[b][2][py + 2][px]);
+            sd[1][1] = d1<R>(sq[b][2][py][px - 2], sq[b][2][py][px - 1], sq[b][2][py][px + 1], sq[b][2][py][px + 2]) +
+                       d1<R>(sq[b][1][py - 2][px], sq[b][1][py - 1][px], sq[b][1][py + 1][px], sq[b][1][py + 2][px]);
+            sd[1][2] = d1<R>(sq[b][3][py][px - 2], sq[b][3][py][px - 1], sq[b][3][py][px + 1], sq[b][3][py][px + 2]) +
+                       d1<R>(sq[b][4][py - 2][px], sq[b][4][py - 1][px], sq[b][4][py + 1][px], sq[b][4][py + 2][px]);
             if (out) {
                 const R ri = R(1) / in.rho;
 #pragma unroll
@@ -315,10 +322,19 @@ k_iter_fused3(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, It
             }
         }
         // every lane stores; lanes without an output point write nowhere
-        const unsigned io = out ? (col + plane * (unsigned)(z0 + k - 8)) * (unsigned)sizeof(R) : OUT;
+        const unsigned io = out ? (col + plane * (unsigned)(z0 + k - 9)) * (unsigned)sizeof(R) : OUT;
 #pragma unroll
         for (int a = 0; a < 3; ++a) bstore<R>(bV[a], io, un[a]);
         load_own(k + 2, in);
+        // 4. the ring takes the lead plane
+#pragma unroll
+        for (int s_ = 0; s_ < 4; ++s_)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) ur[s_][a] = ur[s_ + 1][a];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) ur[4][a] = in.u[a];
+        load_lead(k + 2, in);
+        __syncthreads();
     };
 
     StepIn<R> A, B;
