@@ -17,7 +17,7 @@ def _meta():
         return json.load(fh)
 
 
-@pytest.mark.parametrize("name", ["slab_column", "droplet48", "batch16"])
+@pytest.mark.parametrize("name", ["slab_column", "droplet48", "batch16", "batch512_100"])
 def test_reference_is_consistent(name):
     meta = _meta()[name]
     idx = np.load(os.path.join(GOLD, f"{name}_idx.npy"))
@@ -27,7 +27,7 @@ def test_reference_is_consistent(name):
     assert vals.shape[0] == ncp and vals.shape[2] == idx.size
     assert np.all(np.isfinite(vals))
     assert np.unique(idx).size == idx.size and idx.min() >= 0
-    if name == "batch16":
+    if name.startswith("batch"):
         assert vals.shape[1] == 3   # rho, u_x, u_y
         umax = np.array(meta["umax_per_domain"]).T      # [checkpoint][domain]
         rmax = np.array(meta["rhomax_per_domain"]).T
