@@ -45,10 +45,19 @@ CASES = [
     ("d2q21_stencil", 21, (40, 24), dict(flags=2)),
     ("d3q59_stencil", 59, (20, 12, 10), dict(flags=2)),
     ("d3q59_stencil_tiles", 59, (40, 24, 36), dict(flags=2)),
+    # the stencil formulation with the pulling collision (gamma != 0), with
+    # the Chebyshev solver and the two-sweep j~ form, and at rho0 = 1
+    ("d2q21_stencil_gamma", 21, (40, 24), dict(flags=2)),
+    ("d3q59_stencil_gamma", 59, (20, 12, 10), dict(flags=2)),
+    ("d3q59_stencil_cheb_unfused", 59, (20, 12, 10), dict(CHEB, flags=3)),
+    ("d3q59_stencil_rho0", 59, (20, 12, 10), dict(flags=2)),
+    # gamma != 0 with the Chebyshev solver
+    ("d3q59_gamma_cheb", 59, (20, 12, 10), CHEB),
 ]
 NSTEPS = {"d3q59_tiles": 3, "d3q59_tiles_wide": 3}
-GAMMA = {"d2q21_gamma": 0.4, "d2q21_gamma_neg": -0.4, "d3q59_gamma": 0.4}
-RHO0 = {"d2q21_rho0": 1.0, "d3q59_rho0": 1.0}
+GAMMA = {"d2q21_gamma": 0.4, "d2q21_gamma_neg": -0.4, "d3q59_gamma": 0.4, "d2q21_stencil_gamma": -0.3,
+         "d3q59_stencil_gamma": 0.3, "d3q59_gamma_cheb": -0.2}
+RHO0 = {"d2q21_rho0": 1.0, "d3q59_rho0": 1.0, "d3q59_stencil_rho0": 1.0}
 
 
 def case(name, lattice, shape):
