@@ -78,14 +78,15 @@ def _run_single(L, m, rho, u, storage, nsteps, **extra):
         return dict(n=n, rho=r, u=uu, iters=ctx.stats()["iters"])
 
 
+@pytest.mark.parametrize("flags", [0, 2])   # 2: the stencil formulation of items 10-11
 @pytest.mark.parametrize("dim", [2, 3])
-def test_batch_matches_oracle_per_domain(orc, L, dim):
+def test_batch_matches_oracle_per_domain(orc, L, dim, flags):
     doms = _domains_2d() if dim == 2 else _domains_3d()
     nsteps = 4
-    res, _ = _run_batch(L, doms, L.STORE_F64, nsteps, tol=1e-14)
+    res, _ = _run_batch(L, doms, L.STORE_F64, nsteps, tol=1e-14, flags=flags)
     c_lib = L.velocities(doms[0][0]["Q"])
     for k, (m, rho, u) in enumerate(doms):
-        om = orc.Model(**m, tol=1e-14, max_iter=2000)
+        om = orc.Model(**m, tol=1e-14, max_iter=2000, flags=flags)
         n = orc.init(om, rho, u.T.copy())
         orc.step(om, n, nsteps)
         F = orc.fields(om, n)
