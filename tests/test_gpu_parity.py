@@ -195,3 +195,32 @@ def test_warm_start_forms_reach_the_same_fixed_point(orc, L, warm, lattice, shap
     print("warm", warm, lattice, {k: f"{v:.2e}" for k, v in e.items()}, flush=True)
     for k, v in e.items():
         assert v <= F64_TOL, (k, v)
+
+
+# BF16 and FP16 deviation storage on the small grids, with FP32 and with
+# FP64 fields (the field precision of the iteration is independent of the
+# storage format): the populations after one step, rho and u after ten,
+# within the stated bounds of the reduced forms (e_rho, e_u: BF16 2e-2 and
+# 0.5, FP16 3e-4 and 0.15), and the FP64-field form no worse than the
+# FP32-field one beyond a factor of 2 (the storage's rounding sets both).
+REDUCED_BOUNDS = {"STORE_BF16": (2e-2, 0.5), "STORE_F16": (3e-4, 0.15)}
+
+
+@pytest.mark.parametrize("storage", ["STORE_BF16", "STORE_F16"])
+@pytest.mark.parametrize("name,lattice,shape,extra", [c for c in CASES if c[0] in (
+    "d2q21", "d3q59", "d3q59_tiles", "d3q59_stencil")])
+def test_reduced_storage_matches_oracle(orc, L, name, lattice, shape, extra, storage):
+    rho, u, model = case(name, lattice, shape)
+    ns = NSTEPS.get(name, 10)
+    ref = oracle_reference(orc, model, rho, u, nsteps_long=ns)
+    st = getattr(L, storage)
+    e32 = compare(orc, ref, gpu_run(L, model, st, rho, u, nsteps_long=ns, iter_prec=L.ITER_F32, **extra))
+    e64 = compare(orc, ref, gpu_run(L, model, st, rho, u, nsteps_long=ns, iter_prec=L.ITER_F64, tol=1e-13,
+                                    **extra))
+    print(name, storage, "f32 fields", {k: f"{e32[k]:.2e}" for k in ("pop_t1", "rho_tL", "u_tL")},
+          "f64 fields", {k: f"{e64[k]:.2e}" for k in ("pop_t1", "rho_tL", "u_tL")}, flush=True)
+    b_rho, b_u = REDUCED_BOUNDS[storage]
+    for e in (e32, e64):
+        assert e["rho_tL"] <= b_rho and e["u_tL"] <= b_u, e
+    for k in ("pop_t1", "rho_tL", "u_tL"):
+        assert e64[k] <= 2.0 * e32[k] + 1e-12, (k, e32[k], e64[k])
