@@ -481,6 +481,7 @@ def main():
             sites=bN, steps=args.batch_steps, ms_per_step=round(1e3 * bres["seconds"] / args.batch_steps, 4),
             solve=f"{args.batch_iters} j~ passes per step (fixed), all timed steps in one HIP graph launch",
             resid_over_jscale=float(f"{bres['stats']['resid'] / max(bres['stats']['jscale'], 1e-300):.3e}"),
+            resid_note="largest last-pass residual over the domains / largest max|j0'| over the domains",
             max_rel_mass_drift=float(f"{bres['mass_drift']:.3e}"),
             roofline=dict(broof, note="per-kernel HIP events from 4 eager steps after the graph run"),
             kernels={k: v for k, v in bkern.items() if v["launches"]})
