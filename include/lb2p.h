@@ -233,6 +233,15 @@ lb2p_status lb2p_create_batch(int ndom, const lb2p_params *per_dom, void *hip_st
  * Errors: EINVAL, ESTATE, EHIP. */
 lb2p_status lb2p_domain_totals(lb2p_ctx *ctx, double *out);
 
+/* The last j~ solve of each domain (of the last lb2p_step, or of
+ * lb2p_moments when that ran since): the passes it ran, the residual
+ * max_r |j~new - j~| of its last pass and max_r |j0'|, the two sides of the
+ * stop rule of Sec. IX, and whether the rule held (1) or max_iter ended it
+ * (0; always 1 with a fixed pass count).  Host arrays of ndom entries; any
+ * may be NULL.  Synchronises the context's stream.
+ * Errors: EINVAL, ESTATE (no solve yet), EHIP. */
+lb2p_status lb2p_domain_solve(lb2p_ctx *ctx, int *iters, double *resid, double *jscale, int *converged);
+
 /* Pick the kernel block shapes of this context by timing `steps` steps of
  * each candidate on the current state (which is saved and restored), and
  * remember the choice per (lattice, storage, domain sizes) for the process.

@@ -312,6 +312,7 @@ struct lb2p_ctx {
     HostReadback* host = nullptr;               // pinned readback area
     bool status_pending = false;               // tolerance-mode status not yet read
     bool initialized = false;
+    bool solved = false;         // a j~ solve ran since lb2p_init (lb2p_domain_solve)
     bool have_prev = false;      // a time step's j~ exists to start the next solve
     int nprev = 0;               // solves since init whose j~ can start the next one
     // lb2p_moments re-solves the current state into the j~ buffers; the last
@@ -720,6 +721,7 @@ struct Impl {
             c->prev_keep = false;
             c->nprev = std::min(c->nprev + 1, 3);
         }
+        c->solved = true;
         return LB2P_OK;
     }
 
@@ -1407,6 +1409,7 @@ lb2p_status lb2p_init(lb2p_ctx* c, const void* rho, const void* u, int dtype, in
     c->status_pending = false;
     HIPCHK(hipStreamSynchronize(c->stream));
     c->initialized = true;
+    c->solved = false;
     c->have_prev = false;
     c->prev_keep = false;
     c->nprev = 0;
@@ -1553,6 +1556,32 @@ lb2p_status lb2p_domain_totals(lb2p_ctx* c, double* out)
     return LB2P_OK;
 }
 
+lb2p_status lb2p_domain_solve(lb2p_ctx* c, int* iters, double* resid, double* jscale, int* converged)
+{
+    if (!c) return LB2P_EINVAL;
+    if (!c->initialized || !c->solved) return LB2P_ESTATE;
+    std::vector<SolveInfo> info(c->ndom);
+    std::vector<unsigned long long> res((size_t)c->ndom * c->stride), js(c->ndom);
+    HIPCHK(hipMemcpyAsync(info.data(), c->info, c->ndom * sizeof(SolveInfo), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(res.data(), c->res, res.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                          c->stream));
+    HIPCHK(hipMemcpyAsync(js.data(), c->jscale, c->ndom * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                          c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (int d = 0; d < c->ndom; ++d) {
+        const int k = info[d].iters;
+        if (iters) iters[d] = k;
+        if (converged) converged[d] = info[d].converged;
+        if (resid) {
+            double r = 0.0;
+            if (k > 0) std::memcpy(&r, &res[(size_t)d * c->stride + (k - 1)], sizeof(r));
+            resid[d] = r;
+        }
+        if (jscale) std::memcpy(&jscale[d], &js[d], sizeof(double));
+    }
+    return LB2P_OK;
+}
+
 lb2p_status lb2p_get_field(lb2p_ctx* c, int field, void* out, int dtype, int on_device)
 {
     if (!c || !out) return LB2P_EINVAL;
@@ -1632,6 +1661,7 @@ lb2p_status lb2p_set_populations(lb2p_ctx* c, const double* n_in, int on_device)
     c->status_pending = false;
     HIPCHK(hipStreamSynchronize(c->stream));
     c->initialized = true;
+    c->solved = false;
     c->have_prev = false;
     c->prev_keep = false;
     c->nprev = 0;

@@ -62,7 +62,7 @@ class _Stats(ctypes.Structure):
 
 
 EXPORTED = [
-    "lb2p_default_params", "lb2p_create", "lb2p_create_batch", "lb2p_domain_totals",
+    "lb2p_default_params", "lb2p_create", "lb2p_create_batch", "lb2p_domain_totals", "lb2p_domain_solve",
     "lb2p_autotune", "lb2p_init", "lb2p_step", "lb2p_moments", "lb2p_moments_noalloc",
     "lb2p_get_field", "lb2p_get_populations", "lb2p_set_populations", "lb2p_velocities",
     "lb2p_stats_get", "lb2p_profile_enable", "lb2p_profile_read", "lb2p_destroy", "lb2p_strerror",
@@ -94,6 +94,8 @@ def lib():
         L.lb2p_create.argtypes = [pp, vp, ctypes.POINTER(vp)]
         L.lb2p_create_batch.argtypes = [ctypes.c_int, pp, vp, ctypes.POINTER(vp)]
         L.lb2p_domain_totals.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+        L.lb2p_domain_solve.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
         L.lb2p_autotune.argtypes = [vp, ctypes.c_int]
         L.lb2p_init.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int]
         L.lb2p_step.argtypes = [vp, ctypes.c_int]
@@ -328,6 +330,20 @@ class Context:
         self._check(lib().lb2p_domain_totals(self._ctx, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
                     "lb2p_domain_totals")
         return out
+
+    def domain_solve(self) -> dict:
+        """Per domain, the last j~ solve: passes, last residual, max|j0'| and
+        whether the stop rule held (numpy arrays of ndom entries)."""
+        n = len(self.domains)
+        it = np.zeros(n, dtype=np.int32)
+        res = np.zeros(n)
+        js = np.zeros(n)
+        cv = np.zeros(n, dtype=np.int32)
+        ip = ctypes.POINTER(ctypes.c_int)
+        dp = ctypes.POINTER(ctypes.c_double)
+        self._check(lib().lb2p_domain_solve(self._ctx, it.ctypes.data_as(ip), res.ctypes.data_as(dp),
+                                            js.ctypes.data_as(dp), cv.ctypes.data_as(ip)), "lb2p_domain_solve")
+        return dict(iters=it, resid=res, jscale=js, converged=cv.astype(bool))
 
     def autotune(self, steps: int = 2):
         return self._check(lib().lb2p_autotune(self._ctx, int(steps)), "lb2p_autotune")

@@ -171,3 +171,35 @@ def test_batch_reduced_storage_conserves_mass(L, storage, bound):
     dm = np.abs(t1[:, 0] - t0[:, 0]) / t0[:, 0]
     print(storage, "per-domain relative mass drift over 301 steps: max", f"{dm.max():.2e}", flush=True)
     assert dm.max() <= bound
+
+
+def test_domain_solve_reports_each_domains_stop_rule(L):
+    """lb2p_domain_solve: the stop rule of Sec. IX holds per domain of a
+    batch.  In tolerance mode each domain's last residual meets its own rule,
+    resid <= tol * max|j0'| of that domain; with a fixed pass count every
+    domain reports that count; with max_iter 1 and a tolerance no pass can
+    meet, every domain reports that its rule did not hold."""
+    doms = _domains_2d()
+    rho = np.concatenate([r for _, r, _ in doms])
+    u = np.concatenate([uu for _, _, uu in doms], axis=1)
+    tol = 1e-10
+    with L.Context([_params(L, m, L.STORE_F64, tol=tol) for m, _, _ in doms]) as ctx:
+        with pytest.raises(L.Lb2pError):
+            ctx.domain_solve()          # no solve since init
+        ctx.init(rho, np.ascontiguousarray(u))
+        ctx.step(3)
+        ds = ctx.domain_solve()
+        assert ds["converged"].all() and (ds["iters"] >= 1).all()
+        assert np.all(ds["resid"] <= tol * ds["jscale"]), (ds["resid"], ds["jscale"])
+        assert np.all(ds["jscale"] > 0)
+    with L.Context([_params(L, m, L.STORE_F64, fixed_iter=5) for m, _, _ in doms]) as ctx:
+        ctx.init(rho, np.ascontiguousarray(u))
+        ctx.step(2)
+        ds = ctx.domain_solve()
+        assert (ds["iters"] == 5).all() and ds["converged"].all()
+    with L.Context([_params(L, m, L.STORE_F64, tol=1e-30, max_iter=1) for m, _, _ in doms]) as ctx:
+        ctx.init(rho, np.ascontiguousarray(u))
+        ctx.step(1, allow=(L.ENOCONV,))
+        ds = ctx.domain_solve()
+        assert (ds["iters"] == 1).all() and not ds["converged"].any()
+        assert np.all(ds["resid"] > 0)
