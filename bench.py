@@ -163,7 +163,7 @@ def run_batch(workload, steps, warmup, fixed_iter, graph=True, limit=None, autot
         prof = ctx.profile_read()
         ctx.profile_enable(False)
         out.update(seconds=t1 - t0, prof=prof, stats=st, N=ctx.N, Q=21, D=2, ndom=len(doms),
-                   resid_ratio_max=float(np.max(ds["resid"] / np.maximum(ds["jscale"], 1e-300))),
+                   resid_ratio=ds["resid"] / np.maximum(ds["jscale"], 1e-300), resid_jscale=ds["jscale"],
                    pull=any(p.gamma != 0.0 for p in plist), workload=workload, storage="f32",
                    mass_drift=float(np.max(np.abs(tot[:, 0] - tot0[:, 0]) / tot0[:, 0])))
     return out
@@ -484,9 +484,13 @@ def main():
             value=round(bN * args.batch_steps / bres["seconds"] / 1e6, 2), unit="MLUPS",
             sites=bN, steps=args.batch_steps, ms_per_step=round(1e3 * bres["seconds"] / args.batch_steps, 4),
             solve=f"{args.batch_iters} j~ passes per step (fixed), all timed steps in one HIP graph launch",
-            resid_over_jscale=float(f"{bres['resid_ratio_max']:.3e}"),
-            resid_note="largest over the domains of the last pass's residual / that domain's max|j0'| "
-                       "(the stop rule's two sides, per domain)",
+            resid_over_jscale=dict(
+                worst=float(f"{bres['resid_ratio'].max():.3e}"),
+                worst_domain_max_j0p=float(f"{bres['resid_jscale'][int(bres['resid_ratio'].argmax())]:.3e}"),
+                median=float(f"{np.median(bres['resid_ratio']):.3e}"),
+                note="per domain: the last pass's residual / the domain's max|j0'| (the stop rule's two sides); "
+                     "a domain whose droplet has dissolved has max|j0'| near 0 and its residual at the FP32 "
+                     "floor, so its ratio grows without the iteration being any less converged"),
             max_rel_mass_drift=float(f"{bres['mass_drift']:.3e}"),
             roofline=dict(broof, note="per-kernel HIP events from 4 eager steps after the graph run"),
             kernels={k: v for k, v in bkern.items() if v["launches"]})
