@@ -202,7 +202,7 @@ typedef struct lb2p_ctx lb2p_ctx;
  * rho1 0.3, rho2 1.0, A 0, cs2_rho1 0.45, rho0 = rho1, the given storage,
  * tol 1e-13 (F64), 4e-7 (F32: twice the floor of the FP32 iteration; on the
  * slab workload the FP32 velocity stays within 1e-5 of FP64 over 100 steps)
- * or the format's unit roundoff (BF16 2^-9, F16 2^-12: j0' comes from
+ * or half the format's unit roundoff (BF16 2^-9, F16 2^-12: j0' comes from
  * populations rounded to that relative size, so a tighter rule only spends
  * passes on storage noise), max_iter 200, warm_start 1, iter_prec AUTO, no
  * graph. */

@@ -846,9 +846,10 @@ size_t field_bytes(const lb2p_params& p)
 }
 
 // Default stop-rule tolerance per storage form.  FP64: 1e-13.  FP32: 4e-7,
-// twice the floor of the FP32 iteration.  BF16 and FP16: the format's unit
-// roundoff (2^-9, 2^-12): j0' comes from populations that carry relative
-// rounding of that size, so the fixed point is not known better than that,
+// twice the floor of the FP32 iteration.  BF16 and FP16: half the format's
+// unit roundoff (2^-9, 2^-12, the roundoffs being 2^-8 and 2^-11): j0' comes
+// from populations that carry relative rounding of that size, so the fixed
+// point is not known better than that,
 // and a tighter rule spends passes on the storage noise (measured on the
 // slab workload: the velocity error is the same from 1e-3 to 4e-7).
 double default_tol(int storage)

@@ -29,7 +29,7 @@ SOLVER_FIXED_POINT, SOLVER_CHEBYSHEV = 0, 1
 ITER_AUTO, ITER_F32, ITER_F64 = 0, 1, 2
 F32_TOL_FLOOR = 2e-7
 F32_TOL_DEFAULT = 4e-7
-# lb2p_default_params: FP64 1e-13, FP32 4e-7, BF16/F16 the format's unit roundoff
+# lb2p_default_params: FP64 1e-13, FP32 4e-7, BF16/F16 half the format's unit roundoff
 DEFAULT_TOL = {0: 1e-13, 1: F32_TOL_DEFAULT, 2: 2.0**-9, 3: 2.0**-12}
 STORAGE_NAMES = {"f64": STORE_F64, "f32": STORE_F32, "bf16": STORE_BF16, "f16": STORE_F16}
 
