@@ -700,8 +700,17 @@ __global__ void __launch_bounds__(256) k_iter_jt(const Domain* __restrict__ tab,
 }
 
 // One thread per domain.
-__global__ void k_iter_finish(IterCtl ic, int launched, int ndom, SolveInfo* info, int* nconv)
+// gated = 1: launched ahead of the host's check of the stop rule, it does
+// nothing unless that check found every domain done (go = 1).  gated = 0: it
+// runs and sets go = 1 for the kernels after it.
+__global__ void k_iter_finish(IterCtl ic, int launched, int ndom, SolveInfo* info, int* nconv, int* go,
+                              int gated)
 {
+    if (gated) {
+        if (*go == 0) return;
+    } else if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *go = 1;
+    }
     const int dom = blockIdx.x * blockDim.x + threadIdx.x;
     if (dom >= ndom) return;
     int d = *((volatile int*)(ic.done_at + dom));
@@ -721,8 +730,9 @@ __global__ void k_iter_finish(IterCtl ic, int launched, int ndom, SolveInfo* inf
 // After `launched` passes: apply the stop rule to the last pass of every
 // domain still iterating (as the next pass would), and report for the host's
 // early exit the number of domains whose rule has held (out[0]) and the
-// largest pass count at which it held (out[1]).
-__global__ void k_check_done(IterCtl ic, int launched, int ndom, int* out)
+// largest pass count at which it held (out[1]); go = 1 when that is every
+// domain, else 0 (the kernels that follow a solve run only when go = 1).
+__global__ void k_check_done(IterCtl ic, int launched, int ndom, int* out, int* go)
 {
     __shared__ int cnt, last;
     if (threadIdx.x == 0) { cnt = 0; last = 0; }
@@ -743,7 +753,11 @@ __global__ void k_check_done(IterCtl ic, int launched, int ndom, int* out)
         }
     }
     __syncthreads();
-    if (threadIdx.x == 0) { out[0] = cnt; out[1] = last; }
+    if (threadIdx.x == 0) {
+        out[0] = cnt;
+        out[1] = last;
+        *go = cnt >= ndom ? 1 : 0;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -764,11 +778,13 @@ __global__ void __launch_bounds__(256) k_collide(const Domain* __restrict__ tab,
                                                  const R* __restrict__ u,
                                                  const R* __restrict__ f, const R* __restrict__ jtA,
                                                  const R* __restrict__ jtB, const R* __restrict__ Sig,
-                                                 const R* __restrict__ Xi, const double* __restrict__ mass)
+                                                 const R* __restrict__ Xi, const double* __restrict__ mass,
+                                                 const int* __restrict__ go)
 {
     // multiply-adds fused only as written in each expression, so that both
     // instantiations round a gamma = 0 site identically
 #pragma clang fp contract(on)
+    if (*go == 0) return;   // the solve is not finished (launched ahead of the host's check)
     // Precision.  The O(1) parts -- c_s^2, the local weights and the
     // per-shell rest part (1-g)(w_k rho - o_k) -- are FP64 in every form.
     // The per-velocity Hermite terms (E) are FP64 beside FP64 and FP32
@@ -997,7 +1013,7 @@ __global__ void __launch_bounds__(256) k_import(const Domain* __restrict__ tab,
 
 // Small helpers.
 __global__ void k_reset_ctl(unsigned long long* res, long long nres, unsigned long long* jscale,
-                            int* done_at, int ndom, int* nconv)
+                            int* done_at, int ndom, int* nconv, int* go)
 {
     const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (t < nres) res[t] = 0ull;
@@ -1006,6 +1022,7 @@ __global__ void k_reset_ctl(unsigned long long* res, long long nres, unsigned lo
         done_at[t] = -1;
     }
     if (t == 0 && nconv) *nconv = 0;
+    if (t == 0) *go = 1;
 }
 
 // Deterministic sum of block partials [first, last) (one block).

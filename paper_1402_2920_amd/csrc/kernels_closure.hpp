@@ -30,7 +30,7 @@ template <class R, int TX, int TY>
 __global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 1)))
 k_closure2_zm(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, const R* __restrict__ rho,
               const R* __restrict__ u, const R* __restrict__ X, const R* __restrict__ T,
-              const R* __restrict__ Y, R* __restrict__ Sig)
+              const R* __restrict__ Y, R* __restrict__ Sig, const int* __restrict__ go)
 {
     constexpr int UX = TX + 4, UY = TY + 4;   // tile + 2-wide frame
     constexpr int NFRAME = UX * UY - TX * TY;
@@ -38,6 +38,7 @@ k_closure2_zm(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, co
     // planar fields: X, Txx, Txy, Tyy, Txz, Tyz, Yx, Yy, Yz, rho ux, rho uy, ux, uy, uz
     __shared__ R sl[14][UY][UX];
 
+    if (*go == 0) return;   // the solve is not finished (launched ahead of the host's check)
     const Tile tl = tiles[blockIdx.x];
     if (tl.dom < 0) return;   // uniform per block
     const Domain& dm = tab[tl.dom];
@@ -251,8 +252,10 @@ __global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(si
 k_closure1_zm(const Domain* __restrict__ tab, const Tile* __restrict__ tiles,
               const SolveInfo* __restrict__ info, const R* __restrict__ pf, const R* __restrict__ rho,
               const R* __restrict__ j0p, R* u0, const R* u1, R* jtA, R* jtB, R* __restrict__ X,
-              R* __restrict__ T, R* __restrict__ Y, R* __restrict__ Xi, int form)
+              R* __restrict__ T, R* __restrict__ Y, R* __restrict__ Xi, int form,
+              const int* __restrict__ go)
 {
+    if (*go == 0) return;   // the solve is not finished (launched ahead of the host's check)
     // form = 1 (after a velocity-form solve): the final iterate is u in u0
     // or u1 (by the pass count); j~ = rho u - j0' is formed here at each site
     // (item 7) and stored in the j~ buffer the pass count selects, and u is
@@ -689,12 +692,14 @@ __global__ void __launch_bounds__(TX * TY)
 k_closure1_t2(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, const SolveInfo* __restrict__ info,
               const R* __restrict__ pf, const R* __restrict__ rho, const R* __restrict__ j0p, R* u0,
               const R* __restrict__ u1, R* __restrict__ jtA, R* __restrict__ jtB, R* __restrict__ X,
-              R* __restrict__ T, R* __restrict__ Y, R* __restrict__ Xi, int form)
+              R* __restrict__ T, R* __restrict__ Y, R* __restrict__ Xi, int form,
+              const int* __restrict__ go)
 {
     constexpr int D = 2;
     constexpr int UX = TX + 4, UY = TY + 4;
     __shared__ R sl[4][UY][UX];   // p - p_ref, c_s^2 - c_s^2_ref, ux, uy
 
+    if (*go == 0) return;   // the solve is not finished (launched ahead of the host's check)
     const Tile tl = tiles[blockIdx.x];
     if (tl.dom < 0) return;   // uniform per block
     const Domain& dm = tab[tl.dom];
@@ -814,13 +819,14 @@ template <class R, int TX, int TY>
 __global__ void __launch_bounds__(TX * TY)
 k_closure2_t2(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, const R* __restrict__ rho,
               const R* __restrict__ u, const R* __restrict__ X, const R* __restrict__ T,
-              const R* __restrict__ Y, R* __restrict__ Sig)
+              const R* __restrict__ Y, R* __restrict__ Sig, const int* __restrict__ go)
 {
     constexpr int D = 2;
     constexpr int UX = TX + 4, UY = TY + 4;
     // X, Txx, Tyy, Txy, Yx, Yy, rho ux, rho uy, ux, uy
     __shared__ R sl[10][UY][UX];
 
+    if (*go == 0) return;   // the solve is not finished (launched ahead of the host's check)
     const Tile tl = tiles[blockIdx.x];
     if (tl.dom < 0) return;   // uniform per block
     const Domain& dm = tab[tl.dom];
@@ -1026,10 +1032,12 @@ template <int Q, class R>
 __global__ void __launch_bounds__(256) k_sigma_stencil(const Domain* __restrict__ tab,
                                                        const Tile* __restrict__ tiles,
                                                        const R* __restrict__ pf, const double* __restrict__ mass,
-                                                       const R* __restrict__ u, R* __restrict__ Sig)
+                                                       const R* __restrict__ u, R* __restrict__ Sig,
+                                                       const int* __restrict__ go)
 {
     using L = Lattice<Q>;
     constexpr int D = L::D;
+    if (*go == 0) return;   // the solve is not finished (launched ahead of the host's check)
     const Where w = locate(tab, tiles);
     if (!w.ok) return;
     const Domain& dm = tab[w.dom];

@@ -301,6 +301,7 @@ struct lb2p_ctx {
     int* flags = nullptr;
     int* nconv = nullptr;
     int* ndone = nullptr;
+    int* go = nullptr;           // 1: the last solve is finished (the kernels after it run)
     double* sums = nullptr;
     struct HostReadback {
         int ndone;       // domains whose stop rule has held
@@ -310,6 +311,7 @@ struct lb2p_ctx {
         double sums[4];
     };
     HostReadback* host = nullptr;               // pinned readback area
+    hipEvent_t spec_ev = nullptr;               // marks the arrival of a stop-rule read in host
     bool status_pending = false;               // tolerance-mode status not yet read
     bool initialized = false;
     bool solved = false;         // a j~ solve ran since lb2p_init (lb2p_domain_solve)
@@ -575,6 +577,23 @@ struct Impl {
                            write_fields ? (R*)c->pf : (R*)nullptr);
     }
 
+    static IterCtl iter_ctl(lb2p_ctx* c)
+    {
+        const lb2p_params& p = c->prm;
+        return IterCtl{c->res, c->jscale, c->done_at, c->stride, p.fixed_iter > 0 ? -1.0 : p.tol, c->omega, c->pmax};
+    }
+
+    // State of one solve's pass loop: passes launched, the pass count at
+    // which the last domain met the stop rule (-1 while unknown), the pass
+    // count of the host's next read of the rule, and whether a read is in
+    // flight (its copy lands in c->host when c->spec_ev completes).
+    struct SolveRun {
+        int launched = 0;
+        int last_done = -1;
+        int next_check = 1;
+        bool pending = false;
+    };
+
     // Items 1-8.  In the default (tolerance) mode the host reads how many
     // domains have met the stop rule: first one pass after the previous
     // solve's pass count, then every check_every passes (default 1).  Passes
@@ -588,7 +607,10 @@ struct Impl {
     // form_final: store j~ = rho u - j0' (and u) after a velocity-form
     // solve; a time step leaves that to the first closure kernel
     // (k_closure1_zm, k_closure1_t2), which reads the same words anyway.
-    static lb2p_status solve(lb2p_ctx* c, bool advance = true, bool form_final = true)
+    // spec: return at the first read of the stop rule without waiting for
+    // it (spec->pending); the caller launches the rest of the step, gated on
+    // the device by the rule's outcome, and then finishes the solve.
+    static lb2p_status solve(lb2p_ctx* c, bool advance = true, bool form_final = true, SolveRun* spec = nullptr)
     {
         const lb2p_params& p = c->prm;
         const int max_it = p.fixed_iter > 0 ? p.fixed_iter : p.max_iter;
@@ -596,9 +618,9 @@ struct Impl {
         const long long nres = (long long)c->ndom * c->stride;
         hipLaunchKernelGGL(k_reset_ctl, dim3((unsigned)((std::max<long long>(nres, c->ndom) + 255) / 256)),
                            dim3(256), 0, c->stream, c->res, nres, c->jscale, c->done_at, c->ndom,
-                           (int*)nullptr);
+                           (int*)nullptr, c->go);
         launch_moments(c, true);
-        IterCtl ic{c->res, c->jscale, c->done_at, c->stride, p.fixed_iter > 0 ? -1.0 : p.tol, c->omega, c->pmax};
+        const IterCtl ic = iter_ctl(c);
         {
             ProfScope _ps(c, LB2P_K_FORCE);
             const SolveInfo* prev =
@@ -630,6 +652,29 @@ struct Impl {
             hipLaunchKernelGGL(k_reduce_max, dim3(c->ndom), dim3(256), 0, c->stream, (const double*)c->pmax,
                                (const int*)c->clos_range, c->jscale, 1LL, (const int*)nullptr);
         }
+        SolveRun run;
+        run.next_check = std::max(1, c->last_iters + 1);
+        lb2p_status st = iterate(c, run, spec != nullptr);
+        if (st != LB2P_OK) return st;
+        if (run.pending) {
+            *spec = run;
+            return LB2P_OK;
+        }
+        st = launch_finish(c, run, form_final, false);
+        if (st != LB2P_OK) return st;
+        book(c, run, advance);
+        return LB2P_OK;
+    }
+
+    // Passes run.launched, run.launched + 1, ... until the stop rule holds
+    // in every domain (read by the host at run.next_check, then every
+    // check_every passes) or max_iter.  speculate: at the first read, record
+    // c->spec_ev after the copy and return with run.pending set.
+    static lb2p_status iterate(lb2p_ctx* c, SolveRun& run, bool speculate)
+    {
+        const lb2p_params& p = c->prm;
+        const int max_it = p.fixed_iter > 0 ? p.fixed_iter : p.max_iter;
+        const IterCtl ic = iter_ctl(c);
         const bool fused = !(p.flags & LB2P_FLAG_UNFUSED_SOLVE);
         constexpr int kFusedTX = Lattice<Q>::D == 3 ? fused_tx<R>() : kFused2TX;
         constexpr int kTY = Lattice<Q>::D == 3 ? kFusedTY : kFused2TY;
@@ -638,10 +683,7 @@ struct Impl {
         const dim3 fblock(kFusedTX + 4, Lattice<Q>::D == 3 ? kTY + 4 : kTY, 1);
         const dim3 fgrid((unsigned)c->fused_host.size());
         const int every = p.check_every > 0 ? p.check_every : 1;
-        int next_check = std::max(1, c->last_iters + 1);
-        int last_done = -1;
-        int launched = 0;
-        for (int it = 0; it < max_it; ++it) {
+        for (int it = run.launched; it < max_it; ++it) {
             R* jold = (R*)((it & 1) ? c->jt1 : c->jt0);
             R* jnew = (R*)((it & 1) ? c->jt0 : c->jt1);
             R* uold = (R*)((it & 1) ? c->u1 : c->u);
@@ -685,22 +727,39 @@ struct Impl {
             hipLaunchKernelGGL(k_reduce_max, dim3(c->ndom), dim3(256), 0, c->stream, (const double*)c->pmax,
                                (const int*)(fused ? c->fused_range : c->site_range), c->res + it,
                                (long long)c->stride, (const int*)c->done_at);
-            launched = it + 1;
-            if (p.fixed_iter <= 0 && launched >= next_check && launched < max_it) {
-                next_check = launched + every;
-                hipLaunchKernelGGL(k_check_done, dim3(1), dim3(256), 0, c->stream, ic, launched, c->ndom,
-                                   c->ndone);
+            run.launched = it + 1;
+            if (p.fixed_iter <= 0 && run.launched >= run.next_check && run.launched < max_it) {
+                run.next_check = run.launched + every;
+                hipLaunchKernelGGL(k_check_done, dim3(1), dim3(256), 0, c->stream, ic, run.launched, c->ndom,
+                                   c->ndone, c->go);
                 HIPCHK(hipMemcpyAsync(&c->host->ndone, c->ndone, 2 * sizeof(int), hipMemcpyDeviceToHost,
                                       c->stream));
+                if (speculate) {
+                    HIPCHK(hipEventRecord(c->spec_ev, c->stream));
+                    run.pending = true;
+                    return LB2P_OK;
+                }
                 HIPCHK(hipStreamSynchronize(c->stream));
                 if (c->host->ndone >= c->ndom) {
-                    last_done = c->host->ndone_last;
+                    run.last_done = c->host->ndone_last;
                     break;
                 }
             }
         }
+        return LB2P_OK;
+    }
+
+    // The solve's final record (SolveInfo per domain; the count of domains
+    // that reached max_iter) and, unless a time step leaves it to the first
+    // closure kernel, the final j~ and u.  gated: launched before the
+    // host's read of the stop rule (k_iter_finish then does nothing unless
+    // the rule held in every domain); ungated it also sets go = 1.
+    static lb2p_status launch_finish(lb2p_ctx* c, const SolveRun& run, bool form_final, bool gated)
+    {
+        const IterCtl ic = iter_ctl(c);
+        const bool fused = !(c->prm.flags & LB2P_FLAG_UNFUSED_SOLVE);
         hipLaunchKernelGGL(k_iter_finish, dim3((c->ndom + 255) / 256), dim3(256), 0, c->stream, ic,
-                           launched, c->ndom, c->info, c->nconv);
+                           run.launched, c->ndom, c->info, c->nconv, c->go, gated ? 1 : 0);
         if (fused && form_final)
             hipLaunchKernelGGL((k_jt_final<Q, R>), sgrid(c), sblock(c), 0, c->stream, c->dtab,
                                c->site_tiles, (const SolveInfo*)c->info, (const R*)c->rho,
@@ -710,11 +769,17 @@ struct Impl {
                                c->site_tiles, (const SolveInfo*)c->info, (const R*)c->rho,
                                (const R*)c->j0p, (const R*)c->jt0, (const R*)c->jt1, (R*)c->u);
         HIPCHK(hipGetLastError());
-        if (p.fixed_iter <= 0) {
-            c->last_iters = last_done >= 0 ? last_done : launched;
+        return LB2P_OK;
+    }
+
+    // Host bookkeeping once the solve's pass count is known.
+    static void book(lb2p_ctx* c, const SolveRun& run, bool advance)
+    {
+        if (c->prm.fixed_iter <= 0) {
+            c->last_iters = run.last_done >= 0 ? run.last_done : run.launched;
             c->status_pending = true;
         } else {
-            c->last_iters = max_it;
+            c->last_iters = c->prm.fixed_iter;
         }
         if (advance) {
             c->have_prev = true;
@@ -722,7 +787,6 @@ struct Impl {
             c->nprev = std::min(c->nprev + 1, 3);
         }
         c->solved = true;
-        return LB2P_OK;
     }
 
     // Before lb2p_moments re-solves the current state: move the last step's
@@ -742,8 +806,64 @@ struct Impl {
         // after the fused solve the first closure kernel forms the final j~
         // and u (k_closure1_zm in 3D, k_closure1_t2 in 2D)
         const bool closure_forms = !(c->prm.flags & LB2P_FLAG_UNFUSED_SOLVE);
-        lb2p_status st = solve(c, true, !closure_forms);
+        // Tolerance mode: the rest of the step is launched behind the
+        // host's first read of the stop rule, without waiting for it, so the
+        // GPU does not idle while the read travels.  Those kernels run only
+        // if the rule then held in every domain (go = 1, set on the device by
+        // that check); otherwise they do nothing, the passes go on and the
+        // rest of the step is launched again after them.
+        const bool speculate = closure_forms && c->prm.fixed_iter <= 0 && !c->capturing;
+        SolveRun run;
+        lb2p_status st = solve(c, true, !closure_forms, speculate ? &run : nullptr);
         if (st != LB2P_OK) return st;
+        if (!run.pending) return post_solve(c, closure_forms);
+        st = launch_finish(c, run, false, true);
+        if (st != LB2P_OK) return st;
+        const size_t mark = c->pending.size();
+        st = post_kernels(c, closure_forms);
+        if (st != LB2P_OK) return st;
+        HIPCHK(hipEventSynchronize(c->spec_ev));
+        if (c->host->ndone >= c->ndom) {
+            run.last_done = c->host->ndone_last;
+        } else {
+            // the launches behind the read did nothing: drop their timing
+            // records, run the remaining passes and launch them again
+            for (size_t k = mark; k < c->pending.size(); ++k) {
+                c->pool.push_back(c->pending[k].a);
+                c->pool.push_back(c->pending[k].b);
+            }
+            c->pending.resize(mark);
+            run.pending = false;
+            st = iterate(c, run, false);
+            if (st != LB2P_OK) return st;
+            st = launch_finish(c, run, false, false);
+            if (st != LB2P_OK) return st;
+            st = post_kernels(c, closure_forms);
+            if (st != LB2P_OK) return st;
+        }
+        book(c, run, true);
+        return end_step(c);
+    }
+
+    static lb2p_status post_solve(lb2p_ctx* c, bool closure_forms)
+    {
+        lb2p_status st = post_kernels(c, closure_forms);
+        if (st != LB2P_OK) return st;
+        return end_step(c);
+    }
+
+    static lb2p_status end_step(lb2p_ctx* c)
+    {
+        std::swap(c->A, c->B);
+        c->sigma_valid = true;
+        return LB2P_OK;
+    }
+
+    // Items 9-13 after the solve: the closure fields, Sigma and the
+    // collision into the other population buffer.  Each kernel runs only if
+    // go = 1 (the solve is finished).
+    static lb2p_status post_kernels(lb2p_ctx* c, bool closure_forms)
+    {
         {
             ProfScope _ps(c, LB2P_K_CLOSURE1);
             if constexpr (Lattice<Q>::D == 3) {
@@ -752,19 +872,22 @@ struct Impl {
                                    dim3(TX, kFusedTY, 1), 0, c->stream, c->dtab, c->clos_tiles,
                                    (const SolveInfo*)c->info, (const R*)c->pf, (const R*)c->rho,
                                    (const R*)c->j0p, (R*)c->u, (const R*)c->u1, (R*)c->jt0, (R*)c->jt1,
-                                   (R*)c->X, (R*)c->T, (R*)c->Y, (R*)c->Xi, closure_forms ? 1 : 0);
+                                   (R*)c->X, (R*)c->T, (R*)c->Y, (R*)c->Xi, closure_forms ? 1 : 0,
+                                   (const int*)c->go);
             } else {
                 hipLaunchKernelGGL((k_closure1_t2<R, kClos2TX, kClos2TY>), dim3((unsigned)c->clos_host.size()),
                                    dim3(kClos2TX, kClos2TY, 1), 0, c->stream, c->dtab, c->clos_tiles,
                                    (const SolveInfo*)c->info, (const R*)c->pf, (const R*)c->rho,
                                    (const R*)c->j0p, (R*)c->u, (const R*)c->u1, (R*)c->jt0, (R*)c->jt1,
-                                   (R*)c->X, (R*)c->T, (R*)c->Y, (R*)c->Xi, closure_forms ? 1 : 0);
+                                   (R*)c->X, (R*)c->T, (R*)c->Y, (R*)c->Xi, closure_forms ? 1 : 0,
+                                   (const int*)c->go);
             }
         }
         if (c->prm.flags & LB2P_FLAG_STENCIL_CLOSURE) {
             ProfScope _ps(c, LB2P_K_CLOSURE2);
             hipLaunchKernelGGL((k_sigma_stencil<Q, R>), sgrid(c), sblock(c), 0, c->stream, c->dtab, c->site_tiles,
-                               (const R*)c->pf, (const double*)c->mass, (const R*)c->u, (R*)c->Sig);
+                               (const R*)c->pf, (const double*)c->mass, (const R*)c->u, (R*)c->Sig,
+                               (const int*)c->go);
         } else {
             ProfScope _ps(c, LB2P_K_CLOSURE2);
             if constexpr (Lattice<Q>::D == 3) {
@@ -772,12 +895,12 @@ struct Impl {
                 hipLaunchKernelGGL((k_closure2_zm<R, TX, kFusedTY>), dim3((unsigned)c->clos_host.size()),
                                    dim3(TX, kFusedTY, 1), 0, c->stream, c->dtab, c->clos_tiles,
                                    (const R*)c->rho, (const R*)c->u, (const R*)c->X, (const R*)c->T,
-                                   (const R*)c->Y, (R*)c->Sig);
+                                   (const R*)c->Y, (R*)c->Sig, (const int*)c->go);
             } else {
                 hipLaunchKernelGGL((k_closure2_t2<R, kClos2TX, kClos2TY>), dim3((unsigned)c->clos_host.size()),
                                    dim3(kClos2TX, kClos2TY, 1), 0, c->stream, c->dtab, c->clos_tiles,
                                    (const R*)c->rho, (const R*)c->u, (const R*)c->X, (const R*)c->T,
-                                   (const R*)c->Y, (R*)c->Sig);
+                                   (const R*)c->Y, (R*)c->Sig, (const int*)c->go);
             }
         }
         {
@@ -786,11 +909,10 @@ struct Impl {
             hipLaunchKernelGGL(kc, sgrid(c), sblock(c), 0, c->stream, c->dtab,
                                c->site_tiles, (const SolveInfo*)c->info, (const S*)c->A, (S*)c->B,
                                (const R*)c->u, (const R*)c->f, (const R*)c->jt0,
-                               (const R*)c->jt1, (const R*)c->Sig, (const R*)c->Xi, (const double*)c->mass);
+                               (const R*)c->jt1, (const R*)c->Sig, (const R*)c->Xi, (const double*)c->mass,
+                               (const int*)c->go);
         }
         HIPCHK(hipGetLastError());
-        std::swap(c->A, c->B);
-        c->sigma_valid = true;
         return LB2P_OK;
     }
 
@@ -978,6 +1100,7 @@ void free_ctx(lb2p_ctx* c)
     if (c->fused_tiles) (void)hipFree(c->fused_tiles);
     if (c->clos_tiles) (void)hipFree(c->clos_tiles);
     if (c->host) (void)hipHostFree(c->host);
+    if (c->spec_ev) (void)hipEventDestroy(c->spec_ev);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (auto& p : c->pending) {
         (void)hipEventDestroy(p.a);
@@ -1132,6 +1255,7 @@ lb2p_status create_impl(int ndom, const lb2p_params* pp, void* hip_stream, lb2p_
                           sizeof(int) + 2 * sizeof(SolveInfo)) * (size_t)ndom + 64;
     if (e == hipSuccess) e = hipMalloc(&c->ctl, sbytes);
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->host, sizeof(lb2p_ctx::HostReadback), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->spec_ev, hipEventDisableTiming);
     if (e == hipSuccess && p0.solver == LB2P_SOLVER_CHEBYSHEV)
         e = hipMalloc((void**)&c->omega, sizeof(double) * nres);
     if (e == hipSuccess) e = hipMalloc((void**)&c->mass, sizeof(double) * (size_t)S);
@@ -1156,6 +1280,7 @@ lb2p_status create_impl(int ndom, const lb2p_params* pp, void* hip_stream, lb2p_
     c->flags = (int*)(sb + 0);
     c->nconv = (int*)(sb + 4);
     c->ndone = (int*)(sb + 8);   // two ints
+    c->go = (int*)(sb + 16);
     c->sums = (double*)(sb + 64);
     c->res = (unsigned long long*)(sb + 256);
     c->jscale = c->res + nres;
