@@ -327,13 +327,23 @@ typedef enum {
     LB2P_NKERNEL = 8
 } lb2p_kernel;
 
-/* Diagnostic timing: when enabled, every launch of the classes above is
- * bracketed by HIP events on the context's stream.  enable resets the
- * totals; read synchronises the stream and returns, per class, the summed
- * event time in ms (ms_out[LB2P_NKERNEL]) and the launch count
+/* Diagnostic timing: when enabled, every launch of the selected classes
+ * (lb2p_profile_classes; by default all of the above) is bracketed by HIP
+ * events on the context's stream, and every launch of the others is
+ * counted.  enable resets the totals; read synchronises the stream and
+ * returns, per class, the summed event time in ms (ms_out[LB2P_NKERNEL];
+ * 0 for a class not selected) and the launch count
  * (count_out[LB2P_NKERNEL]).  Errors: EINVAL. */
 lb2p_status lb2p_profile_enable(lb2p_ctx *ctx, int on);
 lb2p_status lb2p_profile_read(lb2p_ctx *ctx, double *ms_out, long long *count_out);
+
+/* Select the classes the profiler brackets with events: bit (1u << k) for
+ * class k of lb2p_kernel; (1u << LB2P_NKERNEL) - 1 selects all (the
+ * default).  Each bracketed launch adds two event records to the stream, which
+ * the GPU processes between kernels, so a caller that times one class
+ * selects only that one.  Applies to launches after the call; totals are
+ * kept.  Errors: EINVAL (NULL context, or a bit at LB2P_NKERNEL or above). */
+lb2p_status lb2p_profile_classes(lb2p_ctx *ctx, unsigned mask);
 
 /* Release everything the context owns.  NULL is accepted. */
 void lb2p_destroy(lb2p_ctx *ctx);

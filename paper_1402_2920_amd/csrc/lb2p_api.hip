@@ -341,6 +341,7 @@ struct lb2p_ctx {
     struct Pending { hipEvent_t a, b; int kid; };
     std::vector<Pending> pending;
     std::vector<hipEvent_t> pool;
+    unsigned prof_mask = ~0u;    // classes bracketed by events (the others are counted)
     double prof_ms[LB2P_NKERNEL] = {0};
     long long prof_n[LB2P_NKERNEL] = {0};
 };
@@ -365,29 +366,49 @@ hipEvent_t prof_event(lb2p_ctx* c)
     return e;
 }
 
-// Bracket one launch of kernel class `kid` with events on the context stream.
+// Bracket one launch of kernel class `kid` with events on the context stream
+// (classes outside prof_mask are only counted: a record without events).
 struct ProfScope {
     lb2p_ctx* c;
     int kid;
+    bool on = false;
     hipEvent_t a = nullptr;
     ProfScope(lb2p_ctx* cc, int k) : c(cc), kid(k)
     {
         if (c->prof && !c->capturing) {
-            a = prof_event(c);
-            if (a) (void)hipEventRecord(a, c->stream);
+            on = true;
+            if ((c->prof_mask >> k) & 1u) {
+                a = prof_event(c);
+                if (a) (void)hipEventRecord(a, c->stream);
+            }
         }
     }
     ~ProfScope()
     {
+        if (!on) return;
         if (a) {
             hipEvent_t b = prof_event(c);
             if (b) {
                 (void)hipEventRecord(b, c->stream);
                 c->pending.push_back({a, b, kid});
+            } else {
+                c->pool.push_back(a);
             }
+        } else {
+            c->pending.push_back({nullptr, nullptr, kid});
         }
     }
 };
+
+// Return the events of records [from, end) to the pool and drop the records.
+void prof_drop(lb2p_ctx* c, size_t from)
+{
+    for (size_t k = from; k < c->pending.size(); ++k) {
+        if (c->pending[k].a) c->pool.push_back(c->pending[k].a);
+        if (c->pending[k].b) c->pool.push_back(c->pending[k].b);
+    }
+    c->pending.resize(std::min(from, c->pending.size()));
+}
 
 // Resolve recorded events into per-class totals (synchronises the stream).
 void prof_collect(lb2p_ctx* c)
@@ -395,15 +416,17 @@ void prof_collect(lb2p_ctx* c)
     if (c->pending.empty()) return;
     (void)hipStreamSynchronize(c->stream);
     for (auto& p : c->pending) {
+        if (!p.a) {   // counted, not timed
+            c->prof_n[p.kid] += 1;
+            continue;
+        }
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
             c->prof_ms[p.kid] += ms;
             c->prof_n[p.kid] += 1;
         }
-        c->pool.push_back(p.a);
-        c->pool.push_back(p.b);
     }
-    c->pending.clear();
+    prof_drop(c, 0);
 }
 
 // Deal a domain-ordered tile list to workgroup ids: id b runs on XCD b % 8,
@@ -828,11 +851,7 @@ struct Impl {
         } else {
             // the launches behind the read did nothing: drop their timing
             // records, run the remaining passes and launch them again
-            for (size_t k = mark; k < c->pending.size(); ++k) {
-                c->pool.push_back(c->pending[k].a);
-                c->pool.push_back(c->pending[k].b);
-            }
-            c->pending.resize(mark);
+            prof_drop(c, mark);
             run.pending = false;
             st = iterate(c, run, false);
             if (st != LB2P_OK) return st;
@@ -1102,10 +1121,7 @@ void free_ctx(lb2p_ctx* c)
     if (c->host) (void)hipHostFree(c->host);
     if (c->spec_ev) (void)hipEventDestroy(c->spec_ev);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
-    for (auto& p : c->pending) {
-        (void)hipEventDestroy(p.a);
-        (void)hipEventDestroy(p.b);
-    }
+    prof_drop(c, 0);   // records of counted-only launches hold no events
     for (auto e : c->pool) (void)hipEventDestroy(e);
     delete c;
 }
@@ -1901,6 +1917,13 @@ lb2p_status lb2p_profile_enable(lb2p_ctx* c, int on)
         c->prof_n[k] = 0;
     }
     c->prof = on != 0;
+    return LB2P_OK;
+}
+
+lb2p_status lb2p_profile_classes(lb2p_ctx* c, unsigned mask)
+{
+    if (!c || (mask >> LB2P_NKERNEL) != 0u) return LB2P_EINVAL;
+    c->prof_mask = mask;
     return LB2P_OK;
 }
 

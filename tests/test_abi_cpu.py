@@ -62,6 +62,11 @@ def test_default_params(L):
     assert L.DEFAULT_TOL[L.STORE_BF16] == 2.0**-9 and L.DEFAULT_TOL[L.STORE_F16] == 2.0**-12
 
 
+def test_profile_classes_rejects_null_context(L):
+    assert L.lib().lb2p_profile_classes(None, 1) == L.EINVAL
+    assert L.lib().lb2p_profile_classes(None, 0) == L.EINVAL
+
+
 def _p(L, **kw):
     base = dict(lattice=59, nx=16, ny=16, nz=16, A=0.745, cs2_rho1=0.39, kappa=0.01)
     base.update(kw)

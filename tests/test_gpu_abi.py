@@ -1,6 +1,6 @@
 """C-ABI entry points without a test elsewhere: lb2p_set_populations (a
 state handed in from outside, then advanced) and the diagnostic profiler
-(lb2p_profile_enable / lb2p_profile_read)."""
+(lb2p_profile_enable / lb2p_profile_read / lb2p_profile_classes)."""
 import numpy as np
 import pytest
 
@@ -84,3 +84,38 @@ def test_profiler_counts_launches(L):
         ctx.step(1)
         q = ctx.profile_read()
         assert q["moments"][1] == 1 and q["collide"][1] == 1
+        # one class timed, every class still counted
+        ctx.profile_classes(["collide"])
+        ctx.profile_enable(True)
+        ctx.step(2)
+        r = ctx.profile_read()
+        assert r["collide"][1] == 2 and r["collide"][0] > 0.0
+        for k in ("moments", "force", "closure1", "closure2"):
+            assert r[k] == (0.0, 2), (k, r[k])
+        assert r["iter_fused"][1] >= 2 and r["iter_fused"][0] == 0.0
+        assert L.lib().lb2p_profile_classes(ctx._ctx, 1 << len(L.KERNEL_NAMES)) == L.EINVAL
+        ctx.profile_classes(None)
+        ctx.profile_enable(True)
+        ctx.step(1)
+        assert all(v[1] >= 1 and v[0] > 0.0 for k, v in ctx.profile_read().items()
+                   if k not in ("iter_q", "iter_jt"))
+
+
+def test_profiler_teardown_leaves_no_hip_error(L):
+    """Launches of classes the profiler only counts leave records without
+    events; a context destroyed with such records pending (here the moments
+    launch of lb2p_stats_get) must not leave a HIP error behind for the
+    caller's next runtime call."""
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so")
+    hip.hipGetLastError.restype = ctypes.c_int
+    rho, u, model = small_case(59, (20, 12, 10))
+    hip.hipGetLastError()
+    with L.Context(_params(L, model, L.STORE_F32, tol=1e-6, max_iter=200)) as ctx:
+        ctx.init(rho, u)
+        ctx.profile_classes(["iter_fused"])
+        ctx.profile_enable(True)
+        ctx.step(2)
+        ctx.profile_read()
+        ctx.stats()
+    assert hip.hipGetLastError() == 0
