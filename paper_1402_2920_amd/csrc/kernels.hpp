@@ -74,8 +74,9 @@ struct Domain {
 // One block's work: a tile of a domain (dom < 0: padding, the block exits).
 struct Tile {
     int dom, x0, y0, z0;
-    int len;   // planes marched by the solve kernel (z chunk)
-    int pad0, pad1, pad2;
+    int len;    // planes (3D) or rows (2D) marched by the solve kernel
+    int slot;   // 2D solve strips: the block's residual slot (see block_max_part)
+    int pad1, pad2;
 };
 
 template <class S>
@@ -362,10 +363,11 @@ __device__ __forceinline__ double wave_sum(double v)
 // thousands of atomics (or coherent loads) on one address serialise across
 // the XCDs.  Slots are in domain order: a launch grid of n blocks (a multiple
 // of 8) runs tile (b % 8) * (n / 8) + b / 8 of the domain-ordered list at
-// workgroup b (the XCD deal), so that is the block's slot.
+// workgroup b (the XCD deal), so that is the block's slot, unless the tile
+// list was reordered and the tile names its slot (slot >= 0).
 // NaN is stored as +inf so that it is never lost.  Every thread of the block
 // must call it.
-__device__ inline void block_max_part(double* part, double v)
+__device__ inline void block_max_part(double* part, double v, int slot = -1)
 {
     __shared__ double red[16];
     if (v != v) v = __longlong_as_double(0x7ff0000000000000LL);
@@ -379,7 +381,7 @@ __device__ inline void block_max_part(double* part, double v)
         double m = red[0];
         for (int k = 1; k < nw; ++k) m = fmax(m, red[k]);
         const unsigned n = gridDim.x, b = blockIdx.x;
-        part[(b % 8u) * (n / 8u) + b / 8u] = m;
+        part[slot >= 0 ? (unsigned)slot : (b % 8u) * (n / 8u) + b / 8u] = m;
     }
 }
 

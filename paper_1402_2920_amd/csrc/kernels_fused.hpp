@@ -542,7 +542,7 @@ k_iter_fused2(const Domain* __restrict__ tab, const Tile* __restrict__ tiles, It
 #pragma unroll
         for (int a = 0; a < 2; ++a) bstore<R>(bV[a], io, un[a]);
     }
-    block_max_part(ic.part, dsum == dsum ? (double)dmax : (double)dsum);
+    block_max_part(ic.part, dsum == dsum ? (double)dmax : (double)dsum, tl.slot);
 }
 
 // u = (j0' + j~)/rho for the final iterate (item 8).

@@ -528,7 +528,22 @@ lb2p_status build_tiles(lb2p_ctx* c)
     frange[c->ndom] = (int)fused.size();
     crange[c->ndom] = (int)clos.size();
     c->site_host = deal_xcd(site);
-    c->fused_host = fused.empty() ? fused : deal_xcd(fused);
+    if (c->D == 2 && !fused.empty()) {
+        // The 2D solve strips differ in length (a domain's height) by up to
+        // 8x.  They run longest first, dealt round-robin to the XCDs, so no
+        // long strip starts at the end of a pass; each keeps its slot in the
+        // domain-ordered list for its residual partial.
+        for (size_t k = 0; k < fused.size(); ++k) fused[k].slot = (int)k;
+        std::vector<Tile> srt = fused;
+        std::stable_sort(srt.begin(), srt.end(), [](const Tile& a, const Tile& b) { return a.len > b.len; });
+        const size_t n = (srt.size() + 7) / 8 * 8, per = n / 8;
+        std::vector<Tile> pre(n);
+        for (auto& t : pre) t.dom = -1;
+        for (size_t j = 0; j < srt.size(); ++j) pre[(j % 8) * per + j / 8] = srt[j];
+        c->fused_host = deal_xcd(pre);
+    } else {
+        c->fused_host = fused.empty() ? fused : deal_xcd(fused);
+    }
     c->clos_host = clos.empty() ? clos : deal_xcd(clos);
     auto upload = [&](const std::vector<Tile>& h, Tile*& dptr, size_t& cap) -> lb2p_status {
         if (h.empty()) return LB2P_OK;
