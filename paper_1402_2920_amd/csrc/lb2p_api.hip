@@ -529,17 +529,44 @@ lb2p_status build_tiles(lb2p_ctx* c)
     crange[c->ndom] = (int)clos.size();
     c->site_host = deal_xcd(site);
     if (c->D == 2 && !fused.empty()) {
-        // The 2D solve strips differ in length (a domain's height) by up to
-        // 8x.  They run longest first, dealt round-robin to the XCDs, so no
-        // long strip starts at the end of a pass; each keeps its slot in the
-        // domain-ordered list for its residual partial.
+        // The 2D solve strips differ in length (their domain's height), by
+        // up to 8x in a batch.  Longest first, and neighbours together: the
+        // domains, tallest first, are cut into runs of adjacent strips (at
+        // most 1/32 of the pass's strip rows each, so a large domain still
+        // spreads over the XCDs), and each run goes to the XCD with the
+        // fewest strip rows so far.  An XCD then runs its strips in that
+        // order, with a strip's x-neighbours (whose columns its stencil
+        // reads) on the same XCD and in the same L2.  Each strip keeps its
+        // slot in the domain-ordered list for its residual partial; XCDs
+        // with fewer strips are padded with empty tiles.
         for (size_t k = 0; k < fused.size(); ++k) fused[k].slot = (int)k;
-        std::vector<Tile> srt = fused;
-        std::stable_sort(srt.begin(), srt.end(), [](const Tile& a, const Tile& b) { return a.len > b.len; });
-        const size_t n = (srt.size() + 7) / 8 * 8, per = n / 8;
-        std::vector<Tile> pre(n);
+        long long rows_total = 0;
+        for (const Tile& t : fused) rows_total += t.len;
+        const long long cap = std::max(1LL, rows_total / 32);
+        std::vector<int> order(c->ndom);
+        for (int d = 0; d < c->ndom; ++d) order[d] = d;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int a, int b) { return c->dom[a].g.ny > c->dom[b].g.ny; });
+        std::vector<std::vector<Tile>> per_xcd(8);
+        long long load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int d : order) {
+            const int h = std::max(1, c->dom[d].g.ny);
+            const int run = (int)std::max(1LL, cap / h);
+            for (int t0 = frange[d]; t0 < frange[d + 1]; t0 += run) {
+                const int t1 = std::min(frange[d + 1], t0 + run);
+                int k = 0;
+                for (int q = 1; q < 8; ++q)
+                    if (load[q] < load[k]) k = q;
+                for (int t = t0; t < t1; ++t) per_xcd[k].push_back(fused[t]);
+                load[k] += (long long)(t1 - t0) * h;
+            }
+        }
+        size_t per = 0;
+        for (const auto& v : per_xcd) per = std::max(per, v.size());
+        std::vector<Tile> pre(8 * per);
         for (auto& t : pre) t.dom = -1;
-        for (size_t j = 0; j < srt.size(); ++j) pre[(j % 8) * per + j / 8] = srt[j];
+        for (int k = 0; k < 8; ++k)
+            for (size_t i = 0; i < per_xcd[k].size(); ++i) pre[k * per + i] = per_xcd[k][i];
         c->fused_host = deal_xcd(pre);
     } else {
         c->fused_host = fused.empty() ? fused : deal_xcd(fused);
