@@ -123,10 +123,12 @@ def run_gpu(workload, storage, steps, warmup, shape=None, profile=True, tol=None
         # run; the timed window samples the run after that transient
         ctx.step(settle + warmup)
         prof_all = dom = None
+        passes_all = passes = None
         if profile:
             ctx.profile_enable(True)
             ctx.step(prof_steps)
             prof_all = ctx.profile_read()
+            passes_all = ctx.profile_passes()
             dom = dominant_class(prof_all)
             ctx.profile_classes([dom])
             ctx.profile_enable(True)
@@ -135,9 +137,14 @@ def run_gpu(workload, storage, steps, warmup, shape=None, profile=True, tol=None
         ctx.step(steps)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        prof = ctx.profile_read() if profile else None
+        if profile:
+            prof = ctx.profile_read()
+            passes = ctx.profile_passes()
+        else:
+            prof = None
         stats = ctx.stats()
-        out.update(seconds=t1 - t0, prof=prof, prof_all=prof_all, dominant=dom,
+        out.update(seconds=t1 - t0, prof=prof, prof_all=prof_all, dominant=dom, passes=passes,
+                   passes_all=passes_all,
                    prof_steps=prof_steps if profile else 0, stats=stats, N=P.N, Q=P.lattice, D=d,
                    shape=shape, params=P, pull=P.gamma != 0.0, workload=workload, storage=storage,
                    tol=P.to_c().tol)
@@ -181,8 +188,9 @@ def run_batch(workload, steps, warmup, fixed_iter, graph=True, limit=None, autot
         ctx.profile_enable(True)
         ctx.step(4)
         prof = ctx.profile_read()
+        passes = ctx.profile_passes()
         ctx.profile_enable(False)
-        out.update(seconds=t1 - t0, prof=prof, stats=st, N=ctx.N, Q=21, D=2, ndom=len(doms),
+        out.update(seconds=t1 - t0, prof=prof, passes=passes, stats=st, N=ctx.N, Q=21, D=2, ndom=len(doms),
                    resid_ratio=ds["resid"] / np.maximum(ds["jscale"], 1e-300), resid_jscale=ds["jscale"],
                    pull=any(p.gamma != 0.0 for p in plist), workload=workload, storage="f32",
                    mass_drift=float(np.max(np.abs(tot[:, 0] - tot0[:, 0]) / tot0[:, 0])))
@@ -210,22 +218,37 @@ def roofline(res, storage, warm=2, cheb=False):
     pull = res.get("pull", False)
     dom = res.get("dominant") or dominant_class(prof)
     ms, n = prof[dom]
-    avg_s = ms / 1e3 / max(n, 1)
+    # the solve pass: per pass that did work (launches after the stop rule
+    # held return at once; their few microseconds stay in the total)
+    work = work_launches(dom, n, res.get("passes"))
+    avg_s = ms / 1e3 / max(work, 1)
     design = site_bytes(dom, Q, D, s, r, warm, cheb, pull)
     alg = minimal_pass_bytes(D, r, cheb) if dom == "iter_fused" else design
     achieved = alg * N / avg_s / 1e9
-    per_kernel = {k: dict(ms_total=round(v[0], 3), launches=v[1],
-                          avg_us=round(1e3 * v[0] / max(v[1], 1), 2),
-                          gbs=round(site_bytes(k, Q, D, s, r, warm, cheb, pull) * N / (v[0] / 1e3 / max(v[1], 1)) / 1e9, 1)
-                          if v[1] else None)
-                  for k, v in (res.get("prof_all") or prof).items()}
+    pk = res.get("prof_all") or prof
+    pk_passes = res.get("passes_all") if res.get("prof_all") else res.get("passes")
+    per_kernel = {}
+    for k, v in pk.items():
+        w = work_launches(k, v[1], pk_passes)
+        per_kernel[k] = dict(ms_total=round(v[0], 3), launches=v[1], working_launches=w,
+                             avg_us=round(1e3 * v[0] / max(w, 1), 2),
+                             gbs=round(site_bytes(k, Q, D, s, r, warm, cheb, pull) * N / (v[0] / 1e3 / max(w, 1)) / 1e9, 1)
+                             if v[1] else None)
     traffic = measured_traffic(dom, res)
     out = dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic, bytes_per_site=alg, launches=n,
-               avg_launch_us=round(avg_s * 1e6, 2))
+               working_launches=work, avg_launch_us=round(avg_s * 1e6, 2))
     if alg != design:
         out.update(design_bytes_per_site=design, design_frac=round(design * N / avg_s / 1e9 / HBM_PEAK_GBS, 4))
     return out, per_kernel
+
+
+def work_launches(kernel, launches, passes):
+    """Launches of a kernel class that did work: for the solve pass, the
+    passes the library counted (`lb2p_profile_passes`), when known."""
+    if kernel in ("iter_fused", "iter_q", "iter_jt") and passes is not None and launches:
+        return min(launches, passes)
+    return launches
 
 
 def traffic_table(res):
@@ -297,15 +320,17 @@ def step_hbm(res, storage, warm, cheb, steps, secs, copy_gbs):
                     bytes_per_site_step=round(total_bytes / (N * steps), 1))
 
     floor = rate(2 * Q * s * N * steps)
-    model = rate(sum(site_bytes(k, Q, D, s, r, warm, cheb, pull) * N * v[1] for k, v in prof.items() if v[1]))
+    work = {k: work_launches(k, v[1], res.get("passes")) for k, v in prof.items()}
+    model = rate(sum(site_bytes(k, Q, D, s, r, warm, cheb, pull) * N * work[k] for k, v in prof.items() if v[1]))
     tt = traffic_table(res)
     meas = None
     if tt is not None and all(k in tt for k, v in prof.items() if v[1]):
-        meas = rate(sum(tt[k] * v[1] for k, v in prof.items() if v[1]))
+        meas = rate(sum(tt[k] * work[k] for k, v in prof.items() if v[1]))
     return dict(peak_gbs=HBM_PEAK_GBS, copy_gbs=round(copy_gbs, 1) if copy_gbs else None,
                 population_floor=floor, algorithmic=model, measured=meas,
-                note="time: the whole timed region; bytes: every kernel launch in it except the "
-                     "residual reductions (a few KB each)")
+                note="time: the whole timed region; bytes: every kernel launch in it that did work (the "
+                     "solve-pass launches after the stop rule held return at once), except the residual "
+                     "reductions (a few KB each)")
 
 
 def cpu_baseline(workload, nsteps_max=30, budget_s=15.0):

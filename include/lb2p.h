@@ -258,7 +258,11 @@ lb2p_status lb2p_init(lb2p_ctx *ctx, const void *rho, const void *u, int dtype, 
 /* Advance nsteps >= 0 time steps (Supplemental items 1-12 each).
  * Asynchronous on the context's stream when fixed_iter > 0; otherwise the
  * host reads the convergence count back during each solve (check_every),
- * and the max_iter count and the non-finite flag once per call.
+ * and the max_iter count and the non-finite flag once per call.  In that
+ * mode the rest of a step is enqueued before the host waits for the solve's
+ * first read (it runs only if every domain's stop rule held, else it is
+ * enqueued again after the remaining passes), so the call returns with the
+ * last step's closure and collision still in flight on the stream.
  * Returns ENOCONV if any step's solve hit max_iter, ENONFINITE once a NaN or
  * Inf density was seen (sticky until lb2p_init).
  * Errors: ESTATE (no init), ENOCONV, EHIP. */
@@ -344,6 +348,14 @@ lb2p_status lb2p_profile_read(lb2p_ctx *ctx, double *ms_out, long long *count_ou
  * selects only that one.  Applies to launches after the call; totals are
  * kept.  Errors: EINVAL (NULL context, or a bit at LB2P_NKERNEL or above). */
 lb2p_status lb2p_profile_classes(lb2p_ctx *ctx, unsigned mask);
+
+/* Solve passes that did work since lb2p_profile_enable (while profiling is
+ * on): per solve, the pass count at which the last domain met the stop rule
+ * (in fixed mode, or when max_iter ends it: the passes launched).  The
+ * solve-pass launch counts of lb2p_profile_read also hold the launches after
+ * the stop rule held, which return at once; their event time is a few
+ * microseconds each.  Errors: EINVAL (NULL argument). */
+lb2p_status lb2p_profile_passes(lb2p_ctx *ctx, long long *passes_out);
 
 /* Release everything the context owns.  NULL is accepted. */
 void lb2p_destroy(lb2p_ctx *ctx);

@@ -342,6 +342,7 @@ struct lb2p_ctx {
     std::vector<Pending> pending;
     std::vector<hipEvent_t> pool;
     unsigned prof_mask = ~0u;    // classes bracketed by events (the others are counted)
+    long long prof_passes = 0;   // solve passes that did work while profiling
     double prof_ms[LB2P_NKERNEL] = {0};
     long long prof_n[LB2P_NKERNEL] = {0};
 };
@@ -846,6 +847,7 @@ struct Impl {
         } else {
             c->last_iters = c->prm.fixed_iter;
         }
+        if (c->prof && !c->capturing) c->prof_passes += c->last_iters;
         if (advance) {
             c->have_prev = true;
             c->prev_keep = false;
@@ -1959,6 +1961,14 @@ lb2p_status lb2p_profile_enable(lb2p_ctx* c, int on)
         c->prof_n[k] = 0;
     }
     c->prof = on != 0;
+    c->prof_passes = 0;
+    return LB2P_OK;
+}
+
+lb2p_status lb2p_profile_passes(lb2p_ctx* c, long long* passes_out)
+{
+    if (!c || !passes_out) return LB2P_EINVAL;
+    *passes_out = c->prof_passes;
     return LB2P_OK;
 }
 

@@ -65,7 +65,7 @@ EXPORTED = [
     "lb2p_default_params", "lb2p_create", "lb2p_create_batch", "lb2p_domain_totals", "lb2p_domain_solve",
     "lb2p_autotune", "lb2p_init", "lb2p_step", "lb2p_moments", "lb2p_moments_noalloc",
     "lb2p_get_field", "lb2p_get_populations", "lb2p_set_populations", "lb2p_velocities",
-    "lb2p_stats_get", "lb2p_profile_enable", "lb2p_profile_read", "lb2p_profile_classes", "lb2p_destroy", "lb2p_strerror",
+    "lb2p_stats_get", "lb2p_profile_enable", "lb2p_profile_read", "lb2p_profile_classes", "lb2p_profile_passes", "lb2p_destroy", "lb2p_strerror",
 ]
 KERNEL_NAMES = ["moments", "force", "iter_q", "iter_jt", "closure1", "closure2", "collide",
                 "iter_fused"]
@@ -108,6 +108,7 @@ def lib():
         L.lb2p_stats_get.argtypes = [vp, ctypes.POINTER(_Stats)]
         L.lb2p_profile_enable.argtypes = [vp, ctypes.c_int]
         L.lb2p_profile_classes.argtypes = [vp, ctypes.c_uint]
+        L.lb2p_profile_passes.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong)]
         L.lb2p_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_longlong)]
         L.lb2p_destroy.argtypes = [vp]
@@ -322,6 +323,13 @@ class Context:
         the others are counted."""
         mask = (1 << len(KERNEL_NAMES)) - 1 if names is None else sum(1 << KERNEL_NAMES.index(k) for k in names)
         return self._check(lib().lb2p_profile_classes(self._ctx, mask), "lb2p_profile_classes")
+
+    def profile_passes(self) -> int:
+        """Solve passes that did work since profile_enable (the solve-pass
+        launch count also holds launches after the stop rule held)."""
+        n = ctypes.c_longlong(0)
+        self._check(lib().lb2p_profile_passes(self._ctx, ctypes.byref(n)), "lb2p_profile_passes")
+        return n.value
 
     def profile_read(self) -> dict:
         """{kernel class: (total ms, launches)} since profile_enable."""

@@ -65,6 +65,8 @@ def test_default_params(L):
 def test_profile_classes_rejects_null_context(L):
     assert L.lib().lb2p_profile_classes(None, 1) == L.EINVAL
     assert L.lib().lb2p_profile_classes(None, 0) == L.EINVAL
+    n = ctypes.c_longlong(0)
+    assert L.lib().lb2p_profile_passes(None, ctypes.byref(n)) == L.EINVAL
 
 
 def _p(L, **kw):

@@ -73,6 +73,24 @@ def test_roofline_solve_pass_on_its_minimal_bytes():
     assert roof["kernel"] == "collide" and roof["bytes_per_site"] == 350 and "design_bytes_per_site" not in roof
 
 
+def test_solve_pass_priced_per_working_pass():
+    # launches after the stop rule held return at once: the solve pass's
+    # average is taken over the passes that did work, when they are known
+    N = 1 << 20
+    prof = {k: (0.0, 0) for k in ("moments", "force", "closure1", "closure2", "collide")}
+    prof.update(collide=(1.0, 5), iter_fused=(4.0, 29))
+    res = dict(prof=prof, Q=59, D=3, N=N, workload="none", storage="f32", passes=25)
+    roof, kern = bench.roofline(res, "f32", warm=1)
+    assert roof["kernel"] == "iter_fused" and roof["launches"] == 29 and roof["working_launches"] == 25
+    assert roof["avg_launch_us"] == pytest.approx(4000.0 / 25, abs=0.01)
+    assert kern["iter_fused"]["working_launches"] == 25 and kern["collide"]["working_launches"] == 5
+    # without the count, every launch counts
+    roof, _ = bench.roofline(dict(res, passes=None), "f32", warm=1)
+    assert roof["working_launches"] == 29
+    assert bench.work_launches("collide", 5, 3) == 5
+    assert bench.work_launches("iter_fused", 29, 40) == 29
+
+
 def test_traffic_table_matches_workload_only():
     res = dict(workload="no_such_workload", storage="f32")
     assert bench.traffic_table(res) is None

@@ -101,6 +101,28 @@ def test_profiler_counts_launches(L):
                    if k not in ("iter_q", "iter_jt"))
 
 
+def test_profiler_counts_working_passes(L):
+    """lb2p_profile_passes counts the solve passes that did work: per step
+    the pass count of its solve (lb2p_stats_get), while the launch count
+    also holds the launches after the stop rule held."""
+    import ctypes
+    rho, u, model = small_case(59, (20, 12, 10))
+    with L.Context(_params(L, model, L.STORE_F32, tol=1e-6, max_iter=200)) as ctx:
+        ctx.init(rho, u)
+        ctx.step(2)
+        ctx.profile_enable(True)
+        iters = []
+        for _ in range(4):
+            ctx.step(1)
+            iters.append(ctx.stats()["iters"])
+        passes = ctx.profile_passes()
+        launches = ctx.profile_read()["iter_fused"][1]
+        assert passes == sum(iters) and 4 <= passes <= launches, (iters, passes, launches)
+        assert L.lib().lb2p_profile_passes(ctx._ctx, None) == L.EINVAL
+        ctx.profile_enable(True)
+        assert ctx.profile_passes() == 0
+
+
 def test_profiler_teardown_leaves_no_hip_error(L):
     """Launches of classes the profiler only counts leave records without
     events; a context destroyed with such records pending (here the moments
