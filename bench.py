@@ -459,7 +459,7 @@ def main():
     ap.add_argument("--batch-iters", type=int, default=7, help="fixed j~ passes per batched step")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(the step would shard by z-slabs with halo exchange; not built).", file=sys.stderr)
         sys.exit(2)
 
