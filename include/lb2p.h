@@ -249,6 +249,14 @@ lb2p_status lb2p_domain_solve(lb2p_ctx *ctx, int *iters, double *resid, double *
  * Errors: ESTATE, ENOMEM, EHIP. */
 lb2p_status lb2p_autotune(lb2p_ctx *ctx, int steps);
 
+/* Set the choices the autotuner makes: the site kernels' block shape
+ * (bx x by threads with bx * by = 256, one site each, a bx x by patch of a
+ * plane; or bx = 256, by = 0: blocks of 256 consecutive sites in index
+ * order, which leave no lane idle on narrow domains) and the plane count tz
+ * of the 3D solve pass's chunks.  Results do not depend on the choice.
+ * Errors: EINVAL (NULL context, another shape, tz < 1), ENOMEM, EHIP. */
+lb2p_status lb2p_set_tiling(lb2p_ctx *ctx, int bx, int by, int tz);
+
 /* Set the initial populations n_i(r, 0) = n_eq(rho(r), u(r)) of Sec. III with
  * the local weights.  rho [N], u [d][N]; dtype lb2p_dtype; host or device.
  * Resets the sticky status and the warm-start j~ to zero.

@@ -74,9 +74,10 @@ struct Domain {
 // One block's work: a tile of a domain (dom < 0: padding, the block exits).
 struct Tile {
     int dom, x0, y0, z0;
-    int len;    // planes (3D) or rows (2D) marched by the solve kernel
+    int len;    // planes (3D) or rows (2D) marched by the solve kernel; sites of a linear tile
     int slot;   // 2D solve strips: the block's residual slot (see block_max_part)
-    int pad1, pad2;
+    int lin;    // site kernels: 1 = the block covers sites x0 .. x0+len-1 of the domain in index order
+    int pad2;
 };
 
 template <class S>
@@ -223,15 +224,32 @@ struct Where {
     bool ok;
 };
 
+// The site of this thread: a bx x by patch of a plane at (x0, y0, z0), or,
+// for a linear tile, site x0 + (thread index) in the domain's index order
+// x + nx (y + ny z), so that no lane of a narrow domain's tile idles.
 __device__ __forceinline__ Where locate(const Domain* __restrict__ tab, const Tile* __restrict__ tiles)
 {
     const Tile t = tiles[blockIdx.x];
     Where w;
     w.dom = t.dom;
+    w.ok = false;
+    if (t.lin) {
+        const int lid = (int)(threadIdx.x + blockDim.x * threadIdx.y);
+        w.x = 0; w.y = 0; w.z = 0;
+        if (t.dom >= 0 && lid < t.len) {
+            const Geom& g = tab[t.dom].g;
+            const int i = t.x0 + lid;
+            const int row = i / g.nx;
+            w.x = i - row * g.nx;
+            w.z = row / g.ny;
+            w.y = row - w.z * g.ny;
+            w.ok = true;
+        }
+        return w;
+    }
     w.x = t.x0 + threadIdx.x;
     w.y = t.y0 + threadIdx.y;
     w.z = t.z0;
-    w.ok = false;
     if (t.dom >= 0) {
         const Geom& g = tab[t.dom].g;
         w.ok = w.x < g.nx && w.y < g.ny;

@@ -474,19 +474,29 @@ lb2p_status build_tiles(lb2p_ctx* c)
         // every z: after the XCD deal each XCD owns one slab, so the planes a
         // z-stencil revisits (z +- 2) are a slab's share of a plane and stay
         // in that XCD's L2.  Small domains stay whole (one XCD each).
-        const int rows = (g.ny + c->by - 1) / c->by;
+        // by == 0 selects linear site tiles: 256 consecutive sites each.
+        const int by = std::max(c->by, 1);
+        const int rows = (g.ny + by - 1) / by;
         const int frows = (g.ny + kFusedTY - 1) / kFusedTY;
         const bool slabs = c->D == 3 && (long long)rows * g.nz * ((g.nx + c->bx - 1) / c->bx) >= 4096;
         const int nslab = slabs ? 8 : 1;
-        for (int sl = 0; sl < nslab; ++sl) {
-            const int r0 = (int)((long long)rows * sl / nslab), r1 = (int)((long long)rows * (sl + 1) / nslab);
-            for (int z = 0; z < g.nz; ++z)
-                for (int r = r0; r < r1; ++r)
-                    for (int x = 0; x < g.nx; x += c->bx) {
-                        Tile t{};
-                        t.dom = d; t.x0 = x; t.y0 = r * c->by; t.z0 = z; t.len = 1;
-                        site.push_back(t);
-                    }
+        if (c->by == 0) {
+            for (long long i = 0; i < g.N; i += 256) {
+                Tile t{};
+                t.dom = d; t.x0 = (int)i; t.len = (int)std::min<long long>(256, g.N - i); t.lin = 1;
+                site.push_back(t);
+            }
+        } else {
+            for (int sl = 0; sl < nslab; ++sl) {
+                const int r0 = (int)((long long)rows * sl / nslab), r1 = (int)((long long)rows * (sl + 1) / nslab);
+                for (int z = 0; z < g.nz; ++z)
+                    for (int r = r0; r < r1; ++r)
+                        for (int x = 0; x < g.nx; x += c->bx) {
+                            Tile t{};
+                            t.dom = d; t.x0 = x; t.y0 = r * c->by; t.z0 = z; t.len = 1;
+                            site.push_back(t);
+                        }
+            }
         }
         if (c->D == 2) {
             // the 2D fused solve pass: kFused2TX-wide strips over the whole
@@ -626,7 +636,7 @@ lb2p_status build_tiles(lb2p_ctx* c)
 template <int Q, class R, class S>
 struct Impl {
     static dim3 sgrid(lb2p_ctx* c) { return dim3((unsigned)c->site_host.size()); }
-    static dim3 sblock(lb2p_ctx* c) { return dim3(c->bx, c->by, 1); }
+    static dim3 sblock(lb2p_ctx* c) { return c->by == 0 ? dim3(256, 1, 1) : dim3(c->bx, c->by, 1); }
 
     static void launch_init(lb2p_ctx* c)
     {
@@ -1214,7 +1224,8 @@ void load_tune_file()
     char key[128];
     int bx, by, tz;
     while (std::fscanf(fh, "%127s %d %d %d", key, &bx, &by, &tz) == 4)
-        if (bx > 0 && by > 0 && bx * by == 256 && tz > 0) tune_cache()[key] = TuneChoice{bx, by, tz};
+        if (((bx > 0 && by > 0 && bx * by == 256) || (bx == 256 && by == 0)) && tz > 0)
+            tune_cache()[key] = TuneChoice{bx, by, tz};
     std::fclose(fh);
 }
 
@@ -1877,14 +1888,15 @@ lb2p_status lb2p_autotune(lb2p_ctx* c, int steps)
     c->prm.graph_steps = 0;
     const bool prof_keep = c->prof;
     c->prof = false;
-    const int shapes[4][2] = {{64, 4}, {128, 2}, {256, 1}, {32, 8}};
+    // site-tile shapes (bx, by); (256, 0): linear tiles of 256 consecutive sites
+    const int shapes[5][2] = {{64, 4}, {128, 2}, {256, 1}, {32, 8}, {256, 0}};
     const int tzs[4] = {16, 32, 64, 128};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     lb2p_status st = LB2P_OK;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) st = LB2P_EHIP;
     TuneChoice best{c->bx, c->by, c->tz};
     float best_ms = 1e30f;
-    for (int si = 0; si < 4 && st == LB2P_OK; ++si)
+    for (int si = 0; si < 5 && st == LB2P_OK; ++si)
         for (int ti = 0; ti < (c->D == 3 ? 4 : 1) && st == LB2P_OK; ++ti) {
             c->bx = shapes[si][0];
             c->by = shapes[si][1];
@@ -1970,6 +1982,16 @@ lb2p_status lb2p_profile_passes(lb2p_ctx* c, long long* passes_out)
     if (!c || !passes_out) return LB2P_EINVAL;
     *passes_out = c->prof_passes;
     return LB2P_OK;
+}
+
+lb2p_status lb2p_set_tiling(lb2p_ctx* c, int bx, int by, int tz)
+{
+    if (!c || tz < 1) return LB2P_EINVAL;
+    if (!((bx > 0 && by > 0 && bx * by == 256) || (bx == 256 && by == 0))) return LB2P_EINVAL;
+    c->bx = bx;
+    c->by = by;
+    c->tz = tz;
+    return build_tiles(c);
 }
 
 lb2p_status lb2p_profile_classes(lb2p_ctx* c, unsigned mask)

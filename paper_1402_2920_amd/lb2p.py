@@ -65,7 +65,8 @@ EXPORTED = [
     "lb2p_default_params", "lb2p_create", "lb2p_create_batch", "lb2p_domain_totals", "lb2p_domain_solve",
     "lb2p_autotune", "lb2p_init", "lb2p_step", "lb2p_moments", "lb2p_moments_noalloc",
     "lb2p_get_field", "lb2p_get_populations", "lb2p_set_populations", "lb2p_velocities",
-    "lb2p_stats_get", "lb2p_profile_enable", "lb2p_profile_read", "lb2p_profile_classes", "lb2p_profile_passes", "lb2p_destroy", "lb2p_strerror",
+    "lb2p_stats_get", "lb2p_profile_enable", "lb2p_profile_read", "lb2p_profile_classes", "lb2p_profile_passes",
+    "lb2p_set_tiling", "lb2p_destroy", "lb2p_strerror",
 ]
 KERNEL_NAMES = ["moments", "force", "iter_q", "iter_jt", "closure1", "closure2", "collide",
                 "iter_fused"]
@@ -108,6 +109,7 @@ def lib():
         L.lb2p_stats_get.argtypes = [vp, ctypes.POINTER(_Stats)]
         L.lb2p_profile_enable.argtypes = [vp, ctypes.c_int]
         L.lb2p_profile_classes.argtypes = [vp, ctypes.c_uint]
+        L.lb2p_set_tiling.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.lb2p_profile_passes.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong)]
         L.lb2p_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_longlong)]
@@ -362,6 +364,11 @@ class Context:
 
     def autotune(self, steps: int = 2):
         return self._check(lib().lb2p_autotune(self._ctx, int(steps)), "lb2p_autotune")
+
+    def set_tiling(self, bx: int, by: int, tz: int = 128):
+        """The site kernels' block shape (bx * by = 256, or bx = 256, by = 0
+        for blocks of 256 consecutive sites) and the 3D solve chunk length."""
+        return self._check(lib().lb2p_set_tiling(self._ctx, int(bx), int(by), int(tz)), "lb2p_set_tiling")
 
     def stats(self) -> dict:
         st = _Stats()

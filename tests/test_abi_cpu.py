@@ -67,6 +67,7 @@ def test_profile_classes_rejects_null_context(L):
     assert L.lib().lb2p_profile_classes(None, 0) == L.EINVAL
     n = ctypes.c_longlong(0)
     assert L.lib().lb2p_profile_passes(None, ctypes.byref(n)) == L.EINVAL
+    assert L.lib().lb2p_set_tiling(None, 256, 0, 128) == L.EINVAL
 
 
 def _p(L, **kw):
