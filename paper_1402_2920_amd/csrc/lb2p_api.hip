@@ -800,9 +800,13 @@ struct Impl {
                                        (const R*)c->j0p, (const R*)jold, jnew, (R*)c->u);
                 }
             }
-            hipLaunchKernelGGL(k_reduce_max, dim3(c->ndom), dim3(256), 0, c->stream, (const double*)c->pmax,
-                               (const int*)(fused ? c->fused_range : c->site_range), c->res + it,
-                               (long long)c->stride, (const int*)c->done_at);
+            // the pass's residual per domain: read by the next pass's stop
+            // rule (tolerance mode); with a fixed pass count only the last
+            // one is read (lb2p_domain_solve, lb2p_stats_get)
+            if (p.fixed_iter <= 0 || it == max_it - 1)
+                hipLaunchKernelGGL(k_reduce_max, dim3(c->ndom), dim3(256), 0, c->stream, (const double*)c->pmax,
+                                   (const int*)(fused ? c->fused_range : c->site_range), c->res + it,
+                                   (long long)c->stride, (const int*)c->done_at);
             run.launched = it + 1;
             if (p.fixed_iter <= 0 && run.launched >= run.next_check && run.launched < max_it) {
                 run.next_check = run.launched + every;
