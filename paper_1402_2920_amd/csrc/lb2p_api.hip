@@ -311,7 +311,7 @@ struct lb2p_ctx {
         double sums[4];
     };
     HostReadback* host = nullptr;               // pinned readback area
-    hipEvent_t spec_ev = nullptr;               // marks the arrival of a stop-rule read in host
+    hipEvent_t spec_ev = nullptr;               // marks the arrival of a stop-rule read in pinned host memory
     bool status_pending = false;               // tolerance-mode status not yet read
     bool initialized = false;
     bool solved = false;         // a j~ solve ran since lb2p_init (lb2p_domain_solve)
@@ -936,7 +936,7 @@ struct Impl {
         return LB2P_OK;
     }
 
-    // Items 9-13 after the solve: the closure fields, Sigma and the
+    // Items 9-12 after the solve: the closure fields, Sigma and the
     // collision into the other population buffer.  Each kernel runs only if
     // go = 1 (the solve is finished).
     static lb2p_status post_kernels(lb2p_ctx* c, bool closure_forms)
