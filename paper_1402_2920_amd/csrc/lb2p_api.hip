@@ -38,7 +38,7 @@ constexpr double kPi = 3.14159265358979323846;
 template <class R>
 constexpr int fused_tx() { return sizeof(R) == 4 ? 64 : 32; }
 constexpr int kFusedTY = 8;
-constexpr int kClosTZ = 32;     // z chunk of the 3D closure kernels
+constexpr int kClosTZ = 32;     // longest z chunk of the 3D closure kernels (clos_tz picks it per context)
 constexpr int kFused2TX = 32, kFused2TY = 8;    // 2D solve pass: 32-wide strips, 8-row chunks (36 x 8 threads)
 constexpr int kClos2TX = 32, kClos2TY = 8;      // 2D closure kernels: LDS tiles (256 threads)
 int fused_tx_of(size_t rsize) { return rsize == 4 ? fused_tx<float>() : fused_tx<double>(); }
@@ -463,6 +463,22 @@ void free_graphs(lb2p_ctx* c)
 // (Re)build both tile lists for the current block shapes.
 lb2p_status build_tiles(lb2p_ctx* c)
 {
+    // z chunk of the 3D force and closure kernels: 32 planes, halved (to 8
+    // at least) while a launch would have fewer than 1024 blocks, i.e. two
+    // rounds of two blocks per CU (a 128^3 grid has 32 tiles per plane:
+    // 8-plane chunks take its step from 0.89 to 0.77 ms; at 256^3, 128
+    // tiles per plane, 32-plane chunks are the fastest)
+    int ctz = kClosTZ;
+    if (c->D == 3) {
+        auto blocks = [&](int tz) {
+            long long n = 0;
+            for (const auto& dd : c->dom)
+                n += (long long)((dd.g.nx + fused_tx_of(c->rsize) - 1) / fused_tx_of(c->rsize)) *
+                     ((dd.g.ny + kFusedTY - 1) / kFusedTY) * ((dd.g.nz + tz - 1) / tz);
+            return n;
+        };
+        while (ctz > 8 && blocks(ctz) < 1024) ctz /= 2;
+    }
     std::vector<Tile> site, fused, clos;
     std::vector<int> srange(c->ndom + 1, 0), frange(c->ndom + 1, 0), crange(c->ndom + 1, 0);
     for (int d = 0; d < c->ndom; ++d) {
@@ -514,11 +530,11 @@ lb2p_status build_tiles(lb2p_ctx* c)
                     clos.push_back(t);
                 }
         } else {
-            // the solve pass marches tz planes; the closure kernels, which
-            // have registers for two blocks per CU, march kClosTZ (more
-            // blocks in flight)
+            // the solve pass marches tz planes; the force and closure
+            // kernels, which have registers for two blocks per CU, march
+            // ctz planes (more blocks in flight)
             for (int pass = 0; pass < 2; ++pass) {
-                const int tz = std::min(pass == 0 ? c->tz : kClosTZ, g.nz);
+                const int tz = std::min(pass == 0 ? c->tz : ctz, g.nz);
                 std::vector<Tile>& lst = pass == 0 ? fused : clos;
                 for (int sl = 0; sl < nslab; ++sl) {
                     const int r0 = (int)((long long)frows * sl / nslab),
