@@ -1910,14 +1910,14 @@ lb2p_status lb2p_autotune(lb2p_ctx* c, int steps)
     c->prof = false;
     // site-tile shapes (bx, by); (256, 0): linear tiles of 256 consecutive sites
     const int shapes[5][2] = {{64, 4}, {128, 2}, {256, 1}, {32, 8}, {256, 0}};
-    const int tzs[4] = {16, 32, 64, 128};
+    const int tzs[5] = {8, 16, 32, 64, 128};   // solve-pass chunks (8 pays on grids of 64^3 and below)
     hipEvent_t e0 = nullptr, e1 = nullptr;
     lb2p_status st = LB2P_OK;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) st = LB2P_EHIP;
     TuneChoice best{c->bx, c->by, c->tz};
     float best_ms = 1e30f;
     for (int si = 0; si < 5 && st == LB2P_OK; ++si)
-        for (int ti = 0; ti < (c->D == 3 ? 4 : 1) && st == LB2P_OK; ++ti) {
+        for (int ti = 0; ti < (c->D == 3 ? 5 : 1) && st == LB2P_OK; ++ti) {
             c->bx = shapes[si][0];
             c->by = shapes[si][1];
             c->tz = tzs[ti];

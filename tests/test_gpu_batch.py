@@ -153,10 +153,11 @@ def test_autotune_keeps_state_and_results(L):
 
 
 def test_site_tilings_give_identical_results(L):
-    """The site kernels' block shape changes which thread handles a site,
-    not what it computes: plane patches and linear tiles of 256 consecutive
-    sites (lb2p_set_tiling) give the same populations to the bit, for a 3D
-    domain and for a batch of narrow 2D domains; other shapes are refused."""
+    """The site kernels' block shape and the solve pass's chunk length
+    change which thread handles a site, not what it computes: plane patches,
+    linear tiles of 256 consecutive sites and 8- or 32-plane chunks
+    (lb2p_set_tiling) give the same populations to the bit, for a 3D domain
+    and for a batch of narrow 2D domains; other shapes are refused."""
     rho, u, m = small_case(59, (40, 24, 36))
     P = _params(L, m, L.STORE_F32, tol=1e-6)
     doms = _domains_2d(8)
@@ -165,13 +166,14 @@ def test_site_tilings_give_identical_results(L):
     u2 = np.ascontiguousarray(np.concatenate([uu for _, _, uu in doms], axis=1))
     for params, r_, u_ in ((P, rho, np.ascontiguousarray(u)), (plist, rho2, u2)):
         outs = []
-        for shape in ((64, 4), (256, 0), (32, 8)):
+        # (bx, by, solve-pass chunk planes)
+        for shape in ((64, 4, 32), (256, 0, 32), (32, 8, 32), (64, 4, 8)):
             with L.Context(params) as ctx:
-                ctx.set_tiling(shape[0], shape[1], 32)
+                ctx.set_tiling(*shape)
                 ctx.init(r_, u_)
                 ctx.step(3)
                 outs.append(ctx.populations())
-        assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+        assert all(np.array_equal(outs[0], o) for o in outs[1:])
     with L.Context(P) as ctx:
         for bad in ((128, 4, 32), (256, 1, 0), (255, 0, 32), (0, 256, 32)):
             assert L.lib().lb2p_set_tiling(ctx._ctx, *bad) == L.EINVAL, bad
